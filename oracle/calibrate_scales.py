@@ -1,0 +1,116 @@
+"""Compute the global rate scale s of each synthetic mechanism with the oracle.
+
+The literal generators (A up to 1e14 cm^3/mol/s, |Delta G/RT| up to ~100)
+produce chemistry far too stiff for any explicit fast method at the stated
+substep sizes.  Every forward and reverse rate is therefore multiplied by one
+constant s per mechanism (K_c unchanged), chosen so that the longest RK4
+substep h_max of the workload satisfies
+
+    s = 0.5 / (h_max * max over initial cells of rho(J_F))
+
+with rho(J_F) the spectral radius of the (S+1)x(S+1) Jacobian of f^F at s=1
+(J_F scales linearly with s).  0.5 sits well inside the RK4 stability
+interval (2.785 on the negative real axis).  Heat release moves cells to
+stiffer states during a run, so s is then lowered until the same bound holds
+at every stage start of the workload's full run (all slow steps, fast stages
+only) on an evenly spaced sample of cells, and the run stays finite.
+
+Writes paper_2211_03293_amd/rate_scales.json.  Only the oracle computes here.
+
+Usage:  python oracle/calibrate_scales.py [--sample N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, _ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2211_03293_amd import inputs as I  # noqa: E402
+
+TARGET = 0.5
+
+
+def spectral_radii(orc, y, n_cells, chunk=8192):
+    out = []
+    for a in range(0, n_cells, chunk):
+        b = min(n_cells, a + chunk)
+        J = orc.jacobians_soa(np.ascontiguousarray(y[:, a:b]), b - a)
+        out.append(np.abs(np.linalg.eigvals(J)).max(axis=1))
+    return np.concatenate(out)
+
+
+def calibrate(config: int, sample: int | None, traj_sample: int = 1024):
+    cfg = I.CONFIGS[config]
+    mech = I.make_mechanism(config, with_scale=False)
+    orc = O.Oracle(mech)
+    y = I.initial_state(config)
+    n_cells = cfg.n_cells
+    idx = np.arange(n_cells)
+    if sample and sample < n_cells:
+        idx = np.sort(np.random.Generator(np.random.PCG64(7)).choice(n_cells, sample, replace=False))
+    ys = np.ascontiguousarray(y[:, idx])
+    rho = spectral_radii(orc, ys, idx.size)
+    h_max = I.longest_substep(config)
+    s0 = TARGET / (h_max * rho.max())
+    s, hist = s0, []
+    for _ in range(12):
+        worst = trajectory_h_rho(config, mech.with_scale(s), n_sample=traj_sample)
+        hist.append((s, worst))
+        if worst <= TARGET * 1.0001:
+            break
+        s = s * (TARGET / worst if np.isfinite(worst) else 0.25)
+    return dict(s=float(s), s_initial=float(s0), h_max=h_max,
+                rho_max_unscaled=float(rho.max()),
+                rho_median_unscaled=float(np.median(rho)), cells_used=int(idx.size),
+                trajectory_sample=traj_sample, iterations=[[float(a), float(b)] for a, b in hist],
+                target_h_rho=TARGET)
+
+
+def trajectory_h_rho(config, mech, n_sample):
+    """Max h*rho(J_F) over stage starts and run end of the full fast-only run."""
+    cfg = I.CONFIGS[config]
+    tb = I.table_mis_kw3()
+    orc = O.Oracle(mech)
+    y = I.initial_state(config)
+    idx = np.linspace(0, cfg.n_cells - 1, min(n_sample, cfg.n_cells)).astype(np.int64)
+    ys = np.ascontiguousarray(y[:, idx])
+    n = idx.size
+    worst = 0.0
+    for _step in range(cfg.n_slow_steps):
+        for i in range(1, tb.s):
+            L = (tb.c[i] - tb.c[i - 1]) * cfg.H
+            h = L / cfg.n_sub
+            worst = max(worst, h * spectral_radii(orc, ys, n).max())
+            ys, st, _, _ = orc.fast_stage_soa(ys, np.zeros((1, ys.shape[0], n)), L,
+                                              O.rk4_opts(cfg.n_sub))
+            if (st != 0).any():
+                return float("inf")
+    h_max = I.longest_substep(config)
+    return max(worst, h_max * spectral_radii(orc, ys, n).max())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sample", type=int, default=65536)
+    args = ap.parse_args()
+    res = {}
+    for mc in (0, 1, 3):
+        res[str(mc)] = calibrate(mc, args.sample)
+        print(mc, res[str(mc)], flush=True)
+    out = dict(
+        note="global rate scale per mechanism; written by oracle/calibrate_scales.py",
+        scales=res)
+    with open(I.SCALES_PATH, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", I.SCALES_PATH)
+
+
+if __name__ == "__main__":
+    main()

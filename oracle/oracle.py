@@ -1,0 +1,275 @@
+"""ctypes loader for the CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The product path never imports this module.
+
+Arrays are numpy float64 / int32, C-contiguous.  State layout is SoA:
+y[comp, cell] with comp 0..S-1 the mass fractions Y_k and comp S the
+temperature T; the leading dimension `ld` is y.shape[1].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "mlp_oracle.c")]
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+             "-std=c11", "-Wall"]
+
+ST_NONFINITE, ST_MAXSTEPS, ST_TRANGE, ST_NEARTIE = 1, 2, 4, 8
+
+
+def build(force: bool = False) -> str:
+    srcs = [s for s in _SRC if os.path.exists(s)]
+    stale = force or not os.path.exists(_LIB) or any(
+        os.path.getmtime(s) > os.path.getmtime(_LIB) for s in srcs)
+    if stale:
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, *srcs, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Mech(C.Structure):
+    _fields_ = [("S", C.c_int), ("R", C.c_int),
+                ("reac", C.POINTER(C.c_int32)), ("prod", C.POINTER(C.c_int32)),
+                ("lnA", C.POINTER(C.c_double)), ("beta", C.POINTER(C.c_double)),
+                ("theta", C.POINTER(C.c_double)), ("g_a", C.POINTER(C.c_double)),
+                ("g_b", C.POINTER(C.c_double)), ("W", C.POINTER(C.c_double)),
+                ("cv", C.POINTER(C.c_double)), ("rho", C.c_double), ("T_ref", C.c_double)]
+
+
+class Fast(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int), ("mech", C.POINTER(Mech)),
+                ("A", C.POINTER(C.c_double))]
+
+
+class Table(C.Structure):
+    _fields_ = [("s", C.c_int), ("n_gamma", C.c_int), ("c", C.POINTER(C.c_double)),
+                ("gamma", C.POINTER(C.c_double))]
+
+
+class FastOpts(C.Structure):
+    _fields_ = [("method", C.c_int), ("n_sub", C.c_int), ("rtol", C.c_double),
+                ("atol_Y", C.c_double), ("atol_T", C.c_double), ("max_steps", C.c_int)]
+
+
+class AdvDiff(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("u", C.c_double * 3), ("D", C.c_double), ("dx", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _lib.ora_energy.restype = C.c_double
+        _lib.ora_zonneveld_try.restype = C.c_double
+        _lib.ora_num_threads.restype = C.c_int
+    return _lib
+
+
+def _p(a, ct=C.c_double):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """Holds a mechanism (or a linear fast RHS) and the ctypes structures."""
+
+    def __init__(self, mech=None, A_fast=None):
+        self._keep = []
+        if mech is not None:
+            d = dict(reac=np.ascontiguousarray(mech.reactants, dtype=np.int32),
+                     prod=np.ascontiguousarray(mech.products, dtype=np.int32),
+                     lnA=_f64(mech.lnA), beta=_f64(mech.beta), theta=_f64(mech.theta),
+                     g_a=_f64(mech.g_a), g_b=_f64(mech.g_b), W=_f64(mech.W), cv=_f64(mech.cv))
+            self._keep.append(d)
+            self.m = Mech(mech.n_species, mech.n_reactions, _p(d["reac"], C.c_int32),
+                          _p(d["prod"], C.c_int32), _p(d["lnA"]), _p(d["beta"]),
+                          _p(d["theta"]), _p(d["g_a"]), _p(d["g_b"]), _p(d["W"]), _p(d["cv"]),
+                          float(mech.rho), float(mech.T_ref))
+            self.n = mech.n_species + 1
+            self.f = Fast(0, self.n, C.pointer(self.m), None)
+        else:
+            A = _f64(A_fast)
+            self._keep.append(A)
+            self.n = A.shape[0]
+            self.f = Fast(1, self.n, None, _p(A))
+        self.L = lib()
+
+    # ---- single-cell chemistry -------------------------------------------
+    def rhs(self, y):
+        y = _f64(y)
+        out = np.zeros(self.n)
+        self.L.ora_fast_rhs(C.byref(self.f), _p(y), _p(out))
+        return out
+
+    def rhs_parts(self, y):
+        y = _f64(y)
+        S, R = self.m.S, self.m.R
+        out, kf, kr, q, wd = np.zeros(self.n), np.zeros(R), np.zeros(R), np.zeros(R), np.zeros(S)
+        self.L.ora_chem_rhs_parts(C.byref(self.m), _p(y), _p(out), _p(kf), _p(kr), _p(q), _p(wd))
+        return dict(ydot=out, kf=kf, kr=kr, q=q, wdot=wd)
+
+    def energy(self, y):
+        return self.L.ora_energy(C.byref(self.m), _p(_f64(y)))
+
+    def rhs_soa(self, y):
+        y = _f64(y)
+        out = np.zeros_like(y)
+        self.L.ora_fast_rhs_soa(C.byref(self.f), y.shape[1], y.shape[1], _p(y), _p(out))
+        return out
+
+    def jacobian(self, y):
+        y = _f64(y)
+        J = np.zeros((self.n, self.n))
+        self.L.ora_jacobian_fd(C.byref(self.f), _p(y), _p(J))
+        return J
+
+    def jacobians_soa(self, y, n_cells=None):
+        y = _f64(y)
+        n_cells = n_cells or y.shape[1]
+        J = np.zeros((n_cells, self.n, self.n))
+        self.L.ora_jacobian_fd_soa(C.byref(self.f), n_cells, y.shape[1], _p(y), _p(J))
+        return J
+
+    # ---- one fast stage ----------------------------------------------------
+    def rk4_stage(self, y, rho_poly, L, n_sub):
+        """Single cell; rho_poly [n_poly][n]."""
+        y = _f64(y)
+        rho = _f64(np.atleast_2d(rho_poly))
+        out = np.zeros(self.n)
+        st = self.L.ora_rk4_stage(C.byref(self.f), _p(y), rho.shape[0], _p(rho), C.c_double(L),
+                                  int(n_sub), _p(out))
+        return out, st
+
+    def zonneveld_try(self, y, t, h, L, rho_poly, opts):
+        y = _f64(y)
+        rho = _f64(np.atleast_2d(rho_poly))
+        out = np.zeros(self.n)
+        err = self.L.ora_zonneveld_try(C.byref(self.f), _p(y), C.c_double(t), C.c_double(h),
+                                       C.c_double(L), rho.shape[0], _p(rho), C.byref(opts), _p(out))
+        return out, err
+
+    def zonneveld_stage(self, y, rho_poly, L, opts, forced=None):
+        y = _f64(y)
+        rho = _f64(np.atleast_2d(rho_poly))
+        out = np.zeros(self.n)
+        acc, rej = C.c_int32(0), C.c_int32(0)
+        if forced is not None:
+            fz = np.ascontiguousarray(forced, dtype=np.int8)
+            fp, nf = _p(fz, C.c_int8), fz.size
+        else:
+            fp, nf = None, 0
+        st = self.L.ora_zonneveld_stage(C.byref(self.f), _p(y), rho.shape[0], _p(rho),
+                                        C.c_double(L), C.byref(opts), _p(out), C.byref(acc),
+                                        C.byref(rej), fp, nf)
+        return out, st, acc.value, rej.value
+
+    def fast_stage_soa(self, y, rho_poly, L, opts, n_cells=None):
+        y = _f64(y)
+        ld = y.shape[1]
+        n_cells = n_cells or ld
+        rho = _f64(rho_poly)
+        n_poly = rho.shape[0] if rho.ndim == 3 else 0
+        out = np.zeros_like(y)
+        st = np.zeros(ld, dtype=np.int32)
+        steps = np.zeros(ld, dtype=np.int32)
+        rej = np.zeros(ld, dtype=np.int32)
+        self.L.ora_fast_stage_soa(C.byref(self.f), C.byref(opts), n_cells, ld, _p(y), _p(out),
+                                  n_poly, _p(rho), C.c_double(L), _p(st, C.c_int32),
+                                  _p(steps, C.c_int32), _p(rej, C.c_int32))
+        return out, st, steps, rej
+
+    # ---- MRI slow step -------------------------------------------------------
+    @staticmethod
+    def table(tb):
+        c = _f64(tb.c)
+        g = _f64(tb.gamma)
+        t = Table(c.size, g.shape[0], _p(c), _p(g))
+        t._keep = (c, g)
+        return t
+
+    def mri_step_given(self, tb, opts, F, y, H, t=0.0, n_cells=None):
+        y = _f64(y).copy()
+        ld = y.shape[1]
+        n_cells = n_cells or ld
+        F = _f64(F)
+        T = self.table(tb)
+        st = np.zeros(ld, dtype=np.int32)
+        steps = np.zeros(ld, dtype=np.int32)
+        ns = self.L.ora_mri_step_given(C.byref(self.f), C.byref(T), C.byref(opts), _p(F),
+                                       C.c_double(t), C.c_double(H), n_cells, ld, _p(y),
+                                       _p(st, C.c_int32), _p(steps, C.c_int32))
+        return y, st, steps, ns
+
+    def mri_step_linear(self, tb, opts, AS, y, H, t=0.0):
+        y = _f64(y).copy()
+        if y.ndim == 1:
+            y = y[:, None]
+        ld = y.shape[1]
+        AS = _f64(AS)
+        T = self.table(tb)
+        st = np.zeros(ld, dtype=np.int32)
+        steps = np.zeros(ld, dtype=np.int32)
+        ns = self.L.ora_mri_step_linear(C.byref(self.f), C.byref(T), C.byref(opts), _p(AS),
+                                        C.c_double(t), C.c_double(H), ld, ld, _p(y),
+                                        _p(st, C.c_int32), _p(steps, C.c_int32))
+        return y, st, steps, ns
+
+    def mri_step_advdiff(self, tb, opts, grid, y, H, u=(10.0, 10.0, 10.0), D=1e-5, dx=1e-4,
+                         t=0.0):
+        y = _f64(y).copy()
+        ld = y.shape[1]
+        n_cells = int(np.prod(grid))
+        T = self.table(tb)
+        g = AdvDiff(grid[0], grid[1], grid[2], (C.c_double * 3)(*u), D, dx)
+        st = np.zeros(ld, dtype=np.int32)
+        steps = np.zeros(ld, dtype=np.int32)
+        ns = self.L.ora_mri_step_advdiff(C.byref(self.f), C.byref(T), C.byref(opts), C.byref(g),
+                                         C.c_double(t), C.c_double(H), n_cells, ld, _p(y),
+                                         _p(st, C.c_int32), _p(steps, C.c_int32))
+        return y, st, steps, ns
+
+
+def advdiff(y, grid, u=(10.0, 10.0, 10.0), D=1e-5, dx=1e-4):
+    y = _f64(y)
+    out = np.zeros_like(y)
+    g = AdvDiff(grid[0], grid[1], grid[2], (C.c_double * 3)(*u), D, dx)
+    lib().ora_advdiff(C.byref(g), y.shape[0], y.shape[1], _p(y), _p(out))
+    return out
+
+
+def rk4_opts(n_sub):
+    return FastOpts(0, int(n_sub), 0.0, 0.0, 0.0, 0)
+
+
+def zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000):
+    return FastOpts(1, 0, rtol, atol_Y, atol_T, max_steps)
+
+
+def zonneveld_tableau():
+    c, a, b, bh = np.zeros(5), np.zeros(20), np.zeros(5), np.zeros(5)
+    lib().ora_zonneveld_tableau(_p(c), _p(a), _p(b), _p(bh))
+    return c, a.reshape(5, 4), b, bh
+
+
+def set_threads(n):
+    lib().ora_set_num_threads(int(n))
+
+
+def num_threads():
+    return lib().ora_num_threads()

@@ -1,0 +1,232 @@
+"""Pins for the oracle's integrators: classic RK4, Zonneveld 4(3), the explicit
+MRI-GARK slow step (Sec. 2.1) and the advection-diffusion stencil.
+
+References used here are independent of the oracle: the RK4 stability
+polynomial, closed-form solutions of linear ODEs (scipy's expm), the order
+conditions of Runge-Kutta methods, the Knoth-Wolke ERK written out directly,
+and the discrete Fourier symbol of the centred stencil.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from paper_2211_03293_amd import inputs as I
+
+# Two-rate linear test problem: non-commuting fast and slow matrices.
+A_F = np.array([[-6.0, 5.0], [-5.0, -4.0]])
+A_S = np.array([[0.3, 1.0], [-1.2, 0.2]])
+
+
+def _P4(Z):
+    """RK4 stability polynomial 1 + Z + Z^2/2 + Z^3/6 + Z^4/24 (matrix argument)."""
+    n = Z.shape[0]
+    I_ = np.eye(n)
+    return I_ + Z + Z @ Z / 2 + Z @ Z @ Z / 6 + Z @ Z @ Z @ Z / 24
+
+
+def test_rk4_amplification_matrix(oracle_mod):
+    A = np.array([[-3.0, 7.0], [-7.0, -1.0]])
+    orc = oracle_mod.Oracle(A_fast=A)
+    y0 = np.array([0.7, -1.3])
+    L, n_sub = 0.9, 13
+    out, st = orc.rk4_stage(y0, np.zeros((1, 2)), L, n_sub)
+    ref = np.linalg.matrix_power(_P4(A * (L / n_sub)), n_sub) @ y0
+    np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-15)
+    assert st == 0
+
+
+def test_rk4_forcing_polynomial_converges_at_order_4(oracle_mod):
+    """v' = lam v + r0 + r1 tau + r2 tau^2, tau = theta/L: closed form via an
+    augmented matrix exponential; errors fall 16x per halving of h."""
+    lam, L = -2.5, 1.7
+    r = np.array([0.4, -1.1, 2.3])
+    orc = oracle_mod.Oracle(A_fast=np.array([[lam]]))
+    y0 = 0.8
+    # augmented system z = [v, 1, tau, tau^2] with tau' = 1/L
+    M = np.zeros((4, 4))
+    M[0, 0], M[0, 1], M[0, 2], M[0, 3] = lam, r[0], r[1], r[2]
+    M[2, 1] = 1.0 / L
+    M[3, 2] = 2.0 / L
+    exact = (expm(M * L) @ np.array([y0, 1.0, 0.0, 0.0]))[0]
+    errs = []
+    for n_sub in (8, 16, 32, 64):
+        out, _ = orc.rk4_stage([y0], r.reshape(3, 1), L, n_sub)
+        errs.append(abs(out[0] - exact))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates[1:] > 3.85) and np.all(rates[1:] < 4.2), rates
+
+
+def test_zonneveld_tableau_order_conditions(oracle_mod):
+    c, A, b, bh = oracle_mod.zonneveld_tableau()
+    Af = np.zeros((5, 5))
+    Af[:, :4] = A
+    np.testing.assert_allclose(Af.sum(1), c, atol=1e-15)           # row sums = nodes
+    Ac = Af @ c
+    # propagated solution: order 4
+    for w, tol in ((b, 1e-15),):
+        assert abs(w.sum() - 1) < tol
+        assert abs(w @ c - 1 / 2) < tol
+        assert abs(w @ c ** 2 - 1 / 3) < tol
+        assert abs(w @ Ac - 1 / 6) < tol
+        assert abs(w @ c ** 3 - 1 / 4) < tol
+        assert abs(w @ (c * Ac) - 1 / 8) < tol
+        assert abs(w @ (Af @ c ** 2) - 1 / 12) < tol
+        assert abs(w @ (Af @ Ac) - 1 / 24) < tol
+    # embedded: order 3 exactly, not 4
+    assert abs(bh.sum() - 1) < 1e-14
+    assert abs(bh @ c - 1 / 2) < 1e-14
+    assert abs(bh @ c ** 2 - 1 / 3) < 1e-14
+    assert abs(bh @ Ac - 1 / 6) < 1e-14
+    assert abs(bh @ c ** 3 - 1 / 4) > 1e-3 or abs(bh @ (Af @ Ac) - 1 / 24) > 1e-3
+
+
+def test_zonneveld_error_estimate_on_linear_problem(oracle_mod):
+    """For v' = lam v the estimate is |h sum_i (b_i - bh_i) K_i| w with the stage
+    values K_i built here from the pinned tableau."""
+    c, A, b, bh = oracle_mod.zonneveld_tableau()
+    lam, y0, h = -3.0, 1.2, 0.05
+    K = np.zeros(5)
+    for i in range(5):
+        K[i] = lam * (y0 + h * sum(A[i, j] * K[j] for j in range(min(i, 4))))
+    est = abs(h * ((b - bh) @ K))
+    opts = oracle_mod.zonneveld_opts(rtol=1e-6, atol_Y=1e-9)
+    w = 1.0 / (1e-9 + 1e-6 * abs(y0))
+    orc = oracle_mod.Oracle(A_fast=np.array([[lam]]))
+    out, err = orc.zonneveld_try([y0], 0.0, h, 1.0, np.zeros((1, 1)), opts)
+    assert err == pytest.approx(est * w, rel=1e-12)
+    # propagated solution is the RK4 step
+    assert out[0] == pytest.approx(_P4(np.array([[lam * h]]))[0, 0] * y0, rel=1e-14)
+
+
+def test_zonneveld_adaptive_accuracy_and_monotone_work(oracle_mod):
+    orc = oracle_mod.Oracle(A_fast=A_F)
+    y0 = np.array([1.0, 0.5])
+    rho = np.array([[0.3, -0.2]])
+    L = 1.0
+    exact_M = np.zeros((3, 3))
+    exact_M[:2, :2] = A_F
+    exact_M[:2, 2] = rho[0]
+    exact = (expm(exact_M * L) @ np.array([1.0, 0.5, 1.0]))[:2]
+    prev = 0
+    for tol in (1e-4, 1e-6, 1e-8, 1e-10):
+        opts = oracle_mod.zonneveld_opts(rtol=tol, atol_Y=tol, max_steps=100000)
+        out, st, acc, rej = orc.zonneveld_stage(y0, rho, L, opts)
+        assert st == 0
+        assert np.abs(out - exact).max() < 50 * tol
+        assert acc >= prev
+        prev = acc
+    # a cap of one accepted step is reported as MAXSTEPS
+    opts = oracle_mod.zonneveld_opts(rtol=1e-10, atol_Y=1e-10, max_steps=1)
+    _, st, _, _ = orc.zonneveld_stage(y0, rho, L, opts)
+    assert st & oracle_mod.ST_MAXSTEPS
+
+
+def test_zonneveld_forced_decisions_replay(oracle_mod):
+    orc = oracle_mod.Oracle(A_fast=A_F)
+    opts = oracle_mod.zonneveld_opts(rtol=1e-6, atol_Y=1e-6, max_steps=1000)
+    y0 = np.array([1.0, 0.5])
+    out, st, acc, rej = orc.zonneveld_stage(y0, np.zeros((1, 2)), 1.0, opts)
+    # replaying "accept everything" yields no rejections
+    out2, st2, acc2, rej2 = orc.zonneveld_stage(y0, np.zeros((1, 2)), 1.0, opts,
+                                                forced=np.ones(10000, np.int8))
+    assert rej2 == 0
+
+
+# ---------------------------------------------------------------------------
+# MRI-GARK slow step
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("table", [I.table_mis_kw3(), I.table_erk33a()])
+def test_table_consistency(table):
+    """sum_j sum_k Gamma^(k)_ij/(k+1) = dc_i, strictly lower triangular."""
+    dc = np.diff(table.c)
+    for i in range(1, table.s):
+        tot = sum(table.gamma[k, i, :].sum() / (k + 1) for k in range(table.n_gamma))
+        assert tot == pytest.approx(dc[i - 1], abs=1e-15)
+    for k in range(table.n_gamma):
+        assert np.all(np.triu(table.gamma[k]) == 0)
+
+
+def _kw3_erk_step(A, y, H):
+    """Knoth-Wolke 3rd-order ERK on y' = A y, written out directly."""
+    k1 = A @ y
+    k2 = A @ (y + H / 3 * k1)
+    k3 = A @ (y + H * (-3 / 16 * k1 + 15 / 16 * k2))
+    return y + H * (k1 / 6 + 3 / 10 * k2 + 8 / 15 * k3)
+
+
+def test_mri_zero_fast_reduces_to_slow_erk(oracle_mod):
+    orc = oracle_mod.Oracle(A_fast=np.zeros((2, 2)))
+    y0 = np.array([0.9, -0.4])
+    H = 0.3
+    out, st, _, n_slow = orc.mri_step_linear(I.table_mis_kw3(), oracle_mod.rk4_opts(3), A_S, y0, H)
+    np.testing.assert_allclose(out[:, 0], _kw3_erk_step(A_S, y0, H), rtol=1e-14)
+    assert n_slow == 3                     # three new slow evaluations per step (s = 4)
+
+
+def test_mri_zero_slow_is_fast_flow(oracle_mod):
+    orc = oracle_mod.Oracle(A_fast=A_F)
+    y0 = np.array([0.9, -0.4])
+    H, n_sub = 0.2, 40
+    out, st, steps, _ = orc.mri_step_linear(I.table_mis_kw3(), oracle_mod.rk4_opts(n_sub),
+                                            np.zeros((2, 2)), y0, H)
+    ref = y0.copy()
+    for dc in np.diff(I.table_mis_kw3().c):
+        ref = np.linalg.matrix_power(_P4(A_F * dc * H / n_sub), n_sub) @ ref
+    np.testing.assert_allclose(out[:, 0], ref, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(out[:, 0], expm(A_F * H) @ y0, rtol=1e-6)
+    assert steps[0] == 3 * n_sub
+
+
+@pytest.mark.parametrize("table", [I.table_mis_kw3(), I.table_erk33a()])
+def test_mri_order_three_on_linear_two_rate_problem(oracle_mod, table):
+    """Sec. 2.1: MIS and MRI-GARK slow tables are third order; exact flow
+    expm((A_F + A_S) t) y0; fast stages resolved finely."""
+    orc = oracle_mod.Oracle(A_fast=A_F)
+    y0 = np.array([1.0, 0.5])
+    T_end = 1.0
+    errs = []
+    for n_steps in (8, 16, 32, 64):
+        H = T_end / n_steps
+        y = y0.copy()
+        for _ in range(n_steps):
+            y, st, _, _ = orc.mri_step_linear(table, oracle_mod.rk4_opts(64), A_S, y, H)
+            y = y[:, 0]
+        errs.append(np.abs(y - expm((A_F + A_S) * T_end) @ y0).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 2.7), rates
+    assert rates[-1] < 3.6, rates
+
+
+def test_mri_forcing_uses_given_slow_evaluations(oracle_mod):
+    """With f^F = 0 and fixed slow tendencies F_j, stage i adds H sum_j Gamma_ij F_j."""
+    tb = I.table_mis_kw3()
+    orc = oracle_mod.Oracle(A_fast=np.zeros((2, 2)))
+    rng = np.random.Generator(np.random.PCG64(3))
+    F = rng.normal(size=(3, 2, 1))
+    y0 = np.array([[0.2], [0.1]])
+    H = 0.7
+    out, _, _, n_slow = orc.mri_step_given(tb, oracle_mod.rk4_opts(2), F, y0, H)
+    ref = y0[:, 0] + H * sum(tb.gamma[0, 3, j] * F[j, :, 0] for j in range(3)) \
+        + H * sum(tb.gamma[0, 2, j] * F[j, :, 0] for j in range(2)) \
+        + H * tb.gamma[0, 1, 0] * F[0, :, 0]
+    np.testing.assert_allclose(out[:, 0], ref, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Slow side: 2nd-order centred periodic advection-diffusion
+# ---------------------------------------------------------------------------
+def test_advdiff_fourier_symbol(oracle_mod):
+    nx, ny, nz = 8, 6, 10
+    dx, D, u = 1e-4, 1e-5, (10.0, -3.0, 4.0)
+    kx, ky, kz = 2, 1, 3
+    a, b, c = 2 * np.pi * kx / nx, 2 * np.pi * ky / ny, 2 * np.pi * kz / nz
+    z, yy, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    th = a * x + b * yy + c * z + 0.3
+    phi = np.cos(th).reshape(1, -1)
+    out = oracle_mod.advdiff(phi, (nx, ny, nz), u=u, D=D, dx=dx)
+    adv = -(u[0] * math.sin(a) + u[1] * math.sin(b) + u[2] * math.sin(c)) / dx * np.sin(th)
+    lap = (2 * math.cos(a) + 2 * math.cos(b) + 2 * math.cos(c) - 6) / dx ** 2 * np.cos(th)
+    ref = -adv + D * lap
+    np.testing.assert_allclose(out[0], ref.reshape(-1), atol=1e-9 * np.abs(ref).max())

@@ -1,0 +1,120 @@
+"""System-level pins for the oracle on the synthetic chemistry: relaxation to
+the mechanism's equilibrium, brute-force step refinement (order 4), energy
+drift of order h^4, linear invariants of a full MRI step, and the stored rate
+scales."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2211_03293_amd import inputs as I
+
+R_GAS = 8.314462618
+
+
+def _cell(config, i=0, seed=21):
+    m = I.make_mechanism(config)
+    y = I.independent_cells(8, m.n_species, np.random.Generator(np.random.PCG64(seed)), ld=8)
+    return m, y[:, i].copy()
+
+
+def test_relaxation_to_equilibrium(oracle_mod):
+    """A long fast-only integration ends where every reaction satisfies
+    ln Q_j = -Delta G_j(T)/(R T) (mass-action equilibrium)."""
+    m = I.make_mechanism(0)
+    # narrow rates and |Delta G/RT| ~ 1 so that an explicit adaptive run reaches
+    # equilibrium in a few thousand steps
+    m.lnA[:] = np.log(3e9)
+    m.beta[:] = 0.0
+    m.theta[:] = 0.0
+    m.g_a = m.g_a * 0.01
+    m.g_b = m.g_b * 0.01
+    orc = oracle_mod.Oracle(m)
+    y0 = I.independent_cells(4, m.n_species, np.random.Generator(np.random.PCG64(9)), ld=4)[:, 1]
+    opts = oracle_mod.zonneveld_opts(rtol=1e-10, atol_Y=1e-14, atol_T=1e-8, max_steps=200000)
+    y, st, acc, rej = orc.zonneveld_stage(y0, np.zeros((1, y0.size)), 1e-2, opts)
+    assert st == 0
+    S = m.n_species
+    T = y[S]
+    C = 1e-3 * y[:S] / (m.W * 1e3)
+    g = m.g_a + m.g_b * T
+    a, b = m.reactants[:, 0], m.reactants[:, 1]
+    c, d = m.products[:, 0], m.products[:, 1]
+    lnQ = np.log(C[c]) + np.log(C[d]) - np.log(C[a]) - np.log(C[b])
+    lnK = -((g[c] + g[d]) - (g[a] + g[b])) / (R_GAS * T)
+    assert np.abs(lnQ - lnK).max() < 1e-8
+    # the relaxed state is far from the initial one
+    assert np.abs(y[:S] - y0[:S]).max() > 1e-2
+
+
+def test_brute_force_refinement_converges_at_order_4(oracle_mod):
+    m, v0 = _cell(0)
+    orc = oracle_mod.Oracle(m)
+    cfg = I.CONFIGS[0]
+    L = (5.0 / 12.0) * cfg.H
+    rho = np.zeros((1, v0.size))
+    sols = [orc.rk4_stage(v0, rho, L, cfg.n_sub * 2 ** k)[0] for k in range(6)]
+    ref = sols[-1]
+    errs = [np.abs(s - ref).max() for s in sols[:3]]
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 3.7) and np.all(rates < 4.4), rates
+    # the config's n_sub result agrees with the refined limit to the RK4 error
+    rel = np.abs(sols[0] - ref) / np.maximum(np.abs(ref), 1e-12)
+    assert rel.max() < 1e-4
+
+
+def test_energy_drift_scales_as_h4(oracle_mod):
+    m, v0 = _cell(0, i=4)
+    orc = oracle_mod.Oracle(m)
+    L = (5.0 / 12.0) * I.CONFIGS[0].H
+    E0 = orc.energy(v0)
+    drifts = []
+    for n_sub in (5, 10, 20, 40):
+        out, st = orc.rk4_stage(v0, np.zeros((1, v0.size)), L, n_sub)
+        drifts.append(abs(orc.energy(out) - E0))
+    assert out[-1] - v0[-1] > 100.0          # strongly reacting cell
+    rates = np.log2(np.array(drifts[:-1]) / np.array(drifts[1:]))
+    assert np.all(rates > 3.8) and np.all(rates < 4.3), (drifts, rates)
+
+
+def test_mri_step_keeps_linear_invariants(oracle_mod):
+    """With mass-sum-free slow tendencies, sum_k Y_k is conserved by the whole MRI
+    step (RK methods preserve linear invariants), and so is each element total
+    when the slow tendencies are zero."""
+    cfg = I.CONFIGS[0]
+    m = I.make_mechanism(0)
+    orc = oracle_mod.Oracle(m)
+    y0 = I.initial_state(0)[:, :64].copy()
+    S = m.n_species
+    rng = np.random.Generator(np.random.PCG64(2))
+    F = rng.normal(size=(3, S + 1, 64)) * 1e3
+    F[:, :S, :] -= F[:, :S, :].mean(axis=1, keepdims=True)
+    tb = I.table_mis_kw3()
+    y1, st, steps, n_slow = orc.mri_step_given(tb, oracle_mod.rk4_opts(cfg.n_sub), F, y0, cfg.H)
+    assert np.all(st == 0)
+    assert np.all(steps[:64] == 3 * cfg.n_sub)
+    np.testing.assert_allclose(y1[:S].sum(0), y0[:S].sum(0), rtol=0, atol=2e-14)
+    y2, st, _, _ = orc.mri_step_given(tb, oracle_mod.rk4_opts(cfg.n_sub), np.zeros_like(F), y0,
+                                      cfg.H)
+    comp = m.composition.astype(float)
+    e0 = comp.T @ (y0[:S] / m.W[:, None])
+    e2 = comp.T @ (y2[:S] / m.W[:, None])
+    np.testing.assert_allclose(e2, e0, rtol=1e-13)
+    # and the chemistry did move the state
+    assert np.abs(y2[S] - y0[S]).max() > 10.0
+
+
+def test_stored_rate_scale_config0_reproduces(oracle_mod):
+    """The stored scale for the config-0 mechanism keeps h*rho(J_F) <= 0.5 at
+    every stage start of the config-0 run (the calibration criterion)."""
+    with open(I.SCALES_PATH) as f:
+        stored = json.load(f)["scales"]["0"]
+    from oracle import calibrate_scales as cal
+    m = I.make_mechanism(0)
+    assert m.rate_scale == pytest.approx(stored["s"], rel=0)
+    worst = cal.trajectory_h_rho(0, m, n_sample=512)
+    assert worst <= 0.5 * 1.0001
+    # and the unscaled initial-state spectral radius matches the stored value
+    m0 = I.make_mechanism(0, with_scale=False)
+    rho = cal.spectral_radii(oracle_mod.Oracle(m0), I.initial_state(0), 512)
+    assert rho.max() == pytest.approx(stored["rho_max_unscaled"], rel=1e-6)
