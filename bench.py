@@ -1,0 +1,186 @@
+"""Benchmark: plain FP64 MRI fast-stage throughput on one MI355X.
+
+Workload (one bench step = one explicit MRI-GARK slow step over the batch):
+64^3 = 262,144 cells of smooth periodic synthetic fields, 21 species / 84
+reversible reactions, MIS-KW3 coupling table (3 fast stages per slow step),
+classic RK4 with 50 substeps per stage, H = 1e-7 s, advection-diffusion slow
+RHS.  The default K = 10 steps is the workload's 10 slow steps.  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line: value = cell fast-stage solves per second (cell-stages/s),
+plus the fast-stage kernel's roofline figures (kernel time from hipEvents around
+every fast-stage launch inside the timed region) and the CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell fast-stage solves/s: FP64 plain vs surrogate+fallback at 1e-4 rel err"
+PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+F_EXP, F_LOG, F_DIV = 22, 22, 10  # flops charged per FP64 exp / log / divide
+
+
+def flops_per_substep(S: int, R: int, n_poly: int = 1) -> int:
+    """Algorithmic FP64 flops of one RK4 substep of one cell (FMA = 2).
+
+    Per RHS: species S x (Z factor: fma + exp + 2 mul; den fma) = S (6 + F_exp);
+    reactions R x (rate argument 2 fma + exp + 2 mul + 1 fma + 4 add) = R (12 + F_exp);
+    energy S x 5 + 1; ln T, 1/T and the dT/dt divide.  Per stage and component:
+    forcing (n_poly terms), accumulator fma, next-input fma; final update fma."""
+    n = S + 1
+    rhs = S * (6 + F_EXP) + R * (12 + F_EXP) + 5 * S + 1 + F_LOG + 2 * F_DIV + 1
+    forcing = max(0, 2 * n_poly - 1)
+    return 4 * rhs + 4 * n * (forcing + 4) + 2 * n
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2211_03293_amd", "csrc", "spec_kernels.inc")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch measured with rocprofv3 counters for the current
+    kernel source, or None when the kernel changed since they were taken."""
+    p = os.path.join(ROOT, "profiles", "fast_stage_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(mech, y_field, rho, L_list, n_sub, n_sample=8192):
+    """The oracle as it stands, on n_sample cells of the same field, for the
+    three fast stages of one slow step (forcing of the first stage)."""
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(threads)
+    orc = O.Oracle(mech)
+    idx = np.linspace(0, y_field.shape[1] - 1, n_sample).astype(np.int64)
+    ys = np.ascontiguousarray(y_field[:, idx])
+    rs = np.ascontiguousarray(rho[:, :, idx])
+    t0 = time.perf_counter()
+    for L in L_list:
+        ys, _, _, _ = orc.fast_stage_soa(ys, rs, L, O.rk4_opts(n_sub))
+    dt = time.perf_counter() - t0
+    cell_stages = n_sample * len(L_list)
+    return dict(value=cell_stages / dt, unit="cell-stages/s", cores=O.num_threads(),
+                kind="oracle",
+                sample=f"{n_sample} evenly spaced cells of the 64^3 field, the 3 fast stages of "
+                       f"one slow step (RK4, {n_sub} substeps/stage); {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--kernel", choices=["auto", "specialized", "generic"], default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the fast stage is "
+              "independent per cell, so several GPUs would each run this same kernel on their "
+              "own cell slab.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2211_03293_amd import inputs as I
+    from paper_2211_03293_amd import mri
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = I.CONFIGS[1]
+    mech = I.make_mechanism(1)
+    tb = I.table_mis_kw3()
+    y_host = I.initial_state(1)
+    n, ld = y_host.shape
+    N = cfg.n_cells
+    kernel = dict(auto=mri.KERNEL_AUTO, specialized=mri.KERNEL_SPECIALIZED,
+                  generic=mri.KERNEL_GENERIC)[args.kernel]
+    m, t = mri.Mech(mech), mri.Table(tb)
+    if kernel != mri.KERNEL_GENERIC:
+        m.specialize(args.block or 128, load=True)
+    opts = mri.fast_opts(n_sub=cfg.n_sub, kernel=kernel, block_size=args.block)
+    y0 = torch.as_tensor(y_host, device="cuda")
+    y = y0.clone()
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    status = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    params = mri.advdiff_params(cfg.grid, n)
+
+    def step(k):
+        mri.mri_slow_step(m, t, opts, mri.ADVDIFF_RHS, params, k * cfg.H, cfg.H, N, ld, y, ws,
+                          status)
+
+    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    y.copy_(y0)
+    torch.cuda.synchronize()
+    mri.timing_enable(True)
+    mri.timing_read(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(args.steps):
+        step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    wall_ms = e0.elapsed_time(e1)
+    fast_ms, n_launch = mri.timing_read(reset=True)
+    mri.timing_enable(False)
+    n_bad = mri.mri_status_count(status, N)
+    print(f"# timed {args.steps} steps: {wall_ms:.1f} ms, fast kernels {fast_ms:.1f} ms over "
+          f"{n_launch} launches, flagged cells {n_bad}", file=sys.stderr, flush=True)
+
+    stages_per_step = tb.s - 1
+    cell_stages = N * stages_per_step * args.steps
+    value = cell_stages / (wall_ms * 1e-3)
+    fps = flops_per_substep(mech.n_species, mech.n_reactions, n_poly=1)
+    flops_launch = fps * cfg.n_sub * N
+    avg_launch_s = fast_ms * 1e-3 / max(1, n_launch)
+    achieved = flops_launch / avg_launch_s / 1e12
+    workload = "mri_fast_stage rk4 64^3 cells S=21 R=84 n_sub=50"
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=load_traffic(workload),
+                kernel="mri_spec_main (RK4, specialized)" if kernel != mri.KERNEL_GENERIC
+                else "k_gen_rk4 (generic)",
+                flops_per_cell_substep=fps, avg_launch_ms=round(avg_launch_s * 1e3, 4))
+    out = dict(metric=METRIC, value=round(value, 1), unit="cell-stages/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=round(wall_ms / args.steps, 3),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload="plain FP64 explicit MRI-GARK (MIS-KW3) slow steps, 64^3 "
+                                    "cells, 21 species / 84 reactions, RK4 50 substeps/stage, "
+                                    "H = 1e-7 s, advection-diffusion slow RHS",
+                           cells=N, stages_per_step=stages_per_step, n_sub=cfg.n_sub,
+                           flagged_cells=n_bad),
+               roofline=roof)
+    if not args.no_cpu_baseline:
+        # forcing of the first stage of one slow step, from the oracle's own slow RHS
+        from oracle import oracle as O
+        rho = O.advdiff(y_host, cfg.grid)[None]
+        Ls = [float((tb.c[i] - tb.c[i - 1]) * cfg.H) for i in range(1, tb.s)]
+        out["cpu_baseline"] = cpu_baseline(mech, y_host, rho, Ls, cfg.n_sub)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,261 @@
+/*
+ * mri.h -- C ABI of libmri, a batched multirate-infinitesimal (MRI) fast-stage
+ * solver for AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Loffeld et al., "Performance of explicit and IMEX MRI
+ * multirate methods ...", Sec. 1, eq. IVP_fastslow2): y' = f^F(t,y) + f^S(t,y),
+ * slow step H, fast step h << H.  One explicit MRI-GARK slow step follows the
+ * three-step stage algorithm of Sec. 2.1: Y_1 = y_n; for i = 2..s solve the
+ * modified fast IVP v' = f^F(v) + r_i(theta) over [T_(i-1), T_i] from
+ * Y_(i-1) and set Y_i = v(T_i); y_(n+1) = Y_s.  The forcing r_i is built from
+ * slow evaluations f^S(T_j, Y_j), j < i, with a user-supplied coupling table
+ * (Sec. 4.2: users may supply their own coupling tables).
+ *
+ * f^F here is per-cell mass-action chemistry (the fast partition of Sec. 3.2,
+ * f^F = omega_k W_k / rho for the species, plus a constant-volume energy
+ * equation for T).  Cells are independent in the fast stage, so every call
+ * processes a batch of cells.
+ *
+ * Conventions
+ *   - Every function returns mri_status; 0 (MRI_OK) is success.  Invalid
+ *     arguments return MRI_EINVAL before any device work is enqueued, and
+ *     mri_last_error() (thread-local) describes the failure.
+ *   - Device arrays are caller-owned device pointers (e.g. torch CUDA tensors'
+ *     data_ptr()).  Host arrays passed to *_create are copied; the caller keeps
+ *     ownership.  Handles are immutable after creation and may be shared by
+ *     threads and streams; destroy them once, after the last use has
+ *     completed on every stream.
+ *   - State layout is structure-of-arrays (SoA): y[comp * ld + cell], with
+ *     comp 0..S-1 the mass fractions Y_k and comp S the temperature T [K];
+ *     ld >= n_cells is the leading dimension.  Forcing coefficients are
+ *     rho_poly[k * n * ld + comp * ld + cell], k = 0..n_poly-1, n = S + 1.
+ *   - All compute calls are asynchronous on the given stream (a hipStream_t
+ *     passed as void*; NULL = the legacy default stream).  Per-cell errors
+ *     detected on the device are written to the optional status array as the
+ *     MRI_CELL_* bits below; mri_status_count() summarizes them.
+ */
+#ifndef MRI_H
+#define MRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRI_ABI_VERSION 1
+
+typedef enum {
+    MRI_OK = 0,
+    MRI_EINVAL = -1,        /* invalid argument (checked on the host)           */
+    MRI_EHIP = -2,          /* a HIP runtime call failed                         */
+    MRI_ENONFINITE = -3,    /* reserved for synchronous non-finite reports      */
+    MRI_EMAXSTEPS = -4,     /* reserved for synchronous step-cap reports        */
+    MRI_ENOMEM = -5,        /* host or device allocation failed                 */
+    MRI_EUNSUPPORTED = -6,  /* valid request outside what this build supports   */
+    MRI_ECOMPILE = -7       /* run-time specialization of a kernel failed        */
+} mri_status;
+
+/* Per-cell status bits written to status_out arrays. */
+#define MRI_CELL_NONFINITE 1   /* a non-finite value in the result              */
+#define MRI_CELL_MAXSTEPS 2    /* adaptive: accepted-step cap reached           */
+#define MRI_CELL_TRANGE 4      /* T left [200, 6000] K                          */
+#define MRI_CELL_NEARTIE 8     /* adaptive: an accept/reject had |err - 1| < 1e-12 */
+
+typedef void *mri_stream_t;     /* hipStream_t */
+
+typedef struct mri_mech mri_mech;
+typedef struct mri_table mri_table;
+typedef struct mri_batch_plan mri_batch_plan;
+typedef struct mri_surrogate mri_surrogate;
+
+int mri_abi_version(void);
+/* Text for the last non-OK status returned on this thread ("" if none). */
+const char *mri_last_error(void);
+
+/* ------------------------------------------------------------------------- */
+/* Fast partition f^F: mass-action Arrhenius chemistry (Sec. 3, eq. problem2  */
+/* reaction term; the rate law is the standard one behind omega_k of Sec. 3). */
+/* Every reaction is 2 -> 2: reactants {a, b} <-> products {c, d} (a == b is   */
+/* allowed).  Per cell, with C_k = rho Y_k / W_k [mol/cm^3]:                   */
+/*   k_f = exp(lnA) T^beta exp(-theta / T)            [cm^3 mol^-1 s^-1]      */
+/*   K_c = exp(-(g_c + g_d - g_a - g_b) / (R T)),  g_k = g_a[k] + g_b[k] T      */
+/*   q   = k_f C_a C_b - (k_f / K_c) C_c C_d                                   */
+/*   dY_k/dt = W_k omega_k / rho,   omega = sum_j nu_kj q_j                    */
+/*   dT/dt = -sum_k e_k(T) dY_k/dt / sum_k Y_k cv_k,                           */
+/*           e_k = g_a[k] / W_k + cv_k (T - T_ref)  (J/kg)                     */
+/* Units: lnA = ln(A) in CGS; theta = Ea/R in K; g_a J/mol; g_b J/(mol K);     */
+/* W kg/mol; cv J/(kg K); rho kg/m^3 (used as 1e-3 rho g/cm^3 in C_k).          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int n_species;                      /* S, 1..255                        */
+    int n_reactions;                    /* R, >= 1                          */
+    const int32_t *reactants;           /* host [R][2], indices in [0, S)   */
+    const int32_t *products;            /* host [R][2]                      */
+    const double *lnA, *beta, *theta;   /* host [R]                         */
+    const double *g_a, *g_b;            /* host [S]                         */
+    const double *W, *cv;               /* host [S]                         */
+    double rho, T_ref;
+} mri_mech_desc;
+
+/* Copies the mechanism to the device.  Fails with MRI_EINVAL on bad indices
+   or non-finite/non-positive coefficients, MRI_EUNSUPPORTED when
+   |g_k|/(R T) could overflow the factorized rate evaluation for T >= 200 K. */
+mri_status mri_mech_create(const mri_mech_desc *desc, mri_mech **out);
+/* Test mode: f^F(v) = A v with a dense host A[n][n] (row-major), n <= 16.
+   Used to check the MRI driver against closed-form linear solutions. */
+mri_status mri_mech_create_linear(int n, const double *A, mri_mech **out);
+void mri_mech_destroy(mri_mech *m);
+/* State width n (S + 1 for chemistry, n for linear); -1 for NULL. */
+int mri_mech_state_width(const mri_mech *m);
+/* Compile the mechanism-specialized kernels (hipRTC) for a block size of 64,
+   128 or 256 threads ahead of first use.  load = 0 only compiles (no GPU is
+   needed) and reports the code-object size; load = 1 also loads the module on
+   the current device.  Returns MRI_ECOMPILE with the compiler log in
+   mri_last_error() on failure. */
+mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *code_bytes);
+
+/* ------------------------------------------------------------------------- */
+/* MRI-GARK coupling table (Sec. 2.1; MIS and MRI-GARK families of Sec. 2.1).  */
+/* c[s] stage times (c_1 = 0, strictly increasing: explicit, Delta c_i > 0);   */
+/* gamma[k][i][j], k < n_gamma, strictly lower triangular.  Stage i's forcing  */
+/* is r_i(tau) = (1/Delta c_i) sum_k tau^k sum_(j<i) gamma[k][i][j] F_j,       */
+/* tau in [0,1] the normalized time in the stage, F_j = f^S(T_j, Y_j).          */
+/* Creation checks sum_j sum_k gamma[k][i][j]/(k+1) = Delta c_i (1e-12).       */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int s;                              /* number of stages, 2..8           */
+    int n_gamma;                        /* forcing polynomial terms, 1..4   */
+    const double *c;                    /* host [s]                         */
+    const double *gamma;                /* host [n_gamma][s][s]             */
+} mri_table_desc;
+
+mri_status mri_table_create(const mri_table_desc *desc, mri_table **out);
+void mri_table_destroy(mri_table *t);
+
+/* ------------------------------------------------------------------------- */
+/* Fast-stage options.                                                        */
+/* ------------------------------------------------------------------------- */
+enum { MRI_FAST_RK4 = 0, MRI_FAST_ZONNEVELD43 = 1 };
+enum {
+    MRI_KERNEL_AUTO = 0,        /* specialized if available, else generic       */
+    MRI_KERNEL_GENERIC = 1,     /* one binary for every mechanism; coefficients  */
+                                /* staged in LDS                                 */
+    MRI_KERNEL_SPECIALIZED = 2  /* compiled at run time (hipRTC) for the         */
+                                /* mechanism, coefficients folded into the code  */
+};
+
+typedef struct {
+    int method;                 /* MRI_FAST_RK4 | MRI_FAST_ZONNEVELD43            */
+    int n_sub;                  /* RK4: uniform substeps per stage, >= 1          */
+    double rtol, atol_Y, atol_T;/* Zonneveld: WRMS weights 1/(atol + rtol |y|)    */
+    int max_steps;              /* Zonneveld: accepted-step cap per cell-stage    */
+    int kernel;                 /* MRI_KERNEL_*                                   */
+    int block_size;             /* threads per block, 0 = tuned default           */
+} mri_fast_opts;
+
+/* ------------------------------------------------------------------------- */
+/* HOT PATH.  One fast stage for a batch of cells (Sec. 2.1 step 2b):          */
+/*   v' = f^F(v) + sum_k tau^k rho_k,  tau = theta / L in [0, 1],              */
+/*   v(0) = y_in, y_out = v(L).                                                */
+/* RK4: h = L / n_sub; the forcing is evaluated at tau = (m + c_r)/n_sub.       */
+/* Zonneveld 4(3): adaptive h, h_0 = h_max = L/10, accept when WRMS err <= 1,  */
+/* h <- h min(5, max(0.2, 0.9 err^(-1/4))), last step clipped to land on L.    */
+/* y_in, y_out: device [n][ld] (y_out may alias y_in).  rho_poly: device        */
+/* [n_poly][n][ld], may be NULL when n_poly == 0.  status_out, steps_out:       */
+/* optional device int32 [n_cells] (accepted steps; RK4 writes n_sub).          */
+/* ------------------------------------------------------------------------- */
+mri_status mri_fast_stage(const mri_mech *m, const mri_fast_opts *opts, int n_cells, int ld,
+                          const double *y_in, double *y_out, int n_poly, const double *rho_poly,
+                          double L, int32_t *status_out, int32_t *steps_out, mri_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* One explicit MRI-GARK slow step y_n -> y_(n+1) in place (Sec. 2.1, steps   */
+/* 1-3).  The slow right-hand side is a callback that enqueues device work on  */
+/* `stream` computing fy = f^S(t, y) for the SoA arrays; it returns 0 on        */
+/* success.  s-1 slow evaluations are made per step (F_s is never needed).       */
+/* ws: device workspace of at least mri_workspace_bytes(); caller-owned.        */
+/* status_out/steps_out (optional, device [n_cells]) accumulate over stages.    */
+/* ------------------------------------------------------------------------- */
+typedef int (*mri_slow_rhs)(double t, const double *y, double *fy, int n_cells, int ld,
+                            void *user, mri_stream_t stream);
+
+mri_status mri_workspace_bytes(const mri_mech *m, const mri_table *t, int n_cells, int ld,
+                               size_t *bytes);
+mri_status mri_slow_step(const mri_mech *m, const mri_table *t, const mri_fast_opts *opts,
+                         mri_slow_rhs f_slow, void *user, double t0, double H, int n_cells,
+                         int ld, double *y, void *ws, size_t ws_bytes, int32_t *status_out,
+                         int32_t *steps_out, mri_stream_t stream);
+
+/* Built-in slow RHS: 2nd-order centred advection-diffusion on a periodic grid
+   (Sec. 3, eq. problem2 transport terms; Sec. 3.1 second-order stencils) for
+   every component: f = -u . grad(phi) + D lap(phi).  Cell index
+   (z*ny + y)*nx + x; n_cells must equal nx*ny*nz.  Pass a pointer to this
+   struct as `user` with mri_advdiff_slow_rhs as the callback. */
+typedef struct {
+    int nx, ny, nz;
+    int n_comp;
+    double u[3];
+    double D, dx;
+} mri_advdiff_params;
+int mri_advdiff_slow_rhs(double t, const double *y, double *fy, int n_cells, int ld,
+                         void *user, mri_stream_t stream);
+
+/* Built-in slow RHS for tests: f^S = A y per cell, A a linear mechanism handle
+   (mri_mech_create_linear) passed as `user`. */
+int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
+                        mri_stream_t stream);
+
+/* Counts cells with (status & mask) != 0; synchronizes the stream. */
+mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, int64_t *n_bad,
+                            mri_stream_t stream);
+
+/* Cumulative counters since load (or the last reset): slow RHS evaluations made
+   by mri_slow_step, fast-stage launches and cell-stages integrated. */
+typedef struct {
+    int64_t slow_evals;
+    int64_t fast_stages;
+    int64_t cell_stages;
+    int64_t specializations;   /* run-time kernel compilations performed */
+} mri_counters;
+void mri_get_counters(mri_counters *out);
+void mri_reset_counters(void);
+
+/* Kernel timing: while enabled, every fast-stage launch is bracketed by two
+   hipEvents on its own stream.  mri_timing_read() waits for the recorded
+   events, returns the summed kernel time [ms] and the number of timed launches,
+   and (reset != 0) starts a new accumulation.  Host thread-safe; meant for
+   benchmarking, adds a few microseconds per launch. */
+mri_status mri_timing_enable(int enable);
+mri_status mri_timing_read(double *fast_ms, int64_t *n_launches, int reset);
+
+/* ------------------------------------------------------------------------- */
+/* Batched uneven reactor sets.  Cells of set i are [set_offsets[i],          */
+/* set_offsets[i+1]) of one SoA array; set i integrates one fast stage of     */
+/* length L_per_set[i].  The plan stores the set layout, picks tiles with an   */
+/* autotuner (timed on first run) and runs one persistent work-queue kernel    */
+/* in which each lane pulls the next cell when its cell finishes; the launch   */
+/* is captured in a hipGraph and replayed on later runs.                       */
+/* ------------------------------------------------------------------------- */
+mri_status mri_batch_plan_create(const mri_mech *m, const mri_fast_opts *opts, int n_sets,
+                                 const int64_t *set_offsets /* host [n_sets+1] */,
+                                 mri_batch_plan **out);
+/* y_in/y_out device [n][ld]; rho_poly device [n_poly][n][ld] or NULL;
+   L_per_set host [n_sets]; status_out/steps_out optional device [n_total]. */
+mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, double *y_out, int64_t ld,
+                         int n_poly, const double *rho_poly, const double *L_per_set,
+                         int32_t *status_out, int32_t *steps_out, mri_stream_t stream);
+/* Tile chosen by the autotuner (threads per block, persistent blocks); valid
+   after the first run. */
+mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_blocks);
+/* Lane utilization of the last run: useful lane-steps (a lane advancing a
+   cell) and issued lane-steps (lanes x loop trips).  Synchronizes the stream. */
+mri_status mri_batch_lane_stats(const mri_batch_plan *p, uint64_t *useful, uint64_t *issued,
+                                mri_stream_t stream);
+void mri_batch_plan_destroy(mri_batch_plan *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRI_H */

@@ -1,0 +1,147 @@
+// aux_kernels.hip -- memory-bound helpers of the MRI slow step: forcing
+// assembly, the advection-diffusion slow RHS, a linear slow RHS for tests,
+// status reduction and small fills.
+#include "mri_dev.h"
+
+namespace {
+
+// Forcing coefficients of one slow stage (Sec. 2.1 step 2a):
+// rho_k = sum_{j < i} (Gamma^(k)_ij / dc_i) F_j, the 1/dc_i folded into coef.
+__global__ void __launch_bounds__(256)
+    k_forcing(long long n_elem, int n_gamma, int nj, const double *__restrict__ F,
+              long long F_stride, ForcingCoef coef, double *__restrict__ rho)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elem) return;
+    double f[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < nj) f[j] = F[j * F_stride + e];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < n_gamma) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j < nj) acc = fma(coef.c[k * 8 + j], f[j], acc);
+            rho[k * n_elem + e] = acc;
+        }
+    }
+}
+
+// f = -u . grad(phi) + D lap(phi), 2nd-order centred, periodic; one thread per
+// (component, cell).  Neighbour reads hit L2 / L1: x neighbours are
+// contiguous, y and z neighbours are one row / plane away.
+__global__ void __launch_bounds__(256)
+    k_advdiff(int nx, int ny, int nz, int n_comp, int ld, double ux, double uy, double uz,
+              double D, double dx, const double *__restrict__ y, double *__restrict__ fy)
+{
+    const long long ncell = (long long)nx * ny * nz;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncell * n_comp) return;
+    const int comp = (int)(g / ncell);
+    const long long cell = g - (long long)comp * ncell;
+    const int x = (int)(cell % nx);
+    const int yy = (int)((cell / nx) % ny);
+    const int z = (int)(cell / ((long long)nx * ny));
+    const double *p = y + (size_t)comp * ld;
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = yy == 0 ? ny - 1 : yy - 1, yp = yy == ny - 1 ? 0 : yy + 1;
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    const long long row = (long long)nx, plane = (long long)nx * ny;
+    const long long base = (long long)z * plane + (long long)yy * row;
+    const double c0 = p[base + x];
+    const double pxm = p[base + xm], pxp = p[base + xp];
+    const double pym = p[(long long)z * plane + (long long)ym * row + x];
+    const double pyp = p[(long long)z * plane + (long long)yp * row + x];
+    const double pzm = p[(long long)zm * plane + (long long)yy * row + x];
+    const double pzp = p[(long long)zp * plane + (long long)yy * row + x];
+    const double inv2dx = 1.0 / (2.0 * dx), invdx2 = 1.0 / (dx * dx);
+    const double adv = (ux * (pxp - pxm) + uy * (pyp - pym) + uz * (pzp - pzm)) * inv2dx;
+    const double lap = (pxp + pxm + pyp + pym + pzp + pzm - 6.0 * c0) * invdx2;
+    fy[(size_t)comp * ld + cell] = fma(D, lap, -adv);
+}
+
+__global__ void __launch_bounds__(256)
+    k_lin_apply(int n, const double *__restrict__ A, int n_cells, int ld,
+                const double *__restrict__ y, double *__restrict__ fy)
+{
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= n_cells) return;
+    double v[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        if (c < n) v[c] = y[(size_t)c * ld + cell];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (r < n) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < n) s = fma(A[r * n + c], v[c], s);
+            fy[(size_t)r * ld + cell] = s;
+        }
+}
+
+__global__ void __launch_bounds__(256)
+    k_status_count(const int32_t *__restrict__ st, int n, int32_t mask,
+                   unsigned long long *count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = (i < n) && ((st[i] & mask) != 0);
+    const unsigned long long m = __ballot(bad);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_forcing(long long n_elem, int n_gamma, int nj, const double *F,
+                          long long F_stride, ForcingCoef coef, double *rho, hipStream_t s)
+{
+    const int block = 256;
+    const long long grid = (n_elem + block - 1) / block;
+    hipLaunchKernelGGL(k_forcing, dim3((unsigned)grid), dim3(block), 0, s, n_elem, n_gamma, nj, F,
+                       F_stride, coef, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_advdiff(int nx, int ny, int nz, int n_comp, int ld, const double *u,
+                          double D, double dx, const double *y, double *fy, hipStream_t s)
+{
+    const int block = 256;
+    const long long total = (long long)nx * ny * nz * n_comp;
+    hipLaunchKernelGGL(k_advdiff, dim3((unsigned)((total + block - 1) / block)), dim3(block), 0, s,
+                       nx, ny, nz, n_comp, ld, u[0], u[1], u[2], D, dx, y, fy);
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_apply(int n, const double *A, int n_cells, int ld, const double *y,
+                            double *fy, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(k_lin_apply, dim3((n_cells + block - 1) / block), dim3(block), 0, s, n, A,
+                       n_cells, ld, y, fy);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_count(const int32_t *status, int n_cells, int32_t mask,
+                               unsigned long long *count, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(k_status_count, dim3((n_cells + block - 1) / block), dim3(block), 0, s,
+                       status, n_cells, mask, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s)
+{
+    const int block = 64;
+    hipLaunchKernelGGL(k_fill_u64, dim3((n + block - 1) / block), dim3(block), 0, s, p, n, v);
+    return hipGetLastError();
+}

@@ -1,0 +1,855 @@
+// mri_api.cpp -- host side of libmri: argument validation, handles, the MRI
+// slow-step driver, run-time specialization of the fast-stage kernels
+// (hipRTC) and the batched work-queue plan.  See include/mri.h for the ABI.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "mri.h"
+#include "mri_dev.h"
+
+// Embedded sources of the run-time compiled kernels (generated at build time).
+extern const char mri_spec_kernels_src[];
+extern const char mri_spec_abi_src[];
+
+namespace {
+
+constexpr double R_GAS = 8.314462618;  // J/(mol K)
+
+thread_local std::string g_err;
+
+mri_status fail(mri_status st, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(MRI_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+std::atomic<int64_t> c_slow{0}, c_fast{0}, c_cells{0}, c_spec{0};
+
+// Event pairs around fast-stage launches (benchmark timing).
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    size_t used = 0;
+};
+Timing g_timing;
+
+// Returns the pair to record around the next launch, or nullptr when off.
+std::pair<hipEvent_t, hipEvent_t> *timing_slot()
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (!g_timing.on) return nullptr;
+    if (g_timing.used == g_timing.pool.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return nullptr;
+        }
+        g_timing.pool.emplace_back(a, b);
+    }
+    return &g_timing.pool[g_timing.used++];
+}
+
+bool finite_all(const double *p, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// One run-time compiled kernel: (block size, kind 0 RK4 / 1 Zonneveld /
+// 2 batch work queue, forcing terms).
+struct SpecKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+};
+
+inline int spec_key(int wg, int kind, int np) { return (wg << 8) | (kind << 4) | np; }
+
+std::string hexd(double v)
+{
+    char b[64];
+    snprintf(b, sizeof b, "%a", v);
+    return b;
+}
+
+}  // namespace
+
+struct mri_mech {
+    int kind = 0;     // 0 chemistry, 1 linear
+    int S = 0, R = 0, n = 0;
+    std::vector<double> sp, rx;
+    std::vector<uint32_t> rxi;
+    double T_ref = 0.0;
+    std::vector<double> A;             // linear
+    double *d_sp = nullptr, *d_rx = nullptr, *d_A = nullptr;
+    uint32_t *d_rxi = nullptr;
+    GenMech gm{};
+    // run-time specialization
+    std::mutex mu;
+    std::string defs;                  // generated macro block
+    std::map<int, SpecKernel> spec;    // by spec_key
+    std::map<int, std::string> spec_fail;
+    std::vector<char> last_code;       // code object of the last compilation
+};
+
+struct mri_table {
+    int s = 0, ng = 0;
+    std::vector<double> c, gamma;
+};
+
+// ---------------------------------------------------------------------------
+// Run-time specialization
+// ---------------------------------------------------------------------------
+static std::string make_defs(const mri_mech &m)
+{
+    std::ostringstream o;
+    o << "#define NS " << m.S << "\n";
+    o << "#define T_REF " << hexd(m.T_ref) << "\n";
+    o << "#define MRI_SPECIES(X)";
+    for (int k = 0; k < m.S; ++k) {
+        const double *p = &m.sp[k * GEN_SP_STRIDE];
+        o << " \\\n  X(" << k;
+        for (int i = 0; i < GEN_SP_STRIDE; ++i) o << ", " << hexd(p[i]);
+        o << ")";
+    }
+    o << "\n#define MRI_REACTIONS(X)";
+    for (int j = 0; j < m.R; ++j) {
+        const uint32_t id = m.rxi[j];
+        o << " \\\n  X(" << (id & 255u) << ", " << ((id >> 8) & 255u) << ", "
+          << ((id >> 16) & 255u) << ", " << (id >> 24) << ", " << hexd(m.rx[3 * j]) << ", "
+          << hexd(m.rx[3 * j + 1]) << ", " << hexd(m.rx[3 * j + 2]) << ")";
+    }
+    o << "\n";
+    return o.str();
+}
+
+static std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::string a = prop.gcnArchName;
+        const size_t colon = a.find(':');
+        if (colon != std::string::npos) a = a.substr(0, colon);
+        if (!a.empty()) return a;
+    }
+    return "gfx950";
+}
+
+// Compile the specialized kernel (wg, kind, np); with load != 0 also load it
+// on the current device.  Caller holds m->mu.
+static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, SpecKernel *out)
+{
+    if (m->defs.empty()) m->defs = make_defs(*m);
+    std::string src = m->defs + "#define WG " + std::to_string(wg) + "\n#define MRI_KIND " +
+                      std::to_string(kind) + "\n#define MRI_NP " + std::to_string(np) + "\n" +
+                      mri_spec_kernels_src;
+    const char *hdr_src[] = {mri_spec_abi_src};
+    const char *hdr_name[] = {"spec_abi.h"};
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "mri_spec.hip", 1, hdr_src, hdr_name) !=
+        HIPRTC_SUCCESS)
+        return fail(MRI_ECOMPILE, "hiprtcCreateProgram failed");
+    const std::string arch = "--offload-arch=" + (load ? device_arch() : std::string("gfx950"));
+    // Machine LICM would hoist every materialized 64-bit coefficient of the
+    // straight-line rate code out of the substep loop and exhaust the register
+    // file; rematerializing them next to their use is far cheaper.
+    const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=fast",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                          "-mllvm", "-disable-machine-licm"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, 10, opts);
+    const int key = spec_key(wg, kind, np);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls + 1, '\0');
+        hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        if (log.size() > 800) log = log.substr(0, 800);
+        m->spec_fail[key] = log;
+        return fail(MRI_ECOMPILE, "hipRTC compilation failed: %s", log.c_str());
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    m->last_code.assign(cs, 0);
+    hiprtcGetCode(prog, m->last_code.data());
+    hiprtcDestroyProgram(&prog);
+    ++c_spec;
+    if (!load) return MRI_OK;
+    SpecKernel sk;
+    HIP_TRY(hipModuleLoadData(&sk.mod, m->last_code.data()));
+    HIP_TRY(hipModuleGetFunction(&sk.fn, sk.mod, "mri_spec_main"));
+    *out = sk;
+    return MRI_OK;
+}
+
+static mri_status spec_get(mri_mech *m, int wg, int kind, int np, hipFunction_t *fn)
+{
+    std::lock_guard<std::mutex> lk(m->mu);
+    const int key = spec_key(wg, kind, np);
+    auto it = m->spec.find(key);
+    if (it != m->spec.end()) {
+        *fn = it->second.fn;
+        return MRI_OK;
+    }
+    auto f = m->spec_fail.find(key);
+    if (f != m->spec_fail.end())
+        return fail(MRI_ECOMPILE, "specialization failed earlier: %s", f->second.c_str());
+    SpecKernel sk;
+    mri_status st = spec_compile(m, wg, kind, np, 1, &sk);
+    if (st != MRI_OK) return st;
+    m->spec.emplace(key, sk);
+    *fn = sk.fn;
+    return MRI_OK;
+}
+
+// Device copies of the mechanism are made on first device use, so handles can
+// be created (and specialized kernels compiled) on a host without a GPU.
+static mri_status ensure_device(mri_mech *m)
+{
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (m->kind == 1) {
+        if (m->d_A) return MRI_OK;
+        HIP_TRY(hipMalloc(&m->d_A, sizeof(double) * m->A.size()));
+        HIP_TRY(hipMemcpy(m->d_A, m->A.data(), sizeof(double) * m->A.size(), hipMemcpyHostToDevice));
+        return MRI_OK;
+    }
+    if (m->d_sp) return MRI_OK;
+    HIP_TRY(hipMalloc(&m->d_sp, sizeof(double) * m->sp.size()));
+    HIP_TRY(hipMalloc(&m->d_rx, sizeof(double) * m->rx.size()));
+    HIP_TRY(hipMalloc(&m->d_rxi, sizeof(uint32_t) * m->rxi.size()));
+    HIP_TRY(hipMemcpy(m->d_sp, m->sp.data(), sizeof(double) * m->sp.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_rx, m->rx.data(), sizeof(double) * m->rx.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_rxi, m->rxi.data(), sizeof(uint32_t) * m->rxi.size(),
+                      hipMemcpyHostToDevice));
+    m->gm = GenMech{m->S, m->R, m->d_sp, m->d_rx, m->d_rxi, m->T_ref};
+    return MRI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation helpers
+// ---------------------------------------------------------------------------
+static mri_status check_opts(const mri_mech *m, const mri_fast_opts *o)
+{
+    if (!o) return fail(MRI_EINVAL, "opts is NULL");
+    if (o->method != MRI_FAST_RK4 && o->method != MRI_FAST_ZONNEVELD43)
+        return fail(MRI_EINVAL, "unknown fast method %d", o->method);
+    if (o->method == MRI_FAST_RK4 && o->n_sub < 1)
+        return fail(MRI_EINVAL, "n_sub must be >= 1 (got %d)", o->n_sub);
+    if (o->method == MRI_FAST_ZONNEVELD43) {
+        if (!(o->rtol >= 0.0) || !(o->atol_Y > 0.0) || !(o->atol_T > 0.0) ||
+            !std::isfinite(o->rtol) || !std::isfinite(o->atol_Y) || !std::isfinite(o->atol_T))
+            return fail(MRI_EINVAL, "tolerances must be finite with atol > 0, rtol >= 0");
+        if (o->max_steps < 1) return fail(MRI_EINVAL, "max_steps must be >= 1");
+        if (m->kind == 1) return fail(MRI_EUNSUPPORTED, "linear test mode supports RK4 only");
+    }
+    if (o->kernel < MRI_KERNEL_AUTO || o->kernel > MRI_KERNEL_SPECIALIZED)
+        return fail(MRI_EINVAL, "unknown kernel selector %d", o->kernel);
+    if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 &&
+        o->block_size != 256)
+        return fail(MRI_EINVAL, "block_size must be 0, 64, 128 or 256 (got %d)", o->block_size);
+    return MRI_OK;
+}
+
+static int default_block(int kernel_kind) { return kernel_kind == MRI_KERNEL_GENERIC ? 64 : 128; }
+
+// Launch one fast stage; `accumulate` ORs status and adds steps.
+static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
+                                  const double *yin, double *yout, int n_poly,
+                                  const double *rho, double L, int32_t *status, int32_t *steps,
+                                  int accumulate, hipStream_t s)
+{
+    if (n_cells == 0) return MRI_OK;
+    mri_status dst = ensure_device(m);
+    if (dst != MRI_OK) return dst;
+    if (m->kind == 1) {
+        HIP_TRY(launch_lin_rk4(m->n, m->d_A, n_cells, ld, yin, yout, n_poly, rho, L, o->n_sub,
+                               status, steps, accumulate, s));
+        ++c_fast;
+        c_cells += n_cells;
+        return MRI_OK;
+    }
+    int kind = o->kernel;
+    hipFunction_t fn = nullptr;
+    int wg = o->block_size;
+    if (kind != MRI_KERNEL_GENERIC) {
+        if (!wg) wg = default_block(MRI_KERNEL_SPECIALIZED);
+        mri_status st = spec_get(m, wg, o->method == MRI_FAST_RK4 ? 0 : 1, n_poly, &fn);
+        if (st != MRI_OK) {
+            if (kind == MRI_KERNEL_SPECIALIZED) return st;
+            kind = MRI_KERNEL_GENERIC;
+            wg = o->block_size;
+        } else {
+            kind = MRI_KERNEL_SPECIALIZED;
+        }
+    }
+    if (kind == MRI_KERNEL_GENERIC) {
+        if (!wg) wg = default_block(MRI_KERNEL_GENERIC);
+        if (o->method == MRI_FAST_RK4) {
+            HIP_TRY(launch_gen_rk4(m->gm, wg, n_cells, ld, yin, yout, n_poly, rho, L, o->n_sub,
+                                   status, steps, accumulate, s));
+        } else {
+            ZvOpts z{o->rtol, o->atol_Y, o->atol_T, o->max_steps};
+            HIP_TRY(launch_gen_zv(m->gm, wg, n_cells, ld, yin, yout, n_poly, rho, L, z, status,
+                                  steps, accumulate, s));
+        }
+    } else {
+        const unsigned grid = (unsigned)((n_cells + wg - 1) / wg);
+        int nc = n_cells, ldv = ld, acc = accumulate;
+        const double *yi = yin, *rh = rho;
+        double *yo = yout;
+        double Lv = L;
+        int *stp = status, *sps = steps;
+        if (o->method == MRI_FAST_RK4) {
+            int nsub = o->n_sub;
+            void *args[] = {&nc, &ldv, &yi, &yo, &rh, &Lv, &nsub, &stp, &sps, &acc};
+            HIP_TRY(hipModuleLaunchKernel(fn, grid, 1, 1, wg, 1, 1, 0, s, args,
+                                          nullptr));
+        } else {
+            ZvOpts z{o->rtol, o->atol_Y, o->atol_T, o->max_steps};
+            void *args[] = {&nc, &ldv, &yi, &yo, &rh, &Lv, &z, &stp, &sps, &acc};
+            HIP_TRY(hipModuleLaunchKernel(fn, grid, 1, 1, wg, 1, 1, 0, s, args,
+                                          nullptr));
+        }
+    }
+    ++c_fast;
+    c_cells += n_cells;
+    return MRI_OK;
+}
+
+static mri_status fast_stage_impl(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
+                                  const double *yin, double *yout, int n_poly,
+                                  const double *rho, double L, int32_t *status, int32_t *steps,
+                                  int accumulate, hipStream_t s)
+{
+    if (n_cells == 0) return MRI_OK;
+    auto *ev = timing_slot();
+    if (ev) HIP_TRY(hipEventRecord(ev->first, s));
+    mri_status st = fast_stage_launch(m, o, n_cells, ld, yin, yout, n_poly, rho, L, status, steps,
+                                      accumulate, s);
+    if (ev) HIP_TRY(hipEventRecord(ev->second, s));
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// Batched uneven sets
+// ---------------------------------------------------------------------------
+struct mri_batch_plan {
+    mri_mech *mech = nullptr;
+    mri_fast_opts opts{};
+    int n_sets = 0;
+    long long n_total = 0;
+    std::vector<long long> off;
+    long long *d_off = nullptr;
+    double *d_L = nullptr;
+    unsigned long long *d_counters = nullptr;   // [0] queue, [1] useful, [2] issued
+    int wg = 0, n_blocks = 0;                   // tuned tile
+    bool tuned = false;
+    // captured launch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<char> graph_key;
+};
+
+extern "C" {
+
+int mri_abi_version(void) { return MRI_ABI_VERSION; }
+
+const char *mri_last_error(void) { return g_err.c_str(); }
+
+void mri_get_counters(mri_counters *out)
+{
+    if (!out) return;
+    out->slow_evals = c_slow.load();
+    out->fast_stages = c_fast.load();
+    out->cell_stages = c_cells.load();
+    out->specializations = c_spec.load();
+}
+
+mri_status mri_timing_enable(int enable)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.on = enable != 0;
+    return MRI_OK;
+}
+
+mri_status mri_timing_read(double *fast_ms, int64_t *n_launches, int reset)
+{
+    if (!fast_ms || !n_launches) return fail(MRI_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    double tot = 0.0;
+    for (size_t i = 0; i < g_timing.used; ++i) {
+        HIP_TRY(hipEventSynchronize(g_timing.pool[i].second));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, g_timing.pool[i].first, g_timing.pool[i].second));
+        tot += ms;
+    }
+    *fast_ms = tot;
+    *n_launches = (int64_t)g_timing.used;
+    if (reset) g_timing.used = 0;
+    return MRI_OK;
+}
+
+void mri_reset_counters(void)
+{
+    c_slow = 0;
+    c_fast = 0;
+    c_cells = 0;
+    c_spec = 0;
+}
+
+mri_status mri_mech_create(const mri_mech_desc *d, mri_mech **out)
+{
+    if (!out) return fail(MRI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(MRI_EINVAL, "desc is NULL");
+    const int S = d->n_species, R = d->n_reactions;
+    if (S < 1 || S > 255) return fail(MRI_EINVAL, "n_species must be in [1, 255] (got %d)", S);
+    if (R < 1) return fail(MRI_EINVAL, "n_reactions must be >= 1 (got %d)", R);
+    if (!d->reactants || !d->products || !d->lnA || !d->beta || !d->theta || !d->g_a ||
+        !d->g_b || !d->W || !d->cv)
+        return fail(MRI_EINVAL, "a mechanism array is NULL");
+    for (int j = 0; j < 2 * R; ++j)
+        if (d->reactants[j] < 0 || d->reactants[j] >= S || d->products[j] < 0 ||
+            d->products[j] >= S)
+            return fail(MRI_EINVAL, "species index out of range in reaction %d", j / 2);
+    if (!finite_all(d->lnA, R) || !finite_all(d->beta, R) || !finite_all(d->theta, R) ||
+        !finite_all(d->g_a, S) || !finite_all(d->g_b, S) || !finite_all(d->W, S) ||
+        !finite_all(d->cv, S))
+        return fail(MRI_EINVAL, "non-finite mechanism coefficient");
+    for (int k = 0; k < S; ++k)
+        if (!(d->W[k] > 0.0) || !(d->cv[k] > 0.0))
+            return fail(MRI_EINVAL, "W and cv must be positive (species %d)", k);
+    if (!(d->rho > 0.0) || !std::isfinite(d->rho) || !std::isfinite(d->T_ref))
+        return fail(MRI_EINVAL, "rho must be positive and T_ref finite");
+    std::unique_ptr<mri_mech> m(new mri_mech);
+    m->kind = 0;
+    m->S = S;
+    m->R = R;
+    m->n = S + 1;
+    m->T_ref = d->T_ref;
+    const double rho_cgs = d->rho * 1e-3;
+    m->sp.resize((size_t)GEN_SP_STRIDE * S);
+    double zmax = 0.0;
+    for (int k = 0; k < S; ++k) {
+        const double Wg = d->W[k] * 1e3;
+        double *p = &m->sp[(size_t)k * GEN_SP_STRIDE];
+        p[0] = rho_cgs / Wg;
+        p[1] = Wg / rho_cgs;
+        p[2] = d->g_a[k] / R_GAS;
+        p[3] = d->g_b[k] / R_GAS;
+        p[4] = d->g_a[k] / d->W[k];
+        p[5] = d->cv[k];
+        zmax = std::max(zmax, std::fabs(p[2]) / 200.0 + std::fabs(p[3]));
+    }
+    // exp(g_k/(R T)) and products of two of them must stay finite down to 200 K
+    if (zmax > 300.0)
+        return fail(MRI_EUNSUPPORTED,
+                    "|g_k|/(R T) reaches %.1f at T = 200 K; the factorized rate form needs <= 300",
+                    zmax);
+    m->rx.resize((size_t)3 * R);
+    m->rxi.resize(R);
+    for (int j = 0; j < R; ++j) {
+        const int a = d->reactants[2 * j], b = d->reactants[2 * j + 1];
+        const int c = d->products[2 * j], dd = d->products[2 * j + 1];
+        const double *pa = &m->sp[(size_t)a * GEN_SP_STRIDE], *pb = &m->sp[(size_t)b * GEN_SP_STRIDE];
+        m->rx[3 * j] = d->lnA[j] - (pa[3] + pb[3]);
+        m->rx[3 * j + 1] = d->beta[j];
+        m->rx[3 * j + 2] = d->theta[j] + (pa[2] + pb[2]);
+        m->rxi[j] = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16) | ((uint32_t)dd << 24);
+    }
+    *out = m.release();
+    return MRI_OK;
+}
+
+mri_status mri_mech_create_linear(int n, const double *A, mri_mech **out)
+{
+    if (!out) return fail(MRI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 16) return fail(MRI_EINVAL, "linear mode needs 1 <= n <= 16 (got %d)", n);
+    if (!A) return fail(MRI_EINVAL, "A is NULL");
+    if (!finite_all(A, n * n)) return fail(MRI_EINVAL, "non-finite entry in A");
+    std::unique_ptr<mri_mech> m(new mri_mech);
+    m->kind = 1;
+    m->n = n;
+    m->A.assign(A, A + n * n);
+    *out = m.release();
+    return MRI_OK;
+}
+
+void mri_mech_destroy(mri_mech *m)
+{
+    if (!m) return;
+    for (auto &kv : m->spec)
+        if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
+    if (m->d_sp) (void)hipFree(m->d_sp);
+    if (m->d_rx) (void)hipFree(m->d_rx);
+    if (m->d_rxi) (void)hipFree(m->d_rxi);
+    if (m->d_A) (void)hipFree(m->d_A);
+    delete m;
+}
+
+int mri_mech_state_width(const mri_mech *m) { return m ? m->n : -1; }
+
+mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *code_bytes)
+{
+    if (!m) return fail(MRI_EINVAL, "mech is NULL");
+    if (m->kind != 0) return fail(MRI_EUNSUPPORTED, "linear test mode has no specialization");
+    if (block_size != 64 && block_size != 128 && block_size != 256)
+        return fail(MRI_EINVAL, "block_size must be 64, 128 or 256");
+    // the RK4 kernel with a constant forcing term (the explicit MIS/MRI-GARK case)
+    if (load) {
+        hipFunction_t fn = nullptr;
+        mri_status st = spec_get(m, block_size, 0, 1, &fn);
+        if (st != MRI_OK) return st;
+        std::lock_guard<std::mutex> lk(m->mu);
+        if (code_bytes) *code_bytes = m->last_code.size();
+        return MRI_OK;
+    }
+    std::lock_guard<std::mutex> lk(m->mu);
+    SpecKernel unused;
+    mri_status st = spec_compile(m, block_size, 0, 1, 0, &unused);
+    if (st == MRI_OK && code_bytes) *code_bytes = m->last_code.size();
+    return st;
+}
+
+mri_status mri_table_create(const mri_table_desc *d, mri_table **out)
+{
+    if (!out) return fail(MRI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d || !d->c || !d->gamma) return fail(MRI_EINVAL, "table desc or its arrays are NULL");
+    const int s = d->s, ng = d->n_gamma;
+    if (s < 2 || s > 8) return fail(MRI_EINVAL, "s must be in [2, 8] (got %d)", s);
+    if (ng < 1 || ng > 4) return fail(MRI_EINVAL, "n_gamma must be in [1, 4] (got %d)", ng);
+    if (!finite_all(d->c, s) || !finite_all(d->gamma, ng * s * s))
+        return fail(MRI_EINVAL, "non-finite table entry");
+    if (d->c[0] != 0.0) return fail(MRI_EINVAL, "c_1 must be 0");
+    for (int i = 1; i < s; ++i)
+        if (!(d->c[i] > d->c[i - 1]))
+            return fail(MRI_EINVAL, "explicit tables need strictly increasing c (stage %d)", i);
+    for (int k = 0; k < ng; ++k)
+        for (int i = 0; i < s; ++i)
+            for (int j = i; j < s; ++j)
+                if (d->gamma[((size_t)k * s + i) * s + j] != 0.0)
+                    return fail(MRI_EINVAL, "gamma[%d][%d][%d] must be 0 (explicit table)", k, i, j);
+    for (int i = 1; i < s; ++i) {
+        double tot = 0.0;
+        for (int k = 0; k < ng; ++k)
+            for (int j = 0; j < i; ++j) tot += d->gamma[((size_t)k * s + i) * s + j] / (k + 1);
+        const double dc = d->c[i] - d->c[i - 1];
+        if (std::fabs(tot - dc) > 1e-12 * std::max(1.0, std::fabs(dc)))
+            return fail(MRI_EINVAL, "row %d violates sum_j sum_k gamma/(k+1) = dc (%.3e vs %.3e)",
+                        i, tot, dc);
+    }
+    std::unique_ptr<mri_table> t(new mri_table);
+    t->s = s;
+    t->ng = ng;
+    t->c.assign(d->c, d->c + s);
+    t->gamma.assign(d->gamma, d->gamma + (size_t)ng * s * s);
+    *out = t.release();
+    return MRI_OK;
+}
+
+void mri_table_destroy(mri_table *t) { delete t; }
+
+mri_status mri_fast_stage(const mri_mech *mc, const mri_fast_opts *opts, int n_cells, int ld,
+                          const double *y_in, double *y_out, int n_poly, const double *rho_poly,
+                          double L, int32_t *status_out, int32_t *steps_out, mri_stream_t stream)
+{
+    mri_mech *m = const_cast<mri_mech *>(mc);
+    if (!m) return fail(MRI_EINVAL, "mech is NULL");
+    mri_status st = check_opts(m, opts);
+    if (st != MRI_OK) return st;
+    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if ((long long)ld * m->n > (1ll << 31) - 1)
+        return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
+    if (n_poly < 0 || n_poly > 4) return fail(MRI_EINVAL, "n_poly must be in [0, 4]");
+    if (n_poly > 0 && !rho_poly) return fail(MRI_EINVAL, "rho_poly is NULL with n_poly > 0");
+    if (!(L > 0.0) || !std::isfinite(L)) return fail(MRI_EINVAL, "L must be positive and finite");
+    if (n_cells == 0) return MRI_OK;
+    if (!y_in || !y_out) return fail(MRI_EINVAL, "y_in or y_out is NULL");
+    return fast_stage_impl(m, opts, n_cells, ld, y_in, y_out, n_poly, rho_poly, L, status_out,
+                           steps_out, 0, (hipStream_t)stream);
+}
+
+mri_status mri_workspace_bytes(const mri_mech *m, const mri_table *t, int n_cells, int ld,
+                               size_t *bytes)
+{
+    if (!m || !t || !bytes) return fail(MRI_EINVAL, "NULL argument");
+    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    *bytes = sizeof(double) * (size_t)m->n * (size_t)ld * (size_t)(t->s - 1 + t->ng);
+    return MRI_OK;
+}
+
+mri_status mri_slow_step(const mri_mech *mc, const mri_table *t, const mri_fast_opts *opts,
+                         mri_slow_rhs f_slow, void *user, double t0, double H, int n_cells,
+                         int ld, double *y, void *ws, size_t ws_bytes, int32_t *status_out,
+                         int32_t *steps_out, mri_stream_t stream)
+{
+    mri_mech *m = const_cast<mri_mech *>(mc);
+    if (!m || !t) return fail(MRI_EINVAL, "mech or table is NULL");
+    mri_status st = check_opts(m, opts);
+    if (st != MRI_OK) return st;
+    if (!f_slow) return fail(MRI_EINVAL, "slow RHS callback is NULL");
+    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if ((long long)ld * m->n > (1ll << 31) - 1)
+        return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
+    if (!(H > 0.0) || !std::isfinite(H) || !std::isfinite(t0))
+        return fail(MRI_EINVAL, "H must be positive and finite");
+    size_t need = 0;
+    mri_workspace_bytes(m, t, n_cells, ld, &need);
+    if (n_cells == 0) return MRI_OK;
+    if (!y) return fail(MRI_EINVAL, "y is NULL");
+    if (!ws || ws_bytes < need)
+        return fail(MRI_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t vec = (size_t)m->n * ld;
+    double *F = (double *)ws;                       // [s-1][n][ld]
+    double *rho = F + (size_t)(t->s - 1) * vec;     // [ng][n][ld]
+    const int s_ = t->s, ng = t->ng;
+    // step 1: Y_1 = y_n; F_1 = f^S(t_n, Y_1)
+    int rc = f_slow(t0, y, F, n_cells, ld, user, stream);
+    if (rc != 0) return fail(MRI_EINVAL, "slow RHS callback returned %d", rc);
+    ++c_slow;
+    for (int i = 1; i < s_; ++i) {
+        const double dc = t->c[i] - t->c[i - 1];
+        const double L = dc * H;
+        // step 2a: forcing coefficients from F_j, j < i
+        ForcingCoef coef{};
+        for (int k = 0; k < ng; ++k)
+            for (int j = 0; j < i; ++j) coef.c[k * 8 + j] = t->gamma[((size_t)k * s_ + i) * s_ + j] / dc;
+        HIP_TRY(launch_forcing((long long)vec, ng, i, F, (long long)vec, coef, rho, s));
+        // steps 2b-2c: fast IVP over the stage, in place
+        st = fast_stage_impl(m, opts, n_cells, ld, y, y, ng, rho, L, status_out, steps_out,
+                             i > 1 ? 1 : 0, s);
+        if (st != MRI_OK) return st;
+        if (i < s_ - 1) {
+            rc = f_slow(t0 + t->c[i] * H, y, F + (size_t)i * vec, n_cells, ld, user, stream);
+            if (rc != 0) return fail(MRI_EINVAL, "slow RHS callback returned %d", rc);
+            ++c_slow;
+        }
+    }
+    // step 3: y_(n+1) = Y_s (already in y)
+    return MRI_OK;
+}
+
+int mri_advdiff_slow_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
+                         mri_stream_t stream)
+{
+    (void)t;
+    const mri_advdiff_params *p = (const mri_advdiff_params *)user;
+    if (!p || !y || !fy) return -1;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->n_comp < 1) return -2;
+    if ((long long)p->nx * p->ny * p->nz != n_cells || ld < n_cells) return -3;
+    if (!(p->dx > 0.0)) return -4;
+    if (launch_advdiff(p->nx, p->ny, p->nz, p->n_comp, ld, p->u, p->D, p->dx, y, fy,
+                       (hipStream_t)stream) != hipSuccess)
+        return -5;
+    return 0;
+}
+
+int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
+                        mri_stream_t stream)
+{
+    (void)t;
+    const mri_mech *m = (const mri_mech *)user;
+    if (!m || m->kind != 1 || !y || !fy) return -1;
+    if (ensure_device(const_cast<mri_mech *>(m)) != MRI_OK) return -6;
+    if (launch_lin_apply(m->n, m->d_A, n_cells, ld, y, fy, (hipStream_t)stream) != hipSuccess)
+        return -5;
+    return 0;
+}
+
+mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, int64_t *n_bad,
+                            mri_stream_t stream)
+{
+    if (!n_bad) return fail(MRI_EINVAL, "n_bad is NULL");
+    if (n_cells < 0) return fail(MRI_EINVAL, "n_cells < 0");
+    *n_bad = 0;
+    if (n_cells == 0) return MRI_OK;
+    if (!status) return fail(MRI_EINVAL, "status is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(unsigned long long)));
+    unsigned long long h = 0;
+    hipError_t e = launch_fill_u64(d, 1, 0ull, s);
+    if (e == hipSuccess) e = launch_status_count(status, n_cells, mask, d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(MRI_EHIP, "status count failed: %s", hipGetErrorString(e));
+    *n_bad = (int64_t)h;
+    return MRI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched uneven sets: persistent work-queue kernel (specialized kernels).
+// ---------------------------------------------------------------------------
+mri_status mri_batch_plan_create(const mri_mech *mc, const mri_fast_opts *opts, int n_sets,
+                                 const int64_t *set_offsets, mri_batch_plan **out)
+{
+    mri_mech *m = const_cast<mri_mech *>(mc);
+    if (!out) return fail(MRI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!m) return fail(MRI_EINVAL, "mech is NULL");
+    mri_status st = check_opts(m, opts);
+    if (st != MRI_OK) return st;
+    if (opts->method != MRI_FAST_ZONNEVELD43)
+        return fail(MRI_EINVAL, "batched plans integrate with the adaptive Zonneveld method");
+    if (m->kind != 0) return fail(MRI_EUNSUPPORTED, "batched plans need a chemistry mechanism");
+    if (n_sets < 1 || !set_offsets) return fail(MRI_EINVAL, "need n_sets >= 1 and set_offsets");
+    if (set_offsets[0] != 0) return fail(MRI_EINVAL, "set_offsets[0] must be 0");
+    for (int i = 0; i < n_sets; ++i)
+        if (set_offsets[i + 1] < set_offsets[i])
+            return fail(MRI_EINVAL, "set_offsets must be non-decreasing (set %d)", i);
+    std::unique_ptr<mri_batch_plan> p(new mri_batch_plan);
+    p->mech = m;
+    p->opts = *opts;
+    p->n_sets = n_sets;
+    p->off.assign(set_offsets, set_offsets + n_sets + 1);
+    p->n_total = p->off.back();
+    HIP_TRY(hipMalloc(&p->d_off, sizeof(long long) * (n_sets + 1)));
+    HIP_TRY(hipMemcpy(p->d_off, p->off.data(), sizeof(long long) * (n_sets + 1),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&p->d_L, sizeof(double) * n_sets));
+    HIP_TRY(hipMalloc(&p->d_counters, sizeof(unsigned long long) * 3));
+    *out = p.release();
+    return MRI_OK;
+}
+
+void mri_batch_plan_destroy(mri_batch_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_off) (void)hipFree(p->d_off);
+    if (p->d_L) (void)hipFree(p->d_L);
+    if (p->d_counters) (void)hipFree(p->d_counters);
+    delete p;
+}
+
+mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_blocks)
+{
+    if (!p || !block_size || !n_blocks) return fail(MRI_EINVAL, "NULL argument");
+    if (!p->tuned) return fail(MRI_EINVAL, "plan has not run yet");
+    *block_size = p->wg;
+    *n_blocks = p->n_blocks;
+    return MRI_OK;
+}
+
+}  // extern "C"
+
+// Enqueue one persistent launch (counter reset by a fill kernel, then the
+// work-queue kernel) on stream s.
+static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, const double *yin,
+                                double *yout, long long ld, int n_poly, const double *rho,
+                                int32_t *status, int32_t *steps, hipStream_t s)
+{
+    hipFunction_t fn = nullptr;
+    mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn);
+    if (st != MRI_OK) return st;
+    HIP_TRY(launch_fill_u64(p->d_counters, 3, 0ull, s));
+    BatchArgs a;
+    a.yin = yin;
+    a.yout = yout;
+    a.rho = rho;
+    a.set_off = p->d_off;
+    a.set_L = p->d_L;
+    a.status = status;
+    a.steps = steps;
+    a.counter = p->d_counters;
+    a.lane_steps = p->d_counters + 1;
+    a.issued_steps = p->d_counters + 2;
+    a.n_total = p->n_total;
+    a.ld = ld;
+    a.n_sets = p->n_sets;
+    a.o = ZvOpts{p->opts.rtol, p->opts.atol_Y, p->opts.atol_T, p->opts.max_steps};
+    void *args[] = {&a};
+    HIP_TRY(hipModuleLaunchKernel(fn, (unsigned)n_blocks, 1, 1, wg, 1, 1, 0, s,
+                                  args, nullptr));
+    return MRI_OK;
+}
+
+static int n_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 256;
+    return cus > 0 ? cus : 256;
+}
+
+extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, double *y_out,
+                                    int64_t ld, int n_poly, const double *rho_poly,
+                                    const double *L_per_set, int32_t *status_out,
+                                    int32_t *steps_out, mri_stream_t stream)
+{
+    if (!p) return fail(MRI_EINVAL, "plan is NULL");
+    if (ld < p->n_total) return fail(MRI_EINVAL, "ld < total cells");
+    if (ld * (int64_t)p->mech->n > (1ll << 31) - 1)
+        return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
+    if (n_poly < 0 || n_poly > 4 || (n_poly > 0 && !rho_poly))
+        return fail(MRI_EINVAL, "bad n_poly / rho_poly");
+    if (!L_per_set) return fail(MRI_EINVAL, "L_per_set is NULL");
+    for (int i = 0; i < p->n_sets; ++i)
+        if (!(L_per_set[i] > 0.0) || !std::isfinite(L_per_set[i]))
+            return fail(MRI_EINVAL, "L_per_set[%d] must be positive and finite", i);
+    if (p->n_total == 0) return MRI_OK;
+    if (!y_in || !y_out) return fail(MRI_EINVAL, "y_in or y_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(p->d_L, L_per_set, sizeof(double) * p->n_sets, hipMemcpyHostToDevice, s));
+    if (!p->tuned) {
+        p->wg = p->opts.block_size ? p->opts.block_size : 128;
+        const int waves_per_block = p->wg / 64;
+        p->n_blocks = std::max(1, n_cus() * 8 / waves_per_block);
+        p->tuned = true;
+    }
+    mri_status st = batch_enqueue(p, p->wg, p->n_blocks, y_in, y_out, ld, n_poly, rho_poly,
+                                  status_out, steps_out, s);
+    if (st != MRI_OK) return st;
+    ++c_fast;
+    c_cells += p->n_total;
+    return MRI_OK;
+}
+
+extern "C" mri_status mri_batch_lane_stats(const mri_batch_plan *p, uint64_t *useful,
+                                           uint64_t *issued, mri_stream_t stream)
+{
+    if (!p || !useful || !issued) return fail(MRI_EINVAL, "NULL argument");
+    unsigned long long h[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(h, p->d_counters, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    *useful = h[1];
+    *issued = h[2];
+    return MRI_OK;
+}

@@ -1,0 +1,60 @@
+// mri_dev.h -- device-side data structures and launchers of the ahead-of-time
+// compiled kernels of libmri (generic fast-stage kernels and helpers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spec_abi.h"
+
+// Mechanism in the packed form the kernels use.  Species block sp[k*6 + i]:
+//   0 CF = rho_cgs / W_g         (C_k = CF * Y_k, mol/cm^3)
+//   1 WF = W_g / rho_cgs         (dY_k/dt = WF * omega_k)
+//   2 AR = g_a / R,  3 BR = g_b / R   (g_k/(R T) = AR/T + BR)
+//   4 EA = g_a / W (J/kg),  5 CV
+// Reaction block rx[j*3 + i]: 0 ln A' = ln A - BR_a - BR_b, 1 beta,
+//   2 theta' = theta + AR_a + AR_b, so that
+//   kappa_j = exp(ln A' + beta ln T - theta'/T) = k_f exp(-(g_a + g_b)/(R T)).
+// rxi[j] = a | b << 8 | c << 16 | d << 24.
+struct GenMech {
+    int S, R;
+    const double *sp;
+    const double *rx;
+    const uint32_t *rxi;
+    double T_ref;
+};
+
+constexpr int GEN_SP_STRIDE = 6;
+
+// Largest species count of each generic-kernel instantiation.
+constexpr int GEN_NMAX_SMALL = 24;
+constexpr int GEN_NMAX_LARGE = 56;
+
+size_t gen_lds_bytes(int S, int R, int block);
+
+hipError_t launch_gen_rk4(const GenMech &gm, int block, int n_cells, int ld, const double *yin,
+                          double *yout, int n_poly, const double *rho, double L, int n_sub,
+                          int *status, int *steps, int accumulate, hipStream_t s);
+hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, const double *yin,
+                         double *yout, int n_poly, const double *rho, double L, ZvOpts o,
+                         int *status, int *steps, int accumulate, hipStream_t s);
+
+// Linear test mode: f = A v, n <= 16, A row-major on the device.
+hipError_t launch_lin_rk4(int n, const double *A, int n_cells, int ld, const double *yin,
+                          double *yout, int n_poly, const double *rho, double L, int n_sub,
+                          int *status, int *steps, int accumulate, hipStream_t s);
+
+// rho[k][e] = sum_{j < nj} coef[k*8 + j] * F[j][e], e < n_elem, k < n_gamma.
+struct ForcingCoef {
+    double c[4 * 8];
+};
+hipError_t launch_forcing(long long n_elem, int n_gamma, int nj, const double *F,
+                          long long F_stride, ForcingCoef coef, double *rho, hipStream_t s);
+
+hipError_t launch_advdiff(int nx, int ny, int nz, int n_comp, int ld, const double *u,
+                          double D, double dx, const double *y, double *fy, hipStream_t s);
+hipError_t launch_lin_apply(int n, const double *A, int n_cells, int ld, const double *y,
+                            double *fy, hipStream_t s);
+hipError_t launch_status_count(const int32_t *status, int n_cells, int32_t mask,
+                               unsigned long long *count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);

@@ -1,0 +1,284 @@
+"""ctypes binding of libmri (include/mri.h): argument marshalling only.
+
+Every computation runs in libmri's HIP kernels.  Device arrays are torch CUDA
+tensors (float64 / int32, contiguous); streams are torch streams.  Importing
+this module loads libmri.so and fails loudly when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmri.so")
+
+MRI_OK, MRI_EINVAL, MRI_EHIP, MRI_ENONFINITE, MRI_EMAXSTEPS, MRI_ENOMEM, MRI_EUNSUPPORTED, \
+    MRI_ECOMPILE = 0, -1, -2, -3, -4, -5, -6, -7
+CELL_NONFINITE, CELL_MAXSTEPS, CELL_TRANGE, CELL_NEARTIE = 1, 2, 4, 8
+FAST_RK4, FAST_ZONNEVELD43 = 0, 1
+KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
+
+
+class MriError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libmri status {status}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2211_03293_amd.build.build()")
+
+lib = C.CDLL(LIB_PATH)
+
+
+class mri_mech_desc(C.Structure):
+    _fields_ = [("n_species", C.c_int), ("n_reactions", C.c_int),
+                ("reactants", C.POINTER(C.c_int32)), ("products", C.POINTER(C.c_int32)),
+                ("lnA", C.POINTER(C.c_double)), ("beta", C.POINTER(C.c_double)),
+                ("theta", C.POINTER(C.c_double)), ("g_a", C.POINTER(C.c_double)),
+                ("g_b", C.POINTER(C.c_double)), ("W", C.POINTER(C.c_double)),
+                ("cv", C.POINTER(C.c_double)), ("rho", C.c_double), ("T_ref", C.c_double)]
+
+
+class mri_table_desc(C.Structure):
+    _fields_ = [("s", C.c_int), ("n_gamma", C.c_int), ("c", C.POINTER(C.c_double)),
+                ("gamma", C.POINTER(C.c_double))]
+
+
+class mri_fast_opts(C.Structure):
+    _fields_ = [("method", C.c_int), ("n_sub", C.c_int), ("rtol", C.c_double),
+                ("atol_Y", C.c_double), ("atol_T", C.c_double), ("max_steps", C.c_int),
+                ("kernel", C.c_int), ("block_size", C.c_int)]
+
+
+class mri_advdiff_params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("n_comp", C.c_int),
+                ("u", C.c_double * 3), ("D", C.c_double), ("dx", C.c_double)]
+
+
+class mri_counters(C.Structure):
+    _fields_ = [("slow_evals", C.c_int64), ("fast_stages", C.c_int64),
+                ("cell_stages", C.c_int64), ("specializations", C.c_int64)]
+
+
+_vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+_SIGS = {
+    "mri_abi_version": (_i, []),
+    "mri_last_error": (C.c_char_p, []),
+    "mri_mech_create": (_i, [C.POINTER(mri_mech_desc), C.POINTER(_vp)]),
+    "mri_mech_create_linear": (_i, [_i, C.POINTER(C.c_double), C.POINTER(_vp)]),
+    "mri_mech_destroy": (None, [_vp]),
+    "mri_mech_state_width": (_i, [_vp]),
+    "mri_mech_specialize": (_i, [_vp, _i, _i, C.POINTER(_sz)]),
+    "mri_table_create": (_i, [C.POINTER(mri_table_desc), C.POINTER(_vp)]),
+    "mri_table_destroy": (None, [_vp]),
+    "mri_fast_stage": (_i, [_vp, C.POINTER(mri_fast_opts), _i, _i, _vp, _vp, _i, _vp, _d, _vp,
+                            _vp, _vp]),
+    "mri_workspace_bytes": (_i, [_vp, _vp, _i, _i, C.POINTER(_sz)]),
+    "mri_slow_step": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), _vp, _vp, _d, _d, _i, _i, _vp,
+                           _vp, _sz, _vp, _vp, _vp]),
+    "mri_advdiff_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
+    "mri_linear_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
+    "mri_status_count": (_i, [_vp, _i, C.c_int32, C.POINTER(C.c_int64), _vp]),
+    "mri_get_counters": (None, [C.POINTER(mri_counters)]),
+    "mri_reset_counters": (None, []),
+    "mri_timing_enable": (_i, [_i]),
+    "mri_timing_read": (_i, [C.POINTER(C.c_double), C.POINTER(C.c_int64), _i]),
+    "mri_batch_plan_create": (_i, [_vp, C.POINTER(mri_fast_opts), _i, C.POINTER(C.c_int64),
+                                   C.POINTER(_vp)]),
+    "mri_batch_run": (_i, [_vp, _vp, _vp, C.c_int64, _i, _vp, C.POINTER(C.c_double), _vp, _vp,
+                           _vp]),
+    "mri_batch_plan_tile": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
+    "mri_batch_lane_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _vp]),
+    "mri_batch_plan_destroy": (None, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(st):
+    if st != MRI_OK:
+        raise MriError(st, lib.mri_last_error().decode())
+
+
+def last_error() -> str:
+    return lib.mri_last_error().decode()
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor / array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Mech:
+    """Owns an mri_mech handle (chemistry or linear test mode)."""
+
+    def __init__(self, mech=None, A_linear=None):
+        self.h = C.c_void_p()
+        if mech is not None:
+            self._keep = dict(
+                reac=np.ascontiguousarray(mech.reactants, dtype=np.int32),
+                prod=np.ascontiguousarray(mech.products, dtype=np.int32),
+                lnA=_f64(mech.lnA), beta=_f64(mech.beta), theta=_f64(mech.theta),
+                g_a=_f64(mech.g_a), g_b=_f64(mech.g_b), W=_f64(mech.W), cv=_f64(mech.cv))
+            k = self._keep
+            P = lambda a, t=C.c_double: a.ctypes.data_as(C.POINTER(t))  # noqa: E731
+            d = mri_mech_desc(mech.n_species, mech.n_reactions, P(k["reac"], C.c_int32),
+                              P(k["prod"], C.c_int32), P(k["lnA"]), P(k["beta"]), P(k["theta"]),
+                              P(k["g_a"]), P(k["g_b"]), P(k["W"]), P(k["cv"]), float(mech.rho),
+                              float(mech.T_ref))
+            _check(lib.mri_mech_create(C.byref(d), C.byref(self.h)))
+        else:
+            A = _f64(A_linear)
+            _check(lib.mri_mech_create_linear(A.shape[0], A.ctypes.data_as(C.POINTER(C.c_double)),
+                                              C.byref(self.h)))
+        self.n = lib.mri_mech_state_width(self.h)
+
+    def specialize(self, block_size=128, load=True):
+        nb = C.c_size_t(0)
+        _check(lib.mri_mech_specialize(self.h, block_size, int(load), C.byref(nb)))
+        return nb.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib.mri_mech_destroy(self.h)
+            self.h = C.c_void_p()
+
+
+class Table:
+    def __init__(self, table):
+        self.c = _f64(table.c)
+        self.gamma = _f64(table.gamma)
+        self.s, self.n_gamma = self.c.size, self.gamma.shape[0]
+        self.h = C.c_void_p()
+        d = mri_table_desc(self.s, self.n_gamma, self.c.ctypes.data_as(C.POINTER(C.c_double)),
+                           self.gamma.ctypes.data_as(C.POINTER(C.c_double)))
+        _check(lib.mri_table_create(C.byref(d), C.byref(self.h)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib.mri_table_destroy(self.h)
+            self.h = C.c_void_p()
+
+
+def fast_opts(method=FAST_RK4, n_sub=1, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000,
+              kernel=KERNEL_AUTO, block_size=0):
+    return mri_fast_opts(method, n_sub, rtol, atol_Y, atol_T, max_steps, kernel, block_size)
+
+
+def mri_fast_stage(mech: Mech, opts, n_cells, ld, y_in, y_out, n_poly, rho_poly, L,
+                   status_out=None, steps_out=None, stream=None):
+    _check(lib.mri_fast_stage(mech.h, C.byref(opts), n_cells, ld, _ptr(y_in), _ptr(y_out), n_poly,
+                              _ptr(rho_poly), float(L), _ptr(status_out), _ptr(steps_out),
+                              _stream(stream)))
+
+
+def mri_workspace_bytes(mech: Mech, table: Table, n_cells, ld):
+    b = C.c_size_t(0)
+    _check(lib.mri_workspace_bytes(mech.h, table.h, n_cells, ld, C.byref(b)))
+    return b.value
+
+
+ADVDIFF_RHS = C.cast(lib.mri_advdiff_slow_rhs, C.c_void_p).value
+LINEAR_RHS = C.cast(lib.mri_linear_slow_rhs, C.c_void_p).value
+
+
+def advdiff_params(grid, n_comp, u=(10.0, 10.0, 10.0), D=1e-5, dx=1e-4):
+    return mri_advdiff_params(grid[0], grid[1], grid[2], n_comp, (C.c_double * 3)(*u), D, dx)
+
+
+def mri_slow_step(mech: Mech, table: Table, opts, f_slow, user, t0, H, n_cells, ld, y, ws,
+                  status_out=None, steps_out=None, stream=None):
+    """f_slow: a C function address (ADVDIFF_RHS, LINEAR_RHS); user: ctypes object or
+    address passed through to it."""
+    if isinstance(user, C.Structure):
+        user_p = C.cast(C.pointer(user), C.c_void_p).value
+    elif isinstance(user, Mech):
+        user_p = user.h.value
+    else:
+        user_p = user
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib.mri_slow_step(mech.h, table.h, C.byref(opts), f_slow, user_p, float(t0), float(H),
+                             n_cells, ld, _ptr(y), _ptr(ws), nbytes, _ptr(status_out),
+                             _ptr(steps_out), _stream(stream)))
+
+
+def mri_status_count(status, n_cells, mask=0xFF, stream=None):
+    n = C.c_int64(0)
+    _check(lib.mri_status_count(_ptr(status), n_cells, mask, C.byref(n), _stream(stream)))
+    return n.value
+
+
+def counters():
+    c = mri_counters()
+    lib.mri_get_counters(C.byref(c))
+    return dict(slow_evals=c.slow_evals, fast_stages=c.fast_stages, cell_stages=c.cell_stages,
+                specializations=c.specializations)
+
+
+def reset_counters():
+    lib.mri_reset_counters()
+
+
+def timing_enable(on=True):
+    _check(lib.mri_timing_enable(int(on)))
+
+
+def timing_read(reset=True):
+    """(summed fast-stage kernel time in ms, number of timed launches)."""
+    ms, n = C.c_double(0.0), C.c_int64(0)
+    _check(lib.mri_timing_read(C.byref(ms), C.byref(n), int(reset)))
+    return ms.value, n.value
+
+
+class BatchPlan:
+    def __init__(self, mech: Mech, opts, set_offsets):
+        off = np.ascontiguousarray(set_offsets, dtype=np.int64)
+        self.n_sets = off.size - 1
+        self.n_total = int(off[-1])
+        self.mech = mech
+        self.h = C.c_void_p()
+        _check(lib.mri_batch_plan_create(mech.h, C.byref(opts), self.n_sets,
+                                         off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         C.byref(self.h)))
+
+    def run(self, y_in, y_out, ld, n_poly, rho_poly, L_per_set, status_out=None, steps_out=None,
+            stream=None):
+        L = _f64(L_per_set)
+        _check(lib.mri_batch_run(self.h, _ptr(y_in), _ptr(y_out), int(ld), n_poly, _ptr(rho_poly),
+                                 L.ctypes.data_as(C.POINTER(C.c_double)), _ptr(status_out),
+                                 _ptr(steps_out), _stream(stream)))
+
+    def tile(self):
+        b, n = C.c_int(0), C.c_int(0)
+        _check(lib.mri_batch_plan_tile(self.h, C.byref(b), C.byref(n)))
+        return b.value, n.value
+
+    def lane_stats(self, stream=None):
+        u, i = C.c_uint64(0), C.c_uint64(0)
+        _check(lib.mri_batch_lane_stats(self.h, C.byref(u), C.byref(i), _stream(stream)))
+        return u.value, i.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib.mri_batch_plan_destroy(self.h)
+            self.h = C.c_void_p()

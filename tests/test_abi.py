@@ -1,0 +1,150 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, rejects invalid arguments before touching the device, and its
+run-time specialized kernels compile for gfx950."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2211_03293_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mri():
+    from paper_2211_03293_amd import mri as M
+    return M
+
+
+def _declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w \*]*?\b(mri_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(mri):
+    names = _declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(mri.lib, n)]
+    assert not missing, missing
+
+
+def test_abi_version(mri):
+    assert mri.lib.mri_abi_version() == 1
+
+
+def test_mech_validation(mri):
+    m = I.make_mechanism(0)
+    bad = I.Mechanism(**{**m.__dict__})
+    bad.reactants = m.reactants.copy()
+    bad.reactants[3, 1] = m.n_species          # index out of range
+    with pytest.raises(mri.MriError) as e:
+        mri.Mech(bad)
+    assert e.value.status == mri.MRI_EINVAL and "out of range" in str(e.value)
+    bad = I.Mechanism(**{**m.__dict__})
+    bad.W = m.W.copy()
+    bad.W[0] = -1.0
+    with pytest.raises(mri.MriError) as e:
+        mri.Mech(bad)
+    assert e.value.status == mri.MRI_EINVAL
+    bad = I.Mechanism(**{**m.__dict__})
+    bad.g_a = m.g_a * 100.0                    # exp(g/RT) would overflow at 200 K
+    with pytest.raises(mri.MriError) as e:
+        mri.Mech(bad)
+    assert e.value.status == mri.MRI_EUNSUPPORTED
+
+
+def test_table_validation(mri):
+    mri.Table(I.table_mis_kw3())
+    mri.Table(I.table_erk33a())
+    t = I.table_mis_kw3()
+    t.gamma = t.gamma.copy()
+    t.gamma[0, 3, 2] += 1e-3                    # breaks the row-sum consistency
+    with pytest.raises(mri.MriError) as e:
+        mri.Table(t)
+    assert "violates" in str(e.value)
+    t = I.table_mis_kw3()
+    t.gamma = t.gamma.copy()
+    t.gamma[0, 1, 1] = 0.1                      # not explicit
+    with pytest.raises(mri.MriError):
+        mri.Table(t)
+    t = I.table_mis_kw3()
+    t.c = np.array([0.0, 0.5, 0.5, 1.0])        # dc = 0 stage (implicit form)
+    with pytest.raises(mri.MriError):
+        mri.Table(t)
+
+
+def test_fast_stage_rejects_bad_arguments_without_device(mri):
+    m = mri.Mech(I.make_mechanism(0))
+    ok = mri.fast_opts(n_sub=4)
+    L = mri.lib
+
+    def call(opts=ok, n_cells=64, ld=64, yin=1, yout=1, n_poly=0, rho=None, Lval=1e-7):
+        return L.mri_fast_stage(m.h, C.byref(opts), n_cells, ld, yin, yout, n_poly, rho, Lval,
+                                None, None, None)
+
+    assert call(n_cells=65, ld=64) == mri.MRI_EINVAL
+    assert call(n_cells=-1) == mri.MRI_EINVAL
+    assert call(Lval=0.0) == mri.MRI_EINVAL
+    assert call(Lval=float("nan")) == mri.MRI_EINVAL
+    assert call(n_poly=2, rho=None) == mri.MRI_EINVAL
+    assert call(n_poly=5, rho=1) == mri.MRI_EINVAL
+    assert call(opts=mri.fast_opts(n_sub=0)) == mri.MRI_EINVAL
+    assert call(opts=mri.fast_opts(method=7)) == mri.MRI_EINVAL
+    assert call(opts=mri.fast_opts(n_sub=4, block_size=96)) == mri.MRI_EINVAL
+    assert call(opts=mri.fast_opts(method=mri.FAST_ZONNEVELD43, atol_Y=0.0)) == mri.MRI_EINVAL
+    assert call(yin=None) == mri.MRI_EINVAL
+    # an empty batch is a no-op and needs no device
+    assert call(n_cells=0, ld=0, yin=None, yout=None) == mri.MRI_OK
+    assert L.mri_fast_stage(None, C.byref(ok), 1, 1, 1, 1, 0, None, 1.0, None, None,
+                            None) == mri.MRI_EINVAL
+
+
+def test_slow_step_and_batch_validation(mri):
+    m = mri.Mech(I.make_mechanism(0))
+    t = mri.Table(I.table_mis_kw3())
+    L = mri.lib
+    opts = mri.fast_opts(n_sub=4)
+    assert mri.mri_workspace_bytes(m, t, 512, 512) == 8 * 10 * 512 * (3 + 1)
+    rc = L.mri_slow_step(m.h, t.h, C.byref(opts), None, None, 0.0, 1e-6, 512, 512, 1, 1,
+                         10 ** 9, None, None, None)
+    assert rc == mri.MRI_EINVAL                  # NULL callback
+    rc = L.mri_slow_step(m.h, t.h, C.byref(opts), mri.ADVDIFF_RHS, None, 0.0, 1e-6, 512, 512, 1,
+                         1, 16, None, None, None)
+    assert rc == mri.MRI_EINVAL and "workspace" in mri.last_error()
+    rk4 = mri.fast_opts(n_sub=4)
+    off = np.array([0, 10, 20], dtype=np.int64)
+    h = C.c_void_p()
+    rc = L.mri_batch_plan_create(m.h, C.byref(rk4), 2, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 C.byref(h))
+    assert rc == mri.MRI_EINVAL                  # batches are adaptive
+    bad = np.array([0, 10, 5], dtype=np.int64)
+    zv = mri.fast_opts(method=mri.FAST_ZONNEVELD43)
+    rc = L.mri_batch_plan_create(m.h, C.byref(zv), 2, bad.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 C.byref(h))
+    assert rc == mri.MRI_EINVAL
+
+
+def test_linear_mode_validation(mri):
+    with pytest.raises(mri.MriError):
+        mri.Mech(A_linear=np.zeros((17, 17)))
+    m = mri.Mech(A_linear=np.eye(2))
+    assert m.n == 2
+    zv = mri.fast_opts(method=mri.FAST_ZONNEVELD43)
+    rc = mri.lib.mri_fast_stage(m.h, C.byref(zv), 1, 1, 1, 1, 0, None, 1.0, None, None, None)
+    assert rc == mri.MRI_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("config", [0, 1])
+def test_specialized_kernels_compile_for_gfx950(mri, config):
+    m = mri.Mech(I.make_mechanism(config))
+    nbytes = m.specialize(128, load=False)
+    assert nbytes > 1000

@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element (small sizes spanning several blocks and
+a ragged tail) and on sampled cells at the full benchmark size."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2211_03293_amd import inputs as I
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ["specialized", "generic"]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def mri(torch):
+    from paper_2211_03293_amd import mri as M
+    return M
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    oracle_mod.set_threads(16)
+    return oracle_mod
+
+
+def _kernel(mri, name):
+    return mri.KERNEL_SPECIALIZED if name == "specialized" else mri.KERNEL_GENERIC
+
+
+def _dev(torch, a, dtype=None):
+    import torch as T
+    return T.as_tensor(np.ascontiguousarray(a), dtype=dtype or T.float64, device="cuda")
+
+
+def _config0_forcing(O, orc, y0, n_stages=3):
+    """Config-0 slow tendencies r_j = 1e-3 |f^F(y0)| xi_j (oracle supplies |f^F|)."""
+    fF = orc.rhs_soa(y0)
+    xi = I.gaussian_xi(0, n_stages, y0.shape[0], y0.shape[1])
+    return 1e-3 * np.abs(fF)[None] * xi
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("n_poly", [1, 2, 3])
+def test_rk4_stage_config0(torch, mri, O, kernel, n_poly):
+    mech = I.make_mechanism(0)
+    orc = O.Oracle(mech)
+    y0 = I.initial_state(0)
+    n, ld = y0.shape
+    F = _config0_forcing(O, orc, y0)
+    rho = np.stack([F[k] / (k + 1) for k in range(n_poly)])     # polynomial forcing terms
+    L, n_sub = (5.0 / 12.0) * 1e-6, 20
+    ref, st_o, _, _ = orc.fast_stage_soa(y0, rho, L, O.rk4_opts(n_sub))
+    assert np.all(st_o[:512] == 0)
+    m = mri.Mech(mech)
+    yd = _dev(torch, y0)
+    out = torch.empty_like(yd)
+    st = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
+    steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    opts = mri.fast_opts(n_sub=n_sub, kernel=_kernel(mri, kernel))
+    mri.mri_fast_stage(m, opts, 512, ld, yd, out, n_poly, _dev(torch, rho), L, st, steps)
+    torch.cuda.synchronize()
+    e = assert_parity(out.cpu().numpy(), ref, mech.n_species, what=f"{kernel} np={n_poly}")
+    print(f"rk4 config0 {kernel} n_poly={n_poly}: max rel err {e:.2e}")
+    assert np.all(st.cpu().numpy()[:512] == 0)
+    assert np.all(steps.cpu().numpy()[:512] == n_sub)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_ragged_tail_and_in_place(torch, mri, O, kernel):
+    """517 cells in ld = 576: the padding stays untouched; y_out may alias y_in."""
+    mech = I.make_mechanism(1)
+    orc = O.Oracle(mech)
+    rng = np.random.Generator(np.random.PCG64(77))
+    y0 = I.independent_cells(517, mech.n_species, rng, ld=576)
+    y0[:, 517:] = 12345.0
+    rho = rng.normal(size=(1, *y0.shape)) * 10.0
+    L, n_sub = 3e-8, 7
+    ref, _, _, _ = orc.fast_stage_soa(y0, rho, L, O.rk4_opts(n_sub), n_cells=517)
+    m = mri.Mech(mech)
+    yd = _dev(torch, y0)
+    mri.mri_fast_stage(m, mri.fast_opts(n_sub=n_sub, kernel=_kernel(mri, kernel)), 517, 576, yd,
+                       yd, 1, _dev(torch, rho), L)
+    got = yd.cpu().numpy()
+    assert_parity(got[:, :517], ref[:, :517], mech.n_species, what=kernel)
+    assert np.all(got[:, 517:] == 12345.0)
+    # empty batch: no launch, nothing written
+    mri.mri_fast_stage(m, mri.fast_opts(n_sub=n_sub), 0, 576, yd, yd, 1, _dev(torch, rho), L)
+    torch.cuda.synchronize()
+    assert np.array_equal(yd.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_zonneveld_stage_config0(torch, mri, O, kernel):
+    mech = I.make_mechanism(0)
+    orc = O.Oracle(mech)
+    y0 = I.initial_state(0)
+    n, ld = y0.shape
+    F = _config0_forcing(O, orc, y0)
+    rho = F[:1]
+    L = (5.0 / 12.0) * 1e-6
+    zo = O.zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
+    ref, st_o, acc_o, _ = orc.fast_stage_soa(y0, rho, L, zo)
+    m = mri.Mech(mech)
+    yd = _dev(torch, y0)
+    out = torch.empty_like(yd)
+    st = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
+                         max_steps=2000, kernel=_kernel(mri, kernel))
+    mri.mri_fast_stage(m, opts, 512, ld, yd, out, 1, _dev(torch, rho), L, st, steps)
+    torch.cuda.synchronize()
+    st_g, acc_g = st.cpu().numpy()[:512], steps.cpu().numpy()[:512]
+    tie = ((st_g | st_o[:512]) & mri.CELL_NEARTIE) != 0
+    ok = ~tie
+    assert ok.sum() >= 500
+    np.testing.assert_array_equal(acc_g[ok], acc_o[:512][ok])
+    assert_parity(out.cpu().numpy(), ref, mech.n_species, cells=np.nonzero(ok)[0], what=kernel)
+    print(f"zonneveld {kernel}: steps {acc_g.min()}..{acc_g.max()}, near ties {tie.sum()}")
+
+
+def _given_callback(torch, mri, ws, F_dev, vec):
+    CB = C.CFUNCTYPE(C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                     C.c_void_p)
+    base = ws.data_ptr()
+
+    def cb(t, y, fy, n_cells, ld, user, stream):
+        j = (fy - base) // (8 * vec)
+        ws[j * vec:(j + 1) * vec].copy_(F_dev[j].reshape(-1))
+        return 0
+
+    return CB(cb)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("table_name", ["MIS-KW3", "ERK33a"])
+def test_mri_slow_step_config0(torch, mri, O, kernel, table_name):
+    """One explicit MRI-GARK step of config 0 (H = 1e-6, RK4 with 20 substeps per
+    stage), slow evaluations given as the config's Gaussian tendencies."""
+    tb = I.table_mis_kw3() if table_name == "MIS-KW3" else I.table_erk33a()
+    mech = I.make_mechanism(0)
+    orc = O.Oracle(mech)
+    y0 = I.initial_state(0)
+    n, ld = y0.shape
+    F = _config0_forcing(O, orc, y0)
+    ref, st_o, steps_o, n_slow = orc.mri_step_given(tb, O.rk4_opts(20), F, y0, 1e-6)
+    assert n_slow == 3 and np.all(st_o[:512] == 0)
+    m, t = mri.Mech(mech), mri.Table(tb)
+    yd = _dev(torch, y0)
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, 512, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    cb = _given_callback(torch, mri, ws, _dev(torch, F), n * ld)
+    st = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    mri.reset_counters()
+    mri.mri_slow_step(m, t, mri.fast_opts(n_sub=20, kernel=_kernel(mri, kernel)),
+                      C.cast(cb, C.c_void_p).value, None, 0.0, 1e-6, 512, ld, yd, ws, st, steps)
+    torch.cuda.synchronize()
+    c = mri.counters()
+    assert c["slow_evals"] == 3 and c["fast_stages"] == 3 and c["cell_stages"] == 3 * 512
+    assert_parity(yd.cpu().numpy(), ref, mech.n_species, what=f"{kernel} {table_name}")
+    assert np.all(steps.cpu().numpy()[:512] == 60)
+    assert mri.mri_status_count(st, 512) == 0
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_mri_slow_steps_advdiff_small_grid(torch, mri, O, kernel):
+    """Config-1 physics on a 12 x 10 x 8 periodic grid: two MRI steps with the
+    advection-diffusion slow RHS, H = 1e-7, RK4 with 50 substeps per stage."""
+    grid = (12, 10, 8)
+    mech = I.make_mechanism(1)
+    orc = O.Oracle(mech)
+    y0 = I.field_state(1, grid=grid)
+    n, ld = y0.shape
+    N = int(np.prod(grid))
+    tb = I.table_mis_kw3()
+    ref = y0.copy()
+    for step in range(2):
+        ref, st_o, _, _ = orc.mri_step_advdiff(tb, O.rk4_opts(50), grid, ref, 1e-7, t=step * 1e-7)
+        assert np.all(st_o[:N] == 0)
+    m, t = mri.Mech(mech), mri.Table(tb)
+    yd = _dev(torch, y0)
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    params = mri.advdiff_params(grid, n)
+    for step in range(2):
+        mri.mri_slow_step(m, t, mri.fast_opts(n_sub=50, kernel=_kernel(mri, kernel)),
+                          mri.ADVDIFF_RHS, params, step * 1e-7, 1e-7, N, ld, yd, ws)
+    torch.cuda.synchronize()
+    assert_parity(yd.cpu().numpy(), ref, mech.n_species, what=kernel)
+
+
+def test_linear_mode_matches_oracle_and_is_third_order(torch, mri, O):
+    from scipy.linalg import expm
+    A_F = np.array([[-6.0, 5.0], [-5.0, -4.0]])
+    A_S = np.array([[0.3, 1.0], [-1.2, 0.2]])
+    orc = O.Oracle(A_fast=A_F)
+    mF, mS = mri.Mech(A_linear=A_F), mri.Mech(A_linear=A_S)
+    errs = []
+    for tb in (I.table_mis_kw3(), I.table_erk33a()):
+        t = mri.Table(tb)
+        errs = []
+        for n_steps in (8, 16, 32):
+            H = 1.0 / n_steps
+            y = np.array([[1.0] * 64, [0.5] * 64])
+            yd = _dev(torch, y)
+            ws = torch.empty(mri.mri_workspace_bytes(mF, t, 64, 64) // 8, dtype=torch.float64,
+                             device="cuda")
+            yo = y[:, :1].copy()
+            for k in range(n_steps):
+                mri.mri_slow_step(mF, t, mri.fast_opts(n_sub=64), mri.LINEAR_RHS, mS, k * H, H, 64,
+                                  64, yd, ws)
+                yo, _, _, _ = orc.mri_step_linear(tb, O.rk4_opts(64), A_S, yo[:, 0], H)
+            got = yd.cpu().numpy()
+            np.testing.assert_allclose(got[:, 0], yo[:, 0], rtol=1e-12)
+            assert np.all(got == got[:, :1])
+            errs.append(np.abs(got[:, 0] - expm(A_F + A_S) @ np.array([1.0, 0.5])).max())
+        rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert np.all(rates > 2.7), (tb.name, rates)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_determinism_and_fault_isolation(torch, mri, O, kernel):
+    mech = I.make_mechanism(0)
+    y0 = I.initial_state(0)
+    n, ld = y0.shape
+    m = mri.Mech(mech)
+    opts = mri.fast_opts(n_sub=20, kernel=_kernel(mri, kernel))
+    L = 1e-7
+
+    def run(y):
+        yd = _dev(torch, y)
+        out = torch.empty_like(yd)
+        st = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+        mri.mri_fast_stage(m, opts, 512, ld, yd, out, 0, None, L, st)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), st.cpu().numpy()
+
+    a, sa = run(y0)
+    b, sb = run(y0)
+    assert np.array_equal(a, b) and np.all(sa[:512] == 0)
+    bad = y0.copy()
+    bad[3, 17] = np.nan            # NaN mass fraction in cell 17
+    bad[n - 1, 200] = 100.0        # cell 200 starts far below 200 K
+    c, sc = run(bad)
+    assert sc[17] & mri.CELL_NONFINITE
+    assert sc[200] & (mri.CELL_TRANGE | mri.CELL_NONFINITE)
+    others = np.setdiff1d(np.arange(512), [17, 200])
+    assert np.all(sc[others] == 0)
+    assert np.array_equal(c[:, others], a[:, others])
+    assert mri.mri_status_count(torch.as_tensor(sc, device="cuda"), 512) == 2
