@@ -63,7 +63,7 @@ def load_traffic(workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(mech, y_field, rho, L_list, n_sub, n_sample=8192):
+def cpu_baseline(mech, y_field, rho, L_list, n_sub, n_sample=262144):
     """The oracle as it stands, on n_sample cells of the same field, for the
     three fast stages of one slow step (forcing of the first stage)."""
     from oracle import oracle as O
@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--kernel", choices=["auto", "specialized", "generic"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the fast stage is "
@@ -105,6 +107,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes 2^30 bytes per dispatch
+        src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes_per_dispatch=2 ** 30, dispatches=3)), flush=True)
+        return
     cfg = I.CONFIGS[1]
     mech = I.make_mechanism(1)
     tb = I.table_mis_kw3()

@@ -241,8 +241,10 @@ mri_status mri_timing_read(double *fast_ms, int64_t *n_launches, int reset);
 mri_status mri_batch_plan_create(const mri_mech *m, const mri_fast_opts *opts, int n_sets,
                                  const int64_t *set_offsets /* host [n_sets+1] */,
                                  mri_batch_plan **out);
-/* y_in/y_out device [n][ld]; rho_poly device [n_poly][n][ld] or NULL;
-   L_per_set host [n_sets]; status_out/steps_out optional device [n_total]. */
+/* y_in/y_out device [n][ld], distinct (the first run times tile candidates on
+   a prefix of the sets, writing y_out); rho_poly device [n_poly][n][ld] or
+   NULL; L_per_set host [n_sets], copied to the device on the stream;
+   status_out/steps_out optional device [n_total]. */
 mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, double *y_out, int64_t ld,
                          int n_poly, const double *rho_poly, const double *L_per_set,
                          int32_t *status_out, int32_t *steps_out, mri_stream_t stream);

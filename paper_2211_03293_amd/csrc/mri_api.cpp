@@ -375,10 +375,13 @@ struct mri_batch_plan {
     unsigned long long *d_counters = nullptr;   // [0] queue, [1] useful, [2] issued
     int wg = 0, n_blocks = 0;                   // tuned tile
     bool tuned = false;
-    // captured launch
+    std::vector<std::pair<std::pair<int, int>, float>> tune_log;  // (wg, blocks) -> ms
+    // captured launch (counter reset + persistent kernel), replayed while the
+    // argument key is unchanged
+    hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<char> graph_key;
+    std::vector<uintptr_t> graph_key;
 };
 
 extern "C" {
@@ -752,6 +755,7 @@ void mri_batch_plan_destroy(mri_batch_plan *p)
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->d_off) (void)hipFree(p->d_off);
     if (p->d_L) (void)hipFree(p->d_L);
     if (p->d_counters) (void)hipFree(p->d_counters);
@@ -770,10 +774,10 @@ mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_
 }  // extern "C"
 
 // Enqueue one persistent launch (counter reset by a fill kernel, then the
-// work-queue kernel) on stream s.
-static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, const double *yin,
-                                double *yout, long long ld, int n_poly, const double *rho,
-                                int32_t *status, int32_t *steps, hipStream_t s)
+// work-queue kernel) over the first n_total cells on stream s.
+static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, long long n_total,
+                                const double *yin, double *yout, long long ld, int n_poly,
+                                const double *rho, int32_t *status, int32_t *steps, hipStream_t s)
 {
     hipFunction_t fn = nullptr;
     mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn);
@@ -790,13 +794,12 @@ static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, const d
     a.counter = p->d_counters;
     a.lane_steps = p->d_counters + 1;
     a.issued_steps = p->d_counters + 2;
-    a.n_total = p->n_total;
+    a.n_total = n_total;
     a.ld = ld;
     a.n_sets = p->n_sets;
     a.o = ZvOpts{p->opts.rtol, p->opts.atol_Y, p->opts.atol_T, p->opts.max_steps};
     void *args[] = {&a};
-    HIP_TRY(hipModuleLaunchKernel(fn, (unsigned)n_blocks, 1, 1, wg, 1, 1, 0, s,
-                                  args, nullptr));
+    HIP_TRY(hipModuleLaunchKernel(fn, (unsigned)n_blocks, 1, 1, wg, 1, 1, 0, s, args, nullptr));
     return MRI_OK;
 }
 
@@ -807,6 +810,64 @@ static int n_cus()
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 256;
     return cus > 0 ? cus : 256;
+}
+
+// Autotuner: time every (threads per block, persistent grid) candidate on a
+// prefix of the sets holding about 1/8 of the cells (at least 64k when
+// available), keep the fastest.  Candidates: 64/128/256 threads per block, grid
+// = 1x or 2x the resident capacity reported by the occupancy query.
+static mri_status batch_tune(mri_batch_plan *p, const double *yin, double *yout, long long ld,
+                             int n_poly, const double *rho, hipStream_t s)
+{
+    if (p->opts.block_size) {
+        p->wg = p->opts.block_size;
+        hipFunction_t fn = nullptr;
+        mri_status st = spec_get(p->mech, p->wg, 2, n_poly, &fn);
+        if (st != MRI_OK) return st;
+        int nb = 0;
+        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, p->wg, 0));
+        p->n_blocks = std::max(1, nb) * n_cus();
+        p->tuned = true;
+        return MRI_OK;
+    }
+    long long target = std::max<long long>(std::min<long long>(p->n_total, 65536), p->n_total / 8);
+    int k = 1;
+    while (k < p->n_sets && p->off[k] < target) ++k;
+    const long long n_sample = p->off[k];
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    p->tune_log.clear();
+    for (int wg : {64, 128, 256}) {
+        hipFunction_t fn = nullptr;
+        mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn);
+        if (st != MRI_OK) return st;
+        int nb = 0;
+        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, wg, 0));
+        nb = std::max(1, nb);
+        for (int f : {1, 2}) {
+            const int blocks = nb * n_cus() * f;
+            HIP_TRY(hipEventRecord(e0, s));
+            st = batch_enqueue(p, wg, blocks, n_sample, yin, yout, ld, n_poly, rho, nullptr,
+                               nullptr, s);
+            if (st != MRI_OK) return st;
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            p->tune_log.push_back({{wg, blocks}, ms});
+            if (ms < best) {
+                best = ms;
+                p->wg = wg;
+                p->n_blocks = blocks;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->tuned = true;
+    return MRI_OK;
 }
 
 extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, double *y_out,
@@ -826,17 +887,44 @@ extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, doubl
             return fail(MRI_EINVAL, "L_per_set[%d] must be positive and finite", i);
     if (p->n_total == 0) return MRI_OK;
     if (!y_in || !y_out) return fail(MRI_EINVAL, "y_in or y_out is NULL");
+    if (y_in == y_out) return fail(MRI_EINVAL, "batched runs need y_out distinct from y_in");
+    mri_status st = ensure_device(p->mech);
+    if (st != MRI_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(p->d_L, L_per_set, sizeof(double) * p->n_sets, hipMemcpyHostToDevice, s));
     if (!p->tuned) {
-        p->wg = p->opts.block_size ? p->opts.block_size : 128;
-        const int waves_per_block = p->wg / 64;
-        p->n_blocks = std::max(1, n_cus() * 8 / waves_per_block);
-        p->tuned = true;
+        st = batch_tune(p, y_in, y_out, ld, n_poly, rho_poly, s);
+        if (st != MRI_OK) return st;
     }
-    mri_status st = batch_enqueue(p, p->wg, p->n_blocks, y_in, y_out, ld, n_poly, rho_poly,
-                                  status_out, steps_out, s);
-    if (st != MRI_OK) return st;
+    const std::vector<uintptr_t> key = {(uintptr_t)y_in, (uintptr_t)y_out, (uintptr_t)ld,
+                                        (uintptr_t)n_poly, (uintptr_t)rho_poly,
+                                        (uintptr_t)status_out, (uintptr_t)steps_out,
+                                        (uintptr_t)p->wg, (uintptr_t)p->n_blocks};
+    if (!p->exec || key != p->graph_key) {
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->exec = nullptr;
+        p->graph = nullptr;
+        // compile outside the capture
+        hipFunction_t fn = nullptr;
+        st = spec_get(p->mech, p->wg, 2, n_poly, &fn);
+        if (st != MRI_OK) return st;
+        if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        st = batch_enqueue(p, p->wg, p->n_blocks, p->n_total, y_in, y_out, ld, n_poly, rho_poly,
+                           status_out, steps_out, p->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+        if (st != MRI_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (ce != hipSuccess) return fail(MRI_EHIP, "capture failed: %s", hipGetErrorString(ce));
+        p->graph = g;
+        HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+        p->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(p->exec, s));
     ++c_fast;
     c_cells += p->n_total;
     return MRI_OK;
