@@ -207,6 +207,10 @@ int mri_advdiff_slow_rhs(double t, const double *y, double *fy, int n_cells, int
 int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
                         mri_stream_t stream);
 
+/* Diagnostic: y[i] = 2^x[i] (device arrays, n elements) with the device
+   exponential the fast-stage kernels use, for accuracy tests. */
+mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t stream);
+
 /* Counts cells with (status & mask) != 0; synchronizes the stream. */
 mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, int64_t *n_bad,
                             mri_stream_t stream);

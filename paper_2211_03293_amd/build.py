@@ -37,7 +37,8 @@ def _embed(name: str, symbol: str) -> str:
 def _write_embedded() -> str:
     os.makedirs(BUILD, exist_ok=True)
     path = os.path.join(BUILD, "embedded_sources.cpp")
-    body = _embed("spec_kernels.inc", "mri_spec_kernels_src") + _embed("spec_abi.h", "mri_spec_abi_src")
+    body = (_embed("spec_kernels.inc", "mri_spec_kernels_src") +
+            _embed("spec_abi.h", "mri_spec_abi_src") + _embed("mri_math.h", "mri_math_src"))
     old = open(path).read() if os.path.exists(path) else None
     if old != body:
         with open(path, "w") as f:

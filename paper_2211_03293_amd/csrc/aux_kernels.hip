@@ -2,6 +2,7 @@
 // assembly, the advection-diffusion slow RHS, a linear slow RHS for tests,
 // status reduction and small fills.
 #include "mri_dev.h"
+#include "mri_math.h"
 
 namespace {
 
@@ -93,6 +94,13 @@ __global__ void __launch_bounds__(256)
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
 }
 
+__global__ void __launch_bounds__(256) k_exp2(const double *__restrict__ x, double *__restrict__ y,
+                                             int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = mri_exp2(x[i]);
+}
+
 __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,5 +151,12 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, h
 {
     const int block = 64;
     hipLaunchKernelGGL(k_fill_u64, dim3((n + block - 1) / block), dim3(block), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp2(const double *x, double *y, int n, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(k_exp2, dim3((n + block - 1) / block), dim3(block), 0, s, x, y, n);
     return hipGetLastError();
 }

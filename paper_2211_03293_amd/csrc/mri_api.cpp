@@ -26,6 +26,7 @@
 // Embedded sources of the run-time compiled kernels (generated at build time).
 extern const char mri_spec_kernels_src[];
 extern const char mri_spec_abi_src[];
+extern const char mri_math_src[];
 
 namespace {
 
@@ -130,24 +131,27 @@ struct mri_table {
 // ---------------------------------------------------------------------------
 // Run-time specialization
 // ---------------------------------------------------------------------------
+// Literal tables of the specialized kernels (base-2 forms, see spec_kernels.inc):
+// species (CFE = CF e^BR, WF, AR2 = AR log2 e, EA, CV); reactions
+// (a, b, c, d, AP = e^(ln A'), beta, TH2 = theta' log2 e).
 static std::string make_defs(const mri_mech &m)
 {
+    const double log2e = 1.4426950408889634074;
     std::ostringstream o;
     o << "#define NS " << m.S << "\n";
     o << "#define T_REF " << hexd(m.T_ref) << "\n";
     o << "#define MRI_SPECIES(X)";
     for (int k = 0; k < m.S; ++k) {
         const double *p = &m.sp[k * GEN_SP_STRIDE];
-        o << " \\\n  X(" << k;
-        for (int i = 0; i < GEN_SP_STRIDE; ++i) o << ", " << hexd(p[i]);
-        o << ")";
+        o << " \\\n  X(" << k << ", " << hexd(p[0] * std::exp(p[3])) << ", " << hexd(p[1]) << ", "
+          << hexd(p[2] * log2e) << ", " << hexd(p[4]) << ", " << hexd(p[5]) << ")";
     }
     o << "\n#define MRI_REACTIONS(X)";
     for (int j = 0; j < m.R; ++j) {
         const uint32_t id = m.rxi[j];
         o << " \\\n  X(" << (id & 255u) << ", " << ((id >> 8) & 255u) << ", "
-          << ((id >> 16) & 255u) << ", " << (id >> 24) << ", " << hexd(m.rx[3 * j]) << ", "
-          << hexd(m.rx[3 * j + 1]) << ", " << hexd(m.rx[3 * j + 2]) << ")";
+          << ((id >> 16) & 255u) << ", " << (id >> 24) << ", " << hexd(std::exp(m.rx[3 * j]))
+          << ", " << hexd(m.rx[3 * j + 1]) << ", " << hexd(m.rx[3 * j + 2] * log2e) << ")";
     }
     o << "\n";
     return o.str();
@@ -171,13 +175,24 @@ static std::string device_arch()
 static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, SpecKernel *out)
 {
     if (m->defs.empty()) m->defs = make_defs(*m);
-    std::string src = m->defs + "#define WG " + std::to_string(wg) + "\n#define MRI_KIND " +
+    std::string tune;
+    if (const char *g = std::getenv("MRI_SPEC_GROUP"))   // scheduling-window tuning knob
+        tune = std::string("#define MRI_GROUP ") + std::to_string(std::max(1, std::atoi(g))) + "\n";
+    std::string src = m->defs + tune + "#define WG " + std::to_string(wg) + "\n#define MRI_KIND " +
                       std::to_string(kind) + "\n#define MRI_NP " + std::to_string(np) + "\n" +
                       mri_spec_kernels_src;
-    const char *hdr_src[] = {mri_spec_abi_src};
-    const char *hdr_name[] = {"spec_abi.h"};
+    if (const char *dir = std::getenv("MRI_SPEC_DUMP_DIR")) {
+        // debugging aid: keep the generated source next to its headers
+        const std::string base = std::string(dir) + "/mri_spec_w" + std::to_string(wg) + "_k" +
+                                 std::to_string(kind) + "_p" + std::to_string(np);
+        std::ofstream(base + ".hip") << src;
+        std::ofstream(std::string(dir) + "/spec_abi.h") << mri_spec_abi_src;
+        std::ofstream(std::string(dir) + "/mri_math.h") << mri_math_src;
+    }
+    const char *hdr_src[] = {mri_spec_abi_src, mri_math_src};
+    const char *hdr_name[] = {"spec_abi.h", "mri_math.h"};
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "mri_spec.hip", 1, hdr_src, hdr_name) !=
+    if (hiprtcCreateProgram(&prog, src.c_str(), "mri_spec.hip", 2, hdr_src, hdr_name) !=
         HIPRTC_SUCCESS)
         return fail(MRI_ECOMPILE, "hiprtcCreateProgram failed");
     const std::string arch = "--offload-arch=" + (load ? device_arch() : std::string("gfx950"));
@@ -490,6 +505,10 @@ mri_status mri_mech_create(const mri_mech_desc *d, mri_mech **out)
         m->rx[3 * j + 1] = d->beta[j];
         m->rx[3 * j + 2] = d->theta[j] + (pa[2] + pb[2]);
         m->rxi[j] = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16) | ((uint32_t)dd << 24);
+        if (std::fabs(m->rx[3 * j]) > 700.0)
+            return fail(MRI_EUNSUPPORTED,
+                        "reaction %d: ln A - (g_b,a + g_b,b)/R = %.1f is outside +-700", j,
+                        m->rx[3 * j]);
     }
     *out = m.release();
     return MRI_OK;
@@ -691,6 +710,14 @@ int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int 
     if (launch_lin_apply(m->n, m->d_A, n_cells, ld, y, fy, (hipStream_t)stream) != hipSuccess)
         return -5;
     return 0;
+}
+
+mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(MRI_EINVAL, "bad arguments");
+    if (n == 0) return MRI_OK;
+    HIP_TRY(launch_exp2(x, y, n, (hipStream_t)stream));
+    return MRI_OK;
 }
 
 mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, int64_t *n_bad,

@@ -58,3 +58,4 @@ hipError_t launch_lin_apply(int n, const double *A, int n_cells, int ld, const d
 hipError_t launch_status_count(const int32_t *status, int n_cells, int32_t mask,
                                unsigned long long *count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
+hipError_t launch_exp2(const double *x, double *y, int n, hipStream_t s);

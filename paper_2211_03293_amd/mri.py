@@ -81,6 +81,7 @@ _SIGS = {
                            _vp, _sz, _vp, _vp, _vp]),
     "mri_advdiff_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
     "mri_linear_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
+    "mri_selftest_exp2": (_i, [_vp, _vp, _i, _vp]),
     "mri_status_count": (_i, [_vp, _i, C.c_int32, C.POINTER(C.c_int64), _vp]),
     "mri_get_counters": (None, [C.POINTER(mri_counters)]),
     "mri_reset_counters": (None, []),
@@ -220,6 +221,10 @@ def mri_slow_step(mech: Mech, table: Table, opts, f_slow, user, t0, H, n_cells, 
     _check(lib.mri_slow_step(mech.h, table.h, C.byref(opts), f_slow, user_p, float(t0), float(H),
                              n_cells, ld, _ptr(y), _ptr(ws), nbytes, _ptr(status_out),
                              _ptr(steps_out), _stream(stream)))
+
+
+def mri_selftest_exp2(x, y, stream=None):
+    _check(lib.mri_selftest_exp2(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
 
 
 def mri_status_count(status, n_cells, mask=0xFF, stream=None):
