@@ -273,3 +273,73 @@ def set_threads(n):
 
 def num_threads():
     return lib().ora_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# Surrogate MLP (mlp_oracle.c)
+# ---------------------------------------------------------------------------
+def _mlp_setup():
+    L = lib()
+    L.ora_mlp_loss_grad.restype = C.c_double
+    L.ora_bf16_round.restype = C.c_float
+    L.ora_bf16_round.argtypes = [C.c_float]
+    L.ora_silu.restype = C.c_double
+    L.ora_silu.argtypes = [C.c_double]
+    L.ora_silu_grad.restype = C.c_double
+    L.ora_silu_grad.argtypes = [C.c_double]
+    return L
+
+
+def mlp_param_count(widths):
+    return sum(widths[l + 1] * widths[l] + widths[l + 1] for l in range(len(widths) - 1))
+
+
+def mlp_pack(Ws, bs):
+    """Pack per-layer W [out][in] and b [out] as the oracle expects."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float64).ravel(),
+                                           np.asarray(b, np.float64).ravel()])
+                           for W, b in zip(Ws, bs)])
+
+
+def mlp_forward(widths, params, X, bf16=False, cache=False):
+    L = _mlp_setup()
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    p = _f64(params)
+    X = _f64(X)
+    batch = X.shape[0]
+    Y = np.zeros((batch, widths[-1]))
+    nz = sum(batch * widths[l + 1] for l in range(len(widths) - 1))
+    na = sum(batch * widths[l + 1] for l in range(len(widths) - 2))
+    Z = np.zeros(nz) if cache else None
+    A = np.zeros(max(na, 1)) if cache else None
+    L.ora_mlp_forward(len(widths) - 1, _p(w, C.c_int32), _p(p), batch, _p(X), _p(Y),
+                      _p(Z) if cache else None, _p(A) if cache else None, int(bf16))
+    return (Y, Z, A) if cache else Y
+
+
+def mlp_loss_grad(widths, params, X, T, bf16=False):
+    L = _mlp_setup()
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    p = _f64(params)
+    X, T = _f64(X), _f64(T)
+    g = np.zeros(p.size)
+    loss = L.ora_mlp_loss_grad(len(widths) - 1, _p(w, C.c_int32), _p(p), X.shape[0], _p(X),
+                               _p(T), _p(g), int(bf16))
+    return loss, g
+
+
+def bf16_round(x):
+    L = _mlp_setup()
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.zeros_like(x)
+    L.ora_bf16_round_array(x.ctypes.data_as(C.POINTER(C.c_float)),
+                           y.ctypes.data_as(C.POINTER(C.c_float)), x.size)
+    return y
+
+
+def silu(z):
+    return _mlp_setup().ora_silu(float(z))
+
+
+def silu_grad(z):
+    return _mlp_setup().ora_silu_grad(float(z))
