@@ -1,0 +1,617 @@
+// mlp_kernels.hip -- surrogate MLP kernels: BF16 MFMA GEMM for training,
+// training elementwise kernels (bias + SiLU, MSE gradient, SiLU backward,
+// bias gradient, Adam), feature construction, the fused four-layer inference
+// kernel, the step-doubling gate with compaction, and gather / scatter.
+//
+// MFMA: v_mfma_f32_16x16x32_bf16 (gfx950).  Operand layout, lane l, g = l / 16:
+//   A[i][k]: i = l % 16, k = 8 g + e (e = 0..7, one 16-byte register quad)
+//   B[k][j]: j = l % 16, k = 8 g + e
+//   D[i][j]: j = l % 16, i = 4 g + r (r = 0..3, four f32)
+#include "mlp_dev.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float x)
+{
+    __bf16 b = static_cast<__bf16>(x);   // round to nearest even
+    return __builtin_bit_cast(uint16_t, b);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t u)
+{
+    return __builtin_bit_cast(float, (uint32_t)u << 16);
+}
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float silu_grad_f(float z)
+{
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ __forceinline__ f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f32x4 &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// C[M x N] (f32, ldc) = op(A)[M x K] * op(B)[K x N], bf16 operands.
+// op(A)[m][k] = transA ? A[k*lda + m] : A[m*lda + k]
+// op(B)[k][n] = transB ? B[n*ldb + k] : B[k*ldb + n]
+// Block 256 threads = 4 waves, tile 64 x 64, each wave 32 x 32 (2 x 2 MFMA tiles).
+// ---------------------------------------------------------------------------
+constexpr int GT = 64, GK = 32, GPAD = 8;
+
+__global__ void __launch_bounds__(256)
+    k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda, int transA,
+                const uint16_t *__restrict__ B, int ldb, int transB, float *__restrict__ C,
+                int ldc)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int g = lane >> 4, i16 = lane & 15;
+    f32x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        for (int e = tid; e < GT * GK; e += 256) {
+            const int r = e / GK, k = e % GK;
+            const int m = m0 + r, kk = k0 + k;
+            uint16_t va = 0;
+            if (m < M && kk < K) va = transA ? A[(size_t)kk * lda + m] : A[(size_t)m * lda + kk];
+            As[r][k] = va;
+            const int n = n0 + r;
+            uint16_t vb = 0;
+            if (n < N && kk < K) vb = transB ? B[(size_t)n * ldb + kk] : B[(size_t)kk * ldb + n];
+            Bs[r][k] = vb;
+        }
+        __syncthreads();
+        bf16x8 af[2], bfr[2];
+        for (int t = 0; t < 2; ++t) {
+            af[t] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * t + i16][8 * g]);
+            bfr[t] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * t + i16][8 * g]);
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) acc[a][b] = mfma(af[a], bfr[b], acc[a][b]);
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * a + 4 * g + r, n = n0 + wn + 16 * b + i16;
+                if (m < M && n < N) C[(size_t)m * ldc + n] = acc[a][b][r];
+            }
+}
+
+// Z [rows x N] += bias; A = bf16(silu(Z)) when act != 0.
+__global__ void __launch_bounds__(256)
+    k_bias_act(int rows, int N, float *__restrict__ Z, const float *__restrict__ bias, int act,
+               uint16_t *__restrict__ Aout)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * N) return;
+    const int n = (int)(e % N);
+    const float z = Z[e] + bias[n];
+    Z[e] = z;
+    if (act) Aout[e] = f2bf(silu_f(z));
+}
+
+// dZ = 2 (Y - T) / (rows * N) in f32, its bf16 copy, and the loss sum (f64).
+__global__ void __launch_bounds__(256)
+    k_mse_grad(int rows, int N, const float *__restrict__ Y, const float *__restrict__ T,
+               float *__restrict__ dZ, uint16_t *__restrict__ dZq, double *loss)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)rows * N;
+    double l = 0.0;
+    if (e < tot) {
+        const float d = Y[e] - T[e];
+        const float s = 1.0f / (float)((double)rows * N);
+        const float g = 2.0f * d * s;
+        dZ[e] = g;
+        dZq[e] = f2bf(g);
+        l = (double)d * (double)d / (double)tot;
+    }
+    // wave reduction, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off);
+    if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, l);
+}
+
+// dZ = dA * silu'(Z) (f32) and its bf16 copy.
+__global__ void __launch_bounds__(256)
+    k_silu_bwd(long long n, const float *__restrict__ dA, const float *__restrict__ Z,
+               float *__restrict__ dZ, uint16_t *__restrict__ dZq)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float g = dA[e] * silu_grad_f(Z[e]);
+    dZ[e] = g;
+    dZq[e] = f2bf(g);
+}
+
+// db[n] = sum_r dZ[r][n], fixed summation order (one thread per column).
+__global__ void __launch_bounds__(256)
+    k_colsum(int rows, int N, const float *__restrict__ dZ, float *__restrict__ db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) s += dZ[(size_t)r * N + n];
+    db[n] = s;
+}
+
+__global__ void __launch_bounds__(256)
+    k_adam(long long n, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+           float *__restrict__ v, uint16_t *__restrict__ wq, float lr, float b1, float b2,
+           float eps, float c1, float c2)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    w[i] = wi;
+    if (wq) wq[i] = f2bf(wi);
+}
+
+__global__ void __launch_bounds__(256)
+    k_to_bf16(long long n, const float *__restrict__ x, uint16_t *__restrict__ y)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Raw feature k of one sample read straight from SoA arrays (no private
+// arrays, so per-lane feature indices cost no scratch memory):
+//   k < NS: log max(Y_k, 1e-30); k = NS: T; then the forcing coefficient p of
+//   component c for k = NS + 1 + p NC + c, transformed for half stages; last:
+//   log L (L is the stage length of this inference).
+// half: 0 full stage; 1 first half, r(tau'/2): rho_p / 2^p; 2 second half,
+// r((1 + tau')/2): sum_(q >= p) C(q, p) 2^-q rho_q.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double raw_feature(int k, const double *__restrict__ y,
+                                              const double *__restrict__ rho, long long ld,
+                                              long long s, int n_poly, int half, double L)
+{
+    if (k < MLP_NS) return log(fmax(y[k * ld + s], 1e-30));
+    if (k == MLP_NS) return y[MLP_NS * ld + s];
+    if (k < MLP_NS + 1 + MLP_NPOLY * MLP_NC) {
+        const int q = k - MLP_NS - 1, p = q / MLP_NC, c = q % MLP_NC;
+        double r[MLP_NPOLY];
+#pragma unroll
+        for (int t = 0; t < MLP_NPOLY; ++t)
+            r[t] = (t < n_poly) ? rho[((long long)t * MLP_NC + c) * ld + s] : 0.0;
+        if (half == 0) return p == 0 ? r[0] : (p == 1 ? r[1] : r[2]);
+        if (half == 1) return p == 0 ? r[0] : (p == 1 ? 0.5 * r[1] : 0.25 * r[2]);
+        // C(q, p) 2^-q: p = 0: r0 + r1/2 + r2/4; p = 1: r1/2 + 2 r2/4; p = 2: r2/4
+        return p == 0 ? r[0] + 0.5 * r[1] + 0.25 * r[2]
+                      : (p == 1 ? 0.5 * r[1] + 0.5 * r[2] : 0.25 * r[2]);
+    }
+    if (k == MLP_FEAT - 1) return log(L);
+    return 0.0;
+}
+
+__device__ __forceinline__ float std_feature(int k, const double *__restrict__ y,
+                                             const double *__restrict__ rho, long long ld,
+                                             long long s, int n_poly, int half, double L,
+                                             const double *__restrict__ stats)
+{
+    if (k >= MLP_FEAT) return 0.0f;
+    return (float)((raw_feature(k, y, rho, ld, s, n_poly, half, L) - stats[k]) *
+                   stats[MLP_FEAT + k]);
+}
+
+// Training / evaluation features.  Samples are SoA with leading dimension ld:
+// Y0[c*ld + s] (c < NC), RHO[(p*NC + c)*ld + s] (p < n_poly), Lv[s], Y1 like Y0.
+// idx (nullable) picks the samples of this batch.  X: bf16 [B][MLP_KPAD]
+// standardized features; T (nullable): f32 [B][MLP_NC] standardized targets
+// (Y1 - Y0 - y_mean) / y_std.
+__global__ void __launch_bounds__(256)
+    k_featurize(int B, const int *__restrict__ idx, long long ld, const double *__restrict__ Y0,
+                int n_poly, const double *__restrict__ RHO, const double *__restrict__ Lv,
+                const double *__restrict__ Y1, const double *__restrict__ stats,
+                uint16_t *__restrict__ X, float *__restrict__ T)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const long long s = idx ? idx[b] : b;
+    const double L = Lv[s];
+    for (int k = 0; k < MLP_KPAD; ++k)
+        X[(size_t)b * MLP_KPAD + k] = f2bf(std_feature(k, Y0, RHO, ld, s, n_poly, 0, L, stats));
+    if (T) {
+        const double *ym = stats + 2 * MLP_FEAT, *yi = stats + 2 * MLP_FEAT + MLP_NC;
+        for (int c = 0; c < MLP_NC; ++c)
+            T[(size_t)b * MLP_NC + c] =
+                (float)((Y1[c * ld + s] - Y0[c * ld + s] - ym[c]) * yi[c]);
+    }
+}
+
+// Per-block partial sums for feature / target statistics (FP64): part[block]
+// holds sum and sum of squares of the MLP_FEAT raw features and MLP_NC raw
+// increments over the block's samples.
+__global__ void __launch_bounds__(256)
+    k_stats_partial(long long N, long long ld, const double *__restrict__ Y0, int n_poly,
+                    const double *__restrict__ RHO, const double *__restrict__ Lv,
+                    const double *__restrict__ Y1, double *__restrict__ part)
+{
+    constexpr int NV = MLP_FEAT + MLP_NC;
+    __shared__ double red[256];
+    const long long per = (N + gridDim.x - 1) / gridDim.x;
+    const long long s0 = (long long)blockIdx.x * per, s1 = min(N, s0 + per);
+    for (int v = 0; v < NV; ++v) {
+        double sum = 0.0, sq = 0.0;
+        for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+            const double x = (v < MLP_FEAT)
+                                 ? raw_feature(v, Y0, RHO, ld, s, n_poly, 0, Lv[s])
+                                 : Y1[(v - MLP_FEAT) * ld + s] - Y0[(v - MLP_FEAT) * ld + s];
+            sum += x;
+            sq += x * x;
+        }
+        red[threadIdx.x] = sum;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * 2 * NV + v] = red[0];
+        __syncthreads();
+        red[threadIdx.x] = sq;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * 2 * NV + NV + v] = red[0];
+        __syncthreads();
+    }
+}
+
+// stats = [x_mean (FEAT), x_inv_std (FEAT), y_mean (NC), y_inv_std (NC), y_std (NC)]
+__global__ void k_stats_final(int n_blocks, long long N, const double *__restrict__ part,
+                              double *__restrict__ stats)
+{
+    constexpr int NV = MLP_FEAT + MLP_NC;
+    const int v = threadIdx.x;
+    if (v >= NV) return;
+    double sum = 0.0, sq = 0.0;
+    for (int b = 0; b < n_blocks; ++b) {
+        sum += part[(size_t)b * 2 * NV + v];
+        sq += part[(size_t)b * 2 * NV + NV + v];
+    }
+    const double mean = sum / (double)N;
+    const double var = fmax(sq / (double)N - mean * mean, 0.0);
+    const double sd = sqrt(var);
+    const double inv = (sd > 1e-30 * fmax(1.0, fabs(mean))) ? 1.0 / sd : 1.0;
+    if (v < MLP_FEAT) {
+        stats[v] = mean;
+        stats[MLP_FEAT + v] = inv;
+    } else {
+        const int c = v - MLP_FEAT;
+        stats[2 * MLP_FEAT + c] = mean;
+        stats[2 * MLP_FEAT + MLP_NC + c] = inv;
+        stats[2 * MLP_FEAT + 2 * MLP_NC + c] = (sd > 0.0) ? sd : 1.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference: y_out = y_in + y_mean + y_std * MLP(features(y_in, rho', L')).
+// One wave owns 32 cells (two 16-cell MFMA column tiles); activations stay in
+// registers between layers: the D layout of one layer is the B layout of the
+// next once the next layer's input columns are permuted (done on the host):
+// logical K index 32 t + 8 g + e of a layer holds the previous layer's output
+// 32 t + (e < 4 ? 4 g + e : 16 + 4 g + e - 4).
+// half: 0 full stage (rho, L); 1 first half (rho_k / 2^k, L/2); 2 second half
+// (binomially re-expanded rho, L/2).
+// ---------------------------------------------------------------------------
+struct InferArgs {
+    const double *yin;
+    double *yout;
+    const double *rho;
+    const uint16_t *W[4];       // [out_pad][in_pad] bf16, permuted inputs
+    const float *b[4];          // [out_pad]
+    const double *stats;
+    long long ld;
+    int n_cells;
+    int n_poly;
+    double L;
+    int half;
+};
+
+template <int KB>
+__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int j, int g,
+                                            const bf16x8 (&bin)[8][2], f32x4 (&acc)[16][2])
+{
+#pragma unroll
+    for (int mi = 0; mi < 16; ++mi) {
+        acc[mi][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc[mi][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mi = 0; mi < 16; ++mi) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(
+                W + (size_t)(16 * mi + j) * (32 * KB) + 32 * kb + 8 * g);
+            acc[mi][0] = mfma(af, bin[kb][0], acc[mi][0]);
+            acc[mi][1] = mfma(af, bin[kb][1], acc[mi][1]);
+        }
+}
+
+__device__ __forceinline__ void silu_repack(const float *__restrict__ bias, int g,
+                                            const f32x4 (&acc)[16][2], bf16x8 (&bin)[8][2])
+{
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            bf16x8 v;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = 32 * kb + 16 * h + 4 * g + r;
+                    v[4 * h + r] = static_cast<__bf16>(silu_f(acc[2 * kb + h][t][r] + bias[o]));
+                }
+            bin[kb][t] = v;
+        }
+}
+
+__global__ void __launch_bounds__(256) k_infer(InferArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const long long base = ((long long)blockIdx.x * 4 + wave) * 32;
+    if (base >= a.n_cells) return;              // whole wave idle (no barriers here)
+    const double L = (a.half == 0) ? a.L : 0.5 * a.L;
+    // ---- layer-1 B operand: features of cells base + j (tile 0) and base + 16 + j
+    bf16x8 bin[8][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        long long cell = base + 16 * t + j;
+        if (cell >= a.n_cells) cell = a.n_cells - 1;
+#pragma unroll
+        for (int kb = 0; kb < MLP_KPAD / 32; ++kb) {
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                v[e] = static_cast<__bf16>(std_feature(32 * kb + 8 * g + e, a.yin, a.rho, a.ld,
+                                                       cell, a.n_poly, a.half, L, a.stats));
+            bin[kb][t] = v;
+        }
+    }
+    // ---- three hidden layers
+    f32x4 acc[16][2];
+    dense_layer<MLP_KPAD / 32>(a.W[0], j, g, bin, acc);
+    silu_repack(a.b[0], g, acc, bin);
+    dense_layer<MLP_HID / 32>(a.W[1], j, g, bin, acc);
+    silu_repack(a.b[1], g, acc, bin);
+    dense_layer<MLP_HID / 32>(a.W[2], j, g, bin, acc);
+    silu_repack(a.b[2], g, acc, bin);
+    // ---- output layer: 2 row tiles (32 padded outputs)
+    f32x4 out[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) out[mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(
+                a.W[3] + (size_t)(16 * mi + j) * MLP_HID + 32 * kb + 8 * g);
+            out[mi][0] = mfma(af, bin[kb][0], out[mi][0]);
+            out[mi][1] = mfma(af, bin[kb][1], out[mi][1]);
+        }
+    const double *ym = a.stats + 2 * MLP_FEAT, *ysd = a.stats + 2 * MLP_FEAT + 2 * MLP_NC;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const long long cell = base + 16 * t + j;
+        if (cell >= a.n_cells) continue;
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 16 * mi + 4 * g + r;
+                if (c >= MLP_NC) continue;
+                const double d = ym[c] + ysd[c] * (double)(out[mi][t][r] + a.b[3][c]);
+                a.yout[c * a.ld + cell] = a.yin[c * a.ld + cell] + d;
+            }
+    }
+}
+
+// Step-doubling gate: D = max_c |full_c - dbl_c| / max(|dbl_c|, floor_c),
+// floor 1e-8 for mass fractions, 0 for T.  Accepted cells take the two-half
+// prediction; rejected cells are appended to the fallback list (one atomic per
+// wave, ranks from the ballot mask).
+__global__ void __launch_bounds__(256)
+    k_gate(int n_cells, long long ld, const double *__restrict__ full,
+           const double *__restrict__ dbl, double tol, double *__restrict__ yout,
+           int *__restrict__ used_fallback, int *__restrict__ list, unsigned int *count,
+           float *__restrict__ dmax)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < n_cells;
+    bool reject = false;
+    if (live) {
+        double D = 0.0;
+        for (int c = 0; c < MLP_NC; ++c) {
+            const double a = full[c * ld + i], b = dbl[c * ld + i];
+            const double fl = (c < MLP_NS) ? 1e-8 : 0.0;
+            const double e = fabs(a - b) / fmax(fabs(b), fl);
+            D = (e > D || e != e) ? e : D;       // NaN counts as rejection
+        }
+        reject = !(D <= tol);
+        if (!reject)
+            for (int c = 0; c < MLP_NC; ++c) yout[c * ld + i] = dbl[c * ld + i];
+        if (used_fallback) used_fallback[i] = reject ? 1 : 0;
+        if (dmax) dmax[i] = (float)D;
+    }
+    const unsigned long long m = __ballot(reject);
+    const int lane = threadIdx.x & 63;
+    unsigned int basepos = 0;
+    if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        if (lane == leader) basepos = atomicAdd(count, (unsigned int)__popcll(m));
+        basepos = __shfl(basepos, leader);
+        if (reject) list[basepos + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    }
+}
+
+// dst[c*ldd + k] = src[c*lds + list[k]] for planes c < n_planes, k < *count.
+__global__ void __launch_bounds__(256)
+    k_gather(int n_planes, const unsigned int *count, const int *__restrict__ list,
+             const double *__restrict__ src, long long lds, double *__restrict__ dst,
+             long long ldd)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long long)*count) return;
+    const int cell = list[k];
+    for (int c = 0; c < n_planes; ++c) dst[c * ldd + k] = src[c * lds + cell];
+}
+
+__global__ void __launch_bounds__(256)
+    k_scatter(int n_planes, const unsigned int *count, const int *__restrict__ list,
+              const double *__restrict__ src, long long lds, double *__restrict__ dst,
+              long long ldd)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long long)*count) return;
+    const int cell = list[k];
+    for (int c = 0; c < n_planes; ++c) dst[c * ldd + cell] = src[c * lds + k];
+}
+
+__global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
+
+inline dim3 grid1(long long n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
+
+}  // namespace
+
+hipError_t mlp_gemm(int M, int N, int K, const uint16_t *A, int lda, int transA, const uint16_t *B,
+                    int ldb, int transB, float *C, int ldc, hipStream_t s)
+{
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb,
+                       transB, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t mlp_bias_act(int rows, int N, float *Z, const float *bias, int act, uint16_t *Aout,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bias_act, grid1((long long)rows * N, 256), dim3(256), 0, s, rows, N, Z,
+                       bias, act, Aout);
+    return hipGetLastError();
+}
+
+hipError_t mlp_mse_grad(int rows, int N, const float *Y, const float *T, float *dZ, uint16_t *dZq,
+                        double *loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mse_grad, grid1((long long)rows * N, 256), dim3(256), 0, s, rows, N, Y, T,
+                       dZ, dZq, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_silu_bwd(long long n, const float *dA, const float *Z, float *dZ, uint16_t *dZq,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_silu_bwd, grid1(n, 256), dim3(256), 0, s, n, dA, Z, dZ, dZq);
+    return hipGetLastError();
+}
+
+hipError_t mlp_colsum(int rows, int N, const float *dZ, float *db, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_colsum, grid1(N, 256), dim3(256), 0, s, rows, N, dZ, db);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(long long n, float *w, const float *g, float *m, float *v, uint16_t *wq,
+                    float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, grid1(n, 256), dim3(256), 0, s, n, w, g, m, v, wq, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t mlp_to_bf16(long long n, const float *x, uint16_t *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_bf16, grid1(n, 256), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t mlp_featurize(int B, const int *idx, long long ld, const double *Y0, int n_poly,
+                         const double *RHO, const double *Lv, const double *Y1,
+                         const double *stats, uint16_t *X, float *T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_featurize, grid1(B, 256), dim3(256), 0, s, B, idx, ld, Y0, n_poly, RHO,
+                       Lv, Y1, stats, X, T);
+    return hipGetLastError();
+}
+
+hipError_t mlp_stats(long long N, long long ld, const double *Y0, int n_poly, const double *RHO,
+                     const double *Lv, const double *Y1, double *part, int n_blocks,
+                     double *stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stats_partial, dim3(n_blocks), dim3(256), 0, s, N, ld, Y0, n_poly, RHO,
+                       Lv, Y1, part);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(128), 0, s, n_blocks, N, part, stats);
+    return hipGetLastError();
+}
+
+hipError_t mlp_infer(const double *yin, double *yout, const double *rho, const uint16_t *const *W,
+                     const float *const *b, const double *stats, long long ld, int n_cells,
+                     int n_poly, double L, int half, hipStream_t s)
+{
+    InferArgs a;
+    a.yin = yin;
+    a.yout = yout;
+    a.rho = rho;
+    for (int l = 0; l < 4; ++l) {
+        a.W[l] = W[l];
+        a.b[l] = b[l];
+    }
+    a.stats = stats;
+    a.ld = ld;
+    a.n_cells = n_cells;
+    a.n_poly = n_poly;
+    a.L = L;
+    a.half = half;
+    hipLaunchKernelGGL(k_infer, grid1(n_cells, 128), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t mlp_gate(int n_cells, long long ld, const double *full, const double *dbl, double tol,
+                    double *yout, int *used_fallback, int *list, unsigned int *count, float *dmax,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, count);
+    hipLaunchKernelGGL(k_gate, grid1(n_cells, 256), dim3(256), 0, s, n_cells, ld, full, dbl, tol,
+                       yout, used_fallback, list, count, dmax);
+    return hipGetLastError();
+}
+
+hipError_t mlp_gather(int n_planes, const unsigned int *count, const int *list, long long n_max,
+                      const double *src, long long lds, double *dst, long long ldd, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather, grid1(n_max, 256), dim3(256), 0, s, n_planes, count, list, src,
+                       lds, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t mlp_scatter(int n_planes, const unsigned int *count, const int *list, long long n_max,
+                       const double *src, long long lds, double *dst, long long ldd, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter, grid1(n_max, 256), dim3(256), 0, s, n_planes, count, list, src,
+                       lds, dst, ldd);
+    return hipGetLastError();
+}

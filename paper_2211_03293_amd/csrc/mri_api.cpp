@@ -21,20 +21,18 @@
 #include <vector>
 
 #include "mri.h"
+#include "mri_surrogate.h"
 #include "mri_dev.h"
+#include "mri_internal.h"
 
 // Embedded sources of the run-time compiled kernels (generated at build time).
 extern const char mri_spec_kernels_src[];
 extern const char mri_spec_abi_src[];
 extern const char mri_math_src[];
 
-namespace {
-
-constexpr double R_GAS = 8.314462618;  // J/(mol K)
-
 thread_local std::string g_err;
 
-mri_status fail(mri_status st, const char *fmt, ...)
+mri_status mri_fail(mri_status st, const char *fmt, ...)
 {
     char buf[1024];
     va_list ap;
@@ -44,6 +42,12 @@ mri_status fail(mri_status st, const char *fmt, ...)
     g_err = buf;
     return st;
 }
+
+namespace {
+
+constexpr double R_GAS = 8.314462618;  // J/(mol K)
+
+#define fail mri_fail
 
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
@@ -399,6 +403,18 @@ struct mri_batch_plan {
     std::vector<uintptr_t> graph_key;
 };
 
+mri_status mri_internal_fast_stage(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
+                                   const double *yin, double *yout, int n_poly, const double *rho,
+                                   double L, int32_t *status, int32_t *steps, hipStream_t s)
+{
+    mri_status st = check_opts(m, o);
+    if (st != MRI_OK) return st;
+    return fast_stage_impl(m, o, n_cells, ld, yin, yout, n_poly, rho, L, status, steps, 0, s);
+}
+
+int mri_internal_state_width(const mri_mech *m) { return m ? m->n : -1; }
+int mri_internal_is_chem(const mri_mech *m) { return m && m->kind == 0; }
+
 extern "C" {
 
 int mri_abi_version(void) { return MRI_ABI_VERSION; }
@@ -682,6 +698,23 @@ mri_status mri_slow_step(const mri_mech *mc, const mri_table *t, const mri_fast_
         }
     }
     // step 3: y_(n+1) = Y_s (already in y)
+    return MRI_OK;
+}
+
+mri_status mri_forcing_assemble(const mri_table *t, int stage, int n, int ld, const double *F,
+                                double *rho, mri_stream_t stream)
+{
+    if (!t || !F || !rho) return fail(MRI_EINVAL, "NULL argument");
+    if (stage < 1 || stage >= t->s) return fail(MRI_EINVAL, "stage must be in [1, s)");
+    if (n < 1 || ld < 0) return fail(MRI_EINVAL, "bad n / ld");
+    if (ld == 0) return MRI_OK;
+    const double dc = t->c[stage] - t->c[stage - 1];
+    ForcingCoef coef{};
+    for (int k = 0; k < t->ng; ++k)
+        for (int j = 0; j < stage; ++j)
+            coef.c[k * 8 + j] = t->gamma[((size_t)k * t->s + stage) * t->s + j] / dc;
+    const long long vec = (long long)n * ld;
+    HIP_TRY(launch_forcing(vec, t->ng, stage, F, vec, coef, rho, (hipStream_t)stream));
     return MRI_OK;
 }
 

@@ -94,6 +94,24 @@ _SIGS = {
     "mri_batch_plan_tile": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "mri_batch_lane_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _vp]),
     "mri_batch_plan_destroy": (None, [_vp]),
+    "mri_forcing_assemble": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "mri_mlp_create": (_i, [_i, C.POINTER(C.c_int), C.POINTER(C.c_float), _i, C.POINTER(_vp)]),
+    "mri_mlp_destroy": (None, [_vp]),
+    "mri_mlp_param_count": (C.c_int64, [_vp]),
+    "mri_mlp_get_params": (_i, [_vp, C.POINTER(C.c_float)]),
+    "mri_mlp_get_grads": (_i, [_vp, C.POINTER(C.c_float)]),
+    "mri_mlp_forward": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "mri_mlp_backward": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "mri_adam_step": (_i, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "mri_mlp_feature_stats": (_i, [C.c_int64, C.c_int64, _vp, _i, _vp, _vp, _vp, _vp, _vp]),
+    "mri_mlp_featurize": (_i, [_i, _vp, C.c_int64, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mri_surrogate_create": (_i, [C.POINTER(C.c_int), C.POINTER(C.c_float),
+                                  C.POINTER(C.c_double), C.POINTER(_vp)]),
+    "mri_surrogate_destroy": (None, [_vp]),
+    "mri_surrogate_infer": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _d, _i, _vp]),
+    "mri_surrogate_workspace_bytes": (_i, [_i, _i, _i, C.POINTER(_sz)]),
+    "mri_surrogate_stage": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), _d, _i, _i, _vp, _vp, _i, _vp,
+                                 _d, _vp, _vp, C.POINTER(C.c_int64), _vp, _sz, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -159,9 +177,9 @@ class Mech:
         _check(lib.mri_mech_specialize(self.h, block_size, int(load), C.byref(nb)))
         return nb.value
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.mri_mech_destroy):
         if getattr(self, "h", None) and self.h.value:
-            lib.mri_mech_destroy(self.h)
+            _destroy(self.h)
             self.h = C.c_void_p()
 
 
@@ -175,9 +193,9 @@ class Table:
                            self.gamma.ctypes.data_as(C.POINTER(C.c_double)))
         _check(lib.mri_table_create(C.byref(d), C.byref(self.h)))
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.mri_table_destroy):
         if getattr(self, "h", None) and self.h.value:
-            lib.mri_table_destroy(self.h)
+            _destroy(self.h)
             self.h = C.c_void_p()
 
 
@@ -283,7 +301,101 @@ class BatchPlan:
         _check(lib.mri_batch_lane_stats(self.h, C.byref(u), C.byref(i), _stream(stream)))
         return u.value, i.value
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.mri_batch_plan_destroy):
         if getattr(self, "h", None) and self.h.value:
-            lib.mri_batch_plan_destroy(self.h)
+            _destroy(self.h)
+            self.h = C.c_void_p()
+
+
+# ---------------------------------------------------------------------------
+# Surrogate (include/mri_surrogate.h)
+# ---------------------------------------------------------------------------
+MLP_FEATURES, MLP_KPAD, MLP_OUTPUTS = 89, 96, 22
+MLP_STATS = 2 * 89 + 3 * 22
+
+
+def mri_forcing_assemble(table: Table, stage, n, ld, F, rho, stream=None):
+    _check(lib.mri_forcing_assemble(table.h, stage, n, ld, _ptr(F), _ptr(rho), _stream(stream)))
+
+
+class MLP:
+    """Trainable MLP handle (FP32 master weights, bf16 MFMA arithmetic)."""
+
+    def __init__(self, widths, params, max_batch):
+        self.widths = [int(w) for w in widths]
+        w = (C.c_int * len(self.widths))(*self.widths)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.h = C.c_void_p()
+        _check(lib.mri_mlp_create(len(self.widths) - 1, w, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                  int(max_batch), C.byref(self.h)))
+        self.n_params = lib.mri_mlp_param_count(self.h)
+
+    def params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib.mri_mlp_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def grads(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib.mri_mlp_get_grads(self.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def forward(self, X, Y=None, stream=None):
+        _check(lib.mri_mlp_forward(self.h, X.shape[0], _ptr(X), _ptr(Y), _stream(stream)))
+
+    def backward(self, T, loss=None, stream=None):
+        _check(lib.mri_mlp_backward(self.h, T.shape[0], _ptr(T), _ptr(loss), _stream(stream)))
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib.mri_adam_step(self.h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def __del__(self, _destroy=lib.mri_mlp_destroy):
+        if getattr(self, "h", None) and self.h.value:
+            _destroy(self.h)
+            self.h = C.c_void_p()
+
+
+def mri_mlp_feature_stats(n, ld, Y0, n_poly, RHO, Lv, Y1, stats, stream=None):
+    _check(lib.mri_mlp_feature_stats(int(n), int(ld), _ptr(Y0), n_poly, _ptr(RHO), _ptr(Lv),
+                                     _ptr(Y1), _ptr(stats), _stream(stream)))
+
+
+def mri_mlp_featurize(batch, idx, ld, Y0, n_poly, RHO, Lv, Y1, stats, X, T=None, stream=None):
+    _check(lib.mri_mlp_featurize(int(batch), _ptr(idx), int(ld), _ptr(Y0), n_poly, _ptr(RHO),
+                                 _ptr(Lv), _ptr(Y1), _ptr(stats), _ptr(X), _ptr(T),
+                                 _stream(stream)))
+
+
+class Surrogate:
+    def __init__(self, widths, params, stats):
+        w = (C.c_int * len(widths))(*[int(x) for x in widths])
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        st = np.ascontiguousarray(stats, dtype=np.float64)
+        self.h = C.c_void_p()
+        _check(lib.mri_surrogate_create(w, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                        st.ctypes.data_as(C.POINTER(C.c_double)), C.byref(self.h)))
+
+    def infer(self, n_cells, ld, y_in, y_out, n_poly, rho, L, half=0, stream=None):
+        _check(lib.mri_surrogate_infer(self.h, n_cells, ld, _ptr(y_in), _ptr(y_out), n_poly,
+                                       _ptr(rho), float(L), half, _stream(stream)))
+
+    @staticmethod
+    def workspace_bytes(n_cells, ld, n_poly):
+        b = C.c_size_t(0)
+        _check(lib.mri_surrogate_workspace_bytes(n_cells, ld, n_poly, C.byref(b)))
+        return b.value
+
+    def stage(self, mech: Mech, fallback_opts, gate_tol, n_cells, ld, y_in, y_out, n_poly, rho, L,
+              ws, used_fallback=None, gate_value=None, stream=None):
+        nf = C.c_int64(0)
+        nbytes = ws.numel() * ws.element_size()
+        _check(lib.mri_surrogate_stage(self.h, mech.h, C.byref(fallback_opts), float(gate_tol),
+                                       n_cells, ld, _ptr(y_in), _ptr(y_out), n_poly, _ptr(rho),
+                                       float(L), _ptr(used_fallback), _ptr(gate_value),
+                                       C.byref(nf), _ptr(ws), nbytes, _stream(stream)))
+        return nf.value
+
+    def __del__(self, _destroy=lib.mri_surrogate_destroy):
+        if getattr(self, "h", None) and self.h.value:
+            _destroy(self.h)
             self.h = C.c_void_p()
