@@ -21,6 +21,8 @@ LIB = os.path.join(HERE, "libmri.so")
 ARCH = os.environ.get("MRI_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# developer knobs: extra -D definitions and another output path (tuning builds)
+EXTRA = os.environ.get("MRI_EXTRA_DEFS", "").split()
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", CSRC, "-I", INCLUDE, "-Wall", "-Wno-unused-function"]
@@ -48,16 +50,20 @@ def _write_embedded() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *EXTRA, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC, *COMMON, "-x", "hip", "-c", src, "-o", obj]
+        cmd = [HIPCC, *COMMON, *EXTRA, "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, out: str | None = None) -> str:
+    global BUILD
+    out = out or os.environ.get("MRI_LIB_OUT") or LIB
+    if out != LIB:
+        BUILD = os.path.join(HERE, "_build", os.path.basename(out).replace(".so", ""))
     emb = _write_embedded()
     srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -65,16 +71,16 @@ def build(verbose: bool = True) -> str:
     jobs = int(os.environ.get("MAX_JOBS", "8"))
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
-    tmp = LIB + f".tmp{os.getpid()}"
+    tmp = out + f".tmp{os.getpid()}"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs,
            "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB}", flush=True)
-    return LIB
+        print(f"built {out}", flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -25,7 +25,12 @@ __device__ __forceinline__ float bf2f(uint16_t u)
     return __builtin_bit_cast(float, (uint32_t)u << 16);
 }
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU with the hardware exponential and reciprocal (about 1 ulp each in FP32;
+// the result is rounded to bfloat16 next)
+__device__ __forceinline__ float silu_f(float z)
+{
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 
 __device__ __forceinline__ float silu_grad_f(float z)
 {
@@ -184,7 +189,8 @@ __device__ __forceinline__ double raw_feature(int k, const double *__restrict__ 
                                               const double *__restrict__ rho, long long ld,
                                               long long s, int n_poly, int half, double L)
 {
-    if (k < MLP_NS) return log(fmax(y[k * ld + s], 1e-30));
+    // logarithms in FP32: every feature is rounded to bfloat16 afterwards
+    if (k < MLP_NS) return (double)__logf((float)fmax(y[k * ld + s], 1e-30));
     if (k == MLP_NS) return y[MLP_NS * ld + s];
     if (k < MLP_NS + 1 + MLP_NPOLY * MLP_NC) {
         const int q = k - MLP_NS - 1, p = q / MLP_NC, c = q % MLP_NC;
@@ -198,7 +204,7 @@ __device__ __forceinline__ double raw_feature(int k, const double *__restrict__ 
         return p == 0 ? r[0] + 0.5 * r[1] + 0.25 * r[2]
                       : (p == 1 ? 0.5 * r[1] + 0.5 * r[2] : 0.25 * r[2]);
     }
-    if (k == MLP_FEAT - 1) return log(L);
+    if (k == MLP_FEAT - 1) return (double)__logf((float)L);
     return 0.0;
 }
 
@@ -328,33 +334,74 @@ struct InferArgs {
     int half;
 };
 
-template <int KB>
-__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int j, int g,
-                                            const bf16x8 (&bin)[8][2], f32x4 (&acc)[16][2])
+// Weights are staged through LDS in chunks of 32 input columns (all output
+// rows), shared by the block's four waves; the next chunk's global loads are
+// issued before the current chunk's MFMAs (double buffer).
+constexpr int WROW = 32 + 8;            // padded LDS row (bf16), 80 bytes
+constexpr int WCHUNK = MLP_HID * WROW;  // one chunk: 256 rows x 32 columns
+
+// Loads chunk kb of W [rows][kin] (bf16) into registers: 4 x 16 bytes per
+// thread for 256 rows (rows < n_rows only).
+__device__ __forceinline__ void chunk_load(const uint16_t *__restrict__ W, int kin, int kb,
+                                           int n_rows, uint4 (&r)[4])
 {
 #pragma unroll
-    for (int mi = 0; mi < 16; ++mi) {
-        acc[mi][0] = f32x4{0.f, 0.f, 0.f, 0.f};
-        acc[mi][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q;      // 1024 pieces of 16 bytes
+        const int row = e >> 2, part = e & 3;
+        if (row < n_rows)
+            r[q] = *reinterpret_cast<const uint4 *>(W + (size_t)row * kin + 32 * kb + 8 * part);
     }
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-        for (int mi = 0; mi < 16; ++mi) {
-            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(
-                W + (size_t)(16 * mi + j) * (32 * KB) + 32 * kb + 8 * g);
-            acc[mi][0] = mfma(af, bin[kb][0], acc[mi][0]);
-            acc[mi][1] = mfma(af, bin[kb][1], acc[mi][1]);
-        }
 }
 
+__device__ __forceinline__ void chunk_store(uint16_t *__restrict__ buf, int n_rows,
+                                            const uint4 (&r)[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int row = e >> 2, part = e & 3;
+        if (row < n_rows) *reinterpret_cast<uint4 *>(buf + row * WROW + 8 * part) = r[q];
+    }
+}
+
+// acc (MT row tiles x 2 column tiles) = W [16 MT rows][32 KB cols] . bin
+template <int KB, int MT, int NTT>
+__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, uint16_t *lds, int j,
+                                            int g, const bf16x8 (&bin)[8][NTT],
+                                            f32x4 (&acc)[16][NTT])
+{
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int t = 0; t < NTT; ++t) acc[mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint4 r[4];
+    chunk_load(W, 32 * KB, 0, 16 * MT, r);
+    __syncthreads();                         // previous users of the buffers are done
+    chunk_store(lds, 16 * MT, r);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        __syncthreads();                     // chunk kb visible
+        if (kb + 1 < KB) chunk_load(W, 32 * KB, kb + 1, 16 * MT, r);
+        const uint16_t *buf = lds + (kb & 1) * WCHUNK;
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(buf + (16 * mi + j) * WROW + 8 * g);
+#pragma unroll
+            for (int t = 0; t < NTT; ++t) acc[mi][t] = mfma(af, bin[kb][t], acc[mi][t]);
+        }
+        if (kb + 1 < KB) chunk_store(lds + ((kb + 1) & 1) * WCHUNK, 16 * MT, r);
+    }
+}
+
+template <int NTT>
 __device__ __forceinline__ void silu_repack(const float *__restrict__ bias, int g,
-                                            const f32x4 (&acc)[16][2], bf16x8 (&bin)[8][2])
+                                            const f32x4 (&acc)[16][NTT], bf16x8 (&bin)[8][NTT])
 {
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NTT; ++t) {
             bf16x8 v;
 #pragma unroll
             for (int h = 0; h < 2; ++h)
@@ -367,55 +414,83 @@ __device__ __forceinline__ void silu_repack(const float *__restrict__ bias, int 
         }
 }
 
-__global__ void __launch_bounds__(256) k_infer(InferArgs a)
+constexpr int XROW = MLP_KPAD + 8;     // padded LDS feature row (bf16), 208 bytes
+
+// Column tiles (16 cells each) per wave, and the waves-per-SIMD target.
+#ifndef MLP_NT
+#define MLP_NT 2
+#endif
+#ifndef MLP_WPE
+#define MLP_WPE 2
+#endif
+constexpr int NT = MLP_NT;
+constexpr int CELLS_PER_BLOCK = 4 * 16 * NT;
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WPE))) k_infer(InferArgs a)
 {
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * WCHUNK];
+    __shared__ __attribute__((aligned(16))) uint16_t xs[CELLS_PER_BLOCK * XROW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const long long base = ((long long)blockIdx.x * 4 + wave) * 32;
-    if (base >= a.n_cells) return;              // whole wave idle (no barriers here)
+    // every wave takes part in the block's barriers; idle cells are clamped
+    const long long block0 = (long long)blockIdx.x * CELLS_PER_BLOCK;
+    const long long base = block0 + wave * 16 * NT;
     const double L = (a.half == 0) ? a.L : 0.5 * a.L;
-    // ---- layer-1 B operand: features of cells base + j (tile 0) and base + 16 + j
-    bf16x8 bin[8][2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        long long cell = base + 16 * t + j;
+    // ---- features of the block's cells, computed cooperatively: thread
+    // groups take interleaved features (uniform per wave, coalesced loads)
+    {
+        constexpr int GROUPS = 256 / CELLS_PER_BLOCK;
+        const int c = threadIdx.x % CELLS_PER_BLOCK;
+        const int grp = threadIdx.x / CELLS_PER_BLOCK;
+        long long cell = block0 + c;
         if (cell >= a.n_cells) cell = a.n_cells - 1;
-#pragma unroll
-        for (int kb = 0; kb < MLP_KPAD / 32; ++kb) {
-            bf16x8 v;
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                v[e] = static_cast<__bf16>(std_feature(32 * kb + 8 * g + e, a.yin, a.rho, a.ld,
-                                                       cell, a.n_poly, a.half, L, a.stats));
-            bin[kb][t] = v;
+        if (a.n_poly <= 1) {
+            // constant forcing: every half-stage transform is the identity on
+            // rho_0 and the higher coefficients are zero, so each feature is one
+            // unconditional load plus selects; unrolled so the loads overlap
+            const float logL = __logf((float)L);
+#pragma unroll 8
+            for (int i = 0; i < MLP_KPAD / GROUPS; ++i) {
+                const int k = grp + GROUPS * i;
+                const bool isy = k <= MLP_NS, isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
+                const double *src = isy ? a.yin + (long long)k * a.ld
+                                        : (isr ? a.rho + (long long)(k - MLP_NS - 1) * a.ld : a.yin);
+                const double v = src[cell];
+                float raw = (k < MLP_NS) ? __logf((float)fmax(v, 1e-30)) : (float)v;
+                if (k == MLP_FEAT - 1) raw = logL;
+                const bool live = isy || isr || (k == MLP_FEAT - 1);
+                const float z = live ? (float)((raw - a.stats[min(k, MLP_FEAT - 1)]) *
+                                               a.stats[MLP_FEAT + min(k, MLP_FEAT - 1)])
+                                     : 0.0f;
+                xs[c * XROW + k] = f2bf(z);
+            }
+        } else {
+            for (int k = grp; k < MLP_KPAD; k += GROUPS)
+                xs[c * XROW + k] = f2bf(std_feature(k, a.yin, a.rho, a.ld, cell, a.n_poly, a.half,
+                                                    L, a.stats));
         }
     }
+    __syncthreads();
+    bf16x8 bin[8][NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int kb = 0; kb < MLP_KPAD / 32; ++kb)
+            bin[kb][t] = *reinterpret_cast<const bf16x8 *>(
+                xs + (wave * 16 * NT + 16 * t + j) * XROW + 32 * kb + 8 * g);
     // ---- three hidden layers
-    f32x4 acc[16][2];
-    dense_layer<MLP_KPAD / 32>(a.W[0], j, g, bin, acc);
-    silu_repack(a.b[0], g, acc, bin);
-    dense_layer<MLP_HID / 32>(a.W[1], j, g, bin, acc);
-    silu_repack(a.b[1], g, acc, bin);
-    dense_layer<MLP_HID / 32>(a.W[2], j, g, bin, acc);
-    silu_repack(a.b[2], g, acc, bin);
+    f32x4 acc[16][NT];
+    dense_layer<MLP_KPAD / 32, 16, NT>(a.W[0], lds, j, g, bin, acc);
+    silu_repack<NT>(a.b[0], g, acc, bin);
+    dense_layer<MLP_HID / 32, 16, NT>(a.W[1], lds, j, g, bin, acc);
+    silu_repack<NT>(a.b[1], g, acc, bin);
+    dense_layer<MLP_HID / 32, 16, NT>(a.W[2], lds, j, g, bin, acc);
+    silu_repack<NT>(a.b[2], g, acc, bin);
     // ---- output layer: 2 row tiles (32 padded outputs)
-    f32x4 out[2][2];
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int t = 0; t < 2; ++t) out[mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(
-                a.W[3] + (size_t)(16 * mi + j) * MLP_HID + 32 * kb + 8 * g);
-            out[mi][0] = mfma(af, bin[kb][0], out[mi][0]);
-            out[mi][1] = mfma(af, bin[kb][1], out[mi][1]);
-        }
+    dense_layer<MLP_HID / 32, 2, NT>(a.W[3], lds, j, g, bin, acc);
     const double *ym = a.stats + 2 * MLP_FEAT, *ysd = a.stats + 2 * MLP_FEAT + 2 * MLP_NC;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NT; ++t) {
         const long long cell = base + 16 * t + j;
         if (cell >= a.n_cells) continue;
 #pragma unroll
@@ -424,7 +499,7 @@ __global__ void __launch_bounds__(256) k_infer(InferArgs a)
             for (int r = 0; r < 4; ++r) {
                 const int c = 16 * mi + 4 * g + r;
                 if (c >= MLP_NC) continue;
-                const double d = ym[c] + ysd[c] * (double)(out[mi][t][r] + a.b[3][c]);
+                const double d = ym[c] + ysd[c] * (double)(acc[mi][t][r] + a.b[3][c]);
                 a.yout[c * a.ld + cell] = a.yin[c * a.ld + cell] + d;
             }
     }
@@ -586,7 +661,7 @@ hipError_t mlp_infer(const double *yin, double *yout, const double *rho, const u
     a.n_poly = n_poly;
     a.L = L;
     a.half = half;
-    hipLaunchKernelGGL(k_infer, grid1(n_cells, 128), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_infer, grid1(n_cells, CELLS_PER_BLOCK), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmri.so")
+LIB_PATH = os.environ.get("MRI_LIB_PATH") or os.path.join(_HERE, "libmri.so")
 
 MRI_OK, MRI_EINVAL, MRI_EHIP, MRI_ENONFINITE, MRI_EMAXSTEPS, MRI_ENOMEM, MRI_EUNSUPPORTED, \
     MRI_ECOMPILE = 0, -1, -2, -3, -4, -5, -6, -7
