@@ -369,3 +369,18 @@ def mechanism_arrays(m: Mechanism) -> dict:
         cv=np.ascontiguousarray(m.cv, dtype=np.float64),
         rho=float(m.rho), T_ref=float(m.T_ref),
     )
+
+
+def batch_workload(n_sets: int = 1000, config: int = 2):
+    """Uneven reactor sets: sizes log-uniform in [64, 65536], every cell drawn
+    like the independent-cell workload (T ~ U[1000, 2000] K, Y ~ Dirichlet(1)),
+    and one fast stage per set whose length cycles through the three stage
+    lengths dc_i H of the MIS-KW3 table (H = 1e-7 s).  No slow tendencies are
+    stated for this workload: the stage is unforced (n_poly = 0)."""
+    cfg = CONFIGS[config]
+    sizes = set_sizes(n_sets, config=config)
+    off = set_offsets(sizes)
+    y = independent_cells(int(off[-1]), CONFIGS[cfg.mech_config].n_species, rng_for(config, 1))
+    dc = np.diff(table_mis_kw3().c)
+    L = np.array([dc[i % dc.size] * cfg.H for i in range(n_sets)])
+    return sizes, off, y, L

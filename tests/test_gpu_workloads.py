@@ -196,3 +196,46 @@ def test_slow_step_graph_capture_replays(torch, mri, O):
         mri.mri_slow_step(m, t, opts, mri.ADVDIFF_RHS, params, 0.0, 1e-7, N, ld, tmp, ws)
         torch.cuda.synchronize()
         assert np.array_equal(tmp.cpu().numpy(), ref)
+
+
+def test_batch_fullsize_sampled(torch, mri, O):
+    """The full batched workload (1000 uneven sets, ~1e7 cells) in one persistent
+    launch; sampled cells of every size class against the oracle."""
+    sizes, off, y, Ls = I.batch_workload()
+    mech = I.make_mechanism(2)
+    n, ld = y.shape
+    ntot = int(off[-1])
+    m = mri.Mech(mech)
+    opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
+                         max_steps=2000)
+    plan = mri.BatchPlan(m, opts, off)
+    yd = torch.as_tensor(y, device="cuda")
+    out = torch.empty_like(yd)
+    st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    steps = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    plan.run(yd, out, ld, 0, None, Ls, st, steps)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(12))
+    sets = np.concatenate([[0, off.size - 2], rng.choice(off.size - 1, 30, replace=False)])
+    cells = np.unique(np.concatenate([rng.integers(off[s], off[s + 1], 16) for s in sets]))
+    zo = O.zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
+    orc = O.Oracle(mech)
+    got = out.cpu().numpy()
+    st_g, acc_g = st.cpu().numpy(), steps.cpu().numpy()
+    set_of = np.searchsorted(off, cells, side="right") - 1
+    ok = []
+    for c, s in zip(cells, set_of):
+        o, sto, acc, _ = orc.zonneveld_stage(y[:, c], np.zeros((1, n)), Ls[s], zo)
+        tie = (sto | st_g[c]) & mri.CELL_NEARTIE
+        if tie:
+            continue
+        assert acc == acc_g[c], (c, acc, acc_g[c])
+        ok.append(c)
+        ref_c = o
+        got_c = got[:, c]
+        err = np.abs(got_c - ref_c) / np.maximum(np.abs(ref_c), np.r_[np.full(n - 1, 1e-12), 0.0])
+        assert err.max() <= 1e-10, (c, err.max())
+    assert len(ok) >= 0.95 * cells.size
+    useful, issued = plan.lane_stats()
+    print(f"batch {ntot} cells: {len(ok)} sampled cells match, lane utilization "
+          f"{useful / issued:.3f}, tile {plan.tile()}")
