@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell fast-stage solves/s: FP64 plain vs surrogate+fallback at 1e-4 rel err"
 PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+PEAK_BF16_TFLOPS = 2500.0         # MI355X dense BF16 MFMA
+MLP_FLOPS = 2 * (89 * 256 + 256 * 256 + 256 * 256 + 256 * 22)   # one inference, 89 -> 22
 F_EXP, F_LOG, F_DIV = 22, 22, 10  # flops charged per FP64 exp / log / divide
 
 
@@ -123,6 +125,40 @@ def batch_leg(torch, mri, I, repeats=3):
                 flagged_cells=n_bad)
 
 
+def surrogate_leg(train_steps, n_samples):
+    """Learned surrogate: stage data from the 64^3 workload's plain runs, training
+    with libmri's BF16 MFMA kernels, then the gated stage (tolerance 1e-4) on the
+    first fast stage of the 128^3 workload against the plain FP64 stage."""
+    from paper_2211_03293_amd import surrogate as S
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    data = S.generate_stage_data(n_full=n_samples, log=log)
+    res = S.train(data, steps=train_steps, log=log, log_every=max(1, train_steps // 8))
+    del data
+    ev = S.evaluate_stage(res["params"], res["stats"], config=4, gate_tol=1e-4, log=log)
+    t_inf_s = ev["infer_ms"] * 1e-3
+    achieved = ev["cells"] * MLP_FLOPS / t_inf_s / 1e12
+    ev.update(
+        workload="128^3 cells, 21 species / 84 reactions, first MIS-KW3 fast stage "
+                 "(L = H/3, H = 1e-7 s, advection-diffusion forcing); MLP 89-256-256-256-22 "
+                 "BF16/FP32 trained on the 64^3 workload's stages; fallback plain RK4 "
+                 "50 substeps",
+        value=round(ev["cells"] / (ev["surrogate_stage_ms"] * 1e-3), 1),
+        unit="cell-stages/s", plain_value=round(ev["cells"] / (ev["plain_ms"] * 1e-3), 1),
+        training=dict(samples=int(3 * n_samples), steps=train_steps, batch=4096,
+                      seconds=round(res["train_seconds"], 1),
+                      final_val_mse=res["history"][-1][2] if res["history"] else None),
+        inferences_per_s=round(ev["cells"] / t_inf_s, 1),
+        roofline=dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_BF16_TFLOPS,
+                      unit="TFLOP/s", frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
+                      kernel="k_infer (fused 4-layer BF16 MFMA)", flops_per_inference=MLP_FLOPS),
+        seconds_total=round(time.perf_counter() - t0, 1))
+    return ev
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +168,11 @@ def main():
     ap.add_argument("--kernel", choices=["auto", "specialized", "generic"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-set leg")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--surrogate-steps", type=int, default=20000,
+                    help="training steps of the surrogate leg (batch 4096)")
+    ap.add_argument("--surrogate-samples", type=int, default=1_000_000,
+                    help="full-stage training samples (plus twice as many half-stage ones)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -227,6 +268,9 @@ def main():
     if not args.no_batch:
         print("# batched uneven-set leg", file=sys.stderr, flush=True)
         out["batch"] = batch_leg(torch, mri, I)
+    if not args.no_surrogate:
+        print("# surrogate leg", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_leg(args.surrogate_steps, args.surrogate_samples)
     if not args.no_cpu_baseline:
         # forcing of the first stage of one slow step, from the oracle's own slow RHS
         from oracle import oracle as O

@@ -11,7 +11,10 @@
  * species, T, the 3 forcing-polynomial coefficients of each of the 22 state
  * components (zero where the coupling table has fewer terms), log L (stage
  * length) -- standardized with training-set statistics; 3 hidden layers of
- * 256 with SiLU; 22 outputs = standardized stage increments Y(L) - Y(0).
+ * 256 with SiLU; 22 outputs = standardized stage increments: for a species
+ * log(Y(L) + 1e-8) - log(Y(0) + 1e-8) (Y(0) clamped at 0), so that an output
+ * error is a relative error of Y + 1e-8 (the floor of the gate below); for T
+ * the plain increment T(L) - T(0).
  *
  * Conventions follow mri.h: device arrays are caller-owned; handles own their
  * device copies; invalid arguments return MRI_EINVAL before device work.
@@ -34,7 +37,8 @@ extern "C" {
 #define MRI_MLP_OUTPUTS 22       /* stage increments of the 22 components  */
 #define MRI_MLP_STATS (2 * 89 + 3 * 22)
 /* stats layout (FP64): x_mean[89], x_inv_std[89], y_mean[22], y_inv_std[22],
-   y_std[22] (inverse std 1 where a feature is constant). */
+   y_std[22] (inverse std 1 where a feature is constant); y_* describe the
+   increments defined above. */
 
 typedef struct mri_mlp mri_mlp;
 
@@ -95,7 +99,7 @@ mri_status mri_surrogate_create(const int *widths, const float *params, const do
                                 mri_surrogate **out);
 void mri_surrogate_destroy(mri_surrogate *s);
 
-/* One fused inference: y_out = y_in + predicted increment over a stage of
+/* One fused inference: y_out = y_in advanced by the predicted increment over a stage of
    length L with forcing rho (device [n_poly][22][ld], n_poly <= 3).
    half = 0 the full stage; 1 / 2 the first / second half (length L/2, forcing
    re-expanded on the half).  y_out must not alias y_in. */
@@ -106,9 +110,13 @@ mri_status mri_surrogate_infer(const mri_surrogate *s, int n_cells, int ld, cons
 mri_status mri_surrogate_workspace_bytes(int n_cells, int ld, int n_poly, size_t *bytes);
 
 /* Gated surrogate stage: predicts the stage end once over L and twice over
-   L/2 (step doubling); a cell is accepted when
-   max_c |full_c - doubled_c| / max(|doubled_c|, floor_c) <= gate_tol (floor
-   1e-8 for mass fractions, 0 for T) and then takes the doubled prediction;
+   L/2 (step doubling); a cell is accepted when max(D, I) <= gate_tol with
+   D = max_c |full_c - doubled_c| / max(|doubled_c|, floor_c) (floor 1e-8 for
+   mass fractions, 0 for T) and I the residual of the mass-sum invariant
+   |sum_k (doubled_k - y_in_k) - L sum_p sum_k rho_(p,k) / (p + 1)| /
+   sum_k |y_in_k| (the chemistry conserves sum_k Y_k, so the sum changes only
+   by the integral of the forcing); an accepted cell takes the doubled
+   prediction;
    every other cell is compacted and integrated by the plain FP64 fast stage
    (mech, fallback options) and scattered back.  used_fallback (nullable,
    device int32 [n_cells]) marks fallback cells; gate_value (nullable, device

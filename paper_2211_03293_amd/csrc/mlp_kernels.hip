@@ -9,6 +9,8 @@
 //   D[i][j]: j = l % 16, i = 4 g + r (r = 0..3, four f32)
 #include "mlp_dev.h"
 
+#include <algorithm>
+
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -54,8 +56,12 @@ constexpr int GT = 64, GK = 32, GPAD = 8;
 __global__ void __launch_bounds__(256)
     k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda, int transA,
                 const uint16_t *__restrict__ B, int ldb, int transB, float *__restrict__ C,
-                int ldc)
+                int ldc, int k_chunk)
 {
+    // split K: block z handles [z k_chunk, (z + 1) k_chunk) and writes its own
+    // partial product at C + z M ldc
+    const int kbeg = blockIdx.z * k_chunk, kend = min(K, kbeg + k_chunk);
+    C += (size_t)blockIdx.z * M * ldc;
     __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -65,16 +71,16 @@ __global__ void __launch_bounds__(256)
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
         for (int e = tid; e < GT * GK; e += 256) {
             const int r = e / GK, k = e % GK;
             const int m = m0 + r, kk = k0 + k;
             uint16_t va = 0;
-            if (m < M && kk < K) va = transA ? A[(size_t)kk * lda + m] : A[(size_t)m * lda + kk];
+            if (m < M && kk < kend) va = transA ? A[(size_t)kk * lda + m] : A[(size_t)m * lda + kk];
             As[r][k] = va;
             const int n = n0 + r;
             uint16_t vb = 0;
-            if (n < N && kk < K) vb = transB ? B[(size_t)n * ldb + kk] : B[(size_t)kk * ldb + n];
+            if (n < N && kk < kend) vb = transB ? B[(size_t)n * ldb + kk] : B[(size_t)kk * ldb + n];
             Bs[r][k] = vb;
         }
         __syncthreads();
@@ -141,15 +147,27 @@ __global__ void __launch_bounds__(256)
     dZq[e] = f2bf(g);
 }
 
-// db[n] = sum_r dZ[r][n], fixed summation order (one thread per column).
+// out[e] = sum_z part[z][e], fixed order (deterministic split-K reduction).
 __global__ void __launch_bounds__(256)
-    k_colsum(int rows, int N, const float *__restrict__ dZ, float *__restrict__ db)
+    k_sum_parts(long long n, int parts, const float *__restrict__ part, float *__restrict__ out)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.0f;
+    for (int z = 0; z < parts; ++z) s += part[z * n + e];
+    out[e] = s;
+}
+
+// Partial column sums: part[z][n] = sum over rows [z rc, (z + 1) rc) of dZ[r][n].
+__global__ void __launch_bounds__(256)
+    k_colsum_part(int rows, int N, int rc, const float *__restrict__ dZ, float *__restrict__ part)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const int r0 = blockIdx.y * rc, r1 = min(rows, r0 + rc);
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += dZ[(size_t)r * N + n];
-    db[n] = s;
+    for (int r = r0; r < r1; ++r) s += dZ[(size_t)r * N + n];
+    part[(size_t)blockIdx.y * N + n] = s;
 }
 
 __global__ void __launch_bounds__(256)
@@ -218,11 +236,25 @@ __device__ __forceinline__ float std_feature(int k, const double *__restrict__ y
                    stats[MLP_FEAT + k]);
 }
 
+// Raw target of component c: log-increment for species, plain increment for T.
+__device__ __forceinline__ double raw_target(int c, double y0, double y1)
+{
+    if (c == MLP_NS) return y1 - y0;
+    return log(fmax(y1, 0.0) + MLP_EPS) - log(fmax(y0, 0.0) + MLP_EPS);
+}
+
+// Inverse of raw_target: the end state from the start state and the increment.
+__device__ __forceinline__ double apply_target(int c, double y0, double d)
+{
+    if (c == MLP_NS) return y0 + d;
+    return (fmax(y0, 0.0) + MLP_EPS) * exp(d) - MLP_EPS;
+}
+
 // Training / evaluation features.  Samples are SoA with leading dimension ld:
 // Y0[c*ld + s] (c < NC), RHO[(p*NC + c)*ld + s] (p < n_poly), Lv[s], Y1 like Y0.
 // idx (nullable) picks the samples of this batch.  X: bf16 [B][MLP_KPAD]
 // standardized features; T (nullable): f32 [B][MLP_NC] standardized targets
-// (Y1 - Y0 - y_mean) / y_std.
+// (raw_target - y_mean) / y_std.
 __global__ void __launch_bounds__(256)
     k_featurize(int B, const int *__restrict__ idx, long long ld, const double *__restrict__ Y0,
                 int n_poly, const double *__restrict__ RHO, const double *__restrict__ Lv,
@@ -239,13 +271,13 @@ __global__ void __launch_bounds__(256)
         const double *ym = stats + 2 * MLP_FEAT, *yi = stats + 2 * MLP_FEAT + MLP_NC;
         for (int c = 0; c < MLP_NC; ++c)
             T[(size_t)b * MLP_NC + c] =
-                (float)((Y1[c * ld + s] - Y0[c * ld + s] - ym[c]) * yi[c]);
+                (float)((raw_target(c, Y0[c * ld + s], Y1[c * ld + s]) - ym[c]) * yi[c]);
     }
 }
 
 // Per-block partial sums for feature / target statistics (FP64): part[block]
 // holds sum and sum of squares of the MLP_FEAT raw features and MLP_NC raw
-// increments over the block's samples.
+// targets over the block's samples.
 __global__ void __launch_bounds__(256)
     k_stats_partial(long long N, long long ld, const double *__restrict__ Y0, int n_poly,
                     const double *__restrict__ RHO, const double *__restrict__ Lv,
@@ -260,7 +292,8 @@ __global__ void __launch_bounds__(256)
         for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
             const double x = (v < MLP_FEAT)
                                  ? raw_feature(v, Y0, RHO, ld, s, n_poly, 0, Lv[s])
-                                 : Y1[(v - MLP_FEAT) * ld + s] - Y0[(v - MLP_FEAT) * ld + s];
+                                 : raw_target(v - MLP_FEAT, Y0[(v - MLP_FEAT) * ld + s],
+                                              Y1[(v - MLP_FEAT) * ld + s]);
             sum += x;
             sq += x * x;
         }
@@ -311,7 +344,8 @@ __global__ void k_stats_final(int n_blocks, long long N, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: y_out = y_in + y_mean + y_std * MLP(features(y_in, rho', L')).
+// Fused inference: y_out = apply_target(y_in, y_mean + y_std * MLP(features(y_in,
+// rho', L'))).
 // One wave owns 32 cells (two 16-cell MFMA column tiles); activations stay in
 // registers between layers: the D layout of one layer is the B layout of the
 // next once the next layer's input columns are permuted (done on the host):
@@ -500,32 +534,45 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
                 const int c = 16 * mi + 4 * g + r;
                 if (c >= MLP_NC) continue;
                 const double d = ym[c] + ysd[c] * (double)(acc[mi][t][r] + a.b[3][c]);
-                a.yout[c * a.ld + cell] = a.yin[c * a.ld + cell] + d;
+                a.yout[c * a.ld + cell] = apply_target(c, a.yin[c * a.ld + cell], d);
             }
     }
 }
 
-// Step-doubling gate: D = max_c |full_c - dbl_c| / max(|dbl_c|, floor_c),
-// floor 1e-8 for mass fractions, 0 for T.  Accepted cells take the two-half
-// prediction; rejected cells are appended to the fallback list (one atomic per
-// wave, ranks from the ballot mask).
+// Gate: G = max(D, I).  D = max_c |full_c - dbl_c| / max(|dbl_c|, floor_c)
+// (step doubling; floor 1e-8 for mass fractions, 0 for T).  I = the residual of
+// the mass-sum invariant: the chemistry conserves sum_k Y_k, so over the stage
+// sum_k (dbl_k - y0_k) must equal L sum_p sum_k rho_(p,k) / (p + 1) (the
+// integral of the forcing), relative to sum_k |y0_k|.  Accepted cells take the
+// two-half prediction; rejected cells are appended to the fallback list (one
+// atomic per wave, ranks from the ballot mask).
 __global__ void __launch_bounds__(256)
-    k_gate(int n_cells, long long ld, const double *__restrict__ full,
-           const double *__restrict__ dbl, double tol, double *__restrict__ yout,
-           int *__restrict__ used_fallback, int *__restrict__ list, unsigned int *count,
-           float *__restrict__ dmax)
+    k_gate(int n_cells, long long ld, const double *__restrict__ yin,
+           const double *__restrict__ rho, int n_poly, double L,
+           const double *__restrict__ full, const double *__restrict__ dbl, double tol,
+           double *__restrict__ yout, int *__restrict__ used_fallback, int *__restrict__ list,
+           unsigned int *count, float *__restrict__ dmax)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < n_cells;
     bool reject = false;
     if (live) {
-        double D = 0.0;
+        double D = 0.0, dsum = 0.0, y0sum = 0.0, fsum = 0.0;
         for (int c = 0; c < MLP_NC; ++c) {
             const double a = full[c * ld + i], b = dbl[c * ld + i];
             const double fl = (c < MLP_NS) ? 1e-8 : 0.0;
             const double e = fabs(a - b) / fmax(fabs(b), fl);
             D = (e > D || e != e) ? e : D;       // NaN counts as rejection
+            if (c < MLP_NS) {
+                const double y0 = yin[c * ld + i];
+                dsum += b - y0;
+                y0sum += fabs(y0);
+                for (int p = 0; p < n_poly; ++p)
+                    fsum += rho[((long long)p * MLP_NC + c) * ld + i] / (double)(p + 1);
+            }
         }
+        const double I = fabs(dsum - L * fsum) / fmax(y0sum, 1e-300);
+        D = (I > D || I != I) ? I : D;
         reject = !(D <= tol);
         if (!reject)
             for (int c = 0; c < MLP_NC; ++c) yout[c * ld + i] = dbl[c * ld + i];
@@ -573,11 +620,26 @@ inline dim3 grid1(long long n, int block) { return dim3((unsigned)((n + block - 
 }  // namespace
 
 hipError_t mlp_gemm(int M, int N, int K, const uint16_t *A, int lda, int transA, const uint16_t *B,
-                    int ldb, int transB, float *C, int ldc, hipStream_t s)
+                    int ldb, int transB, float *C, int ldc, hipStream_t s, float *part,
+                    size_t part_elems)
 {
-    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+    // few output tiles and a long K: split K over up to 32 blocks per tile into
+    // `part` and reduce in a fixed order (deterministic)
+    const int tiles = ((N + GT - 1) / GT) * ((M + GT - 1) / GT);
+    int splits = 1;
+    if (part && ldc == N && tiles < 128 && K >= 8 * GK) {
+        splits = std::min(32, std::max(1, 256 / tiles));
+        while (splits > 1 && (size_t)splits * M * N > part_elems) --splits;
+    }
+    const int k_chunk = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+    splits = (K + k_chunk - 1) / k_chunk;
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, splits);
+    float *dst = splits > 1 ? part : C;
     hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb,
-                       transB, C, ldc);
+                       transB, dst, ldc, k_chunk);
+    if (splits > 1)
+        hipLaunchKernelGGL(k_sum_parts, grid1((long long)M * N, 256), dim3(256), 0, s,
+                           (long long)M * N, splits, part, C);
     return hipGetLastError();
 }
 
@@ -604,9 +666,18 @@ hipError_t mlp_silu_bwd(long long n, const float *dA, const float *Z, float *dZ,
     return hipGetLastError();
 }
 
-hipError_t mlp_colsum(int rows, int N, const float *dZ, float *db, hipStream_t s)
+hipError_t mlp_colsum(int rows, int N, const float *dZ, float *db, hipStream_t s, float *part,
+                      size_t part_elems)
 {
-    hipLaunchKernelGGL(k_colsum, grid1(N, 256), dim3(256), 0, s, rows, N, dZ, db);
+    int chunks = std::max(1, std::min(64, rows / 64));
+    while (chunks > 1 && (size_t)chunks * N > part_elems) --chunks;
+    const int rc = (rows + chunks - 1) / chunks;
+    chunks = (rows + rc - 1) / rc;
+    hipLaunchKernelGGL(k_colsum_part, dim3((N + 255) / 256, chunks), dim3(256), 0, s, rows, N, rc,
+                       dZ, chunks > 1 ? part : db);
+    if (chunks > 1)
+        hipLaunchKernelGGL(k_sum_parts, grid1(N, 256), dim3(256), 0, s, (long long)N, chunks,
+                           part, db);
     return hipGetLastError();
 }
 
@@ -665,13 +736,14 @@ hipError_t mlp_infer(const double *yin, double *yout, const double *rho, const u
     return hipGetLastError();
 }
 
-hipError_t mlp_gate(int n_cells, long long ld, const double *full, const double *dbl, double tol,
-                    double *yout, int *used_fallback, int *list, unsigned int *count, float *dmax,
+hipError_t mlp_gate(int n_cells, long long ld, const double *yin, const double *rho, int n_poly,
+                    double L, const double *full, const double *dbl, double tol, double *yout,
+                    int *used_fallback, int *list, unsigned int *count, float *dmax,
                     hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, count);
-    hipLaunchKernelGGL(k_gate, grid1(n_cells, 256), dim3(256), 0, s, n_cells, ld, full, dbl, tol,
-                       yout, used_fallback, list, count, dmax);
+    hipLaunchKernelGGL(k_gate, grid1(n_cells, 256), dim3(256), 0, s, n_cells, ld, yin, rho,
+                       n_poly, L, full, dbl, tol, yout, used_fallback, list, count, dmax);
     return hipGetLastError();
 }
 

@@ -40,6 +40,8 @@ struct mri_mlp {
     const uint16_t *X = nullptr;           // input of the last forward (caller-owned)
     float *dZ = nullptr, *dA = nullptr;
     uint16_t *dZq = nullptr;
+    float *part = nullptr;                 // split-K / split-row partial sums
+    size_t part_elems = 0;
     int step = 0;
     int last_batch = 0;
 };
@@ -101,6 +103,8 @@ mri_status mri_mlp_create(int n_layers, const int *widths, const float *params, 
     HIP_TRY(dalloc(&m->dZ, (size_t)max_batch * wall));
     HIP_TRY(dalloc(&m->dA, (size_t)max_batch * wall));
     HIP_TRY(dalloc(&m->dZq, (size_t)max_batch * wall));
+    m->part_elems = (size_t)32 * wall * wall;
+    HIP_TRY(dalloc(&m->part, m->part_elems));
     HIP_TRY(hipDeviceSynchronize());
     *out = m.release();
     return MRI_OK;
@@ -110,7 +114,7 @@ void mri_mlp_destroy(mri_mlp *m)
 {
     if (!m) return;
     for (void *p : {(void *)m->p, (void *)m->g, (void *)m->m1, (void *)m->m2, (void *)m->pq,
-                    (void *)m->dZ, (void *)m->dA, (void *)m->dZq})
+                    (void *)m->dZ, (void *)m->dA, (void *)m->dZq, (void *)m->part})
         if (p) (void)hipFree(p);
     for (auto *z : m->Z)
         if (z) (void)hipFree(z);
@@ -171,8 +175,9 @@ mri_status mri_mlp_backward(mri_mlp *m, int batch, const float *T, double *loss,
         const int ni = m->w[l], no = m->w[l + 1];
         const uint16_t *in = (l == 0) ? m->X : m->A[l - 1];
         // dW [no x ni] = dZ^T [no x B] . in [B x ni]
-        HIP_TRY(mlp_gemm(no, ni, batch, m->dZq, no, 1, in, ni, 0, m->g + m->woff[l], ni, s));
-        HIP_TRY(mlp_colsum(batch, no, m->dZ, m->g + m->boff[l], s));
+        HIP_TRY(mlp_gemm(no, ni, batch, m->dZq, no, 1, in, ni, 0, m->g + m->woff[l], ni, s,
+                         m->part, m->part_elems));
+        HIP_TRY(mlp_colsum(batch, no, m->dZ, m->g + m->boff[l], s, m->part, m->part_elems));
         if (l > 0) {
             // dA [B x ni] = dZ [B x no] . W [no x ni]
             HIP_TRY(mlp_gemm(batch, ni, no, m->dZq, no, 0, m->pq + m->woff[l], ni, 0, m->dA, ni,
@@ -358,8 +363,8 @@ mri_status mri_surrogate_stage(const mri_surrogate *s, const mri_mech *mech,
     HIP_TRY(mlp_infer(y_in, full, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, 0, st));
     HIP_TRY(mlp_infer(y_in, mid, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, 1, st));
     HIP_TRY(mlp_infer(mid, dbl, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, 2, st));
-    HIP_TRY(mlp_gate(n_cells, ld, full, dbl, gate_tol, y_out, used_fallback, list, count,
-                     gate_value, st));
+    HIP_TRY(mlp_gate(n_cells, ld, y_in, rho, n_poly, L, full, dbl, gate_tol, y_out,
+                     used_fallback, list, count, gate_value, st));
     unsigned int h_count = 0;
     HIP_TRY(hipMemcpyAsync(&h_count, count, sizeof h_count, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -177,10 +177,10 @@ class Mech:
         _check(lib.mri_mech_specialize(self.h, block_size, int(load), C.byref(nb)))
         return nb.value
 
-    def __del__(self, _destroy=lib.mri_mech_destroy):
+    def __del__(self, _destroy=lib.mri_mech_destroy, _null=C.c_void_p):
         if getattr(self, "h", None) and self.h.value:
             _destroy(self.h)
-            self.h = C.c_void_p()
+            self.h = _null()
 
 
 class Table:
@@ -193,10 +193,10 @@ class Table:
                            self.gamma.ctypes.data_as(C.POINTER(C.c_double)))
         _check(lib.mri_table_create(C.byref(d), C.byref(self.h)))
 
-    def __del__(self, _destroy=lib.mri_table_destroy):
+    def __del__(self, _destroy=lib.mri_table_destroy, _null=C.c_void_p):
         if getattr(self, "h", None) and self.h.value:
             _destroy(self.h)
-            self.h = C.c_void_p()
+            self.h = _null()
 
 
 def fast_opts(method=FAST_RK4, n_sub=1, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000,
@@ -301,10 +301,10 @@ class BatchPlan:
         _check(lib.mri_batch_lane_stats(self.h, C.byref(u), C.byref(i), _stream(stream)))
         return u.value, i.value
 
-    def __del__(self, _destroy=lib.mri_batch_plan_destroy):
+    def __del__(self, _destroy=lib.mri_batch_plan_destroy, _null=C.c_void_p):
         if getattr(self, "h", None) and self.h.value:
             _destroy(self.h)
-            self.h = C.c_void_p()
+            self.h = _null()
 
 
 # ---------------------------------------------------------------------------
@@ -349,10 +349,10 @@ class MLP:
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(lib.mri_adam_step(self.h, lr, beta1, beta2, eps, _stream(stream)))
 
-    def __del__(self, _destroy=lib.mri_mlp_destroy):
+    def __del__(self, _destroy=lib.mri_mlp_destroy, _null=C.c_void_p):
         if getattr(self, "h", None) and self.h.value:
             _destroy(self.h)
-            self.h = C.c_void_p()
+            self.h = _null()
 
 
 def mri_mlp_feature_stats(n, ld, Y0, n_poly, RHO, Lv, Y1, stats, stream=None):
@@ -395,7 +395,7 @@ class Surrogate:
                                        C.byref(nf), _ptr(ws), nbytes, _stream(stream)))
         return nf.value
 
-    def __del__(self, _destroy=lib.mri_surrogate_destroy):
+    def __del__(self, _destroy=lib.mri_surrogate_destroy, _null=C.c_void_p):
         if getattr(self, "h", None) and self.h.value:
             _destroy(self.h)
-            self.h = C.c_void_p()
+            self.h = _null()

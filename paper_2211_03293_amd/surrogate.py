@@ -185,3 +185,98 @@ def stage_error(y_pred, y_ref, n_species, floor=1e-8):
     fl = torch.zeros((y_ref.shape[0], 1), dtype=y_ref.dtype, device=y_ref.device)
     fl[:n_species] = floor
     return ((y_pred - y_ref).abs() / torch.maximum(y_ref.abs(), fl)).amax(0)
+
+
+def stage_inputs(config=4, stage=1):
+    """State, forcing and stage length of one fast stage of the config's first
+    slow step (slow RHS by the advection-diffusion kernel, forcing assembly by
+    libmri), as device tensors."""
+    torch = _torch()
+    cfg = I.CONFIGS[config]
+    tb = I.table_mis_kw3()
+    t = mri.Table(tb)
+    y_host = I.initial_state(config)
+    n, ld = y_host.shape
+    N = cfg.n_cells
+    y = torch.as_tensor(y_host, device="cuda")
+    F = torch.empty((tb.s - 1, n, ld), dtype=torch.float64, device="cuda")
+    rho = torch.empty((1, n, ld), dtype=torch.float64, device="cuda")
+    params = mri.advdiff_params(cfg.grid, n)
+    sp = torch.cuda.current_stream().cuda_stream
+    rc = mri.lib.mri_advdiff_slow_rhs(0.0, y.data_ptr(), F[0].data_ptr(), N, ld,
+                                      mri.C.cast(mri.C.pointer(params), mri.C.c_void_p).value, sp)
+    assert rc == 0
+    mri.mri_forcing_assemble(t, stage, n, ld, F, rho)
+    L = float((tb.c[stage] - tb.c[stage - 1]) * cfg.H)
+    return y, rho, L, N, ld
+
+
+def evaluate_stage(params, stats, config=4, gate_tol=1e-4, repeats=3, log=print):
+    """Gated surrogate stage against the plain FP64 stage on every cell of the
+    config's first fast stage: fallback fraction, false accepts, error of the
+    accepted cells, wall times and the fused inference kernel time."""
+    torch = _torch()
+    cfg = I.CONFIGS[config]
+    mech = I.make_mechanism(config)
+    m = mri.Mech(mech)
+    m.specialize(128, load=True)
+    y, rho, L, N, ld = stage_inputs(config)
+    opts = mri.fast_opts(n_sub=cfg.n_sub)
+    ref = torch.empty_like(y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(repeats):
+        mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)
+    e1.record()
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) / repeats
+    sg = mri.Surrogate([mri.MLP_KPAD, 256, 256, 256, mri.MLP_OUTPUTS], params, stats)
+    raw = torch.empty_like(y)
+    sg.infer(N, ld, y, raw, 1, rho, L)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(repeats):
+        sg.infer(N, ld, y, raw, 1, rho, L)
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / repeats
+    ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    used = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    gv = torch.zeros(ld, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(y)
+    nf = sg.stage(m, opts, gate_tol, N, ld, y, out, 1, rho, L, ws, used, gv)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(repeats):
+        t1 = time.perf_counter()
+        nf = sg.stage(m, opts, gate_tol, N, ld, y, out, 1, rho, L, ws, used, gv)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t1) * 1e3)
+    t_sur = float(np.median(times))
+    err = stage_error(out[:, :N], ref[:, :N], mech.n_species)
+    err6 = stage_error(out[:, :N], ref[:, :N], mech.n_species, floor=1e-6)
+    acc = used[:N] == 0
+    n_acc = int(acc.sum().item())
+    err_raw = stage_error(raw[:, :N], ref[:, :N], mech.n_species)
+
+    def q(x, p):
+        return float(torch.quantile(x.float()[:1 << 24], p).item()) if x.numel() else None
+
+    res = dict(cells=N, gate_tol=gate_tol, fallback_cells=int(nf), fallback_frac=nf / N,
+               accepted_cells=n_acc,
+               false_accepts=int(((err > gate_tol) & acc).sum().item()),
+               max_err_accepted=float(err[acc].max().item()) if n_acc else None,
+               p999_err_accepted=q(err[acc], 0.999) if n_acc else None,
+               max_err_accepted_floor_1e6=float(err6[acc].max().item()) if n_acc else None,
+               max_err_all=float(err.max().item()),
+               raw_err_median=q(err_raw, 0.5), raw_err_p90=q(err_raw, 0.9),
+               raw_frac_within_tol=float((err_raw <= gate_tol).float().mean().item()),
+               plain_ms=round(t_plain, 3), surrogate_stage_ms=round(t_sur, 3),
+               infer_ms=round(t_inf, 4), speedup=round(t_plain / t_sur, 3))
+    log(f"# surrogate stage on {N} cells at gate {gate_tol:g}: fallback {nf / N:.3f}, "
+        f"false accepts {res['false_accepts']}, plain {t_plain:.2f} ms, gated {t_sur:.2f} ms, "
+        f"one inference {t_inf:.3f} ms")
+    return res

@@ -151,9 +151,11 @@ def test_fused_inference_matches_training_forward(torch, mri):
         mri.mri_mlp_featurize(ld, None, ld, yd, 1, rd, Lv, None, stats, X)
         net.forward(X, Y)
         torch.cuda.synchronize()
-        inc_ref = st[2 * 89:2 * 89 + 22][:, None] + st[2 * 89 + 44:][:, None] * Y.cpu().numpy().T.astype(np.float64)
-        inc = out.cpu().numpy() - y
-        e = _relnorm(inc[:, :1000], inc_ref[:, :1000])
+        d = st[2 * 89:2 * 89 + 22][:, None] + st[2 * 89 + 44:][:, None] * Y.cpu().numpy().T.astype(np.float64)
+        # species: log-increment of Y + 1e-8; T: plain increment
+        d_out = np.log(np.maximum(out.cpu().numpy()[:22] + 1e-8, 1e-300)) - np.log(np.maximum(y[:22], 0) + 1e-8)
+        d_out[21] = out.cpu().numpy()[21] - y[21]
+        e = _relnorm(d_out[:, :1000], d[:, :1000])
         print(f"half={half}: fused vs training forward rel err {e:.2e}")
         assert e < 2e-2
 
