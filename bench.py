@@ -10,9 +10,13 @@ resident in HBM before the timed region.
 Prints one JSON line: value = cell fast-stage solves per second (cell-stages/s),
 plus the fast-stage kernel's roofline figures (kernel time from hipEvents around
 every fast-stage launch inside the timed region) and the CPU oracle timed on a
-bounded sample of the same workload.
+bounded sample of the same workload.  Further legs, each in its own JSON object:
+the 128^3 large mechanism (53 species / 325 reactions), the batched uneven
+reactor sets (adaptive, persistent work queue) and the learned surrogate
+(training on the GPU, then the gated stage against the plain FP64 stage).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--no-large] [--no-batch] [--no-surrogate]
 """
 from __future__ import annotations
 
@@ -125,6 +129,83 @@ def batch_leg(torch, mri, I, repeats=3):
                 flagged_cells=n_bad)
 
 
+WORKLOADS = {
+    1: "plain FP64 explicit MRI-GARK (MIS-KW3) slow steps, 64^3 cells, 21 species / 84 "
+       "reactions, RK4 50 substeps/stage, H = 1e-7 s, advection-diffusion slow RHS",
+    3: "plain FP64 explicit MRI-GARK (MIS-KW3) slow step, 128^3 cells, 53 species / 325 "
+       "reactions, RK4 100 substeps/stage, H = 5e-8 s, advection-diffusion slow RHS",
+}
+
+
+def plain_leg(torch, mri, I, config, steps, warmup, block, kernel_name):
+    """K timed MRI slow steps of a field workload (W untimed before), wall time
+    from events around the whole steps, fast-stage kernel time from libmri's
+    per-launch events on the launch stream."""
+    cfg = I.CONFIGS[config]
+    mech = I.make_mechanism(config)
+    tb = I.table_mis_kw3()
+    y_host = I.initial_state(config)
+    n, ld = y_host.shape
+    N = cfg.n_cells
+    kernel = dict(auto=mri.KERNEL_AUTO, specialized=mri.KERNEL_SPECIALIZED,
+                  generic=mri.KERNEL_GENERIC)[kernel_name]
+    m, t = mri.Mech(mech), mri.Table(tb)
+    if kernel != mri.KERNEL_GENERIC:
+        m.specialize(block or 128, load=True)
+    opts = mri.fast_opts(n_sub=cfg.n_sub, kernel=kernel, block_size=block)
+    y0 = torch.as_tensor(y_host, device="cuda")
+    del y_host
+    y = y0.clone()
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    status = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    params = mri.advdiff_params(cfg.grid, n)
+
+    def step(k):
+        mri.mri_slow_step(m, t, opts, mri.ADVDIFF_RHS, params, k * cfg.H, cfg.H, N, ld, y, ws,
+                          status)
+
+    print(f"# config {config}: warmup {warmup} steps", file=sys.stderr, flush=True)
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    y.copy_(y0)
+    status.zero_()
+    torch.cuda.synchronize()
+    mri.timing_enable(True)
+    mri.timing_read(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    wall_ms = e0.elapsed_time(e1)
+    fast_ms, n_launch = mri.timing_read(reset=True)
+    mri.timing_enable(False)
+    n_bad = mri.mri_status_count(status, N)
+    print(f"# config {config}: timed {steps} steps: {wall_ms:.1f} ms, fast kernels "
+          f"{fast_ms:.1f} ms over {n_launch} launches, flagged cells {n_bad}", file=sys.stderr,
+          flush=True)
+    stages_per_step = tb.s - 1
+    value = N * stages_per_step * steps / (wall_ms * 1e-3)
+    fps = flops_per_substep(mech.n_species, mech.n_reactions, n_poly=1)
+    avg_launch_s = fast_ms * 1e-3 / max(1, n_launch)
+    achieved = fps * cfg.n_sub * N / avg_launch_s / 1e12
+    workload = (f"mri_fast_stage rk4 {cfg.grid[0]}^3 cells S={mech.n_species} "
+                f"R={mech.n_reactions} n_sub={cfg.n_sub}")
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=load_traffic(workload),
+                kernel="mri_spec_main (RK4, specialized)" if kernel != mri.KERNEL_GENERIC
+                else "k_gen_rk4 (generic)",
+                flops_per_cell_substep=fps, avg_launch_ms=round(avg_launch_s * 1e3, 4))
+    return dict(value=round(value, 1), ms_per_step=round(wall_ms / steps, 3), roofline=roof,
+                config=dict(workload=WORKLOADS[config], cells=N,
+                            stages_per_step=stages_per_step, n_sub=cfg.n_sub,
+                            flagged_cells=n_bad))
+
+
 def surrogate_leg(train_steps, n_samples):
     """Learned surrogate: stage data from the 64^3 workload's plain runs, training
     with libmri's BF16 MFMA kernels, then the gated stage (tolerance 1e-4) on the
@@ -169,6 +250,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-set leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 128^3 large-mechanism leg (53 species / 325 reactions)")
     ap.add_argument("--surrogate-steps", type=int, default=20000,
                     help="training steps of the surrogate leg (batch 4096)")
     ap.add_argument("--surrogate-samples", type=int, default=1_000_000,
@@ -197,74 +280,17 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes_per_dispatch=2 ** 30, dispatches=3)), flush=True)
         return
-    cfg = I.CONFIGS[1]
-    mech = I.make_mechanism(1)
-    tb = I.table_mis_kw3()
-    y_host = I.initial_state(1)
-    n, ld = y_host.shape
-    N = cfg.n_cells
-    kernel = dict(auto=mri.KERNEL_AUTO, specialized=mri.KERNEL_SPECIALIZED,
-                  generic=mri.KERNEL_GENERIC)[args.kernel]
-    m, t = mri.Mech(mech), mri.Table(tb)
-    if kernel != mri.KERNEL_GENERIC:
-        m.specialize(args.block or 128, load=True)
-    opts = mri.fast_opts(n_sub=cfg.n_sub, kernel=kernel, block_size=args.block)
-    y0 = torch.as_tensor(y_host, device="cuda")
-    y = y0.clone()
-    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
-                     device="cuda")
-    status = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    params = mri.advdiff_params(cfg.grid, n)
-
-    def step(k):
-        mri.mri_slow_step(m, t, opts, mri.ADVDIFF_RHS, params, k * cfg.H, cfg.H, N, ld, y, ws,
-                          status)
-
-    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    y.copy_(y0)
-    torch.cuda.synchronize()
-    mri.timing_enable(True)
-    mri.timing_read(reset=True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for k in range(args.steps):
-        step(k)
-    e1.record()
-    torch.cuda.synchronize()
-    wall_ms = e0.elapsed_time(e1)
-    fast_ms, n_launch = mri.timing_read(reset=True)
-    mri.timing_enable(False)
-    n_bad = mri.mri_status_count(status, N)
-    print(f"# timed {args.steps} steps: {wall_ms:.1f} ms, fast kernels {fast_ms:.1f} ms over "
-          f"{n_launch} launches, flagged cells {n_bad}", file=sys.stderr, flush=True)
-
-    stages_per_step = tb.s - 1
-    cell_stages = N * stages_per_step * args.steps
-    value = cell_stages / (wall_ms * 1e-3)
-    fps = flops_per_substep(mech.n_species, mech.n_reactions, n_poly=1)
-    flops_launch = fps * cfg.n_sub * N
-    avg_launch_s = fast_ms * 1e-3 / max(1, n_launch)
-    achieved = flops_launch / avg_launch_s / 1e12
-    workload = "mri_fast_stage rk4 64^3 cells S=21 R=84 n_sub=50"
-    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=load_traffic(workload),
-                kernel="mri_spec_main (RK4, specialized)" if kernel != mri.KERNEL_GENERIC
-                else "k_gen_rk4 (generic)",
-                flops_per_cell_substep=fps, avg_launch_ms=round(avg_launch_s * 1e3, 4))
-    out = dict(metric=METRIC, value=round(value, 1), unit="cell-stages/s", n_gpus=1,
-               steps=args.steps, warmup=args.warmup, ms_per_step=round(wall_ms / args.steps, 3),
+    plain = plain_leg(torch, mri, I, 1, args.steps, args.warmup, args.block, args.kernel)
+    out = dict(metric=METRIC, value=plain["value"], unit="cell-stages/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=plain["ms_per_step"],
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
-               data="synthetic",
-               config=dict(workload="plain FP64 explicit MRI-GARK (MIS-KW3) slow steps, 64^3 "
-                                    "cells, 21 species / 84 reactions, RK4 50 substeps/stage, "
-                                    "H = 1e-7 s, advection-diffusion slow RHS",
-                           cells=N, stages_per_step=stages_per_step, n_sub=cfg.n_sub,
-                           flagged_cells=n_bad),
-               roofline=roof)
+               data="synthetic", config=plain["config"], roofline=plain["roofline"])
+    if not args.no_large:
+        print("# large-mechanism leg", file=sys.stderr, flush=True)
+        big = plain_leg(torch, mri, I, 3, 1, 1, args.block, args.kernel)
+        out["large_mechanism"] = dict(value=big["value"], unit="cell-stages/s",
+                                      ms_per_step=big["ms_per_step"], steps=1, warmup=1,
+                                      config=big["config"], roofline=big["roofline"])
     if not args.no_batch:
         print("# batched uneven-set leg", file=sys.stderr, flush=True)
         out["batch"] = batch_leg(torch, mri, I)
@@ -274,9 +300,11 @@ def main():
     if not args.no_cpu_baseline:
         # forcing of the first stage of one slow step, from the oracle's own slow RHS
         from oracle import oracle as O
+        cfg, tb = I.CONFIGS[1], I.table_mis_kw3()
+        y_host = I.initial_state(1)
         rho = O.advdiff(y_host, cfg.grid)[None]
         Ls = [float((tb.c[i] - tb.c[i - 1]) * cfg.H) for i in range(1, tb.s)]
-        out["cpu_baseline"] = cpu_baseline(mech, y_host, rho, Ls, cfg.n_sub)
+        out["cpu_baseline"] = cpu_baseline(I.make_mechanism(1), y_host, rho, Ls, cfg.n_sub)
     print(json.dumps(out), flush=True)
 
 

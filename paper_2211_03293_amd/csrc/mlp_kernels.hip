@@ -10,6 +10,7 @@
 #include "mlp_dev.h"
 
 #include <algorithm>
+#include <utility>
 
 namespace {
 
@@ -368,64 +369,73 @@ struct InferArgs {
     int half;
 };
 
-// Weights are staged through LDS in chunks of 32 input columns (all output
-// rows), shared by the block's four waves; the next chunk's global loads are
-// issued before the current chunk's MFMAs (double buffer).
-constexpr int WROW = 32 + 8;            // padded LDS row (bf16), 80 bytes
-constexpr int WCHUNK = MLP_HID * WROW;  // one chunk: 256 rows x 32 columns
+// Weights stream through LDS in chunks of 32 input columns (all output rows of
+// one layer; 16 KB for a hidden layer), shared by the block's four waves.  The
+// chunks are copied by direct global -> LDS loads (no register staging) into a
+// ring of three buffers, two chunks ahead of the one being multiplied.  In a
+// buffer, row r's four 16-byte pieces (8 bf16 each) sit at slots 4 r + (q ^ s)
+// with s = (r >> 2) & 3, so that the 16 lanes reading one A fragment column
+// hit 16 distinct bank groups.
+constexpr int WCHUNK = MLP_HID * 32;    // bf16 elements of one chunk buffer
+constexpr int N_BUF = 3;
 
-// Loads chunk kb of W [rows][kin] (bf16) into registers: 4 x 16 bytes per
-// thread for 256 rows (rows < n_rows only).
-__device__ __forceinline__ void chunk_load(const uint16_t *__restrict__ W, int kin, int kb,
-                                           int n_rows, uint4 (&r)[4])
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// The weight stream of one inference: 3 chunks of the first layer (96 padded
+// inputs), 8 of each hidden layer, 8 of the output layer (32 padded rows).
+constexpr int N_CHUNKS = 3 + 8 + 8 + 8;
+__host__ __device__ constexpr int chunk_layer(int c) { return c < 3 ? 0 : (c - 3) / 8 + 1; }
+__host__ __device__ constexpr int chunk_kb(int c) { return c < 3 ? c : (c - 3) % 8; }
+__host__ __device__ constexpr int layer_chunks(int l) { return l == 0 ? 3 : 8; }
+__host__ __device__ constexpr int layer_rows(int l) { return l == 3 ? MLP_OUT_PAD : MLP_HID; }
+// direct-to-LDS loads one wave issues per chunk (the same for all four waves)
+__host__ __device__ constexpr int chunk_loads(int c)
 {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q;      // 1024 pieces of 16 bytes
-        const int row = e >> 2, part = e & 3;
-        if (row < n_rows)
-            r[q] = *reinterpret_cast<const uint4 *>(W + (size_t)row * kin + 32 * kb + 8 * part);
-    }
+    return layer_rows(chunk_layer(c)) == MLP_HID ? 4 : 1;
 }
 
-__device__ __forceinline__ void chunk_store(uint16_t *__restrict__ buf, int n_rows,
-                                            const uint4 (&r)[4])
+// Issues the direct-to-LDS loads of chunk C into buffer `buf` (wave `w`).
+// Hidden-size chunks: 1024 slots, wave w's load i fills slots 256 i + 64 w +
+// lane.  Output chunks: 128 slots, wave w fills slots 32 w + lane (lane < 32).
+template <int C>
+__device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, int w, int lane)
 {
+    constexpr int l = chunk_layer(C), kb = chunk_kb(C), kin = 32 * layer_chunks(l);
+    // uniform base of the chunk's columns + a lane offset that is the same for
+    // every chunk of the layer (one VGPR per load, shared across chunks)
+    const char *W = reinterpret_cast<const char *>(a.W[l] + 32 * kb);
+    if constexpr (chunk_loads(C) == 4) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        const int row = e >> 2, part = e & 3;
-        if (row < n_rows) *reinterpret_cast<uint4 *>(buf + row * WROW + 8 * part) = r[q];
-    }
-}
-
-// acc (MT row tiles x 2 column tiles) = W [16 MT rows][32 KB cols] . bin
-template <int KB, int MT, int NTT>
-__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, uint16_t *lds, int j,
-                                            int g, const bf16x8 (&bin)[8][NTT],
-                                            f32x4 (&acc)[16][NTT])
-{
-#pragma unroll
-    for (int mi = 0; mi < MT; ++mi)
-#pragma unroll
-        for (int t = 0; t < NTT; ++t) acc[mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    uint4 r[4];
-    chunk_load(W, 32 * KB, 0, 16 * MT, r);
-    __syncthreads();                         // previous users of the buffers are done
-    chunk_store(lds, 16 * MT, r);
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-        __syncthreads();                     // chunk kb visible
-        if (kb + 1 < KB) chunk_load(W, 32 * KB, kb + 1, 16 * MT, r);
-        const uint16_t *buf = lds + (kb & 1) * WCHUNK;
-#pragma unroll
-        for (int mi = 0; mi < MT; ++mi) {
-            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(buf + (16 * mi + j) * WROW + 8 * g);
-#pragma unroll
-            for (int t = 0; t < NTT; ++t) acc[mi][t] = mfma(af, bin[kb][t], acc[mi][t]);
+        for (int i = 0; i < 4; ++i) {
+            const int slot = 256 * i + 64 * w + lane;
+            const int row = slot >> 2, q = (slot & 3) ^ ((row >> 2) & 3);
+            const unsigned off = 2u * (unsigned)(row * kin + 8 * q);
+            __builtin_amdgcn_global_load_lds((const void *)(W + off),
+                                             (lds_void_t *)(buf + 8 * (256 * i + 64 * w)), 16,
+                                             0, 0);
         }
-        if (kb + 1 < KB) chunk_store(lds + ((kb + 1) & 1) * WCHUNK, 16 * MT, r);
+    } else {
+        if (lane < 32) {
+            const int slot = 32 * w + lane;
+            const int row = slot >> 2, q = (slot & 3) ^ ((row >> 2) & 3);
+            const unsigned off = 2u * (unsigned)(row * kin + 8 * q);
+            __builtin_amdgcn_global_load_lds((const void *)(W + off),
+                                             (lds_void_t *)(buf + 8 * (32 * w)), 16, 0, 0);
+        }
     }
+}
+
+// Waits until at most N of this wave's vector-memory loads are outstanding
+// (loads complete in issue order), then joins the block barrier.  The empty
+// asm statements keep the compiler from moving LDS accesses across it.
+template <int N>
+__device__ __forceinline__ void wait_loads_and_barrier()
+{
+    static_assert(N >= 0 && N <= 15, "vmcnt field");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4) | (0xf << 8));   // vmcnt(N) only
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 template <int NTT>
@@ -460,43 +470,128 @@ constexpr int XROW = MLP_KPAD + 8;     // padded LDS feature row (bf16), 208 byt
 constexpr int NT = MLP_NT;
 constexpr int CELLS_PER_BLOCK = 4 * 16 * NT;
 
+// The ring: three distinct LDS objects, so that the compiler can tell a read
+// of one buffer from the direct-to-LDS loads still in flight into another (it
+// then needs no wait for those loads before the read).
+struct Ring {
+    uint16_t *b0, *b1, *b2;
+    template <int I>
+    __device__ __forceinline__ uint16_t *get() const
+    {
+        if constexpr (I % N_BUF == 0) return b0;
+        else if constexpr (I % N_BUF == 1) return b1;
+        else return b2;
+    }
+};
+
+// One step of the weight stream: wait for chunk C (the loads of chunk C + 1
+// stay in flight), barrier, issue chunk C + 2 into the buffer that chunk C - 1
+// used, multiply chunk C into the accumulators; SiLU + repack at the end of a
+// hidden layer.
+template <int C>
+__device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring,
+                                            const float *bias, int w, int lane, int j, int g,
+                                            int swz, bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT])
+{
+    constexpr int l = chunk_layer(C), kb = chunk_kb(C), MT = layer_rows(l) / 16;
+    if constexpr (kb == 0) {
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if constexpr (C + 1 < N_CHUNKS)
+        wait_loads_and_barrier<chunk_loads(C + 1)>();
+    else
+        wait_loads_and_barrier<0>();
+    if constexpr (C + 2 < N_CHUNKS) chunk_issue<C + 2>(a, ring.get<C + 2>(), w, lane);
+    const uint16_t *buf = ring.get<C>();
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) {
+        const bf16x8 af =
+            *reinterpret_cast<const bf16x8 *>(buf + 8 * (4 * (16 * mi + j) + (g ^ swz)));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[mi][t] = mfma(af, bin[kb][t], acc[mi][t]);
+    }
+    if constexpr (l < 3 && kb == layer_chunks(l) - 1)
+        silu_repack<NT>(bias + MLP_HID * l, g, acc, bin);
+}
+
+template <int... C>
+__device__ __forceinline__ void weight_stream(const InferArgs &a, const Ring &ring,
+                                              const float *bias, int w, int lane, int j, int g,
+                                              int swz, bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT],
+                                              std::integer_sequence<int, C...>)
+{
+    (weight_step<C>(a, ring, bias, w, lane, j, g, swz, bin, acc), ...);
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WPE))) k_infer(InferArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * WCHUNK];
+    __shared__ __attribute__((aligned(16))) uint16_t wb0[WCHUNK];
+    __shared__ __attribute__((aligned(16))) uint16_t wb1[WCHUNK];
+    __shared__ __attribute__((aligned(16))) uint16_t wb2[WCHUNK];
     __shared__ __attribute__((aligned(16))) uint16_t xs[CELLS_PER_BLOCK * XROW];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, j = lane & 15;
+    const Ring ring{wb0, wb1, wb2};
+    __shared__ float bias[3 * MLP_HID];      // hidden-layer biases
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, j = lane & 15, swz = (j >> 2) & 3;
+    // the first two weight chunks are in flight while the features are built
+    chunk_issue<0>(a, ring.get<0>(), w, lane);
+    chunk_issue<1>(a, ring.get<1>(), w, lane);
+    for (int e = threadIdx.x; e < 3 * MLP_HID; e += 256) bias[e] = a.b[e / MLP_HID][e % MLP_HID];
     // every wave takes part in the block's barriers; idle cells are clamped
     const long long block0 = (long long)blockIdx.x * CELLS_PER_BLOCK;
-    const long long base = block0 + wave * 16 * NT;
+    const long long base = block0 + w * 16 * NT;
     const double L = (a.half == 0) ? a.L : 0.5 * a.L;
     // ---- features of the block's cells, computed cooperatively: thread
-    // groups take interleaved features (uniform per wave, coalesced loads)
+    // groups take interleaved features (the feature index is uniform per wave,
+    // so its source plane is a scalar address and the loads are coalesced)
     {
         constexpr int GROUPS = 256 / CELLS_PER_BLOCK;
+        constexpr int PER = MLP_KPAD / GROUPS;           // features per thread
         const int c = threadIdx.x % CELLS_PER_BLOCK;
-        const int grp = threadIdx.x / CELLS_PER_BLOCK;
+        const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / CELLS_PER_BLOCK);
         long long cell = block0 + c;
         if (cell >= a.n_cells) cell = a.n_cells - 1;
         if (a.n_poly <= 1) {
             // constant forcing: every half-stage transform is the identity on
             // rho_0 and the higher coefficients are zero, so each feature is one
-            // unconditional load plus selects; unrolled so the loads overlap
+            // unconditional load plus selects.  Loads go out in batches of FB
+            // before any of them is used.
+            // The statistics are read through the constant address space
+            // (scalar loads: the feature index is uniform per wave and the
+            // statistics are not written during the launch).
+            constexpr int FB = PER % 48 == 0 ? 48 : (PER % 16 == 0 ? 16 : 8);
+            static_assert(PER % FB == 0, "feature batches");
+            typedef const __attribute__((address_space(4))) double cdouble;
+            cdouble *cst = (cdouble *)a.stats;
             const float logL = __logf((float)L);
-#pragma unroll 8
-            for (int i = 0; i < MLP_KPAD / GROUPS; ++i) {
-                const int k = grp + GROUPS * i;
-                const bool isy = k <= MLP_NS, isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
-                const double *src = isy ? a.yin + (long long)k * a.ld
-                                        : (isr ? a.rho + (long long)(k - MLP_NS - 1) * a.ld : a.yin);
-                const double v = src[cell];
-                float raw = (k < MLP_NS) ? __logf((float)fmax(v, 1e-30)) : (float)v;
-                if (k == MLP_FEAT - 1) raw = logL;
-                const bool live = isy || isr || (k == MLP_FEAT - 1);
-                const float z = live ? (float)((raw - a.stats[min(k, MLP_FEAT - 1)]) *
-                                               a.stats[MLP_FEAT + min(k, MLP_FEAT - 1)])
-                                     : 0.0f;
-                xs[c * XROW + k] = f2bf(z);
+            for (int b0 = 0; b0 < PER; b0 += FB) {
+                double v[FB];
+#pragma unroll
+                for (int i = 0; i < FB; ++i) {
+                    const int k = grp + GROUPS * (b0 + i);
+                    const bool isy = k <= MLP_NS;
+                    const bool isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
+                    const double *src = isy ? a.yin + (long long)k * a.ld
+                                            : (isr ? a.rho + (long long)(k - MLP_NS - 1) * a.ld
+                                                   : a.yin);
+                    v[i] = src[cell];
+                }
+#pragma unroll
+                for (int i = 0; i < FB; ++i) {
+                    const int k = grp + GROUPS * (b0 + i);
+                    const bool isy = k <= MLP_NS;
+                    const bool isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
+                    float raw = (k < MLP_NS) ? __logf((float)fmax(v[i], 1e-30)) : (float)v[i];
+                    if (k == MLP_FEAT - 1) raw = logL;
+                    const bool live = isy || isr || (k == MLP_FEAT - 1);
+                    const int kk = min(k, MLP_FEAT - 1);
+                    const float z = live ? (float)((raw - cst[kk]) * cst[MLP_FEAT + kk]) : 0.0f;
+                    xs[c * XROW + k] = f2bf(z);
+                }
             }
         } else {
             for (int k = grp; k < MLP_KPAD; k += GROUPS)
@@ -511,18 +606,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
 #pragma unroll
         for (int kb = 0; kb < MLP_KPAD / 32; ++kb)
             bin[kb][t] = *reinterpret_cast<const bf16x8 *>(
-                xs + (wave * 16 * NT + 16 * t + j) * XROW + 32 * kb + 8 * g);
-    // ---- three hidden layers
+                xs + (w * 16 * NT + 16 * t + j) * XROW + 32 * kb + 8 * g);
+    // ---- three hidden layers and the output layer, one weight stream
     f32x4 acc[16][NT];
-    dense_layer<MLP_KPAD / 32, 16, NT>(a.W[0], lds, j, g, bin, acc);
-    silu_repack<NT>(a.b[0], g, acc, bin);
-    dense_layer<MLP_HID / 32, 16, NT>(a.W[1], lds, j, g, bin, acc);
-    silu_repack<NT>(a.b[1], g, acc, bin);
-    dense_layer<MLP_HID / 32, 16, NT>(a.W[2], lds, j, g, bin, acc);
-    silu_repack<NT>(a.b[2], g, acc, bin);
-    // ---- output layer: 2 row tiles (32 padded outputs)
-    dense_layer<MLP_HID / 32, 2, NT>(a.W[3], lds, j, g, bin, acc);
+    weight_stream(a, ring, bias, w, lane, j, g, swz, bin, acc,
+                  std::make_integer_sequence<int, N_CHUNKS>{});
+    // ---- output: lane (j, g) holds components 4 g + r (and 16 + 4 g + r) of
+    // cell 16 t + j; the start states are loaded before any is used
     const double *ym = a.stats + 2 * MLP_FEAT, *ysd = a.stats + 2 * MLP_FEAT + 2 * MLP_NC;
+    double y0[NT][2][4], mean[2][4], sd[2][4];
+    float bo[2][4];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+            const int c = min(16 * mi + 4 * g + r4, MLP_NC - 1);
+            mean[mi][r4] = ym[c];
+            sd[mi][r4] = ysd[c];
+            bo[mi][r4] = a.b[3][c];
+        }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const long long cell = min(base + 16 * t + j, (long long)a.n_cells - 1);
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int c = min(16 * mi + 4 * g + r4, MLP_NC - 1);
+                y0[t][mi][r4] = a.yin[c * a.ld + cell];
+            }
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const long long cell = base + 16 * t + j;
@@ -530,11 +643,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int c = 16 * mi + 4 * g + r;
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int c = 16 * mi + 4 * g + r4;
                 if (c >= MLP_NC) continue;
-                const double d = ym[c] + ysd[c] * (double)(acc[mi][t][r] + a.b[3][c]);
-                a.yout[c * a.ld + cell] = apply_target(c, a.yin[c * a.ld + cell], d);
+                const double d = mean[mi][r4] + sd[mi][r4] * (double)(acc[mi][t][r4] + bo[mi][r4]);
+                a.yout[c * a.ld + cell] = apply_target(c, y0[t][mi][r4], d);
             }
     }
 }
