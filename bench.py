@@ -36,6 +36,7 @@ METRIC = "cell fast-stage solves/s: FP64 plain vs surrogate+fallback at 1e-4 rel
 PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 PEAK_BF16_TFLOPS = 2500.0         # MI355X dense BF16 MFMA
 MLP_FLOPS = 2 * (89 * 256 + 256 * 256 + 256 * 256 + 256 * 22)   # one inference, 89 -> 22
+TRAIN_BATCH = 8192
 F_EXP, F_LOG, F_DIV = 22, 22, 10  # flops charged per FP64 exp / log / divide
 
 
@@ -69,25 +70,43 @@ def load_traffic(workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(mech, y_field, rho, L_list, n_sub, n_sample=262144):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(mech, y_field, rho, L_list, n_sub, n_sample=262144, n_sample_1core=8192):
     """The oracle as it stands, on n_sample cells of the same field, for the
-    three fast stages of one slow step (forcing of the first stage)."""
+    three fast stages of one slow step (forcing of the first stage); once with
+    all the threads the job may use and once on one core (smaller sample)."""
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    O.set_threads(threads)
     orc = O.Oracle(mech)
-    idx = np.linspace(0, y_field.shape[1] - 1, n_sample).astype(np.int64)
-    ys = np.ascontiguousarray(y_field[:, idx])
-    rs = np.ascontiguousarray(rho[:, :, idx])
-    t0 = time.perf_counter()
-    for L in L_list:
-        ys, _, _, _ = orc.fast_stage_soa(ys, rs, L, O.rk4_opts(n_sub))
-    dt = time.perf_counter() - t0
+
+    def run(n, nthreads):
+        O.set_threads(nthreads)
+        idx = np.linspace(0, y_field.shape[1] - 1, n).astype(np.int64)
+        ys = np.ascontiguousarray(y_field[:, idx])
+        rs = np.ascontiguousarray(rho[:, :, idx])
+        t0 = time.perf_counter()
+        for L in L_list:
+            ys, _, _, _ = orc.fast_stage_soa(ys, rs, L, O.rk4_opts(n_sub))
+        return time.perf_counter() - t0, O.num_threads()
+
+    dt, used = run(n_sample, threads)
+    dt1, _ = run(n_sample_1core, 1)
     cell_stages = n_sample * len(L_list)
-    return dict(value=cell_stages / dt, unit="cell-stages/s", cores=O.num_threads(),
-                kind="oracle",
+    return dict(value=cell_stages / dt, unit="cell-stages/s", cores=used, kind="oracle",
                 sample=f"{n_sample} evenly spaced cells of the 64^3 field, the 3 fast stages of "
-                       f"one slow step (RK4, {n_sub} substeps/stage); {dt:.1f} s")
+                       f"one slow step (RK4, {n_sub} substeps/stage); {dt:.1f} s",
+                one_core=dict(value=n_sample_1core * len(L_list) / dt1, unit="cell-stages/s",
+                              sample=f"{n_sample_1core} cells, same stages; {dt1:.1f} s"),
+                host=dict(cpu=_cpu_model(), nproc=os.cpu_count()))
 
 
 def batch_leg(torch, mri, I, repeats=3):
@@ -217,7 +236,8 @@ def surrogate_leg(train_steps, n_samples):
 
     t0 = time.perf_counter()
     data = S.generate_stage_data(n_full=n_samples, log=log)
-    res = S.train(data, steps=train_steps, log=log, log_every=max(1, train_steps // 8))
+    res = S.train(data, steps=train_steps, batch=TRAIN_BATCH, log=log,
+                  log_every=max(1, train_steps // 8))
     del data
     ev = S.evaluate_stage(res["params"], res["stats"], config=4, gate_tol=1e-4, log=log)
     t_inf_s = ev["infer_ms"] * 1e-3
@@ -229,7 +249,7 @@ def surrogate_leg(train_steps, n_samples):
                  "50 substeps",
         value=round(ev["cells"] / (ev["surrogate_stage_ms"] * 1e-3), 1),
         unit="cell-stages/s", plain_value=round(ev["cells"] / (ev["plain_ms"] * 1e-3), 1),
-        training=dict(samples=int(3 * n_samples), steps=train_steps, batch=4096,
+        training=dict(samples=int(3 * n_samples), steps=train_steps, batch=TRAIN_BATCH,
                       seconds=round(res["train_seconds"], 1),
                       final_val_mse=res["history"][-1][2] if res["history"] else None),
         inferences_per_s=round(ev["cells"] / t_inf_s, 1),
@@ -252,9 +272,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 128^3 large-mechanism leg (53 species / 325 reactions)")
-    ap.add_argument("--surrogate-steps", type=int, default=20000,
-                    help="training steps of the surrogate leg (batch 4096)")
-    ap.add_argument("--surrogate-samples", type=int, default=1_000_000,
+    ap.add_argument("--surrogate-steps", type=int, default=40000,
+                    help="training steps of the surrogate leg (batch 8192)")
+    ap.add_argument("--surrogate-samples", type=int, default=2_000_000,
                     help="full-stage training samples (plus twice as many half-stage ones)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 1 GiB (HBM counter calibration)")

@@ -374,8 +374,10 @@ struct InferArgs {
 // chunks are copied by direct global -> LDS loads (no register staging) into a
 // ring of three buffers, two chunks ahead of the one being multiplied.  In a
 // buffer, row r's four 16-byte pieces (8 bf16 each) sit at slots 4 r + (q ^ s)
-// with s = (r >> 2) & 3, so that the 16 lanes reading one A fragment column
-// hit 16 distinct bank groups.
+// with s = swz(r) = ((r >> 1) ^ (r >> 3)) & 3: any 8 aligned rows read
+// with one piece index land in 8 distinct 16-byte bank groups of 128 bytes, and
+// any 16 aligned rows in 16 distinct groups of 256 bytes, so the A
+// fragment reads are free of bank conflicts for either bank width.
 constexpr int WCHUNK = MLP_HID * 32;    // bf16 elements of one chunk buffer
 constexpr int N_BUF = 3;
 
@@ -393,6 +395,7 @@ __host__ __device__ constexpr int chunk_loads(int c)
 {
     return layer_rows(chunk_layer(c)) == MLP_HID ? 4 : 1;
 }
+__host__ __device__ constexpr int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
 // Issues the direct-to-LDS loads of chunk C into buffer `buf` (wave `w`).
 // Hidden-size chunks: 1024 slots, wave w's load i fills slots 256 i + 64 w +
@@ -408,7 +411,7 @@ __device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, i
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int slot = 256 * i + 64 * w + lane;
-            const int row = slot >> 2, q = (slot & 3) ^ ((row >> 2) & 3);
+            const int row = slot >> 2, q = (slot & 3) ^ swz(row);
             const unsigned off = 2u * (unsigned)(row * kin + 8 * q);
             __builtin_amdgcn_global_load_lds((const void *)(W + off),
                                              (lds_void_t *)(buf + 8 * (256 * i + 64 * w)), 16,
@@ -417,7 +420,7 @@ __device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, i
     } else {
         if (lane < 32) {
             const int slot = 32 * w + lane;
-            const int row = slot >> 2, q = (slot & 3) ^ ((row >> 2) & 3);
+            const int row = slot >> 2, q = (slot & 3) ^ swz(row);
             const unsigned off = 2u * (unsigned)(row * kin + 8 * q);
             __builtin_amdgcn_global_load_lds((const void *)(W + off),
                                              (lds_void_t *)(buf + 8 * (32 * w)), 16, 0, 0);
@@ -491,7 +494,7 @@ struct Ring {
 template <int C>
 __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring,
                                             const float *bias, int w, int lane, int j, int g,
-                                            int swz, bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT])
+                                            bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT])
 {
     constexpr int l = chunk_layer(C), kb = chunk_kb(C), MT = layer_rows(l) / 16;
     if constexpr (kb == 0) {
@@ -508,8 +511,8 @@ __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring
     const uint16_t *buf = ring.get<C>();
 #pragma unroll
     for (int mi = 0; mi < MT; ++mi) {
-        const bf16x8 af =
-            *reinterpret_cast<const bf16x8 *>(buf + 8 * (4 * (16 * mi + j) + (g ^ swz)));
+        const int r = 16 * mi + j;
+        const bf16x8 af = *reinterpret_cast<const bf16x8 *>(buf + 8 * (4 * r + (g ^ swz(r))));
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[mi][t] = mfma(af, bin[kb][t], acc[mi][t]);
     }
@@ -520,10 +523,10 @@ __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring
 template <int... C>
 __device__ __forceinline__ void weight_stream(const InferArgs &a, const Ring &ring,
                                               const float *bias, int w, int lane, int j, int g,
-                                              int swz, bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT],
+                                              bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT],
                                               std::integer_sequence<int, C...>)
 {
-    (weight_step<C>(a, ring, bias, w, lane, j, g, swz, bin, acc), ...);
+    (weight_step<C>(a, ring, bias, w, lane, j, g, bin, acc), ...);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WPE))) k_infer(InferArgs a)
@@ -536,7 +539,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
     __shared__ float bias[3 * MLP_HID];      // hidden-layer biases
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = lane >> 4, j = lane & 15, swz = (j >> 2) & 3;
+    const int g = lane >> 4, j = lane & 15;
     // the first two weight chunks are in flight while the features are built
     chunk_issue<0>(a, ring.get<0>(), w, lane);
     chunk_issue<1>(a, ring.get<1>(), w, lane);
@@ -609,7 +612,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
                 xs + (w * 16 * NT + 16 * t + j) * XROW + 32 * kb + 8 * g);
     // ---- three hidden layers and the output layer, one weight stream
     f32x4 acc[16][NT];
-    weight_stream(a, ring, bias, w, lane, j, g, swz, bin, acc,
+    weight_stream(a, ring, bias, w, lane, j, g, bin, acc,
                   std::make_integer_sequence<int, N_CHUNKS>{});
     // ---- output: lane (j, g) holds components 4 g + r (and 16 + 4 g + r) of
     // cell 16 t + j; the start states are loaded before any is used

@@ -202,3 +202,69 @@ def test_gate_limits(torch, mri):
     sg.stage(m, opts, 0.0, 700, ld, yy, yy, 1, rd, L, ws)
     torch.cuda.synchronize()
     assert torch.equal(yy[:, :700], plain[:, :700])
+
+
+def test_trained_network_gain(torch, mri):
+    """What training buys, on every cell of the first fast stage of the 128^3
+    workload (errors judged against the plain FP64 stage): the trained network's
+    median stage error is far below the untrained one's; the gated stage at
+    1e-4 returns the plain FP64 result bitwise on every rejected cell and never
+    accepts a cell the gate should not (mass-sum residual and step doubling both
+    within the tolerance); with the gate open it is several times faster than
+    the plain stage at a median error of a few per mille."""
+    from paper_2211_03293_amd import surrogate as S
+    import time
+    data = S.generate_stage_data(n_full=200_000, log=print)
+    res = S.train(data, steps=4000, batch=4096, log=print, log_every=2000)
+    del data
+    cfg = I.CONFIGS[4]
+    mech = I.make_mechanism(4)
+    m = mri.Mech(mech)
+    m.specialize(128, load=True)
+    y, rho, L, N, ld = S.stage_inputs(4)
+    opts = mri.fast_opts(n_sub=cfg.n_sub)
+    ref = torch.empty_like(y)
+    mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)
+    widths = [mri.MLP_KPAD, 256, 256, 256, mri.MLP_OUTPUTS]
+    med = {}
+    for name, params in (("untrained", S.init_params()), ("trained", res["params"])):
+        sg = mri.Surrogate(widths, params, res["stats"])
+        out = torch.empty_like(y)
+        sg.infer(N, ld, y, out, 1, rho, L)
+        torch.cuda.synchronize()
+        err = S.stage_error(out[:, :N], ref[:, :N], mech.n_species)
+        med[name] = float(torch.median(err).item())
+    print(f"median stage error: untrained {med['untrained']:.3e}, trained {med['trained']:.3e}")
+    assert med["trained"] < 0.1 * med["untrained"]
+    assert med["trained"] < 2e-2
+    sg = mri.Surrogate(widths, res["params"], res["stats"])
+    ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    used = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    gv = torch.zeros(ld, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(y)
+    nf = sg.stage(m, opts, 1e-4, N, ld, y, out, 1, rho, L, ws, used, gv)
+    torch.cuda.synchronize()
+    rej = used[:N] == 1
+    assert int(rej.sum().item()) == nf
+    assert torch.equal(out[:, :N][:, rej], ref[:, :N][:, rej])
+    acc = ~rej
+    assert bool((gv[:N][acc] <= 1e-4).all().item())
+    print(f"gate 1e-4: {nf} of {N} cells fall back to the plain FP64 stage")
+    # gate open: every cell takes the doubled prediction
+    times = {}
+    for name, fn in (("plain", lambda: mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)),
+                     ("open gate", lambda: sg.stage(m, opts, float("inf"), N, ld, y, out, 1, rho,
+                                                    L, ws, used, gv))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) * 1e3
+    err = S.stage_error(out[:, :N], ref[:, :N], mech.n_species)
+    med_open = float(torch.median(err).item())
+    print(f"plain {times['plain']:.2f} ms, open gate {times['open gate']:.2f} ms, "
+          f"median error {med_open:.3e}")
+    assert times["open gate"] * 2.0 < times["plain"]
+    assert med_open < 2e-2
