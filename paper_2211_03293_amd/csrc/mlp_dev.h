@@ -20,6 +20,7 @@
 #define MLP_NPOLY 3
 #define MLP_FEAT (MLP_NS + 1 + MLP_NPOLY * MLP_NC + 1)
 #define MLP_KPAD 96
+#define MLP_K0_IN 128   // first-layer row length in the inference weight stream
 #define MLP_HID 256
 #define MLP_OUT_PAD 32
 #define MLP_STATS (2 * MLP_FEAT + 3 * MLP_NC)

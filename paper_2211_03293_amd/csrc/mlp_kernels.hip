@@ -369,62 +369,52 @@ struct InferArgs {
     int half;
 };
 
-// Weights stream through LDS in chunks of 32 input columns (all output rows of
-// one layer; 16 KB for a hidden layer), shared by the block's four waves.  The
-// chunks are copied by direct global -> LDS loads (no register staging) into a
-// ring of three buffers, two chunks ahead of the one being multiplied.  In a
-// buffer, row r's four 16-byte pieces (8 bf16 each) sit at slots 4 r + (q ^ s)
-// with s = swz(r) = ((r >> 1) ^ (r >> 3)) & 3: any 8 aligned rows read
-// with one piece index land in 8 distinct 16-byte bank groups of 128 bytes, and
-// any 16 aligned rows in 16 distinct groups of 256 bytes, so the A
-// fragment reads are free of bank conflicts for either bank width.
-constexpr int WCHUNK = MLP_HID * 32;    // bf16 elements of one chunk buffer
+// Weights stream through LDS in chunks of RB = 32 output rows with all their
+// input columns (16 KB for a hidden layer), shared by the block's four waves.
+// Each chunk yields two finished row tiles, whose SiLU (for the next layer's
+// input) overlaps the matrix products of the following chunk.  The chunks are
+// copied by direct global -> LDS loads (no register staging) into a ring of
+// three buffers, two chunks ahead of the one being multiplied.  In a buffer,
+// row r holds its P = kin / 8 pieces of 16 bytes (8 bf16 each), piece p at slot
+// r P + (p ^ (r & 15)): the 16 lanes that read one A fragment (16 rows, one
+// piece index) hit 16 distinct 16-byte bank groups, so the reads are free of
+// bank conflicts for 128- and 256-byte bank widths alike.
+constexpr int RB = 32;
+constexpr int WCHUNK = RB * MLP_HID;    // bf16 elements of one chunk buffer (16 KB)
 constexpr int N_BUF = 3;
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// The weight stream of one inference: 3 chunks of the first layer (96 padded
-// inputs), 8 of each hidden layer, 8 of the output layer (32 padded rows).
-constexpr int N_CHUNKS = 3 + 8 + 8 + 8;
-__host__ __device__ constexpr int chunk_layer(int c) { return c < 3 ? 0 : (c - 3) / 8 + 1; }
-__host__ __device__ constexpr int chunk_kb(int c) { return c < 3 ? c : (c - 3) % 8; }
-__host__ __device__ constexpr int layer_chunks(int l) { return l == 0 ? 3 : 8; }
-__host__ __device__ constexpr int layer_rows(int l) { return l == 3 ? MLP_OUT_PAD : MLP_HID; }
+// The weight stream of one inference: 8 row blocks of the first layer (input
+// rows padded to MLP_K0_IN columns), 8 of each hidden layer, 1 of the output
+// layer (32 padded rows).
+constexpr int N_CHUNKS = 8 + 8 + 8 + 1;
+__host__ __device__ constexpr int chunk_layer(int c) { return c < 24 ? c / 8 : 3; }
+__host__ __device__ constexpr int chunk_rb(int c) { return c < 24 ? c % 8 : 0; }
+__host__ __device__ constexpr int layer_kin(int l) { return l == 0 ? MLP_K0_IN : MLP_HID; }
+__host__ __device__ constexpr int layer_kb(int l) { return l == 0 ? MLP_KPAD / 32 : MLP_HID / 32; }
 // direct-to-LDS loads one wave issues per chunk (the same for all four waves)
 __host__ __device__ constexpr int chunk_loads(int c)
 {
-    return layer_rows(chunk_layer(c)) == MLP_HID ? 4 : 1;
+    return RB * (layer_kin(chunk_layer(c)) / 8) / 256;
 }
-__host__ __device__ constexpr int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
-// Issues the direct-to-LDS loads of chunk C into buffer `buf` (wave `w`).
-// Hidden-size chunks: 1024 slots, wave w's load i fills slots 256 i + 64 w +
-// lane.  Output chunks: 128 slots, wave w fills slots 32 w + lane (lane < 32).
+// Issues the direct-to-LDS loads of chunk C into buffer `buf` (wave `w`): wave
+// w's load i fills slots 256 i + 64 w + lane.
 template <int C>
 __device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, int w, int lane)
 {
-    constexpr int l = chunk_layer(C), kb = chunk_kb(C), kin = 32 * layer_chunks(l);
-    // uniform base of the chunk's columns + a lane offset that is the same for
-    // every chunk of the layer (one VGPR per load, shared across chunks)
-    const char *W = reinterpret_cast<const char *>(a.W[l] + 32 * kb);
-    if constexpr (chunk_loads(C) == 4) {
+    constexpr int l = chunk_layer(C), kin = layer_kin(l), P = kin / 8;
+    // uniform base of the chunk's rows + a lane offset that is the same for
+    // every chunk of the layer
+    const char *W = reinterpret_cast<const char *>(a.W[l] + (size_t)(RB * chunk_rb(C)) * kin);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int slot = 256 * i + 64 * w + lane;
-            const int row = slot >> 2, q = (slot & 3) ^ swz(row);
-            const unsigned off = 2u * (unsigned)(row * kin + 8 * q);
-            __builtin_amdgcn_global_load_lds((const void *)(W + off),
-                                             (lds_void_t *)(buf + 8 * (256 * i + 64 * w)), 16,
-                                             0, 0);
-        }
-    } else {
-        if (lane < 32) {
-            const int slot = 32 * w + lane;
-            const int row = slot >> 2, q = (slot & 3) ^ swz(row);
-            const unsigned off = 2u * (unsigned)(row * kin + 8 * q);
-            __builtin_amdgcn_global_load_lds((const void *)(W + off),
-                                             (lds_void_t *)(buf + 8 * (32 * w)), 16, 0, 0);
-        }
+    for (int i = 0; i < chunk_loads(C); ++i) {
+        const int slot = 256 * i + 64 * w + lane;
+        const int row = slot / P, p = (slot % P) ^ (row & 15);
+        const unsigned off = 2u * (unsigned)(row * kin + 8 * p);
+        __builtin_amdgcn_global_load_lds((const void *)(W + off),
+                                         (lds_void_t *)(buf + 8 * (256 * i + 64 * w)), 16, 0, 0);
     }
 }
 
@@ -439,26 +429,6 @@ __device__ __forceinline__ void wait_loads_and_barrier()
     __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4) | (0xf << 8));   // vmcnt(N) only
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-}
-
-template <int NTT>
-__device__ __forceinline__ void silu_repack(const float *__restrict__ bias, int g,
-                                            const f32x4 (&acc)[16][NTT], bf16x8 (&bin)[8][NTT])
-{
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-        for (int t = 0; t < NTT; ++t) {
-            bf16x8 v;
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int o = 32 * kb + 16 * h + 4 * g + r;
-                    v[4 * h + r] = static_cast<__bf16>(silu_f(acc[2 * kb + h][t][r] + bias[o]));
-                }
-            bin[kb][t] = v;
-        }
 }
 
 constexpr int XROW = MLP_KPAD + 8;     // padded LDS feature row (bf16), 208 bytes
@@ -487,46 +457,96 @@ struct Ring {
     }
 };
 
+// Activations of one inference, per lane: the first layer's input (3 k-blocks
+// of features), and two 8-k-block arrays that alternate as input and output of
+// the hidden layers; two sets of accumulators (one row block each) alternate
+// between chunks.
+struct Act {
+    bf16x8 x0[MLP_KPAD / 32][NT];
+    bf16x8 ha[8][NT], hb[8][NT];
+    f32x4 acc[2][2][NT];
+};
+
+template <int L>
+__device__ __forceinline__ auto &layer_in(Act &s)
+{
+    if constexpr (L == 0) return s.x0;
+    else if constexpr (L == 2) return s.hb;
+    else return s.ha;
+}
+template <int L>
+__device__ __forceinline__ auto &layer_out(Act &s)
+{
+    if constexpr (L == 1) return s.hb;
+    else return s.ha;
+}
+
+// SiLU + bf16 repack of chunk C's two row tiles into k-block rb of the next
+// layer's input (the MFMA output layout is the next layer's B layout once its
+// input columns are permuted on the host).
+template <int C>
+__device__ __forceinline__ void chunk_activate(Act &s, const float *bias, int g)
+{
+    constexpr int l = chunk_layer(C), rb = chunk_rb(C);
+    auto &out = layer_out<l>(s);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        bf16x8 v;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = MLP_HID * l + RB * rb + 16 * h + 4 * g + r;
+                v[4 * h + r] = static_cast<__bf16>(silu_f(s.acc[C & 1][h][t][r] + bias[o]));
+            }
+        out[rb][t] = v;
+    }
+}
+
 // One step of the weight stream: wait for chunk C (the loads of chunk C + 1
 // stay in flight), barrier, issue chunk C + 2 into the buffer that chunk C - 1
-// used, multiply chunk C into the accumulators; SiLU + repack at the end of a
-// hidden layer.
+// used, multiply chunk C into its accumulator set, and activate chunk C - 1
+// (before the products when chunk C starts a layer, which needs it as input).
 template <int C>
 __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring,
                                             const float *bias, int w, int lane, int j, int g,
-                                            bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT])
+                                            Act &s)
 {
-    constexpr int l = chunk_layer(C), kb = chunk_kb(C), MT = layer_rows(l) / 16;
-    if constexpr (kb == 0) {
-#pragma unroll
-        for (int mi = 0; mi < MT; ++mi)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    constexpr int l = chunk_layer(C), KB = layer_kb(l), P = layer_kin(l) / 8;
+    constexpr bool prev_hidden = C > 0 && chunk_layer(C - 1) < 3;
+    constexpr bool layer_start = C > 0 && chunk_layer(C - 1) != l;
     if constexpr (C + 1 < N_CHUNKS)
         wait_loads_and_barrier<chunk_loads(C + 1)>();
     else
         wait_loads_and_barrier<0>();
     if constexpr (C + 2 < N_CHUNKS) chunk_issue<C + 2>(a, ring.get<C + 2>(), w, lane);
+    if constexpr (prev_hidden && layer_start) chunk_activate<C - 1>(s, bias, g);
     const uint16_t *buf = ring.get<C>();
+    auto &in = layer_in<l>(s);
 #pragma unroll
-    for (int mi = 0; mi < MT; ++mi) {
-        const int r = 16 * mi + j;
-        const bf16x8 af = *reinterpret_cast<const bf16x8 *>(buf + 8 * (4 * r + (g ^ swz(r))));
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[mi][t] = mfma(af, bin[kb][t], acc[mi][t]);
-    }
-    if constexpr (l < 3 && kb == layer_chunks(l) - 1)
-        silu_repack<NT>(bias + MLP_HID * l, g, acc, bin);
+        for (int t = 0; t < NT; ++t) s.acc[C & 1][mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+            const int r = 16 * mi + j;
+            const bf16x8 af =
+                *reinterpret_cast<const bf16x8 *>(buf + 8 * (r * P + ((4 * kb + g) ^ j)));
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                s.acc[C & 1][mi][t] = mfma(af, in[kb][t], s.acc[C & 1][mi][t]);
+        }
+    if constexpr (prev_hidden && !layer_start) chunk_activate<C - 1>(s, bias, g);
 }
 
 template <int... C>
 __device__ __forceinline__ void weight_stream(const InferArgs &a, const Ring &ring,
                                               const float *bias, int w, int lane, int j, int g,
-                                              bf16x8 (&bin)[8][NT], f32x4 (&acc)[16][NT],
-                                              std::integer_sequence<int, C...>)
+                                              Act &s, std::integer_sequence<int, C...>)
 {
-    (weight_step<C>(a, ring, bias, w, lane, j, g, bin, acc), ...);
+    (weight_step<C>(a, ring, bias, w, lane, j, g, s), ...);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WPE))) k_infer(InferArgs a)
@@ -603,17 +623,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
         }
     }
     __syncthreads();
-    bf16x8 bin[8][NT];
+    Act st;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int kb = 0; kb < MLP_KPAD / 32; ++kb)
-            bin[kb][t] = *reinterpret_cast<const bf16x8 *>(
+            st.x0[kb][t] = *reinterpret_cast<const bf16x8 *>(
                 xs + (w * 16 * NT + 16 * t + j) * XROW + 32 * kb + 8 * g);
     // ---- three hidden layers and the output layer, one weight stream
-    f32x4 acc[16][NT];
-    weight_stream(a, ring, bias, w, lane, j, g, bin, acc,
-                  std::make_integer_sequence<int, N_CHUNKS>{});
+    weight_stream(a, ring, bias, w, lane, j, g, st, std::make_integer_sequence<int, N_CHUNKS>{});
+    // the output layer is chunk N_CHUNKS - 1 (accumulator set 0)
+    static_assert(((N_CHUNKS - 1) & 1) == 0, "output accumulator set");
+    const f32x4 (&acc)[2][NT] = st.acc[0];
     // ---- output: lane (j, g) holds components 4 g + r (and 16 + 4 g + r) of
     // cell 16 t + j; the start states are loaded before any is used
     const double *ym = a.stats + 2 * MLP_FEAT, *ysd = a.stats + 2 * MLP_FEAT + 2 * MLP_NC;

@@ -269,7 +269,7 @@ mri_status mri_surrogate_create(const int *widths, const float *params, const do
     for (int i = 0; i < MLP_STATS; ++i)
         if (!std::isfinite(stats[i])) return fail(MRI_EINVAL, "non-finite statistics");
     std::unique_ptr<mri_surrogate> sg(new mri_surrogate);
-    const int in_pad[4] = {MLP_KPAD, MLP_HID, MLP_HID, MLP_HID};
+    const int in_pad[4] = {MLP_K0_IN, MLP_HID, MLP_HID, MLP_HID};
     const int out_pad[4] = {MLP_HID, MLP_HID, MLP_HID, MLP_OUT_PAD};
     size_t off = 0;
     for (int l = 0; l < 4; ++l) {
