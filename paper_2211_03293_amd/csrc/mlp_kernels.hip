@@ -419,16 +419,21 @@ __device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, i
 }
 
 // Waits until at most N of this wave's vector-memory loads are outstanding
-// (loads complete in issue order), then joins the block barrier.  The empty
-// asm statements keep the compiler from moving LDS accesses across it.
+// (loads complete in issue order) and all of its LDS reads have returned (the
+// buffer they read is refilled after this barrier), then joins the block
+// barrier.  Returns a zero that the compiler cannot see through, produced
+// after the barrier: LDS reads and direct-to-LDS loads whose addresses add it
+// cannot be scheduled before the barrier.
 template <int N>
-__device__ __forceinline__ void wait_loads_and_barrier()
+__device__ __forceinline__ int wait_loads_and_barrier()
 {
     static_assert(N >= 0 && N <= 15, "vmcnt field");
     asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4) | (0xf << 8));   // vmcnt(N) only
+    __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4));   // vmcnt(N), lgkmcnt(0)
     __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
+    int z = 0;
+    asm volatile("" : "+v"(z)::"memory");
+    return z;
 }
 
 constexpr int XROW = MLP_KPAD + 8;     // padded LDS feature row (bf16), 208 bytes
@@ -515,11 +520,8 @@ __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring
     constexpr int l = chunk_layer(C), KB = layer_kb(l), P = layer_kin(l) / 8;
     constexpr bool prev_hidden = C > 0 && chunk_layer(C - 1) < 3;
     constexpr bool layer_start = C > 0 && chunk_layer(C - 1) != l;
-    if constexpr (C + 1 < N_CHUNKS)
-        wait_loads_and_barrier<chunk_loads(C + 1)>();
-    else
-        wait_loads_and_barrier<0>();
-    if constexpr (C + 2 < N_CHUNKS) chunk_issue<C + 2>(a, ring.get<C + 2>(), w, lane);
+    const int z = wait_loads_and_barrier < C + 1 < N_CHUNKS ? chunk_loads(C + 1) : 0 > ();
+    if constexpr (C + 2 < N_CHUNKS) chunk_issue<C + 2>(a, ring.get<C + 2>(), w, lane + z);
     if constexpr (prev_hidden && layer_start) chunk_activate<C - 1>(s, bias, g);
     const uint16_t *buf = ring.get<C>();
     auto &in = layer_in<l>(s);
@@ -527,17 +529,27 @@ __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int t = 0; t < NT; ++t) s.acc[C & 1][mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // All A fragments of the chunk are requested before the first product, so
+    // the products start as soon as the first fragments arrive (LDS returns
+    // in order).  The buffer is written only by direct-to-LDS loads, which the
+    // compiler does not see as stores to it, so it would be free to move these
+    // reads above the barrier that orders them after the other waves' loads of
+    // the chunk: their addresses depend on `z`, which the barrier produces.
+    bf16x8 af[KB][2];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-            const int r = 16 * mi + j;
-            const bf16x8 af =
-                *reinterpret_cast<const bf16x8 *>(buf + 8 * (r * P + ((4 * kb + g) ^ j)));
+        for (int mi = 0; mi < 2; ++mi)
+            af[kb][mi] = *reinterpret_cast<const bf16x8 *>(
+                buf + 8 * ((16 * mi + j) * P + ((4 * kb + g) ^ j)) + z);
+    __builtin_amdgcn_sched_barrier(0);       // keep every read ahead of the products
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                s.acc[C & 1][mi][t] = mfma(af, in[kb][t], s.acc[C & 1][mi][t]);
-        }
+                s.acc[C & 1][mi][t] = mfma(af[kb][mi], in[kb][t], s.acc[C & 1][mi][t]);
     if constexpr (prev_hidden && !layer_start) chunk_activate<C - 1>(s, bias, g);
 }
 
