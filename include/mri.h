@@ -115,6 +115,10 @@ int mri_mech_state_width(const mri_mech *m);
    the current device.  Returns MRI_ECOMPILE with the compiler log in
    mri_last_error() on failure. */
 mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *code_bytes);
+/* The same for the kernel of one fast method (MRI_FAST_*) with n_poly forcing
+   terms (0..4); mri_mech_specialize is the RK4 kernel with one term. */
+mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int block_size,
+                                      int load, size_t *code_bytes);
 
 /* ------------------------------------------------------------------------- */
 /* MRI-GARK coupling table (Sec. 2.1; MIS and MRI-GARK families of Sec. 2.1).  */
@@ -137,7 +141,14 @@ void mri_table_destroy(mri_table *t);
 /* ------------------------------------------------------------------------- */
 /* Fast-stage options.                                                        */
 /* ------------------------------------------------------------------------- */
-enum { MRI_FAST_RK4 = 0, MRI_FAST_ZONNEVELD43 = 1 };
+/* Fast methods (Sec. 3.2 pairs the slow MRI method with fast explicit RK
+   methods of orders 2 to 5, the MRI-P(k) family of Sec. 5.1):
+     MRI_FAST_RK4          classic RK4, n_sub uniform substeps per stage
+     MRI_FAST_ZONNEVELD43  Zonneveld 4(3), adaptive (tolerances below)
+     MRI_FAST_HEUN         Heun's 2nd-order method, n_sub uniform substeps
+     MRI_FAST_BS3          Bogacki-Shampine 3rd-order solution, n_sub uniform
+                           substeps (the embedded estimate is not used)    */
+enum { MRI_FAST_RK4 = 0, MRI_FAST_ZONNEVELD43 = 1, MRI_FAST_HEUN = 2, MRI_FAST_BS3 = 3 };
 enum {
     MRI_KERNEL_AUTO = 0,        /* specialized if available, else generic       */
     MRI_KERNEL_GENERIC = 1,     /* one binary for every mechanism; coefficients  */
@@ -147,8 +158,8 @@ enum {
 };
 
 typedef struct {
-    int method;                 /* MRI_FAST_RK4 | MRI_FAST_ZONNEVELD43            */
-    int n_sub;                  /* RK4: uniform substeps per stage, >= 1          */
+    int method;                 /* MRI_FAST_*                                     */
+    int n_sub;                  /* fixed-step methods: substeps per stage, >= 1   */
     double rtol, atol_Y, atol_T;/* Zonneveld: WRMS weights 1/(atol + rtol |y|)    */
     int max_steps;              /* Zonneveld: accepted-step cap per cell-stage    */
     int kernel;                 /* MRI_KERNEL_*                                   */

@@ -15,6 +15,7 @@
  *     through K_c = exp(-dG/RT), species production, constant-volume energy)
  *   linear fast RHS (f^F = A v) for order tests
  *   classic RK4 over one fast stage with a polynomial forcing
+ *   a general explicit Runge-Kutta stage (Heun, Bogacki-Shampine tableaus)
  *   Zonneveld 4(3) adaptive integration over one fast stage
  *   the explicit MRI-GARK slow step (Sec. 2.1 algorithm, steps 1-3)
  *   the 2nd-order centred periodic advection-diffusion slow RHS (Sec. 3.1)
@@ -59,7 +60,9 @@ typedef struct {
 } ora_table;
 
 typedef struct {
-    int method;                          /* 0 = classic RK4, 1 = Zonneveld 4(3) */
+    int method;                          /* 0 = classic RK4, 1 = Zonneveld 4(3),
+                                            2 = Heun (2nd order), 3 = Bogacki-
+                                            Shampine (3rd order), fixed steps   */
     int n_sub;                           /* RK4 substeps per stage            */
     double rtol, atol_Y, atol_T;         /* Zonneveld tolerances              */
     int max_steps;                       /* Zonneveld accepted-step cap       */
@@ -237,6 +240,73 @@ int ora_rk4_stage(const ora_fast *f, const double *y_in, int n_poly, const doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* General explicit Runge-Kutta method over one fast stage: s stages,        */
+/* strictly lower-triangular A (row-major [s][s]), weights b, nodes c.  Each  */
+/* substep stores every stage derivative and forms                           */
+/*   Y_i = v + h sum_(j<i) a_ij k_j,  k_i = f(Y_i) + r((m + c_i)/n_sub),      */
+/*   v <- v + h sum_i b_i k_i.                                                */
+/* The fast methods of Sec. 3.2 of orders 2 and 3 (the MRI-P(k) family):      */
+/* Heun's method and the Bogacki-Shampine 3rd-order solution.                 */
+/* ------------------------------------------------------------------------ */
+static const double HEUN_A[4] = {0.0, 0.0, 1.0, 0.0};
+static const double HEUN_B[2] = {0.5, 0.5};
+static const double HEUN_C[2] = {0.0, 1.0};
+static const double BS3_A[9] = {0.0, 0.0, 0.0, 0.5, 0.0, 0.0, 0.0, 0.75, 0.0};
+static const double BS3_B[3] = {2.0 / 9.0, 1.0 / 3.0, 4.0 / 9.0};
+static const double BS3_C[3] = {0.0, 0.5, 0.75};
+
+/* The tableau of fixed-step method 2 (Heun) or 3 (Bogacki-Shampine); returns
+   the stage count (0 for other methods).  A is [s][s], b and c are [s]. */
+int ora_erk_tableau(int method, double *A, double *b, double *c)
+{
+    const double *a0, *b0, *c0;
+    int s;
+    if (method == 2) {
+        s = 2, a0 = HEUN_A, b0 = HEUN_B, c0 = HEUN_C;
+    } else if (method == 3) {
+        s = 3, a0 = BS3_A, b0 = BS3_B, c0 = BS3_C;
+    } else {
+        return 0;
+    }
+    if (A) memcpy(A, a0, sizeof(double) * s * s);
+    if (b) memcpy(b, b0, sizeof(double) * s);
+    if (c) memcpy(c, c0, sizeof(double) * s);
+    return s;
+}
+
+int ora_erk_stage(const ora_fast *f, const double *y_in, int n_poly, const double *rho,
+                  double L, int n_sub, int s, const double *A, const double *b, const double *c,
+                  double *y_out)
+{
+    const int n = f->n;
+    const double h = L / n_sub;
+    double *v = (double *)malloc(sizeof(double) * n * (s + 3));
+    double *k = v + n, *tmp = v + (size_t)(s + 1) * n, *r = v + (size_t)(s + 2) * n;
+    memcpy(v, y_in, sizeof(double) * n);
+    for (int m = 0; m < n_sub; ++m) {
+        for (int i = 0; i < s; ++i) {
+            for (int e = 0; e < n; ++e) {
+                double sum = 0.0;
+                for (int j = 0; j < i; ++j) sum += A[i * s + j] * k[(size_t)j * n + e];
+                tmp[e] = v[e] + h * sum;
+            }
+            ora_fast_rhs(f, tmp, k + (size_t)i * n);
+            forcing_eval(n, n_poly, rho, (m + c[i]) / n_sub, r);
+            for (int e = 0; e < n; ++e) k[(size_t)i * n + e] += r[e];
+        }
+        for (int e = 0; e < n; ++e) {
+            double sum = 0.0;
+            for (int i = 0; i < s; ++i) sum += b[i] * k[(size_t)i * n + e];
+            v[e] = v[e] + h * sum;
+        }
+    }
+    memcpy(y_out, v, sizeof(double) * n);
+    int st = check_state(f, v);
+    free(v);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Zonneveld 4(3) embedded pair (the 4th-order fast method of Sec. 3.2).     */
 /* Stages 1-4 are classic RK4; stage 5 sits at c = 3/4.  The propagated      */
 /* solution is the RK4 combination; the embedded 3rd-order combination gives */
@@ -388,6 +458,11 @@ void ora_fast_stage_soa(const ora_fast *f, const ora_fast_opts *o, int n_cells, 
             int32_t acc = 0, rej = 0;
             if (o->method == 0) {
                 st = ora_rk4_stage(f, v, n_poly, rho, L, o->n_sub, w);
+                acc = o->n_sub;
+            } else if (o->method == 2 || o->method == 3) {
+                double A[9], b[3], c[3];
+                const int s = ora_erk_tableau(o->method, A, b, c);
+                st = ora_erk_stage(f, v, n_poly, rho, L, o->n_sub, s, A, b, c, w);
                 acc = o->n_sub;
             } else {
                 st = ora_zonneveld_stage(f, v, n_poly, rho, L, o, w, &acc, &rej, NULL, 0);

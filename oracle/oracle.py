@@ -156,6 +156,16 @@ class Oracle:
                                   int(n_sub), _p(out))
         return out, st
 
+    def erk_stage(self, y, rho_poly, L, n_sub, A, b, c):
+        """Single cell, general explicit RK tableau (A [s][s], b [s], c [s])."""
+        y = _f64(y)
+        rho = _f64(np.atleast_2d(rho_poly))
+        A, b, c = _f64(A), _f64(b), _f64(c)
+        out = np.zeros(self.n)
+        st = self.L.ora_erk_stage(C.byref(self.f), _p(y), rho.shape[0], _p(rho), C.c_double(L),
+                                  int(n_sub), b.size, _p(A), _p(b), _p(c), _p(out))
+        return out, st
+
     def zonneveld_try(self, y, t, h, L, rho_poly, opts):
         y = _f64(y)
         rho = _f64(np.atleast_2d(rho_poly))
@@ -259,6 +269,20 @@ def rk4_opts(n_sub):
 
 def zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000):
     return FastOpts(1, 0, rtol, atol_Y, atol_T, max_steps)
+
+
+ERK_HEUN, ERK_BS3 = 2, 3
+
+
+def erk_opts(method, n_sub):
+    """Fixed-step Heun (method 2) or Bogacki-Shampine (method 3)."""
+    return FastOpts(int(method), int(n_sub), 0.0, 0.0, 0.0, 0)
+
+
+def erk_tableau(method):
+    A, b, c = np.zeros(9), np.zeros(3), np.zeros(3)
+    s = lib().ora_erk_tableau(int(method), _p(A), _p(b), _p(c))
+    return A[:s * s].reshape(s, s), b[:s], c[:s]
 
 
 def zonneveld_tableau():

@@ -115,9 +115,9 @@ __device__ __forceinline__ int gen_flags(const double (&Ys)[NMAX], double T, int
 
 template <int NMAX, int NP>
 __global__ void __launch_bounds__(256)
-    k_gen_rk4(GenMech gm, int n_cells, int ld, const double *__restrict__ yin, double *yout,
-              const double *__restrict__ rho, double L, int n_sub, int *status, int *steps,
-              int accumulate)
+    k_gen_rk4(GenMech gm, ErkCoef e, int n_cells, int ld, const double *__restrict__ yin,
+              double *yout, const double *__restrict__ rho, double L, int n_sub, int *status,
+              int *steps, int accumulate)
 {
     const LdsView m = stage_mechanism(gm);
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,10 +142,8 @@ __global__ void __launch_bounds__(256)
         accT = 0.0;
         YcT = y0T;
 #pragma unroll 1
-        for (int st = 0; st < 4; ++st) {
-            const double cn = (st == 0) ? 0.0 : ((st == 3) ? 1.0 : 0.5);
-            const double bw = (st == 0 || st == 3) ? (1.0 / 6.0) : (1.0 / 3.0);
-            const double ah = ((st == 2) ? 1.0 : 0.5) * h;
+        for (int st = 0; st < e.s; ++st) {
+            const double cn = e.c[st], bw = e.b[st], ah = e.a[st] * h;
             const double tau = (it + cn) * inv_nsub;
             const double Tdot = gen_rhs<NMAX>(m, S, R, gm.T_ref, YcT, lane);
 #pragma unroll
@@ -319,7 +317,7 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 template <int NP>
 __global__ void __launch_bounds__(256)
-    k_lin_rk4(int n, const double *__restrict__ A, int n_cells, int ld,
+    k_lin_rk4(int n, const double *__restrict__ A, ErkCoef e, int n_cells, int ld,
               const double *__restrict__ yin, double *yout, const double *__restrict__ rho,
               double L, int n_sub, int *status, int *steps, int accumulate)
 {
@@ -340,10 +338,8 @@ __global__ void __launch_bounds__(256)
                 Yc[c] = y0[c];
             }
 #pragma unroll 1
-        for (int st = 0; st < 4; ++st) {
-            const double cn = (st == 0) ? 0.0 : ((st == 3) ? 1.0 : 0.5);
-            const double bw = (st == 0 || st == 3) ? (1.0 / 6.0) : (1.0 / 3.0);
-            const double ah = ((st == 2) ? 1.0 : 0.5) * h;
+        for (int st = 0; st < e.s; ++st) {
+            const double cn = e.c[st], bw = e.b[st], ah = e.a[st] * h;
             const double tau = (it + cn) * inv_nsub;
 #pragma unroll
             for (int r = 0; r < NM; ++r)
@@ -401,17 +397,18 @@ size_t gen_lds_bytes(int S, int R, int block)
         break;                                                                             \
     }
 
-hipError_t launch_gen_rk4(const GenMech &gm, int block, int n_cells, int ld, const double *yin,
-                          double *yout, int n_poly, const double *rho, double L, int n_sub,
-                          int *status, int *steps, int accumulate, hipStream_t s)
+hipError_t launch_gen_rk4(const GenMech &gm, const ErkCoef &e, int block, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s)
 {
     const dim3 grid((n_cells + block - 1) / block);
     const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
     if (gm.S <= GEN_NMAX_SMALL) {
-        GEN_DISPATCH_NP(k_gen_rk4, GEN_NMAX_SMALL, gm, n_cells, ld, yin, yout, rho, L, n_sub,
+        GEN_DISPATCH_NP(k_gen_rk4, GEN_NMAX_SMALL, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
                         status, steps, accumulate)
     } else {
-        GEN_DISPATCH_NP(k_gen_rk4, GEN_NMAX_LARGE, gm, n_cells, ld, yin, yout, rho, L, n_sub,
+        GEN_DISPATCH_NP(k_gen_rk4, GEN_NMAX_LARGE, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
                         status, steps, accumulate)
     }
     return hipGetLastError();
@@ -433,31 +430,32 @@ hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, cons
     return hipGetLastError();
 }
 
-hipError_t launch_lin_rk4(int n, const double *A, int n_cells, int ld, const double *yin,
-                          double *yout, int n_poly, const double *rho, double L, int n_sub,
-                          int *status, int *steps, int accumulate, hipStream_t s)
+hipError_t launch_lin_rk4(int n, const double *A, const ErkCoef &e, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s)
 {
     const int block = 256;
     const dim3 grid((n_cells + block - 1) / block);
     switch (n_poly) {
     case 0:
-        hipLaunchKernelGGL(k_lin_rk4<0>, grid, dim3(block), 0, s, n, A, n_cells, ld, yin, yout,
+        hipLaunchKernelGGL(k_lin_rk4<0>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
                            rho, L, n_sub, status, steps, accumulate);
         break;
     case 1:
-        hipLaunchKernelGGL(k_lin_rk4<1>, grid, dim3(block), 0, s, n, A, n_cells, ld, yin, yout,
+        hipLaunchKernelGGL(k_lin_rk4<1>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
                            rho, L, n_sub, status, steps, accumulate);
         break;
     case 2:
-        hipLaunchKernelGGL(k_lin_rk4<2>, grid, dim3(block), 0, s, n, A, n_cells, ld, yin, yout,
+        hipLaunchKernelGGL(k_lin_rk4<2>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
                            rho, L, n_sub, status, steps, accumulate);
         break;
     case 3:
-        hipLaunchKernelGGL(k_lin_rk4<3>, grid, dim3(block), 0, s, n, A, n_cells, ld, yin, yout,
+        hipLaunchKernelGGL(k_lin_rk4<3>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
                            rho, L, n_sub, status, steps, accumulate);
         break;
     default:
-        hipLaunchKernelGGL(k_lin_rk4<4>, grid, dim3(block), 0, s, n, A, n_cells, ld, yin, yout,
+        hipLaunchKernelGGL(k_lin_rk4<4>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
                            rho, L, n_sub, status, steps, accumulate);
         break;
     }

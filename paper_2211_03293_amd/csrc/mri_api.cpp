@@ -92,7 +92,7 @@ bool finite_all(const double *p, int n)
 }
 
 // One run-time compiled kernel: (block size, kind 0 RK4 / 1 Zonneveld /
-// 2 batch work queue, forcing terms).
+// 2 batch work queue / 3 Heun / 4 Bogacki-Shampine, forcing terms).
 struct SpecKernel {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
@@ -174,6 +174,62 @@ static std::string device_arch()
     return "gfx950";
 }
 
+static bool fixed_step(int method)
+{
+    return method == MRI_FAST_RK4 || method == MRI_FAST_HEUN || method == MRI_FAST_BS3;
+}
+
+// Tableaus of the fixed-step methods in the form the kernels take (stage i's
+// input uses only k_(i-1)): classic RK4; Heun (c = (0, 1), b = (1/2, 1/2),
+// a21 = 1); Bogacki-Shampine's 3rd-order solution (c = (0, 1/2, 3/4),
+// b = (2/9, 1/3, 4/9), a21 = 1/2, a32 = 3/4, a31 = 0).
+static ErkCoef erk_coef(int method)
+{
+    ErkCoef e{};
+    if (method == MRI_FAST_HEUN) {
+        e.s = 2;
+        e.c[1] = 1.0;
+        e.b[0] = e.b[1] = 0.5;
+        e.a[0] = 1.0;
+    } else if (method == MRI_FAST_BS3) {
+        e.s = 3;
+        e.c[1] = 0.5, e.c[2] = 0.75;
+        e.b[0] = 2.0 / 9.0, e.b[1] = 1.0 / 3.0, e.b[2] = 4.0 / 9.0;
+        e.a[0] = 0.5, e.a[1] = 0.75;
+    } else {
+        e.s = 4;
+        e.c[1] = e.c[2] = 0.5, e.c[3] = 1.0;
+        e.b[0] = e.b[3] = 1.0 / 6.0, e.b[1] = e.b[2] = 1.0 / 3.0;
+        e.a[0] = e.a[1] = 0.5, e.a[2] = 1.0;
+    }
+    return e;
+}
+
+// Run-time compiled kernel kind of a fast method: 0 RK4, 1 Zonneveld, 3 Heun,
+// 4 Bogacki-Shampine (2 is the batched work queue).
+static int spec_kind(int method)
+{
+    return method == MRI_FAST_RK4 ? 0
+           : method == MRI_FAST_ZONNEVELD43 ? 1
+           : method == MRI_FAST_HEUN ? 3 : 4;
+}
+
+// Tableau macros of a fixed-step method for the run-time compiled kernel:
+// per-stage node, weight and next-input coefficient selected by the stage
+// index with literal constants.
+static std::string erk_defs(const ErkCoef &e)
+{
+    auto sel = [&](const double *v) {
+        std::string r = hexd(v[e.s - 1]);
+        for (int i = e.s - 2; i >= 0; --i)
+            r = "((st) == " + std::to_string(i) + " ? " + hexd(v[i]) + " : " + r + ")";
+        return r;
+    };
+    return "#define MRI_ERK_S " + std::to_string(e.s) + "\n#define MRI_ERK_COEF(st, cn, bw, ah) " +
+           "const double cn = " + sel(e.c) + "; const double bw = " + sel(e.b) +
+           "; const double ah = " + sel(e.a) + " * h;\n";
+}
+
 // Compile the specialized kernel (wg, kind, np); with load != 0 also load it
 // on the current device.  Caller holds m->mu.
 static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, SpecKernel *out)
@@ -188,7 +244,8 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     int group = (m->S >= 40) ? 8 : 2;
     if (const char *g = std::getenv("MRI_SPEC_GROUP"))   // tuning knob
         group = std::max(1, std::atoi(g));
-    const std::string tune = "#define MRI_GROUP " + std::to_string(group) + "\n";
+    std::string tune = "#define MRI_GROUP " + std::to_string(group) + "\n";
+    if (kind == 3 || kind == 4) tune += erk_defs(erk_coef(kind == 3 ? MRI_FAST_HEUN : MRI_FAST_BS3));
     std::string src = m->defs + tune + "#define WG " + std::to_string(wg) + "\n#define MRI_KIND " +
                       std::to_string(kind) + "\n#define MRI_NP " + std::to_string(np) + "\n" +
                       mri_spec_kernels_src;
@@ -288,16 +345,17 @@ static mri_status ensure_device(mri_mech *m)
 static mri_status check_opts(const mri_mech *m, const mri_fast_opts *o)
 {
     if (!o) return fail(MRI_EINVAL, "opts is NULL");
-    if (o->method != MRI_FAST_RK4 && o->method != MRI_FAST_ZONNEVELD43)
+    if (!fixed_step(o->method) && o->method != MRI_FAST_ZONNEVELD43)
         return fail(MRI_EINVAL, "unknown fast method %d", o->method);
-    if (o->method == MRI_FAST_RK4 && o->n_sub < 1)
+    if (fixed_step(o->method) && o->n_sub < 1)
         return fail(MRI_EINVAL, "n_sub must be >= 1 (got %d)", o->n_sub);
     if (o->method == MRI_FAST_ZONNEVELD43) {
         if (!(o->rtol >= 0.0) || !(o->atol_Y > 0.0) || !(o->atol_T > 0.0) ||
             !std::isfinite(o->rtol) || !std::isfinite(o->atol_Y) || !std::isfinite(o->atol_T))
             return fail(MRI_EINVAL, "tolerances must be finite with atol > 0, rtol >= 0");
         if (o->max_steps < 1) return fail(MRI_EINVAL, "max_steps must be >= 1");
-        if (m->kind == 1) return fail(MRI_EUNSUPPORTED, "linear test mode supports RK4 only");
+        if (m->kind == 1)
+            return fail(MRI_EUNSUPPORTED, "linear test mode supports fixed-step methods only");
     }
     if (o->kernel < MRI_KERNEL_AUTO || o->kernel > MRI_KERNEL_SPECIALIZED)
         return fail(MRI_EINVAL, "unknown kernel selector %d", o->kernel);
@@ -319,8 +377,8 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
     mri_status dst = ensure_device(m);
     if (dst != MRI_OK) return dst;
     if (m->kind == 1) {
-        HIP_TRY(launch_lin_rk4(m->n, m->d_A, n_cells, ld, yin, yout, n_poly, rho, L, o->n_sub,
-                               status, steps, accumulate, s));
+        HIP_TRY(launch_lin_rk4(m->n, m->d_A, erk_coef(o->method), n_cells, ld, yin, yout, n_poly,
+                               rho, L, o->n_sub, status, steps, accumulate, s));
         ++c_fast;
         c_cells += n_cells;
         return MRI_OK;
@@ -330,7 +388,7 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
     int wg = o->block_size;
     if (kind != MRI_KERNEL_GENERIC) {
         if (!wg) wg = default_block(MRI_KERNEL_SPECIALIZED);
-        mri_status st = spec_get(m, wg, o->method == MRI_FAST_RK4 ? 0 : 1, n_poly, &fn);
+        mri_status st = spec_get(m, wg, spec_kind(o->method), n_poly, &fn);
         if (st != MRI_OK) {
             if (kind == MRI_KERNEL_SPECIALIZED) return st;
             kind = MRI_KERNEL_GENERIC;
@@ -341,9 +399,9 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
     }
     if (kind == MRI_KERNEL_GENERIC) {
         if (!wg) wg = default_block(MRI_KERNEL_GENERIC);
-        if (o->method == MRI_FAST_RK4) {
-            HIP_TRY(launch_gen_rk4(m->gm, wg, n_cells, ld, yin, yout, n_poly, rho, L, o->n_sub,
-                                   status, steps, accumulate, s));
+        if (fixed_step(o->method)) {
+            HIP_TRY(launch_gen_rk4(m->gm, erk_coef(o->method), wg, n_cells, ld, yin, yout, n_poly,
+                                   rho, L, o->n_sub, status, steps, accumulate, s));
         } else {
             ZvOpts z{o->rtol, o->atol_Y, o->atol_T, o->max_steps};
             HIP_TRY(launch_gen_zv(m->gm, wg, n_cells, ld, yin, yout, n_poly, rho, L, z, status,
@@ -356,7 +414,7 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
         double *yo = yout;
         double Lv = L;
         int *stp = status, *sps = steps;
-        if (o->method == MRI_FAST_RK4) {
+        if (fixed_step(o->method)) {
             int nsub = o->n_sub;
             void *args[] = {&nc, &ldv, &yi, &yo, &rh, &Lv, &nsub, &stp, &sps, &acc};
             HIP_TRY(hipModuleLaunchKernel(fn, grid, 1, 1, wg, 1, 1, 0, s, args,
@@ -566,16 +624,20 @@ void mri_mech_destroy(mri_mech *m)
 
 int mri_mech_state_width(const mri_mech *m) { return m ? m->n : -1; }
 
-mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *code_bytes)
+mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int block_size,
+                                      int load, size_t *code_bytes)
 {
     if (!m) return fail(MRI_EINVAL, "mech is NULL");
     if (m->kind != 0) return fail(MRI_EUNSUPPORTED, "linear test mode has no specialization");
     if (block_size != 64 && block_size != 128 && block_size != 256)
         return fail(MRI_EINVAL, "block_size must be 64, 128 or 256");
-    // the RK4 kernel with a constant forcing term (the explicit MIS/MRI-GARK case)
+    if (!fixed_step(method) && method != MRI_FAST_ZONNEVELD43)
+        return fail(MRI_EINVAL, "unknown fast method %d", method);
+    if (n_poly < 0 || n_poly > 4) return fail(MRI_EINVAL, "n_poly must be in [0, 4]");
+    const int kind = spec_kind(method);
     if (load) {
         hipFunction_t fn = nullptr;
-        mri_status st = spec_get(m, block_size, 0, 1, &fn);
+        mri_status st = spec_get(m, block_size, kind, n_poly, &fn);
         if (st != MRI_OK) return st;
         std::lock_guard<std::mutex> lk(m->mu);
         if (code_bytes) *code_bytes = m->last_code.size();
@@ -583,9 +645,15 @@ mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *co
     }
     std::lock_guard<std::mutex> lk(m->mu);
     SpecKernel unused;
-    mri_status st = spec_compile(m, block_size, 0, 1, 0, &unused);
+    mri_status st = spec_compile(m, block_size, kind, n_poly, 0, &unused);
     if (st == MRI_OK && code_bytes) *code_bytes = m->last_code.size();
     return st;
+}
+
+mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *code_bytes)
+{
+    // the RK4 kernel with a constant forcing term (the explicit MIS/MRI-GARK case)
+    return mri_mech_specialize_method(m, MRI_FAST_RK4, 1, block_size, load, code_bytes);
 }
 
 mri_status mri_table_create(const mri_table_desc *d, mri_table **out)

@@ -32,17 +32,28 @@ constexpr int GEN_NMAX_LARGE = 56;
 
 size_t gen_lds_bytes(int S, int R, int block);
 
-hipError_t launch_gen_rk4(const GenMech &gm, int block, int n_cells, int ld, const double *yin,
-                          double *yout, int n_poly, const double *rho, double L, int n_sub,
-                          int *status, int *steps, int accumulate, hipStream_t s);
+// Fixed-step explicit RK method whose stage inputs use only the previous
+// stage derivative (classic RK4, Heun, Bogacki-Shampine): per stage i the node
+// c[i], the weight b[i] and a[i] = a_(i+1,i), the coefficient of k_i in the
+// next stage input (a[s-1] unused).
+struct ErkCoef {
+    int s;
+    double c[4], b[4], a[4];
+};
+
+hipError_t launch_gen_rk4(const GenMech &gm, const ErkCoef &e, int block, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s);
 hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, const double *yin,
                          double *yout, int n_poly, const double *rho, double L, ZvOpts o,
                          int *status, int *steps, int accumulate, hipStream_t s);
 
 // Linear test mode: f = A v, n <= 16, A row-major on the device.
-hipError_t launch_lin_rk4(int n, const double *A, int n_cells, int ld, const double *yin,
-                          double *yout, int n_poly, const double *rho, double L, int n_sub,
-                          int *status, int *steps, int accumulate, hipStream_t s);
+hipError_t launch_lin_rk4(int n, const double *A, const ErkCoef &e, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s);
 
 // rho[k][e] = sum_{j < nj} coef[k*8 + j] * F[j][e], e < n_elem, k < n_gamma.
 struct ForcingCoef {

@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("MRI_LIB_PATH") or os.path.join(_HERE, "libmri.so")
 MRI_OK, MRI_EINVAL, MRI_EHIP, MRI_ENONFINITE, MRI_EMAXSTEPS, MRI_ENOMEM, MRI_EUNSUPPORTED, \
     MRI_ECOMPILE = 0, -1, -2, -3, -4, -5, -6, -7
 CELL_NONFINITE, CELL_MAXSTEPS, CELL_TRANGE, CELL_NEARTIE = 1, 2, 4, 8
-FAST_RK4, FAST_ZONNEVELD43 = 0, 1
+FAST_RK4, FAST_ZONNEVELD43, FAST_HEUN, FAST_BS3 = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
 
 
@@ -72,6 +72,7 @@ _SIGS = {
     "mri_mech_destroy": (None, [_vp]),
     "mri_mech_state_width": (_i, [_vp]),
     "mri_mech_specialize": (_i, [_vp, _i, _i, C.POINTER(_sz)]),
+    "mri_mech_specialize_method": (_i, [_vp, _i, _i, _i, _i, C.POINTER(_sz)]),
     "mri_table_create": (_i, [C.POINTER(mri_table_desc), C.POINTER(_vp)]),
     "mri_table_destroy": (None, [_vp]),
     "mri_fast_stage": (_i, [_vp, C.POINTER(mri_fast_opts), _i, _i, _vp, _vp, _i, _vp, _d, _vp,
@@ -172,9 +173,15 @@ class Mech:
                                               C.byref(self.h)))
         self.n = lib.mri_mech_state_width(self.h)
 
-    def specialize(self, block_size=128, load=True):
+    def specialize(self, block_size=128, load=True, method=None, n_poly=1):
+        """Compile (and with load, load) the run-time specialized kernel: the
+        RK4 kernel with one forcing term by default, else that of `method`."""
         nb = C.c_size_t(0)
-        _check(lib.mri_mech_specialize(self.h, block_size, int(load), C.byref(nb)))
+        if method is None:
+            _check(lib.mri_mech_specialize(self.h, block_size, int(load), C.byref(nb)))
+        else:
+            _check(lib.mri_mech_specialize_method(self.h, int(method), int(n_poly), block_size,
+                                                  int(load), C.byref(nb)))
         return nb.value
 
     def __del__(self, _destroy=lib.mri_mech_destroy, _null=C.c_void_p):

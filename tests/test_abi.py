@@ -99,6 +99,10 @@ def test_fast_stage_rejects_bad_arguments_without_device(mri):
     assert call(n_poly=5, rho=1) == mri.MRI_EINVAL
     assert call(opts=mri.fast_opts(n_sub=0)) == mri.MRI_EINVAL
     assert call(opts=mri.fast_opts(method=7)) == mri.MRI_EINVAL
+    for meth in (mri.FAST_HEUN, mri.FAST_BS3):
+        assert call(opts=mri.fast_opts(method=meth, n_sub=0)) == mri.MRI_EINVAL
+        assert call(opts=mri.fast_opts(method=meth, n_sub=4), n_cells=0, ld=0, yin=None,
+                    yout=None) == mri.MRI_OK
     assert call(opts=mri.fast_opts(n_sub=4, block_size=96)) == mri.MRI_EINVAL
     assert call(opts=mri.fast_opts(method=mri.FAST_ZONNEVELD43, atol_Y=0.0)) == mri.MRI_EINVAL
     assert call(yin=None) == mri.MRI_EINVAL
@@ -148,3 +152,14 @@ def test_specialized_kernels_compile_for_gfx950(mri, config):
     m = mri.Mech(I.make_mechanism(config))
     nbytes = m.specialize(128, load=False)
     assert nbytes > 1000
+
+
+def test_specialized_kernels_compile_for_every_fast_method(mri):
+    m = mri.Mech(I.make_mechanism(0))
+    for meth in (mri.FAST_RK4, mri.FAST_ZONNEVELD43, mri.FAST_HEUN, mri.FAST_BS3):
+        for n_poly in (0, 2):
+            assert m.specialize(64, load=False, method=meth, n_poly=n_poly) > 1000
+    with pytest.raises(mri.MriError):
+        m.specialize(64, load=False, method=9)
+    with pytest.raises(mri.MriError):
+        m.specialize(64, load=False, method=mri.FAST_HEUN, n_poly=5)

@@ -231,6 +231,68 @@ def test_linear_mode_matches_oracle_and_is_third_order(torch, mri, O):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("method", ["heun", "bs3"])
+def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
+    """Heun and Bogacki-Shampine fast stages (the order-2 and order-3 fast
+    methods of the MRI-P(k) family) against the oracle's general explicit RK
+    stage with its own tableaus."""
+    mech = I.make_mechanism(0)
+    orc = O.Oracle(mech)
+    y0 = I.initial_state(0)
+    n, ld = y0.shape
+    F = _config0_forcing(O, orc, y0)
+    rho = np.stack([F[k] / (k + 1) for k in range(2)])
+    L, n_sub = (5.0 / 12.0) * 1e-6, 20
+    om, gm = (O.ERK_HEUN, mri.FAST_HEUN) if method == "heun" else (O.ERK_BS3, mri.FAST_BS3)
+    ref, st_o, _, _ = orc.fast_stage_soa(y0, rho, L, O.erk_opts(om, n_sub))
+    assert np.all(st_o[:512] == 0)
+    m = mri.Mech(mech)
+    yd = _dev(torch, y0)
+    out = torch.empty_like(yd)
+    steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    opts = mri.fast_opts(method=gm, n_sub=n_sub, kernel=_kernel(mri, kernel))
+    mri.mri_fast_stage(m, opts, 512, ld, yd, out, 2, _dev(torch, rho), L, None, steps)
+    torch.cuda.synchronize()
+    e = assert_parity(out.cpu().numpy(), ref, mech.n_species, what=f"{method} {kernel}")
+    print(f"{method} config0 {kernel}: max rel err {e:.2e}")
+    assert np.all(steps.cpu().numpy()[:512] == n_sub)
+
+
+@pytest.mark.parametrize("method,order", [("heun", 2), ("bs3", 3)])
+def test_mri_order_with_low_order_fast_methods(torch, mri, O, method, order):
+    """MRI-P(k) on the linear two-rate problem: MIS-KW3 with k fixed fast
+    substeps per stage and a fast method of order P converges at order
+    min(3, P) in H; every step matches the oracle."""
+    from scipy.linalg import expm
+    A_F = np.array([[-6.0, 5.0], [-5.0, -4.0]])
+    A_S = np.array([[0.3, 1.0], [-1.2, 0.2]])
+    orc = O.Oracle(A_fast=A_F)
+    mF, mS = mri.Mech(A_linear=A_F), mri.Mech(A_linear=A_S)
+    tb = I.table_mis_kw3()
+    t = mri.Table(tb)
+    om, gm = (O.ERK_HEUN, mri.FAST_HEUN) if method == "heun" else (O.ERK_BS3, mri.FAST_BS3)
+    k = 4
+    errs = []
+    for n_steps in (16, 32, 64, 128):
+        H = 1.0 / n_steps
+        y = np.array([[1.0] * 64, [0.5] * 64])
+        yd = _dev(torch, y)
+        ws = torch.empty(mri.mri_workspace_bytes(mF, t, 64, 64) // 8, dtype=torch.float64,
+                         device="cuda")
+        yo = y[:, :1].copy()
+        for step in range(n_steps):
+            mri.mri_slow_step(mF, t, mri.fast_opts(method=gm, n_sub=k), mri.LINEAR_RHS, mS,
+                              step * H, H, 64, 64, yd, ws)
+            yo, _, _, _ = orc.mri_step_linear(tb, O.erk_opts(om, k), A_S, yo[:, 0], H)
+        got = yd.cpu().numpy()
+        np.testing.assert_allclose(got[:, 0], yo[:, 0], rtol=1e-12)
+        errs.append(np.abs(got[:, 0] - expm(A_F + A_S) @ np.array([1.0, 0.5])).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print(f"MRI-{order}({k}) rates {np.round(rates, 2)}")
+    assert np.all(np.abs(rates[1:] - min(3, order)) < 0.3), rates
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 def test_determinism_and_fault_isolation(torch, mri, O, kernel):
     mech = I.make_mechanism(0)
     y0 = I.initial_state(0)

@@ -58,6 +58,51 @@ def test_rk4_forcing_polynomial_converges_at_order_4(oracle_mod):
     assert np.all(rates[1:] > 3.85) and np.all(rates[1:] < 4.2), rates
 
 
+@pytest.mark.parametrize("method,order", [(2, 2), (3, 3)])
+def test_erk_tableau_order_conditions(oracle_mod, method, order):
+    """Heun (order 2) and Bogacki-Shampine (order 3): node consistency, the
+    order conditions up to their order, and failure of the next one."""
+    A, b, c = oracle_mod.erk_tableau(method)
+    np.testing.assert_allclose(A.sum(1), c, atol=1e-15)
+    assert np.allclose(np.tril(A, -1), A)                    # explicit
+    Ac = A @ c
+    conds = [(b.sum(), 1.0), (b @ c, 0.5)]
+    if order >= 3:
+        conds += [(b @ c ** 2, 1 / 3), (b @ Ac, 1 / 6)]
+    for got, want in conds:
+        assert abs(got - want) < 1e-15
+    nxt = (b @ c ** 2, 1 / 3) if order == 2 else (b @ c ** 3, 1 / 4)
+    assert abs(nxt[0] - nxt[1]) > 1e-3
+
+
+@pytest.mark.parametrize("method,order", [(2, 2), (3, 3)])
+def test_erk_forcing_polynomial_converges_at_its_order(oracle_mod, method, order):
+    """The general explicit RK stage with a polynomial forcing against the
+    augmented-matrix-exponential closed form: error ratio 2^order per halving;
+    with the classic RK4 tableau it reproduces the dedicated RK4 stage."""
+    lam, L = -2.5, 1.7
+    r = np.array([0.4, -1.1, 2.3])
+    orc = oracle_mod.Oracle(A_fast=np.array([[lam]]))
+    y0 = 0.8
+    M = np.zeros((4, 4))
+    M[0, 0], M[0, 1], M[0, 2], M[0, 3] = lam, r[0], r[1], r[2]
+    M[2, 1] = 1.0 / L
+    M[3, 2] = 2.0 / L
+    exact = (expm(M * L) @ np.array([y0, 1.0, 0.0, 0.0]))[0]
+    A, b, c = oracle_mod.erk_tableau(method)
+    errs = []
+    for n_sub in (16, 32, 64, 128):
+        out, _ = orc.erk_stage([y0], r.reshape(3, 1), L, n_sub, A, b, c)
+        errs.append(abs(out[0] - exact))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates[1:] - order) < 0.15), rates
+    A4 = np.array([[0, 0, 0, 0], [0.5, 0, 0, 0], [0, 0.5, 0, 0], [0, 0, 1, 0]], float)
+    b4, c4 = np.array([1, 2, 2, 1]) / 6.0, np.array([0, 0.5, 0.5, 1.0])
+    g, _ = orc.erk_stage([y0], r.reshape(3, 1), L, 8, A4, b4, c4)
+    d, _ = orc.rk4_stage([y0], r.reshape(3, 1), L, 8)
+    assert abs(g[0] - d[0]) <= 1e-15 * abs(d[0])
+
+
 def test_zonneveld_tableau_order_conditions(oracle_mod):
     c, A, b, bh = oracle_mod.zonneveld_tableau()
     Af = np.zeros((5, 5))
@@ -197,6 +242,26 @@ def test_mri_order_three_on_linear_two_rate_problem(oracle_mod, table):
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 2.7), rates
     assert rates[-1] < 3.6, rates
+
+
+@pytest.mark.parametrize("method,order", [(2, 2), (3, 3)])
+def test_mri_p_k_order_on_linear_two_rate_problem(oracle_mod, method, order):
+    """MRI-P(k) (Sec. 5.1): the MIS-KW3 slow method with k = 4 fixed substeps
+    per stage of a fast method of order P converges at order min(3, P)."""
+    A_F = np.array([[-6.0, 5.0], [-5.0, -4.0]])
+    A_S = np.array([[0.3, 1.0], [-1.2, 0.2]])
+    orc = oracle_mod.Oracle(A_fast=A_F)
+    tb = I.table_mis_kw3()
+    exact = expm(A_F + A_S) @ np.array([1.0, 0.5])
+    errs = []
+    for n_steps in (16, 32, 64, 128):
+        H = 1.0 / n_steps
+        y = np.array([[1.0], [0.5]])
+        for _ in range(n_steps):
+            y, _, _, _ = orc.mri_step_linear(tb, oracle_mod.erk_opts(method, 4), A_S, y[:, 0], H)
+        errs.append(np.abs(y[:, 0] - exact).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates[1:] - min(3, order)) < 0.25), rates
 
 
 def test_mri_forcing_uses_given_slow_evaluations(oracle_mod):
