@@ -30,6 +30,15 @@ class MriError(RuntimeError):
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2211_03293_amd.build.build()")
 
+# torch ships its own HIP runtime under the same soname as the system one that
+# libmri links.  Loaded first, it is the one libmri binds to, so the process
+# holds a single HIP runtime whichever module the caller imports first (with
+# libmri loaded first, the two runtimes do not see the same devices).
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 lib = C.CDLL(LIB_PATH)
 
 

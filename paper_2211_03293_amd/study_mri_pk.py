@@ -1,0 +1,108 @@
+"""MRI-P(k) convergence and efficiency study on the synthetic reacting-flow
+problem, run on the GPU through libmri (the analogue of the paper's Table 1
+and Fig. 4, Sec. 5.1: a 3rd-order explicit MRI slow method paired with fast
+explicit RK methods of order P, k fast steps per stage).
+
+Problem: the 64^3 periodic fields, 21 species / 84 reactions, advection-
+diffusion slow side, integrated to t = 1e-6 s.  For every fast method
+(Heun P = 2, Bogacki-Shampine P = 3, classic RK4 P = 4) and slow step H the
+errors are taken over all cells against a reference run with H/8 of the finest
+H and RK4 with 4k substeps: the max absolute mass-fraction error (the paper
+reports max-norm errors, Table 1), the max relative temperature error and the
+max relative state error with the mass-fraction floor 1e-8.
+
+    python -m paper_2211_03293_amd.study_mri_pk [--cells-per-side 32] [--k 16]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import mri
+
+T_END = 1e-6
+METHODS = (("Heun", 2), ("Bogacki-Shampine", 3), ("RK4", 4))
+
+
+def _fields(n_side):
+    """The 64^3 workload's initial fields on an n_side^3 periodic grid."""
+    grid = (n_side, n_side, n_side)
+    return I.field_state(1, grid), grid
+
+
+def run(torch, m, t, y_host, grid, method, k, H):
+    n, ld = y_host.shape
+    N = int(np.prod(grid))
+    y = torch.as_tensor(y_host, device="cuda")
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    status = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    params = mri.advdiff_params(grid, n)
+    opts = mri.fast_opts(method=method, n_sub=k)
+    n_steps = int(round(T_END / H))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(n_steps):
+        mri.mri_slow_step(m, t, opts, mri.ADVDIFF_RHS, params, s * H, H, N, ld, y, ws, status)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bad = mri.mri_status_count(status, N)
+    return y.cpu().numpy()[:, :N], dt, bad
+
+
+def errors(y, ref, n_species):
+    """(max absolute mass-fraction error, max relative temperature error, max
+    relative state error with the mass-fraction floor 1e-8) over all cells."""
+    ey = float(np.abs(y[:n_species] - ref[:n_species]).max())
+    eT = float((np.abs(y[n_species] - ref[n_species]) / np.abs(ref[n_species])).max())
+    floor = np.zeros((y.shape[0], 1))
+    floor[:n_species] = 1e-8
+    er = float((np.abs(y - ref) / np.maximum(np.abs(ref), floor)).max())
+    return ey, eT, er
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--cells-per-side", type=int, default=32)
+    ap.add_argument("--k", type=int, default=16, help="fast substeps per stage")
+    ap.add_argument("--H", type=float, nargs="+", default=[1e-7, 5e-8, 2.5e-8, 1.25e-8])
+    args = ap.parse_args(argv)
+    import torch
+    assert torch.cuda.is_available(), "the study runs on a GPU"
+    torch.cuda.set_device(0)
+    mech = I.make_mechanism(1)
+    m = mri.Mech(mech)
+    for meth, _ in ((mri.FAST_HEUN, 0), (mri.FAST_BS3, 0), (mri.FAST_RK4, 0)):
+        m.specialize(128, load=True, method=meth, n_poly=1)
+    t = mri.Table(I.table_mis_kw3())
+    y0, grid = _fields(args.cells_per_side)
+    H_ref = min(args.H) / 8
+    ref, t_ref, bad = run(torch, m, t, y0, grid, mri.FAST_RK4, 4 * args.k, H_ref)
+    print(f"# reference: H = {H_ref:.3e}, RK4 {4 * args.k} substeps/stage, {t_ref:.2f} s, "
+          f"flagged {bad}", flush=True)
+    rows = []
+    for (name, P), meth in zip(METHODS, (mri.FAST_HEUN, mri.FAST_BS3, mri.FAST_RK4)):
+        prev = None
+        for H in args.H:
+            y, dt, bad = run(torch, m, t, y0, grid, meth, args.k, H)
+            e = errors(y, ref, mech.n_species)
+            rate = None if prev is None else [float(np.log2(a / b)) for a, b in zip(prev, e)]
+            prev = e
+            rows.append(dict(method=name, P=P, k=args.k, H=H, err_Y_abs=e[0], err_T_rel=e[1],
+                             err_rel=e[2], rates=rate, seconds=dt, flagged=bad))
+            print(f"MRI-{P}({args.k}) {name:17s} H = {H:.3e}: |dY| {e[0]:.3e}  dT/T {e[1]:.3e}  "
+                  f"rel {e[2]:.3e}" + (" rates " + " ".join(f"{r:.2f}" for r in rate)
+                                      if rate else "") + f"  {dt * 1e3:.1f} ms", flush=True)
+    print(json.dumps(dict(study="MRI-P(k) convergence, MIS-KW3 slow, 21 species / 84 reactions, "
+                                f"{args.cells_per_side}^3 cells, t = {T_END}", rows=rows)))
+    return rows
+
+
+if __name__ == "__main__":
+    main()
+    sys.exit(0)
