@@ -53,6 +53,17 @@ def flops_per_substep(S: int, R: int, n_poly: int = 1) -> int:
     return 4 * rhs + 4 * n * (forcing + 4) + 2 * n
 
 
+def flops_per_zv_attempt(S: int, R: int) -> int:
+    """Algorithmic FP64 flops of one attempted Zonneveld 4(3) step of one cell
+    (unforced): 5 RHS evaluations; per stage and component the solution, error
+    and stage-5 accumulators and the next stage input (4 FMA); the WRMS error
+    (scaling, weight, divide, square: 15 flops per component), the solution
+    update (1 FMA per component) and the step-size factor (one pow, 44 flops)."""
+    n = S + 1
+    rhs = S * (6 + F_EXP) + R * (12 + F_EXP) + 5 * S + 1 + F_LOG + 2 * F_DIV + 1
+    return 5 * rhs + 5 * n * 8 + 15 * n + 2 * n + 2 * F_EXP
+
+
 def kernel_source_hash() -> str:
     p = os.path.join(ROOT, "paper_2211_03293_amd", "csrc", "spec_kernels.inc")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
@@ -133,8 +144,10 @@ def batch_leg(torch, mri, I, repeats=3):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / repeats
-    useful, issued = plan.lane_stats()
+    useful, issued = plan.lane_stats()       # attempted lane-steps of the last run
     wg, nb = plan.tile()
+    fpa = flops_per_zv_attempt(mech.n_species, mech.n_reactions)
+    achieved = useful * fpa / (ms * 1e-3) / 1e12
     sv = steps[:ntot].cpu().numpy()
     n_bad = mri.mri_status_count(st, ntot, mri.CELL_NONFINITE | mri.CELL_MAXSTEPS | mri.CELL_TRANGE)
     return dict(workload="1000 reactor sets, sizes log-uniform in [64, 65536], 21 species / 84 "
@@ -145,7 +158,11 @@ def batch_leg(torch, mri, I, repeats=3):
                                                           median=float(np.median(sv)),
                                                           max=int(sv.max())),
                 lane_utilization=round(useful / max(issued, 1), 4), tile=dict(block=wg, blocks=nb),
-                flagged_cells=n_bad)
+                flagged_cells=n_bad, attempted_steps=int(useful),
+                roofline=dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS,
+                              unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 4),
+                              traffic=None, kernel="mri_spec_main (batched work queue)",
+                              flops_per_attempted_step=fpa))
 
 
 WORKLOADS = {
