@@ -119,20 +119,25 @@ def _cells(torch, mri, n_cells, seed):
     return mech, y, rho
 
 
-def test_fused_inference_matches_training_forward(torch, mri):
+@pytest.mark.parametrize("n_poly", [1, 2])
+def test_fused_inference_matches_training_forward(torch, mri, n_poly):
     """The fused kernel (activations in registers, permuted inputs) reproduces the
-    training-path forward on the same features, for the full and both half stages."""
+    training-path forward on the same features, for the full and both half
+    stages; with two forcing terms the half stages see the forcing polynomial
+    re-expanded on each half (first half: r0 + r1 tau/2; second half:
+    r0 + r1/2 + r1 tau/2), which the training path is given explicitly."""
     widths = [89, 256, 256, 256, 22]
     Ws, bs, rng = _rand_net(widths, 5)
     p = _pack(Ws, bs)
-    mech, y, rho = _cells(torch, mri, 1000, 6)
+    mech, y, rho1 = _cells(torch, mri, 1000, 6)
+    rho = np.concatenate([rho1, 0.5 * rho1[::-1, ::-1]]) if n_poly == 2 else rho1
     n, ld = y.shape
     yd = torch.as_tensor(y, device="cuda")
     rd = torch.as_tensor(rho, device="cuda")
     L = 3e-8
     stats = torch.empty(mri.MLP_STATS, dtype=torch.float64, device="cuda")
     Lv = torch.full((ld,), L, dtype=torch.float64, device="cuda")
-    mri.mri_mlp_feature_stats(1000, ld, yd, 1, rd, Lv, yd, stats)
+    mri.mri_mlp_feature_stats(1000, ld, yd, n_poly, rd, Lv, yd, stats)
     st = stats.cpu().numpy()
     st[2 * 89 + 2 * 22:] = rng.uniform(0.5, 2.0, 22) * 1e-3      # y_std
     st[2 * 89:2 * 89 + 22] = rng.normal(size=22) * 1e-4         # y_mean
@@ -146,9 +151,16 @@ def test_fused_inference_matches_training_forward(torch, mri):
     Y = torch.empty((ld, 22), dtype=torch.float32, device="cuda")
     for half, Lh in ((0, L), (1, 0.5 * L), (2, 0.5 * L)):
         out = torch.empty_like(yd)
-        sg.infer(1000, ld, yd, out, 1, rd, L, half=half)
+        sg.infer(1000, ld, yd, out, n_poly, rd, L, half=half)
         Lv.fill_(Lh)
-        mri.mri_mlp_featurize(ld, None, ld, yd, 1, rd, Lv, None, stats, X)
+        rh = rho.copy()
+        if n_poly == 2 and half == 1:
+            rh[1] = 0.5 * rho[1]
+        elif n_poly == 2 and half == 2:
+            rh[0] = rho[0] + 0.5 * rho[1]
+            rh[1] = 0.5 * rho[1]
+        mri.mri_mlp_featurize(ld, None, ld, yd, n_poly, torch.as_tensor(rh, device="cuda"), Lv,
+                              None, stats, X)
         net.forward(X, Y)
         torch.cuda.synchronize()
         d = st[2 * 89:2 * 89 + 22][:, None] + st[2 * 89 + 44:][:, None] * Y.cpu().numpy().T.astype(np.float64)
