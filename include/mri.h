@@ -147,8 +147,19 @@ void mri_table_destroy(mri_table *t);
      MRI_FAST_ZONNEVELD43  Zonneveld 4(3), adaptive (tolerances below)
      MRI_FAST_HEUN         Heun's 2nd-order method, n_sub uniform substeps
      MRI_FAST_BS3          Bogacki-Shampine 3rd-order solution, n_sub uniform
-                           substeps (the embedded estimate is not used)    */
-enum { MRI_FAST_RK4 = 0, MRI_FAST_ZONNEVELD43 = 1, MRI_FAST_HEUN = 2, MRI_FAST_BS3 = 3 };
+                           substeps (the embedded estimate is not used)
+     MRI_FAST_CK5          Cash-Karp 5th-order solution, n_sub uniform
+                           substeps; generic kernel only (MRI_KERNEL_
+                           SPECIALIZED and mri_mech_specialize_method return
+                           MRI_EUNSUPPORTED), chemistry with at most 24
+                           species (else MRI_EUNSUPPORTED)                 */
+enum {
+    MRI_FAST_RK4 = 0,
+    MRI_FAST_ZONNEVELD43 = 1,
+    MRI_FAST_HEUN = 2,
+    MRI_FAST_BS3 = 3,
+    MRI_FAST_CK5 = 4
+};
 enum {
     MRI_KERNEL_AUTO = 0,        /* specialized if available, else generic       */
     MRI_KERNEL_GENERIC = 1,     /* one binary for every mechanism; coefficients  */

@@ -15,7 +15,7 @@
  *     through K_c = exp(-dG/RT), species production, constant-volume energy)
  *   linear fast RHS (f^F = A v) for order tests
  *   classic RK4 over one fast stage with a polynomial forcing
- *   a general explicit Runge-Kutta stage (Heun, Bogacki-Shampine tableaus)
+ *   a general explicit Runge-Kutta stage (Heun, Bogacki-Shampine, Cash-Karp)
  *   Zonneveld 4(3) adaptive integration over one fast stage
  *   the explicit MRI-GARK slow step (Sec. 2.1 algorithm, steps 1-3)
  *   the 2nd-order centred periodic advection-diffusion slow RHS (Sec. 3.1)
@@ -62,7 +62,8 @@ typedef struct {
 typedef struct {
     int method;                          /* 0 = classic RK4, 1 = Zonneveld 4(3),
                                             2 = Heun (2nd order), 3 = Bogacki-
-                                            Shampine (3rd order), fixed steps   */
+                                            Shampine (3rd order), 4 = Cash-Karp
+                                            (5th order), fixed steps            */
     int n_sub;                           /* RK4 substeps per stage            */
     double rtol, atol_Y, atol_T;         /* Zonneveld tolerances              */
     int max_steps;                       /* Zonneveld accepted-step cap       */
@@ -245,8 +246,9 @@ int ora_rk4_stage(const ora_fast *f, const double *y_in, int n_poly, const doubl
 /* substep stores every stage derivative and forms                           */
 /*   Y_i = v + h sum_(j<i) a_ij k_j,  k_i = f(Y_i) + r((m + c_i)/n_sub),      */
 /*   v <- v + h sum_i b_i k_i.                                                */
-/* The fast methods of Sec. 3.2 of orders 2 and 3 (the MRI-P(k) family):      */
-/* Heun's method and the Bogacki-Shampine 3rd-order solution.                 */
+/* The fast methods of Sec. 3.2 of orders 2, 3 and 5 (the MRI-P(k) family):   */
+/* Heun's method, the Bogacki-Shampine 3rd-order and the Cash-Karp 5th-order  */
+/* solutions.                                                                  */
 /* ------------------------------------------------------------------------ */
 static const double HEUN_A[4] = {0.0, 0.0, 1.0, 0.0};
 static const double HEUN_B[2] = {0.5, 0.5};
@@ -254,9 +256,22 @@ static const double HEUN_C[2] = {0.0, 1.0};
 static const double BS3_A[9] = {0.0, 0.0, 0.0, 0.5, 0.0, 0.0, 0.0, 0.75, 0.0};
 static const double BS3_B[3] = {2.0 / 9.0, 1.0 / 3.0, 4.0 / 9.0};
 static const double BS3_C[3] = {0.0, 0.5, 0.75};
+/* Cash-Karp: the 5th-order solution of the 5(4) pair (the order-5 fast method
+   of Sec. 3.2). */
+static const double CK5_A[36] = {
+    0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+    1.0 / 5.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+    3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0, 0.0,
+    3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0, 0.0,
+    -11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0, 0.0,
+    1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0, 0.0};
+static const double CK5_B[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0,
+                                512.0 / 1771.0};
+static const double CK5_C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
 
-/* The tableau of fixed-step method 2 (Heun) or 3 (Bogacki-Shampine); returns
-   the stage count (0 for other methods).  A is [s][s], b and c are [s]. */
+/* The tableau of fixed-step method 2 (Heun), 3 (Bogacki-Shampine) or 4
+   (Cash-Karp); returns the stage count (0 for other methods).  A is [s][s],
+   b and c are [s]. */
 int ora_erk_tableau(int method, double *A, double *b, double *c)
 {
     const double *a0, *b0, *c0;
@@ -265,6 +280,8 @@ int ora_erk_tableau(int method, double *A, double *b, double *c)
         s = 2, a0 = HEUN_A, b0 = HEUN_B, c0 = HEUN_C;
     } else if (method == 3) {
         s = 3, a0 = BS3_A, b0 = BS3_B, c0 = BS3_C;
+    } else if (method == 4) {
+        s = 6, a0 = CK5_A, b0 = CK5_B, c0 = CK5_C;
     } else {
         return 0;
     }
@@ -459,8 +476,8 @@ void ora_fast_stage_soa(const ora_fast *f, const ora_fast_opts *o, int n_cells, 
             if (o->method == 0) {
                 st = ora_rk4_stage(f, v, n_poly, rho, L, o->n_sub, w);
                 acc = o->n_sub;
-            } else if (o->method == 2 || o->method == 3) {
-                double A[9], b[3], c[3];
+            } else if (o->method >= 2 && o->method <= 4) {
+                double A[36], b[6], c[6];
                 const int s = ora_erk_tableau(o->method, A, b, c);
                 st = ora_erk_stage(f, v, n_poly, rho, L, o->n_sub, s, A, b, c, w);
                 acc = o->n_sub;

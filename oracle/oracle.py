@@ -271,16 +271,16 @@ def zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000):
     return FastOpts(1, 0, rtol, atol_Y, atol_T, max_steps)
 
 
-ERK_HEUN, ERK_BS3 = 2, 3
+ERK_HEUN, ERK_BS3, ERK_CK5 = 2, 3, 4
 
 
 def erk_opts(method, n_sub):
-    """Fixed-step Heun (method 2) or Bogacki-Shampine (method 3)."""
+    """Fixed-step Heun (method 2), Bogacki-Shampine (3) or Cash-Karp (4)."""
     return FastOpts(int(method), int(n_sub), 0.0, 0.0, 0.0, 0)
 
 
 def erk_tableau(method):
-    A, b, c = np.zeros(9), np.zeros(3), np.zeros(3)
+    A, b, c = np.zeros(36), np.zeros(6), np.zeros(6)
     s = lib().ora_erk_tableau(int(method), _p(A), _p(b), _p(c))
     return A[:s * s].reshape(s, s), b[:s], c[:s]
 

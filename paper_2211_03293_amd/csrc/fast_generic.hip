@@ -172,6 +172,88 @@ __global__ void __launch_bounds__(256)
     if (steps) steps[cell] = accumulate ? (steps[cell] + n_sub) : n_sub;
 }
 
+// General explicit RK tableau (at most ERK_SMAX stages), n_sub uniform
+// substeps: stage st takes y0 + h sum_j a[st][j] k_j.  The stage loop is not
+// unrolled (one inlined rate evaluation); the stage derivatives stay in
+// registers with static indices: the input sum runs over every stored
+// derivative (a[st][j] = 0 for j >= st, and the slots start at zero) and a
+// new derivative is written by select.
+template <int NMAX, int NP>
+__global__ void __launch_bounds__(256)
+    k_gen_erk(GenMech gm, ErkFull e, int n_cells, int ld, const double *__restrict__ yin,
+              double *yout, const double *__restrict__ rho, double L, int n_sub, int *status,
+              int *steps, int accumulate)
+{
+    constexpr int NK = ERK_SMAX - 1;   // derivatives a later stage can read
+    const LdsView m = stage_mechanism(gm);
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= n_cells) return;     // no barrier below this point
+    const int S = gm.S, R = gm.R, lane = threadIdx.x & 63;
+    const size_t plane = (size_t)(S + 1) * ld;
+    const size_t offT = (size_t)S * ld + cell;
+    double y0[NMAX], acc[NMAX], kst[NK][NMAX], kT[NK];
+    double y0T = yin[offT], accT;
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+        if (k < S) y0[k] = yin[(size_t)k * ld + cell];
+#pragma unroll
+        for (int j = 0; j < NK; ++j) kst[j][k] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NK; ++j) kT[j] = 0.0;
+    const double h = L / n_sub;
+    const double inv_nsub = 1.0 / n_sub;
+    for (int it = 0; it < n_sub; ++it) {
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
+        accT = 0.0;
+#pragma unroll 1
+        for (int st = 0; st < e.s; ++st) {
+            double ah[NK];
+#pragma unroll
+            for (int j = 0; j < NK; ++j) ah[j] = h * e.a[st][j];
+#pragma unroll
+            for (int k = 0; k < NMAX; ++k)
+                if (k < S) {
+                    double v = y0[k];
+#pragma unroll
+                    for (int j = 0; j < NK; ++j) v = fma(ah[j], kst[j][k], v);
+                    m.Z[k * 64 + lane] = v;
+                }
+            double YcT = y0T;
+#pragma unroll
+            for (int j = 0; j < NK; ++j) YcT = fma(ah[j], kT[j], YcT);
+            const double bw = e.b[st];
+            const double tau = (it + e.c[st]) * inv_nsub;
+            const double Tdot = gen_rhs<NMAX>(m, S, R, gm.T_ref, YcT, lane);
+#pragma unroll
+            for (int k = 0; k < NMAX; ++k)
+                if (k < S) {
+                    const double kc =
+                        m.Wd[k * 64 + lane] + gen_forcing<NP>(rho, plane, (size_t)k * ld + cell, tau);
+                    acc[k] = fma(bw, kc, acc[k]);
+#pragma unroll
+                    for (int j = 0; j < NK; ++j) kst[j][k] = (j == st) ? kc : kst[j][k];
+                }
+            const double kc = Tdot + gen_forcing<NP>(rho, plane, offT, tau);
+            accT = fma(bw, kc, accT);
+#pragma unroll
+            for (int j = 0; j < NK; ++j) kT[j] = (j == st) ? kc : kT[j];
+        }
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k)
+            if (k < S) y0[k] = fma(h, acc[k], y0[k]);
+        y0T = fma(h, accT, y0T);
+    }
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k)
+        if (k < S) yout[(size_t)k * ld + cell] = y0[k];
+    yout[offT] = y0T;
+    const int fl = gen_flags<NMAX>(y0, y0T, S);
+    if (status) status[cell] = accumulate ? (status[cell] | fl) : fl;
+    if (steps) steps[cell] = accumulate ? (steps[cell] + n_sub) : n_sub;
+}
+
 // One attempted Zonneveld 4(3) step (RK4 + stage 5 at c = 3/4, embedded
 // third-order estimate); returns the WRMS error, writes the RK4 solution.
 template <int NMAX, int NP>
@@ -315,6 +397,73 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // Linear test mode f = A v (n <= 16): RK4 with the same stage structure.
 // ---------------------------------------------------------------------------
+// Linear test mode with a general tableau (n <= 16 components), organised
+// like k_gen_erk.
+template <int NP>
+__global__ void __launch_bounds__(256)
+    k_lin_erk(int n, const double *__restrict__ A, ErkFull e, int n_cells, int ld,
+              const double *__restrict__ yin, double *yout, const double *__restrict__ rho,
+              double L, int n_sub, int *status, int *steps, int accumulate)
+{
+    constexpr int NM = 16, NK = ERK_SMAX - 1;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= n_cells) return;
+    const size_t plane = (size_t)n * ld;
+    double y0[NM], acc[NM], Yc[NM], kst[NK][NM];
+#pragma unroll
+    for (int c = 0; c < NM; ++c) {
+        if (c < n) y0[c] = yin[(size_t)c * ld + cell];
+#pragma unroll
+        for (int j = 0; j < NK; ++j) kst[j][c] = 0.0;
+    }
+    const double h = L / n_sub, inv_nsub = 1.0 / n_sub;
+    for (int it = 0; it < n_sub; ++it) {
+#pragma unroll
+        for (int c = 0; c < NM; ++c) acc[c] = 0.0;
+#pragma unroll 1
+        for (int st = 0; st < e.s; ++st) {
+            double ah[NK];
+#pragma unroll
+            for (int j = 0; j < NK; ++j) ah[j] = h * e.a[st][j];
+#pragma unroll
+            for (int c = 0; c < NM; ++c)
+                if (c < n) {
+                    double v = y0[c];
+#pragma unroll
+                    for (int j = 0; j < NK; ++j) v = fma(ah[j], kst[j][c], v);
+                    Yc[c] = v;
+                }
+            const double bw = e.b[st];
+            const double tau = (it + e.c[st]) * inv_nsub;
+#pragma unroll
+            for (int r = 0; r < NM; ++r)
+                if (r < n) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int c = 0; c < NM; ++c)
+                        if (c < n) s = fma(A[r * n + c], Yc[c], s);
+                    const double kc = s + gen_forcing<NP>(rho, plane, (size_t)r * ld + cell, tau);
+                    acc[r] = fma(bw, kc, acc[r]);
+#pragma unroll
+                    for (int j = 0; j < NK; ++j) kst[j][r] = (j == st) ? kc : kst[j][r];
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < NM; ++c)
+            if (c < n) y0[c] = fma(h, acc[c], y0[c]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < NM; ++c)
+        if (c < n) {
+            yout[(size_t)c * ld + cell] = y0[c];
+            s += y0[c];
+        }
+    const int fl = isfinite(s) ? 0 : 1;
+    if (status) status[cell] = accumulate ? (status[cell] | fl) : fl;
+    if (steps) steps[cell] = accumulate ? (steps[cell] + n_sub) : n_sub;
+}
+
 template <int NP>
 __global__ void __launch_bounds__(256)
     k_lin_rk4(int n, const double *__restrict__ A, ErkCoef e, int n_cells, int ld,
@@ -426,6 +575,52 @@ hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, cons
     } else {
         GEN_DISPATCH_NP(k_gen_zv, GEN_NMAX_LARGE, gm, n_cells, ld, yin, yout, rho, L, o, status,
                         steps, accumulate)
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_erk(const GenMech &gm, const ErkFull &e, int block, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s)
+{
+    const dim3 grid((n_cells + block - 1) / block);
+    if (gm.S > GEN_NMAX_SMALL || e.s < 1 || e.s > ERK_SMAX) return hipErrorInvalidValue;
+    const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
+    GEN_DISPATCH_NP(k_gen_erk, GEN_NMAX_SMALL, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
+                    status, steps, accumulate)
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_erk(int n, const double *A, const ErkFull &e, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s)
+{
+    if (n > 16 || e.s < 1 || e.s > ERK_SMAX) return hipErrorInvalidValue;
+    const int block = 256;
+    const dim3 grid((n_cells + block - 1) / block);
+    switch (n_poly) {
+    case 0:
+        hipLaunchKernelGGL(k_lin_erk<0>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
+                           rho, L, n_sub, status, steps, accumulate);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_lin_erk<1>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
+                           rho, L, n_sub, status, steps, accumulate);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_lin_erk<2>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
+                           rho, L, n_sub, status, steps, accumulate);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_lin_erk<3>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
+                           rho, L, n_sub, status, steps, accumulate);
+        break;
+    default:
+        hipLaunchKernelGGL(k_lin_erk<4>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
+                           rho, L, n_sub, status, steps, accumulate);
+        break;
     }
     return hipGetLastError();
 }

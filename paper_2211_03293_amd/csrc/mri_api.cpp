@@ -176,7 +176,31 @@ static std::string device_arch()
 
 static bool fixed_step(int method)
 {
-    return method == MRI_FAST_RK4 || method == MRI_FAST_HEUN || method == MRI_FAST_BS3;
+    return method == MRI_FAST_RK4 || method == MRI_FAST_HEUN || method == MRI_FAST_BS3 ||
+           method == MRI_FAST_CK5;
+}
+
+// Cash-Karp's six-stage tableau, 5th-order solution (Cash and Karp 1990):
+// nodes, weights and the full strictly lower-triangular stage matrix.
+static ErkFull erk_full_ck5()
+{
+    ErkFull e{};
+    e.s = 6;
+    const double c[6] = {0.0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8};
+    const double b[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771};
+    const double a[6][5] = {{0, 0, 0, 0, 0},
+                            {1.0 / 5, 0, 0, 0, 0},
+                            {3.0 / 40, 9.0 / 40, 0, 0, 0},
+                            {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
+                            {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
+                            {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592,
+                             253.0 / 4096}};
+    for (int i = 0; i < 6; ++i) {
+        e.c[i] = c[i];
+        e.b[i] = b[i];
+        for (int j = 0; j < 5; ++j) e.a[i][j] = a[i][j];
+    }
+    return e;
 }
 
 // Tableaus of the fixed-step methods in the form the kernels take (stage i's
@@ -359,6 +383,13 @@ static mri_status check_opts(const mri_mech *m, const mri_fast_opts *o)
     }
     if (o->kernel < MRI_KERNEL_AUTO || o->kernel > MRI_KERNEL_SPECIALIZED)
         return fail(MRI_EINVAL, "unknown kernel selector %d", o->kernel);
+    if (o->method == MRI_FAST_CK5 && m->kind == 0) {
+        if (o->kernel == MRI_KERNEL_SPECIALIZED)
+            return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 has no specialized kernel");
+        if (m->S > GEN_NMAX_SMALL)
+            return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 supports at most %d species",
+                        GEN_NMAX_SMALL);
+    }
     if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 &&
         o->block_size != 256)
         return fail(MRI_EINVAL, "block_size must be 0, 64, 128 or 256 (got %d)", o->block_size);
@@ -376,6 +407,21 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
     if (n_cells == 0) return MRI_OK;
     mri_status dst = ensure_device(m);
     if (dst != MRI_OK) return dst;
+    if (o->method == MRI_FAST_CK5) {
+        // full-tableau method: generic kernels only (stage derivatives held in
+        // registers, so chemistry is limited to GEN_NMAX_SMALL species)
+        if (m->kind == 1) {
+            HIP_TRY(launch_lin_erk(m->n, m->d_A, erk_full_ck5(), n_cells, ld, yin, yout, n_poly,
+                                   rho, L, o->n_sub, status, steps, accumulate, s));
+        } else {
+            HIP_TRY(launch_gen_erk(m->gm, erk_full_ck5(), o->block_size ? o->block_size : 64,
+                                   n_cells, ld, yin, yout, n_poly, rho, L, o->n_sub, status,
+                                   steps, accumulate, s));
+        }
+        ++c_fast;
+        c_cells += n_cells;
+        return MRI_OK;
+    }
     if (m->kind == 1) {
         HIP_TRY(launch_lin_rk4(m->n, m->d_A, erk_coef(o->method), n_cells, ld, yin, yout, n_poly,
                                rho, L, o->n_sub, status, steps, accumulate, s));
@@ -634,6 +680,8 @@ mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int b
     if (!fixed_step(method) && method != MRI_FAST_ZONNEVELD43)
         return fail(MRI_EINVAL, "unknown fast method %d", method);
     if (n_poly < 0 || n_poly > 4) return fail(MRI_EINVAL, "n_poly must be in [0, 4]");
+    if (method == MRI_FAST_CK5)
+        return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 has no specialized kernel");
     const int kind = spec_kind(method);
     if (load) {
         hipFunction_t fn = nullptr;

@@ -41,6 +41,25 @@ struct ErkCoef {
     double c[4], b[4], a[4];
 };
 
+// Fixed-step explicit RK method with a general strictly lower-triangular
+// tableau of at most ERK_SMAX stages (Cash-Karp's 5th-order solution).  The
+// kernels keep the stage derivatives in registers, so mechanisms are limited
+// to GEN_NMAX_SMALL species.
+constexpr int ERK_SMAX = 6;
+struct ErkFull {
+    int s;
+    double c[ERK_SMAX], b[ERK_SMAX], a[ERK_SMAX][ERK_SMAX];
+};
+
+hipError_t launch_gen_erk(const GenMech &gm, const ErkFull &e, int block, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s);
+hipError_t launch_lin_erk(int n, const double *A, const ErkFull &e, int n_cells, int ld,
+                          const double *yin, double *yout, int n_poly, const double *rho,
+                          double L, int n_sub, int *status, int *steps, int accumulate,
+                          hipStream_t s);
+
 hipError_t launch_gen_rk4(const GenMech &gm, const ErkCoef &e, int block, int n_cells, int ld,
                           const double *yin, double *yout, int n_poly, const double *rho,
                           double L, int n_sub, int *status, int *steps, int accumulate,

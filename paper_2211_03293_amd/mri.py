@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("MRI_LIB_PATH") or os.path.join(_HERE, "libmri.so")
 MRI_OK, MRI_EINVAL, MRI_EHIP, MRI_ENONFINITE, MRI_EMAXSTEPS, MRI_ENOMEM, MRI_EUNSUPPORTED, \
     MRI_ECOMPILE = 0, -1, -2, -3, -4, -5, -6, -7
 CELL_NONFINITE, CELL_MAXSTEPS, CELL_TRANGE, CELL_NEARTIE = 1, 2, 4, 8
-FAST_RK4, FAST_ZONNEVELD43, FAST_HEUN, FAST_BS3 = 0, 1, 2, 3
+FAST_RK4, FAST_ZONNEVELD43, FAST_HEUN, FAST_BS3, FAST_CK5 = 0, 1, 2, 3, 4
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
 
 

@@ -99,7 +99,7 @@ def test_fast_stage_rejects_bad_arguments_without_device(mri):
     assert call(n_poly=5, rho=1) == mri.MRI_EINVAL
     assert call(opts=mri.fast_opts(n_sub=0)) == mri.MRI_EINVAL
     assert call(opts=mri.fast_opts(method=7)) == mri.MRI_EINVAL
-    for meth in (mri.FAST_HEUN, mri.FAST_BS3):
+    for meth in (mri.FAST_HEUN, mri.FAST_BS3, mri.FAST_CK5):
         assert call(opts=mri.fast_opts(method=meth, n_sub=0)) == mri.MRI_EINVAL
         assert call(opts=mri.fast_opts(method=meth, n_sub=4), n_cells=0, ld=0, yin=None,
                     yout=None) == mri.MRI_OK
@@ -161,5 +161,29 @@ def test_specialized_kernels_compile_for_every_fast_method(mri):
             assert m.specialize(64, load=False, method=meth, n_poly=n_poly) > 1000
     with pytest.raises(mri.MriError):
         m.specialize(64, load=False, method=9)
+    with pytest.raises(mri.MriError, match="no specialized kernel"):
+        m.specialize(64, load=False, method=mri.FAST_CK5)
     with pytest.raises(mri.MriError):
         m.specialize(64, load=False, method=mri.FAST_HEUN, n_poly=5)
+
+
+def test_cash_karp_limits(mri):
+    """Cash-Karp 5 runs on the generic kernel only and, for chemistry, up to
+    24 species: other requests fail before any device work."""
+    L = mri.lib
+
+    def call(m, **kw):
+        o = mri.fast_opts(method=mri.FAST_CK5, n_sub=4, **kw)
+        return L.mri_fast_stage(m.h, C.byref(o), 0, 0, None, None, 0, None, 1e-7, None, None,
+                                None)
+
+    small = mri.Mech(I.make_mechanism(0))
+    assert call(small) == mri.MRI_OK
+    assert call(small, kernel=mri.KERNEL_GENERIC) == mri.MRI_OK
+    assert call(small, kernel=mri.KERNEL_SPECIALIZED) == mri.MRI_EUNSUPPORTED
+    large = mri.Mech(I.make_mechanism(3))
+    assert large.n - 1 > 24
+    assert call(large) == mri.MRI_EUNSUPPORTED
+    assert "24 species" in mri.last_error()
+    lin = mri.Mech(A_linear=np.eye(3))
+    assert call(lin, kernel=mri.KERNEL_SPECIALIZED) == mri.MRI_OK

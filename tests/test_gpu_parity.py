@@ -230,12 +230,18 @@ def test_linear_mode_matches_oracle_and_is_third_order(torch, mri, O):
         assert np.all(rates > 2.7), (tb.name, rates)
 
 
+def _erk_methods(O, mri, method):
+    return {"heun": (O.ERK_HEUN, mri.FAST_HEUN), "bs3": (O.ERK_BS3, mri.FAST_BS3),
+            "ck5": (O.ERK_CK5, mri.FAST_CK5)}[method]
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("method", ["heun", "bs3"])
+@pytest.mark.parametrize("method", ["heun", "bs3", "ck5"])
 def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
-    """Heun and Bogacki-Shampine fast stages (the order-2 and order-3 fast
-    methods of the MRI-P(k) family) against the oracle's general explicit RK
-    stage with its own tableaus."""
+    """Heun, Bogacki-Shampine and Cash-Karp fast stages (the order-2, 3 and 5
+    fast methods of the MRI-P(k) family) against the oracle's general explicit
+    RK stage with its own tableaus.  Cash-Karp has only the generic kernel: the
+    specialized request is refused before any device work."""
     mech = I.make_mechanism(0)
     orc = O.Oracle(mech)
     y0 = I.initial_state(0)
@@ -243,14 +249,18 @@ def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
     F = _config0_forcing(O, orc, y0)
     rho = np.stack([F[k] / (k + 1) for k in range(2)])
     L, n_sub = (5.0 / 12.0) * 1e-6, 20
-    om, gm = (O.ERK_HEUN, mri.FAST_HEUN) if method == "heun" else (O.ERK_BS3, mri.FAST_BS3)
-    ref, st_o, _, _ = orc.fast_stage_soa(y0, rho, L, O.erk_opts(om, n_sub))
-    assert np.all(st_o[:512] == 0)
+    om, gm = _erk_methods(O, mri, method)
     m = mri.Mech(mech)
     yd = _dev(torch, y0)
     out = torch.empty_like(yd)
     steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
     opts = mri.fast_opts(method=gm, n_sub=n_sub, kernel=_kernel(mri, kernel))
+    if method == "ck5" and kernel == "specialized":
+        with pytest.raises(mri.MriError, match="no specialized kernel"):
+            mri.mri_fast_stage(m, opts, 512, ld, yd, out, 2, _dev(torch, rho), L, None, steps)
+        return
+    ref, st_o, _, _ = orc.fast_stage_soa(y0, rho, L, O.erk_opts(om, n_sub))
+    assert np.all(st_o[:512] == 0)
     mri.mri_fast_stage(m, opts, 512, ld, yd, out, 2, _dev(torch, rho), L, None, steps)
     torch.cuda.synchronize()
     e = assert_parity(out.cpu().numpy(), ref, mech.n_species, what=f"{method} {kernel}")
@@ -258,7 +268,7 @@ def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
     assert np.all(steps.cpu().numpy()[:512] == n_sub)
 
 
-@pytest.mark.parametrize("method,order", [("heun", 2), ("bs3", 3)])
+@pytest.mark.parametrize("method,order", [("heun", 2), ("bs3", 3), ("ck5", 5)])
 def test_mri_order_with_low_order_fast_methods(torch, mri, O, method, order):
     """MRI-P(k) on the linear two-rate problem: MIS-KW3 with k fixed fast
     substeps per stage and a fast method of order P converges at order
@@ -270,7 +280,7 @@ def test_mri_order_with_low_order_fast_methods(torch, mri, O, method, order):
     mF, mS = mri.Mech(A_linear=A_F), mri.Mech(A_linear=A_S)
     tb = I.table_mis_kw3()
     t = mri.Table(tb)
-    om, gm = (O.ERK_HEUN, mri.FAST_HEUN) if method == "heun" else (O.ERK_BS3, mri.FAST_BS3)
+    om, gm = _erk_methods(O, mri, method)
     k = 4
     errs = []
     for n_steps in (16, 32, 64, 128):
