@@ -149,10 +149,9 @@ void mri_table_destroy(mri_table *t);
      MRI_FAST_BS3          Bogacki-Shampine 3rd-order solution, n_sub uniform
                            substeps (the embedded estimate is not used)
      MRI_FAST_CK5          Cash-Karp 5th-order solution, n_sub uniform
-                           substeps; generic kernel only (MRI_KERNEL_
-                           SPECIALIZED and mri_mech_specialize_method return
-                           MRI_EUNSUPPORTED), chemistry with at most 24
-                           species (else MRI_EUNSUPPORTED)                 */
+                           substeps (the embedded estimate is not used);
+                           chemistry with at most 24 species, else
+                           MRI_EUNSUPPORTED                                */
 enum {
     MRI_FAST_RK4 = 0,
     MRI_FAST_ZONNEVELD43 = 1,

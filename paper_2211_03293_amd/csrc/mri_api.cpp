@@ -230,12 +230,34 @@ static ErkCoef erk_coef(int method)
 }
 
 // Run-time compiled kernel kind of a fast method: 0 RK4, 1 Zonneveld, 3 Heun,
-// 4 Bogacki-Shampine (2 is the batched work queue).
+// 4 Bogacki-Shampine, 5 Cash-Karp (2 is the batched work queue).
 static int spec_kind(int method)
 {
     return method == MRI_FAST_RK4 ? 0
            : method == MRI_FAST_ZONNEVELD43 ? 1
-           : method == MRI_FAST_HEUN ? 3 : 4;
+           : method == MRI_FAST_HEUN ? 3
+           : method == MRI_FAST_BS3 ? 4 : 5;
+}
+
+// Tableau macros of a full-tableau method for the run-time compiled kernel:
+// nodes and weights selected by the stage index, the stage matrix by the
+// (row, column) pair, all as literal constants (entries not listed are 0).
+static std::string erk_full_defs(const ErkFull &e)
+{
+    auto sel = [&](const double *v) {
+        std::string r = hexd(v[e.s - 1]);
+        for (int i = e.s - 2; i >= 0; --i)
+            r = "((j) == " + std::to_string(i) + " ? " + hexd(v[i]) + " : " + r + ")";
+        return r;
+    };
+    std::string a = "0.0";
+    for (int i = e.s - 1; i >= 1; --i)
+        for (int j = i - 1; j >= 0; --j)
+            if (e.a[i][j] != 0.0)
+                a = "(((i) == " + std::to_string(i) + " && (j) == " + std::to_string(j) + ") ? " +
+                    hexd(e.a[i][j]) + " : " + a + ")";
+    return "#define MRI_ERK_S " + std::to_string(e.s) + "\n#define MRI_ERK_C(j) " + sel(e.c) +
+           "\n#define MRI_ERK_B(j) " + sel(e.b) + "\n#define MRI_ERK_A(i, j) " + a + "\n";
 }
 
 // Tableau macros of a fixed-step method for the run-time compiled kernel:
@@ -270,6 +292,7 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
         group = std::max(1, std::atoi(g));
     std::string tune = "#define MRI_GROUP " + std::to_string(group) + "\n";
     if (kind == 3 || kind == 4) tune += erk_defs(erk_coef(kind == 3 ? MRI_FAST_HEUN : MRI_FAST_BS3));
+    if (kind == 5) tune += erk_full_defs(erk_full_ck5());
     std::string src = m->defs + tune + "#define WG " + std::to_string(wg) + "\n#define MRI_KIND " +
                       std::to_string(kind) + "\n#define MRI_NP " + std::to_string(np) + "\n" +
                       mri_spec_kernels_src;
@@ -383,13 +406,8 @@ static mri_status check_opts(const mri_mech *m, const mri_fast_opts *o)
     }
     if (o->kernel < MRI_KERNEL_AUTO || o->kernel > MRI_KERNEL_SPECIALIZED)
         return fail(MRI_EINVAL, "unknown kernel selector %d", o->kernel);
-    if (o->method == MRI_FAST_CK5 && m->kind == 0) {
-        if (o->kernel == MRI_KERNEL_SPECIALIZED)
-            return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 has no specialized kernel");
-        if (m->S > GEN_NMAX_SMALL)
-            return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 supports at most %d species",
-                        GEN_NMAX_SMALL);
-    }
+    if (o->method == MRI_FAST_CK5 && m->kind == 0 && m->S > GEN_NMAX_SMALL)
+        return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 supports at most %d species", GEN_NMAX_SMALL);
     if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 &&
         o->block_size != 256)
         return fail(MRI_EINVAL, "block_size must be 0, 64, 128 or 256 (got %d)", o->block_size);
@@ -407,24 +425,14 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
     if (n_cells == 0) return MRI_OK;
     mri_status dst = ensure_device(m);
     if (dst != MRI_OK) return dst;
-    if (o->method == MRI_FAST_CK5) {
-        // full-tableau method: generic kernels only (stage derivatives held in
-        // registers, so chemistry is limited to GEN_NMAX_SMALL species)
-        if (m->kind == 1) {
+    if (m->kind == 1) {
+        if (o->method == MRI_FAST_CK5) {
             HIP_TRY(launch_lin_erk(m->n, m->d_A, erk_full_ck5(), n_cells, ld, yin, yout, n_poly,
                                    rho, L, o->n_sub, status, steps, accumulate, s));
         } else {
-            HIP_TRY(launch_gen_erk(m->gm, erk_full_ck5(), o->block_size ? o->block_size : 64,
-                                   n_cells, ld, yin, yout, n_poly, rho, L, o->n_sub, status,
-                                   steps, accumulate, s));
+            HIP_TRY(launch_lin_rk4(m->n, m->d_A, erk_coef(o->method), n_cells, ld, yin, yout,
+                                   n_poly, rho, L, o->n_sub, status, steps, accumulate, s));
         }
-        ++c_fast;
-        c_cells += n_cells;
-        return MRI_OK;
-    }
-    if (m->kind == 1) {
-        HIP_TRY(launch_lin_rk4(m->n, m->d_A, erk_coef(o->method), n_cells, ld, yin, yout, n_poly,
-                               rho, L, o->n_sub, status, steps, accumulate, s));
         ++c_fast;
         c_cells += n_cells;
         return MRI_OK;
@@ -445,7 +453,12 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
     }
     if (kind == MRI_KERNEL_GENERIC) {
         if (!wg) wg = default_block(MRI_KERNEL_GENERIC);
-        if (fixed_step(o->method)) {
+        if (o->method == MRI_FAST_CK5) {
+            // stage derivatives held in registers: at most GEN_NMAX_SMALL
+            // species (checked with the options)
+            HIP_TRY(launch_gen_erk(m->gm, erk_full_ck5(), wg, n_cells, ld, yin, yout, n_poly,
+                                   rho, L, o->n_sub, status, steps, accumulate, s));
+        } else if (fixed_step(o->method)) {
             HIP_TRY(launch_gen_rk4(m->gm, erk_coef(o->method), wg, n_cells, ld, yin, yout, n_poly,
                                    rho, L, o->n_sub, status, steps, accumulate, s));
         } else {
@@ -680,8 +693,8 @@ mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int b
     if (!fixed_step(method) && method != MRI_FAST_ZONNEVELD43)
         return fail(MRI_EINVAL, "unknown fast method %d", method);
     if (n_poly < 0 || n_poly > 4) return fail(MRI_EINVAL, "n_poly must be in [0, 4]");
-    if (method == MRI_FAST_CK5)
-        return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 has no specialized kernel");
+    if (method == MRI_FAST_CK5 && m->S > GEN_NMAX_SMALL)
+        return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 supports at most %d species", GEN_NMAX_SMALL);
     const int kind = spec_kind(method);
     if (load) {
         hipFunction_t fn = nullptr;

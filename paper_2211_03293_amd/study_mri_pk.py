@@ -5,13 +5,17 @@ explicit RK methods of order P, k fast steps per stage).
 
 Problem: the 64^3 periodic fields, 21 species / 84 reactions, advection-
 diffusion slow side, integrated to t = 1e-6 s.  For every fast method
-(Heun P = 2, Bogacki-Shampine P = 3, classic RK4 P = 4) and slow step H the
+(Heun P = 2, Bogacki-Shampine P = 3, classic RK4 P = 4, which is also the
+propagated solution of Zonneveld's pair, Cash-Karp P = 5) and slow step H the
 errors are taken over all cells against a reference run with H/8 of the finest
-H and RK4 with 4k substeps: the max absolute mass-fraction error (the paper
-reports max-norm errors, Table 1), the max relative temperature error and the
-max relative state error with the mass-fraction floor 1e-8.
+H and RK4 with 4 max(k) substeps: the max absolute mass-fraction error (the
+paper reports max-norm errors, Table 1), the max relative temperature error
+and the max relative state error with the mass-fraction floor 1e-8.  --k takes
+one substep count for every method or one per method (Sec. 5.1 found
+MRI-2(8), MRI-3(4), MRI-4(8) and MRI-5(4) the most efficient pairings).
 
     python -m paper_2211_03293_amd.study_mri_pk [--cells-per-side 32] [--k 16]
+    python -m paper_2211_03293_amd.study_mri_pk --k 8 4 8 4 --H 2.5e-8 1.25e-8 6.25e-9
 """
 from __future__ import annotations
 
@@ -26,7 +30,7 @@ from . import inputs as I
 from . import mri
 
 T_END = 1e-6
-METHODS = (("Heun", 2), ("Bogacki-Shampine", 3), ("RK4", 4))
+METHODS = (("Heun", 2), ("Bogacki-Shampine", 3), ("RK4", 4), ("Cash-Karp", 5))
 
 
 def _fields(n_side):
@@ -69,7 +73,8 @@ def errors(y, ref, n_species):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--cells-per-side", type=int, default=32)
-    ap.add_argument("--k", type=int, default=16, help="fast substeps per stage")
+    ap.add_argument("--k", type=int, nargs="+", default=[16],
+                    help="fast substeps per stage: one value, or one per method (P = 2..5)")
     ap.add_argument("--H", type=float, nargs="+", default=[1e-7, 5e-8, 2.5e-8, 1.25e-8])
     args = ap.parse_args(argv)
     import torch
@@ -77,27 +82,33 @@ def main(argv=None):
     torch.cuda.set_device(0)
     mech = I.make_mechanism(1)
     m = mri.Mech(mech)
-    for meth, _ in ((mri.FAST_HEUN, 0), (mri.FAST_BS3, 0), (mri.FAST_RK4, 0)):
+    if len(args.k) not in (1, len(METHODS)):
+        ap.error(f"--k takes 1 or {len(METHODS)} values")
+    ks = args.k * len(METHODS) if len(args.k) == 1 else args.k
+    for meth in (mri.FAST_HEUN, mri.FAST_BS3, mri.FAST_RK4, mri.FAST_CK5):
         m.specialize(128, load=True, method=meth, n_poly=1)
     t = mri.Table(I.table_mis_kw3())
     y0, grid = _fields(args.cells_per_side)
     H_ref = min(args.H) / 8
-    ref, t_ref, bad = run(torch, m, t, y0, grid, mri.FAST_RK4, 4 * args.k, H_ref)
-    print(f"# reference: H = {H_ref:.3e}, RK4 {4 * args.k} substeps/stage, {t_ref:.2f} s, "
+    k_ref = 4 * max(ks)
+    ref, t_ref, bad = run(torch, m, t, y0, grid, mri.FAST_RK4, k_ref, H_ref)
+    print(f"# reference: H = {H_ref:.3e}, RK4 {k_ref} substeps/stage, {t_ref:.2f} s, "
           f"flagged {bad}", flush=True)
     rows = []
-    for (name, P), meth in zip(METHODS, (mri.FAST_HEUN, mri.FAST_BS3, mri.FAST_RK4)):
+    fast = (mri.FAST_HEUN, mri.FAST_BS3, mri.FAST_RK4, mri.FAST_CK5)
+    for (name, P), meth, k in zip(METHODS, fast, ks):
         prev = None
         for H in args.H:
-            y, dt, bad = run(torch, m, t, y0, grid, meth, args.k, H)
+            y, dt, bad = run(torch, m, t, y0, grid, meth, k, H)
             e = errors(y, ref, mech.n_species)
             rate = None if prev is None else [float(np.log2(a / b)) for a, b in zip(prev, e)]
             prev = e
-            rows.append(dict(method=name, P=P, k=args.k, H=H, err_Y_abs=e[0], err_T_rel=e[1],
+            rows.append(dict(method=name, P=P, k=k, H=H, err_Y_abs=e[0], err_T_rel=e[1],
                              err_rel=e[2], rates=rate, seconds=dt, flagged=bad))
-            print(f"MRI-{P}({args.k}) {name:17s} H = {H:.3e}: |dY| {e[0]:.3e}  dT/T {e[1]:.3e}  "
+            print(f"MRI-{P}({k}) {name:17s} H = {H:.3e}: |dY| {e[0]:.3e}  dT/T {e[1]:.3e}  "
                   f"rel {e[2]:.3e}" + (" rates " + " ".join(f"{r:.2f}" for r in rate)
-                                      if rate else "") + f"  {dt * 1e3:.1f} ms", flush=True)
+                                      if rate else "") + f"  {dt * 1e3:.1f} ms  flagged {bad}",
+                  flush=True)
     print(json.dumps(dict(study="MRI-P(k) convergence, MIS-KW3 slow, 21 species / 84 reactions, "
                                 f"{args.cells_per_side}^3 cells, t = {T_END}", rows=rows)))
     return rows

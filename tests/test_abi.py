@@ -156,20 +156,21 @@ def test_specialized_kernels_compile_for_gfx950(mri, config):
 
 def test_specialized_kernels_compile_for_every_fast_method(mri):
     m = mri.Mech(I.make_mechanism(0))
-    for meth in (mri.FAST_RK4, mri.FAST_ZONNEVELD43, mri.FAST_HEUN, mri.FAST_BS3):
+    for meth in (mri.FAST_RK4, mri.FAST_ZONNEVELD43, mri.FAST_HEUN, mri.FAST_BS3,
+                 mri.FAST_CK5):
         for n_poly in (0, 2):
             assert m.specialize(64, load=False, method=meth, n_poly=n_poly) > 1000
     with pytest.raises(mri.MriError):
         m.specialize(64, load=False, method=9)
-    with pytest.raises(mri.MriError, match="no specialized kernel"):
-        m.specialize(64, load=False, method=mri.FAST_CK5)
+    with pytest.raises(mri.MriError, match="24 species"):
+        mri.Mech(I.make_mechanism(3)).specialize(64, load=False, method=mri.FAST_CK5)
     with pytest.raises(mri.MriError):
         m.specialize(64, load=False, method=mri.FAST_HEUN, n_poly=5)
 
 
 def test_cash_karp_limits(mri):
-    """Cash-Karp 5 runs on the generic kernel only and, for chemistry, up to
-    24 species: other requests fail before any device work."""
+    """Cash-Karp 5 runs chemistry of up to 24 species; larger mechanisms are
+    refused before any device work."""
     L = mri.lib
 
     def call(m, **kw):
@@ -180,7 +181,7 @@ def test_cash_karp_limits(mri):
     small = mri.Mech(I.make_mechanism(0))
     assert call(small) == mri.MRI_OK
     assert call(small, kernel=mri.KERNEL_GENERIC) == mri.MRI_OK
-    assert call(small, kernel=mri.KERNEL_SPECIALIZED) == mri.MRI_EUNSUPPORTED
+    assert call(small, kernel=mri.KERNEL_SPECIALIZED) == mri.MRI_OK
     large = mri.Mech(I.make_mechanism(3))
     assert large.n - 1 > 24
     assert call(large) == mri.MRI_EUNSUPPORTED

@@ -240,8 +240,7 @@ def _erk_methods(O, mri, method):
 def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
     """Heun, Bogacki-Shampine and Cash-Karp fast stages (the order-2, 3 and 5
     fast methods of the MRI-P(k) family) against the oracle's general explicit
-    RK stage with its own tableaus.  Cash-Karp has only the generic kernel: the
-    specialized request is refused before any device work."""
+    RK stage with its own tableaus."""
     mech = I.make_mechanism(0)
     orc = O.Oracle(mech)
     y0 = I.initial_state(0)
@@ -255,10 +254,6 @@ def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
     out = torch.empty_like(yd)
     steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
     opts = mri.fast_opts(method=gm, n_sub=n_sub, kernel=_kernel(mri, kernel))
-    if method == "ck5" and kernel == "specialized":
-        with pytest.raises(mri.MriError, match="no specialized kernel"):
-            mri.mri_fast_stage(m, opts, 512, ld, yd, out, 2, _dev(torch, rho), L, None, steps)
-        return
     ref, st_o, _, _ = orc.fast_stage_soa(y0, rho, L, O.erk_opts(om, n_sub))
     assert np.all(st_o[:512] == 0)
     mri.mri_fast_stage(m, opts, 512, ld, yd, out, 2, _dev(torch, rho), L, None, steps)
