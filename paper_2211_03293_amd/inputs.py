@@ -129,6 +129,36 @@ def table_erk33a() -> Table:
     return Table("MRI-GARK-ERK33a", c, g)
 
 
+# 4th-order explicit MRI-GARK table with a linear-in-time forcing (Sandu's
+# ERK45a, from the MRI-GARK family the paper builds on, Sec. 2.1): six stages at
+# c = (0, 1/5, 2/5, 3/5, 4/5, 1); rows of Gamma^(0) and Gamma^(1) as exact
+# rationals (numerator, denominator), column j = 0, 1, ...
+ERK45A_GAMMA = (
+    (((1, 5),),
+     ((-53, 16), (281, 80)),
+     ((-36562993, 71394880), (34903117, 17848720), (-88770499, 71394880)),
+     ((-7631593, 71394880), (-166232021, 35697440), (6068517, 1519040), (8644289, 8924360)),
+     ((277061, 303808), (-209323, 1139280), (-1360217, 1139280), (-148789, 56964),
+      (147889, 45120))),
+    (((0, 1),),
+     ((503, 80), (-503, 80)),
+     ((-1365537, 35697440), (4963773, 7139488), (-1465833, 2231090)),
+     ((66974357, 35697440), (21445367, 7139488), (-3, 1), (-8388609, 4462180)),
+     ((-18227, 7520), (2, 1), (1, 1), (5, 1), (-41933, 7520))),
+)
+
+
+def table_erk45a() -> Table:
+    """4th-order explicit MRI-GARK table (n_gamma = 2, s = 6), ERK45A_GAMMA."""
+    c = np.arange(6) / 5.0
+    g = np.zeros((2, 6, 6))
+    for k, rows in enumerate(ERK45A_GAMMA):
+        for i, row in enumerate(rows, start=1):
+            for j, (num, den) in enumerate(row):
+                g[k, i, j] = num / den
+    return Table("MRI-GARK-ERK45a", c, g)
+
+
 def table_zero_forcing(c) -> Table:
     """Coupling table with Gamma = 0 (pure fast integration over the stage grid)."""
     c = np.asarray(c, dtype=np.float64)

@@ -198,7 +198,7 @@ def test_zonneveld_forced_decisions_replay(oracle_mod):
 # ---------------------------------------------------------------------------
 # MRI-GARK slow step
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("table", [I.table_mis_kw3(), I.table_erk33a()])
+@pytest.mark.parametrize("table", [I.table_mis_kw3(), I.table_erk33a(), I.table_erk45a()])
 def test_table_consistency(table):
     """sum_j sum_k Gamma^(k)_ij/(k+1) = dc_i, strictly lower triangular."""
     dc = np.diff(table.c)
@@ -207,6 +207,37 @@ def test_table_consistency(table):
         assert tot == pytest.approx(dc[i - 1], abs=1e-15)
     for k in range(table.n_gamma):
         assert np.all(np.triu(table.gamma[k]) == 0)
+
+
+def test_erk45a_consistency_exact_in_rationals():
+    """The 4th-order table's rows meet sum_j (Gamma^(0)_ij + Gamma^(1)_ij / 2) = 1/5
+    exactly as rationals, and the float table is their rounding."""
+    from fractions import Fraction
+    tb = I.table_erk45a()
+    for i in range(1, 6):
+        g0 = [Fraction(n, d) for n, d in I.ERK45A_GAMMA[0][i - 1]]
+        g1 = [Fraction(n, d) for n, d in I.ERK45A_GAMMA[1][i - 1]]
+        assert len(g0) == len(g1) == i
+        assert sum(g0) + sum(g1) / 2 == Fraction(1, 5)
+        for j in range(i):
+            assert tb.gamma[0, i, j] == float(g0[j]) and tb.gamma[1, i, j] == float(g1[j])
+
+
+def test_mri_order_four_on_linear_two_rate_problem(oracle_mod):
+    """Sec. 2.1: explicit MRI-GARK methods reach order 4; the ERK45a table on the
+    non-commuting linear problem against expm((A_F + A_S) t) y0."""
+    orc = oracle_mod.Oracle(A_fast=A_F)
+    y0 = np.array([1.0, 0.5])
+    errs = []
+    for n_steps in (8, 16, 32, 64):
+        H = 1.0 / n_steps
+        y = y0.copy()
+        for _ in range(n_steps):
+            y, st, _, _ = orc.mri_step_linear(I.table_erk45a(), oracle_mod.rk4_opts(64), A_S, y, H)
+            y = y[:, 0]
+        errs.append(np.abs(y - expm(A_F + A_S) @ y0).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 3.8) and rates[-1] < 4.3, rates
 
 
 def _kw3_erk_step(A, y, H):
