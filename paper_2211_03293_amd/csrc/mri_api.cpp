@@ -334,6 +334,11 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     m->last_code.assign(cs, 0);
     hiprtcGetCode(prog, m->last_code.data());
     hiprtcDestroyProgram(&prog);
+    if (const char *dir = std::getenv("MRI_SPEC_DUMP_DIR"))   // debugging aid
+        std::ofstream(std::string(dir) + "/mri_spec_w" + std::to_string(wg) + "_k" +
+                          std::to_string(kind) + "_p" + std::to_string(np) + ".co",
+                      std::ios::binary)
+            .write(m->last_code.data(), (std::streamsize)m->last_code.size());
     ++c_spec;
     if (!load) return MRI_OK;
     SpecKernel sk;
