@@ -209,6 +209,55 @@ mri_status mri_slow_step(const mri_mech *m, const mri_table *t, const mri_fast_o
                          int ld, double *y, void *ws, size_t ws_bytes, int32_t *status_out,
                          int32_t *steps_out, mri_stream_t stream);
 
+/* ------------------------------------------------------------------------- */
+/* Adaptive slow steps (Sec. 7 names adaptive step control as the way to spare */
+/* users the manual choice of fast and slow step sizes).  Integrates y in place */
+/* from t0 to t_end with mri_slow_step, choosing H by step doubling: an attempt */
+/* takes one step of H and two of H/2 from the same state; the error estimate   */
+/* is e = (y_half - y_full) / (2^order - 1) in the WRMS norm over every cell and */
+/* component, sqrt(mean (e / (atol_c + rtol |y_half|))^2), atol_c = atol_T for  */
+/* the temperature of chemistry states and atol_Y otherwise.  ||e|| <= 1 accepts */
+/* (y <- y_half, t <- t + H); either way H <- H min(fac_max, max(fac_min,        */
+/* safety ||e||^(-1/(order+1)))) (fac_max if ||e|| = 0, fac_min if not finite),  */
+/* bounded by H_max; the last step is shortened to end exactly at t_end.         */
+/* Fast side: the adaptive fast method uses opts as given; a fixed-step method   */
+/* keeps the fast step of the first step, opts->n_sub substeps per stage at H0:  */
+/* a step of size h uses max(1, ceil(n_sub h / H0 - 1e-9)) substeps per stage.  */
+/* Fails with MRI_EMAXSTEPS when max_attempts attempts do not reach t_end or a  */
+/* rejected step falls below H_min (stats then describe the state reached; y    */
+/* holds the last accepted state).  status_out (optional, device [n_cells]) is  */
+/* the OR of the cell flags of every accepted step.  Synchronizes the stream    */
+/* once per attempt (the accept decision is taken on the host).                */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double rtol, atol_Y, atol_T;  /* error weights (rtol >= 0, atol > 0)          */
+    double H0;                    /* first step size (> 0)                          */
+    double H_min, H_max;          /* bounds; H_max = 0 means unbounded             */
+    int order;                    /* order p of the slow table, 1..8               */
+    int max_attempts;             /* cap on attempted steps (>= 1)                 */
+    double safety, fac_min, fac_max; /* 0 selects 0.9, 0.2, 5                      */
+} mri_adapt_opts;
+
+typedef struct {
+    int accepted, rejected;       /* slow steps                                     */
+    double t;                     /* time reached                                   */
+    double H_last;                /* last accepted step size                        */
+    double H_next;                /* proposed next step size                        */
+    double err_last;              /* WRMS error estimate of the last attempt       */
+    int64_t fast_steps;           /* fast substeps of the accepted steps' half     */
+                                  /* steps, summed over cells                       */
+} mri_adapt_stats;
+
+/* Workspace of mri_adaptive_run: mri_workspace_bytes plus two state copies,
+   four per-cell counters and the per-block error partials. */
+mri_status mri_adaptive_workspace_bytes(const mri_mech *m, const mri_table *t, int n_cells,
+                                        int ld, size_t *bytes);
+mri_status mri_adaptive_run(const mri_mech *m, const mri_table *t, const mri_fast_opts *opts,
+                            const mri_adapt_opts *a, mri_slow_rhs f_slow, void *user, double t0,
+                            double t_end, int n_cells, int ld, double *y, void *ws,
+                            size_t ws_bytes, int32_t *status_out, mri_adapt_stats *stats,
+                            mri_stream_t stream);
+
 /* Built-in slow RHS: 2nd-order centred advection-diffusion on a periodic grid
    (Sec. 3, eq. problem2 transport terms; Sec. 3.1 second-order stencils) for
    every component: f = -u . grad(phi) + D lap(phi).  Cell index

@@ -291,6 +291,78 @@ def zonneveld_tableau():
     return c, a.reshape(5, 4), b, bh
 
 
+def adaptive_run(step, y0, t0, t_end, order, rtol, atol_Y, atol_T, H0, t_comp=None,
+                 n_cells=None, H_min=0.0, H_max=0.0, max_attempts=10000, safety=0.9,
+                 fac_min=0.2, fac_max=5.0):
+    """Adaptive slow steps by step doubling (the adaptive step control Sec. 7
+    proposes for multirate methods), written out plainly.
+
+    step(y, t, H) -> (y_new, status): one MRI step.  Each attempt takes one step
+    of H and two of H/2 from the same state; the error estimate of the half-step
+    result is (y_half - y_full) / (2^order - 1) (Richardson: the two results
+    differ by (2^order - 1) times the half-step error to leading order).  Its
+    WRMS norm over the first n_cells columns and every component, with weights
+    1 / (atol + rtol |y_half|) (atol_T on row t_comp, atol_Y elsewhere), accepts
+    at <= 1.  Step-size factor safety err^(-1/(order+1)), clipped to
+    [fac_min, fac_max]; the last step ends exactly at t_end.
+    Returns (y, stats, history) with history = [(t, H, err, accepted), ...]."""
+    y = np.array(y0, dtype=np.float64, copy=True)
+    n_cells = y.shape[1] if n_cells is None else n_cells
+    atol = np.full((y.shape[0], 1), float(atol_Y))
+    if t_comp is not None:
+        atol[t_comp] = atol_T
+    t = t0
+    H = min(H0, H_max) if H_max > 0 else H0
+    stats = dict(accepted=0, rejected=0, H_last=0.0)
+    hist = []
+    attempts = 0
+    while t < t_end:
+        if attempts >= max_attempts:
+            raise RuntimeError("attempt cap reached")
+        attempts += 1
+        Hs, last = H, False
+        if t + Hs >= t_end - 1e-12 * (t_end - t0):
+            Hs, last = t_end - t, True
+        y_full, _ = step(y, t, Hs)
+        y_mid, st1 = step(y, t, 0.5 * Hs)
+        y_half, st2 = step(y_mid, t + 0.5 * Hs, 0.5 * Hs)
+        e = (y_half[:, :n_cells] - y_full[:, :n_cells]) / (2.0 ** order - 1.0)
+        w = e / (atol + rtol * np.abs(y_half[:, :n_cells]))
+        err = float(np.sqrt(np.mean(w * w)))
+        if not np.isfinite(err):
+            err = np.inf
+        if err == 0.0:
+            fac = fac_max
+        elif err == np.inf:
+            fac = fac_min
+        else:
+            fac = safety * err ** (-1.0 / (order + 1))
+        fac = min(fac_max, max(fac_min, fac))
+        hist.append((t, Hs, err, err <= 1.0))
+        if err <= 1.0:
+            y = y_half
+            t = t_end if last else t + Hs
+            stats["accepted"] += 1
+            stats["H_last"] = Hs
+        else:
+            stats["rejected"] += 1
+        H = Hs * fac
+        if H_max > 0:
+            H = min(H, H_max)
+        if err > 1.0 and H < H_min:
+            raise RuntimeError("step size fell below H_min")
+    stats["t"] = t
+    stats["H_next"] = H
+    return y, stats, hist
+
+
+def fixed_substeps(n_sub, H, H0):
+    """Substeps per stage of a fixed-step fast method for a slow step H when the
+    fast step of the first step (n_sub at H0) is kept."""
+    import math
+    return max(1, math.ceil(n_sub * (H / H0) - 1e-9))
+
+
 def set_threads(n):
     lib().ora_set_num_threads(int(n))
 

@@ -107,7 +107,80 @@ __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
     if (i < n) p[i] = v;
 }
 
+// Step-doubling error of an adaptive slow step, reduced per block: for every
+// cell and component w = scale (y_half - y_full) / (atol_c + rtol |y_half|),
+// atol_c = atol_T for the last component (temperature) of chemistry states;
+// part_w2[block] = sum of w^2 over the block's cells, part_steps[block] = sum
+// of the fast substeps of the two half steps.  The block reduction runs in a
+// fixed tree order; the host sums the partials in block order.
+__global__ void __launch_bounds__(256)
+    k_step_err(int n, int t_comp, int n_cells, int ld, const double *__restrict__ y_half,
+               const double *__restrict__ y_full, double scale, double rtol, double atol,
+               double atol_t, const int32_t *__restrict__ sp_a, const int32_t *__restrict__ sp_b,
+               double *part_w2, long long *part_steps)
+{
+    __shared__ double w2s[256];
+    __shared__ long long sts[256];
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    long long nst = 0;
+    if (cell < n_cells) {
+        for (int c = 0; c < n; ++c) {
+            const size_t o = (size_t)c * ld + cell;
+            const double yh = y_half[o];
+            const double w = scale * (yh - y_full[o]) / ((c == t_comp ? atol_t : atol) + rtol * fabs(yh));
+            acc = fma(w, w, acc);
+        }
+        if (sp_a) nst += sp_a[cell];
+        if (sp_b) nst += sp_b[cell];
+    }
+    w2s[threadIdx.x] = acc;
+    sts[threadIdx.x] = nst;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            w2s[threadIdx.x] += w2s[threadIdx.x + h];
+            sts[threadIdx.x] += sts[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part_w2[blockIdx.x] = w2s[0];
+        part_steps[blockIdx.x] = sts[0];
+    }
+}
+
+// status_out[cell] |= st_a[cell] | st_b[cell] (flags of an accepted step)
+__global__ void __launch_bounds__(256)
+    k_status_merge(int n_cells, const int32_t *__restrict__ st_a, const int32_t *__restrict__ st_b,
+                   int32_t *status_out)
+{
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell < n_cells) status_out[cell] |= st_a[cell] | st_b[cell];
+}
+
 }  // namespace
+
+hipError_t launch_step_err(int n, int t_comp, int n_cells, int ld, const double *y_half,
+                           const double *y_full, double scale, double rtol, double atol,
+                           double atol_t, const int32_t *sp_a, const int32_t *sp_b,
+                           double *part_w2, long long *part_steps, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(k_step_err, dim3(step_err_blocks(n_cells)), dim3(block), 0, s, n, t_comp,
+                       n_cells, ld, y_half, y_full, scale, rtol, atol, atol_t, sp_a, sp_b, part_w2,
+                       part_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_merge(int n_cells, const int32_t *st_a, const int32_t *st_b,
+                               int32_t *status_out, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(k_status_merge, dim3((n_cells + block - 1) / block), dim3(block), 0, s,
+                       n_cells, st_a, st_b, status_out);
+    return hipGetLastError();
+}
 
 hipError_t launch_forcing(long long n_elem, int n_gamma, int nj, const double *F,
                           long long F_stride, ForcingCoef coef, double *rho, hipStream_t s)

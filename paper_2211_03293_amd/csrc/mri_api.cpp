@@ -842,6 +842,167 @@ mri_status mri_slow_step(const mri_mech *mc, const mri_table *t, const mri_fast_
     return MRI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive slow steps (step doubling)
+// ---------------------------------------------------------------------------
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+mri_status mri_adaptive_workspace_bytes(const mri_mech *m, const mri_table *t, int n_cells,
+                                        int ld, size_t *bytes)
+{
+    size_t base = 0;
+    mri_status st = mri_workspace_bytes(m, t, n_cells, ld, &base);
+    if (st != MRI_OK) return st;
+    const size_t vec = sizeof(double) * (size_t)m->n * (size_t)ld;
+    const size_t nb = (size_t)step_err_blocks(n_cells);
+    *bytes = align256(base) + 2 * align256(vec) + 4 * align256(sizeof(int32_t) * (size_t)ld) +
+             align256(nb * sizeof(double)) + align256(nb * sizeof(long long));
+    return MRI_OK;
+}
+
+mri_status mri_adaptive_run(const mri_mech *mc, const mri_table *t, const mri_fast_opts *opts,
+                            const mri_adapt_opts *a, mri_slow_rhs f_slow, void *user, double t0,
+                            double t_end, int n_cells, int ld, double *y, void *ws,
+                            size_t ws_bytes, int32_t *status_out, mri_adapt_stats *stats,
+                            mri_stream_t stream)
+{
+    mri_mech *m = const_cast<mri_mech *>(mc);
+    if (!m || !t) return fail(MRI_EINVAL, "mech or table is NULL");
+    mri_status st = check_opts(m, opts);
+    if (st != MRI_OK) return st;
+    if (!a) return fail(MRI_EINVAL, "adaptive options are NULL");
+    if (!f_slow) return fail(MRI_EINVAL, "slow RHS callback is NULL");
+    const bool fin = std::isfinite(a->rtol) && std::isfinite(a->atol_Y) &&
+                     std::isfinite(a->atol_T) && std::isfinite(a->H0) &&
+                     std::isfinite(a->H_min) && std::isfinite(a->H_max);
+    if (!fin || !(a->rtol >= 0.0) || !(a->atol_Y > 0.0) || !(a->atol_T > 0.0))
+        return fail(MRI_EINVAL, "tolerances must be finite with atol > 0, rtol >= 0");
+    if (!(a->H0 > 0.0) || !(a->H_min >= 0.0) || !(a->H_max >= 0.0) ||
+        (a->H_max > 0.0 && a->H_max < a->H_min))
+        return fail(MRI_EINVAL, "need H0 > 0, 0 <= H_min <= H_max (H_max = 0: unbounded)");
+    if (a->order < 1 || a->order > 8) return fail(MRI_EINVAL, "order must be in [1, 8]");
+    if (a->max_attempts < 1) return fail(MRI_EINVAL, "max_attempts must be >= 1");
+    const double safety = a->safety == 0.0 ? 0.9 : a->safety;
+    const double fac_min = a->fac_min == 0.0 ? 0.2 : a->fac_min;
+    const double fac_max = a->fac_max == 0.0 ? 5.0 : a->fac_max;
+    if (!(safety > 0.0 && safety <= 1.0) || !(fac_min > 0.0 && fac_min < 1.0) ||
+        !(fac_max > 1.0 && std::isfinite(fac_max)))
+        return fail(MRI_EINVAL, "need 0 < safety <= 1, 0 < fac_min < 1 < fac_max");
+    if (!std::isfinite(t0) || !std::isfinite(t_end) || !(t_end > t0))
+        return fail(MRI_EINVAL, "need finite t0 < t_end");
+    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if ((long long)ld * m->n > (1ll << 31) - 1)
+        return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
+    size_t need = 0, base = 0;
+    mri_adaptive_workspace_bytes(m, t, n_cells, ld, &need);
+    mri_workspace_bytes(m, t, n_cells, ld, &base);
+    mri_adapt_stats loc{};
+    mri_adapt_stats *sp = stats ? stats : &loc;
+    *sp = mri_adapt_stats{};
+    sp->t = t0;
+    sp->H_next = a->H0;
+    if (n_cells == 0) {
+        sp->t = t_end;
+        return MRI_OK;
+    }
+    if (!y) return fail(MRI_EINVAL, "y is NULL");
+    if (!ws || ws_bytes < need)
+        return fail(MRI_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    // workspace: slow-step workspace | y_full | y_half | st_a st_b sp_a sp_b | partials
+    const size_t vec = sizeof(double) * (size_t)m->n * (size_t)ld;
+    const size_t ivec = align256(sizeof(int32_t) * (size_t)ld);
+    const int nb = step_err_blocks(n_cells);
+    char *p = (char *)ws;
+    void *sws = p;
+    p += align256(base);
+    double *yf = (double *)p;
+    p += align256(vec);
+    double *yh = (double *)p;
+    p += align256(vec);
+    int32_t *st_a = (int32_t *)p, *st_b = (int32_t *)(p + ivec);
+    int32_t *sp_a = (int32_t *)(p + 2 * ivec), *sp_b = (int32_t *)(p + 3 * ivec);
+    p += 4 * ivec;
+    double *part_w2 = (double *)p;
+    p += align256(nb * sizeof(double));
+    long long *part_steps = (long long *)p;
+    if (status_out) HIP_TRY(hipMemsetAsync(status_out, 0, sizeof(int32_t) * n_cells, s));
+    const int t_comp = m->kind == 0 ? m->n - 1 : -1;
+    const double scale = 1.0 / (std::ldexp(1.0, a->order) - 1.0);
+    const bool fixed = fixed_step(opts->method);
+    std::vector<double> hw(nb);
+    std::vector<long long> hs(nb);
+    mri_fast_opts fo = *opts;
+    // fixed-step fast methods keep the fast step size of the first step
+    auto nsub_for = [&](double h) {
+        return fixed ? std::max(1, (int)std::ceil(opts->n_sub * (h / a->H0) - 1e-9)) : opts->n_sub;
+    };
+    double tc = t0;
+    double H = a->H_max > 0.0 ? std::min(a->H0, a->H_max) : a->H0;
+    int attempts = 0;
+    while (tc < t_end) {
+        if (attempts >= a->max_attempts)
+            return fail(MRI_EMAXSTEPS, "%d attempted steps did not reach t_end (t = %.17g)",
+                        attempts, tc);
+        ++attempts;
+        double Hs = H;
+        bool last = false;
+        if (tc + Hs >= t_end - 1e-12 * (t_end - t0)) {
+            Hs = t_end - tc;
+            last = true;
+        }
+        HIP_TRY(hipMemcpyAsync(yf, y, vec, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(yh, y, vec, hipMemcpyDeviceToDevice, s));
+        fo.n_sub = nsub_for(Hs);
+        st = mri_slow_step(m, t, &fo, f_slow, user, tc, Hs, n_cells, ld, yf, sws, base, nullptr,
+                           nullptr, stream);
+        if (st != MRI_OK) return st;
+        fo.n_sub = nsub_for(0.5 * Hs);
+        st = mri_slow_step(m, t, &fo, f_slow, user, tc, 0.5 * Hs, n_cells, ld, yh, sws, base,
+                           st_a, sp_a, stream);
+        if (st != MRI_OK) return st;
+        st = mri_slow_step(m, t, &fo, f_slow, user, tc + 0.5 * Hs, 0.5 * Hs, n_cells, ld, yh,
+                           sws, base, st_b, sp_b, stream);
+        if (st != MRI_OK) return st;
+        HIP_TRY(launch_step_err(m->n, t_comp, n_cells, ld, yh, yf, scale, a->rtol, a->atol_Y,
+                                a->atol_T, sp_a, sp_b, part_w2, part_steps, s));
+        HIP_TRY(hipMemcpyAsync(hw.data(), part_w2, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hs.data(), part_steps, sizeof(long long) * nb,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double sum = 0.0;
+        long long fast = 0;
+        for (int b = 0; b < nb; ++b) {
+            sum += hw[b];
+            fast += hs[b];
+        }
+        double err = std::sqrt(sum / ((double)m->n * (double)n_cells));
+        if (!std::isfinite(err)) err = HUGE_VAL;
+        double fac = err == 0.0       ? fac_max
+                     : err == HUGE_VAL ? fac_min
+                                       : safety * std::pow(err, -1.0 / (a->order + 1));
+        fac = std::min(fac_max, std::max(fac_min, fac));
+        sp->err_last = err;
+        if (err <= 1.0) {
+            HIP_TRY(hipMemcpyAsync(y, yh, vec, hipMemcpyDeviceToDevice, s));
+            if (status_out) HIP_TRY(launch_status_merge(n_cells, st_a, st_b, status_out, s));
+            tc = last ? t_end : tc + Hs;
+            ++sp->accepted;
+            sp->H_last = Hs;
+            sp->fast_steps += fast;
+        } else {
+            ++sp->rejected;
+        }
+        H = Hs * fac;
+        if (a->H_max > 0.0) H = std::min(H, a->H_max);
+        sp->t = tc;
+        sp->H_next = H;
+        if (err > 1.0 && H < a->H_min)
+            return fail(MRI_EMAXSTEPS, "step size %.3g fell below H_min at t = %.17g", H, tc);
+    }
+    return MRI_OK;
+}
+
 mri_status mri_forcing_assemble(const mri_table *t, int stage, int n, int ld, const double *F,
                                 double *rho, mri_stream_t stream)
 {

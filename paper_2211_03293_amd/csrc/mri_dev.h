@@ -88,4 +88,13 @@ hipError_t launch_lin_apply(int n, const double *A, int n_cells, int ld, const d
 hipError_t launch_status_count(const int32_t *status, int n_cells, int32_t mask,
                                unsigned long long *count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
+// adaptive slow steps: partial reductions of the step-doubling error (one
+// partial per 256-cell block) and the status merge of an accepted step
+inline int step_err_blocks(int n_cells) { return (n_cells + 255) / 256; }
+hipError_t launch_step_err(int n, int t_comp, int n_cells, int ld, const double *y_half,
+                           const double *y_full, double scale, double rtol, double atol,
+                           double atol_t, const int32_t *sp_a, const int32_t *sp_b,
+                           double *part_w2, long long *part_steps, hipStream_t s);
+hipError_t launch_status_merge(int n_cells, const int32_t *st_a, const int32_t *st_b,
+                               int32_t *status_out, hipStream_t s);
 hipError_t launch_exp2(const double *x, double *y, int n, hipStream_t s);

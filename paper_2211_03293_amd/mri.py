@@ -67,6 +67,19 @@ class mri_advdiff_params(C.Structure):
                 ("u", C.c_double * 3), ("D", C.c_double), ("dx", C.c_double)]
 
 
+class mri_adapt_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol_Y", C.c_double), ("atol_T", C.c_double),
+                ("H0", C.c_double), ("H_min", C.c_double), ("H_max", C.c_double),
+                ("order", C.c_int), ("max_attempts", C.c_int), ("safety", C.c_double),
+                ("fac_min", C.c_double), ("fac_max", C.c_double)]
+
+
+class mri_adapt_stats(C.Structure):
+    _fields_ = [("accepted", C.c_int), ("rejected", C.c_int), ("t", C.c_double),
+                ("H_last", C.c_double), ("H_next", C.c_double), ("err_last", C.c_double),
+                ("fast_steps", C.c_int64)]
+
+
 class mri_counters(C.Structure):
     _fields_ = [("slow_evals", C.c_int64), ("fast_stages", C.c_int64),
                 ("cell_stages", C.c_int64), ("specializations", C.c_int64)]
@@ -89,6 +102,10 @@ _SIGS = {
     "mri_workspace_bytes": (_i, [_vp, _vp, _i, _i, C.POINTER(_sz)]),
     "mri_slow_step": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), _vp, _vp, _d, _d, _i, _i, _vp,
                            _vp, _sz, _vp, _vp, _vp]),
+    "mri_adaptive_workspace_bytes": (_i, [_vp, _vp, _i, _i, C.POINTER(_sz)]),
+    "mri_adaptive_run": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), C.POINTER(mri_adapt_opts), _vp,
+                              _vp, _d, _d, _i, _i, _vp, _vp, _sz, _vp,
+                              C.POINTER(mri_adapt_stats), _vp]),
     "mri_advdiff_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
     "mri_linear_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
     "mri_selftest_exp2": (_i, [_vp, _vp, _i, _vp]),
@@ -255,6 +272,36 @@ def mri_slow_step(mech: Mech, table: Table, opts, f_slow, user, t0, H, n_cells, 
     _check(lib.mri_slow_step(mech.h, table.h, C.byref(opts), f_slow, user_p, float(t0), float(H),
                              n_cells, ld, _ptr(y), _ptr(ws), nbytes, _ptr(status_out),
                              _ptr(steps_out), _stream(stream)))
+
+
+def adapt_opts(rtol, atol_Y, atol_T, H0, order, H_min=0.0, H_max=0.0, max_attempts=10000,
+               safety=0.0, fac_min=0.0, fac_max=0.0):
+    return mri_adapt_opts(rtol, atol_Y, atol_T, H0, H_min, H_max, order, max_attempts, safety,
+                          fac_min, fac_max)
+
+
+def mri_adaptive_workspace_bytes(mech: Mech, table: Table, n_cells, ld):
+    b = C.c_size_t()
+    _check(lib.mri_adaptive_workspace_bytes(mech.h, table.h, n_cells, ld, C.byref(b)))
+    return b.value
+
+
+def mri_adaptive_run(mech: Mech, table: Table, opts, aopts, f_slow, user, t0, t_end, n_cells, ld,
+                     y, ws, status_out=None, stream=None):
+    """Adaptive slow steps from t0 to t_end (step doubling); returns the statistics
+    as a dict.  f_slow and user as for mri_slow_step."""
+    if isinstance(user, C.Structure):
+        user_p = C.cast(C.pointer(user), C.c_void_p).value
+    elif isinstance(user, Mech):
+        user_p = user.h.value
+    else:
+        user_p = user
+    st = mri_adapt_stats()
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib.mri_adaptive_run(mech.h, table.h, C.byref(opts), C.byref(aopts), f_slow, user_p,
+                                float(t0), float(t_end), n_cells, ld, _ptr(y), _ptr(ws), nbytes,
+                                _ptr(status_out), C.byref(st), _stream(stream)))
+    return {f: getattr(st, f) for f, _ in mri_adapt_stats._fields_}
 
 
 def mri_selftest_exp2(x, y, stream=None):

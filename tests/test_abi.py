@@ -188,3 +188,38 @@ def test_cash_karp_limits(mri):
     assert "24 species" in mri.last_error()
     lin = mri.Mech(A_linear=np.eye(3))
     assert call(lin, kernel=mri.KERNEL_SPECIALIZED) == mri.MRI_OK
+
+
+def test_adaptive_run_validation(mri):
+    """Invalid adaptive options fail before any device work; an empty batch
+    reaches t_end without a device."""
+    m = mri.Mech(I.make_mechanism(0))
+    t = mri.Table(I.table_mis_kw3())
+    L = mri.lib
+    fo = mri.fast_opts(n_sub=4)
+    good = mri.adapt_opts(1e-6, 1e-8, 1e-5, 1e-7, 3)
+
+    def call(a=good, fo=fo, t0=0.0, t1=1e-6, n_cells=64, ld=64, ws_bytes=1 << 40, cb=None):
+        st = mri.mri_adapt_stats()
+        rc = L.mri_adaptive_run(m.h, t.h, C.byref(fo), C.byref(a) if a is not None else None,
+                                cb if cb is not None else mri.ADVDIFF_RHS, None, t0, t1, n_cells,
+                                ld, 1, 1, ws_bytes, None, C.byref(st), None)
+        return rc, st
+
+    assert call(a=None)[0] == mri.MRI_EINVAL
+    assert call(a=mri.adapt_opts(-1.0, 1e-8, 1e-5, 1e-7, 3))[0] == mri.MRI_EINVAL
+    assert call(a=mri.adapt_opts(1e-6, 0.0, 1e-5, 1e-7, 3))[0] == mri.MRI_EINVAL
+    assert call(a=mri.adapt_opts(1e-6, 1e-8, 1e-5, 0.0, 3))[0] == mri.MRI_EINVAL
+    assert call(a=mri.adapt_opts(1e-6, 1e-8, 1e-5, 1e-7, 0))[0] == mri.MRI_EINVAL
+    assert call(a=mri.adapt_opts(1e-6, 1e-8, 1e-5, 1e-7, 3, max_attempts=0))[0] == mri.MRI_EINVAL
+    assert call(a=mri.adapt_opts(1e-6, 1e-8, 1e-5, 1e-7, 3, H_min=1e-6, H_max=1e-7))[0] == \
+        mri.MRI_EINVAL
+    assert call(a=mri.adapt_opts(1e-6, 1e-8, 1e-5, 1e-7, 3, fac_max=0.5))[0] == mri.MRI_EINVAL
+    assert call(t0=1e-6, t1=1e-6)[0] == mri.MRI_EINVAL
+    assert call(t1=float("nan"))[0] == mri.MRI_EINVAL
+    assert call(fo=mri.fast_opts(n_sub=0))[0] == mri.MRI_EINVAL
+    assert call(ws_bytes=8)[0] == mri.MRI_EINVAL and "workspace" in mri.last_error()
+    rc, st = call(n_cells=0, ld=0)
+    assert rc == mri.MRI_OK and st.t == 1e-6 and st.accepted == 0
+    need = mri.mri_adaptive_workspace_bytes(m, t, 512, 512)
+    assert need >= mri.mri_workspace_bytes(m, t, 512, 512) + 2 * 8 * 10 * 512

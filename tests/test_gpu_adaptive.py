@@ -1,0 +1,112 @@
+"""Adaptive slow steps through the device path (mri_adaptive_run) against the
+oracle's step-doubling controller: the same accept/reject sequence and final
+state within 1e-10.  The error estimate is the difference of two results that
+agree to about the tolerance, so the device and the oracle (each within ~1e-15
+of exact arithmetic) agree on it only to about 1e-15 / tol relative; the step
+sizes it proposes are compared at 1e-5 relative (tol = 1e-8), and the accept
+decisions of these runs are all far from ties."""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from paper_2211_03293_amd import inputs as I
+from parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mri(torch):
+    from paper_2211_03293_amd import mri
+    return mri
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle.oracle as O
+    return O
+
+
+def test_adaptive_linear_two_rate_matches_oracle(torch, mri, O):
+    A_F = np.array([[-6.0, 5.0], [-5.0, -4.0]])
+    A_S = np.array([[0.3, 1.0], [-1.2, 0.2]])
+    tb = I.table_mis_kw3()
+    orc = O.Oracle(A_fast=A_F)
+    H0, n_sub, T = 0.7, 64, 0.7
+
+    def step(y, t, H):
+        out, st, _, _ = orc.mri_step_linear(tb, O.rk4_opts(O.fixed_substeps(n_sub, H, H0)), A_S,
+                                            y[:, 0], H, t=t)
+        return out, st
+
+    y0 = np.array([[1.0], [0.5]])
+    ref, st_o, hist = O.adaptive_run(step, y0, 0.0, T, 3, 1e-8, 1e-8, 1e-8, H0)
+    mF, mS, t = mri.Mech(A_linear=A_F), mri.Mech(A_linear=A_S), mri.Table(tb)
+    yd = torch.as_tensor(np.repeat(y0, 64, axis=1), device="cuda")
+    ws = torch.empty(mri.mri_adaptive_workspace_bytes(mF, t, 64, 64) // 8 + 1,
+                     dtype=torch.float64, device="cuda")
+    st = mri.mri_adaptive_run(mF, t, mri.fast_opts(n_sub=n_sub),
+                              mri.adapt_opts(1e-8, 1e-8, 1e-8, H0, 3), mri.LINEAR_RHS, mS, 0.0, T,
+                              64, 64, yd, ws)
+    got = yd.cpu().numpy()
+    print(f"linear: {st}")
+    assert (st["accepted"], st["rejected"]) == (st_o["accepted"], st_o["rejected"])
+    assert st["rejected"] >= 1 and st["t"] == T
+    assert st["H_last"] == pytest.approx(st_o["H_last"], rel=1e-5)
+    np.testing.assert_allclose(got[:, 0], ref[:, 0], rtol=1e-10)
+    assert np.all(got == got[:, :1])
+    assert np.abs(got[:, 0] - expm((A_F + A_S) * T) @ y0[:, 0]).max() < 1e-6
+    # fixed-step fast work: the two half steps of every accepted attempt
+    exp_fast = sum(2 * 3 * O.fixed_substeps(n_sub, H / 2, H0) for _, H, _, a in hist if a)
+    assert st["fast_steps"] == 64 * exp_fast
+
+
+def test_adaptive_chemistry_advection_diffusion_matches_oracle(torch, mri, O):
+    """21 species / 84 reactions on an 8 x 6 x 4 periodic grid with the
+    advection-diffusion slow side, MIS-KW3, RK4 keeping the fast step of 100
+    substeps per stage at H0 = 2e-7 (50 at 1e-7); the first attempt is rejected."""
+    grid = (8, 6, 4)
+    N = int(np.prod(grid))
+    mech = I.make_mechanism(1)
+    S = mech.n_species
+    orc = O.Oracle(mech)
+    tb = I.table_mis_kw3()
+    y0 = I.field_state(1, grid)
+    n, ld = y0.shape
+    H0, T = 2e-7, 4e-7
+    rtol, atol_Y, atol_T = 1e-5, 1e-9, 1e-3
+
+    nsub0 = 100        # 50 substeps per stage at Href = H0 / 2
+
+    def step(y, t, H):
+        out, st, _, _ = orc.mri_step_advdiff(tb, O.rk4_opts(O.fixed_substeps(nsub0, H, H0)), grid,
+                                             y, H, t=t)
+        return out, st
+
+    ref, st_o, hist = O.adaptive_run(step, y0, 0.0, T, 3, rtol, atol_Y, atol_T, H0, t_comp=S,
+                                     n_cells=N)
+    errs = np.array([e for _, _, e, _ in hist])
+    assert np.all(np.abs(errs - 1.0) > 0.2), errs       # no decision near a tie
+    m, t = mri.Mech(mech), mri.Table(tb)
+    yd = torch.as_tensor(y0, device="cuda")
+    ws = torch.empty(mri.mri_adaptive_workspace_bytes(m, t, N, ld) // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    status = torch.full((ld,), 7, dtype=torch.int32, device="cuda")
+    st = mri.mri_adaptive_run(m, t, mri.fast_opts(n_sub=nsub0),
+                              mri.adapt_opts(rtol, atol_Y, atol_T, H0, 3), mri.ADVDIFF_RHS,
+                              mri.advdiff_params(grid, n), 0.0, T, N, ld, yd, ws, status)
+    print(f"chemistry: {st}; oracle {st_o}")
+    assert (st["accepted"], st["rejected"]) == (st_o["accepted"], st_o["rejected"])
+    assert st["rejected"] >= 1 and st["t"] == T
+    assert st["H_last"] == pytest.approx(st_o["H_last"], rel=1e-5)
+    assert_parity(yd.cpu().numpy(), ref, S, cells=np.arange(N), what="adaptive chemistry")
+    assert mri.mri_status_count(status, N) == 0
