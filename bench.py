@@ -21,7 +21,6 @@ reactor sets (adaptive, persistent work queue) and the learned surrogate
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -64,19 +63,15 @@ def flops_per_zv_attempt(S: int, R: int) -> int:
     return 5 * rhs + 5 * n * 8 + 15 * n + 2 * n + 2 * F_EXP
 
 
-def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2211_03293_amd", "csrc", "spec_kernels.inc")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
-
-
-def load_traffic(workload: str):
-    """HBM bytes per launch measured with rocprofv3 counters for the current
-    kernel source, or None when the kernel changed since they were taken."""
+def load_traffic(workload: str, code_hash: str):
+    """HBM bytes per launch measured with rocprofv3 counters for the kernel
+    whose code object hashes to code_hash, or None when the compiled kernel
+    changed since the counters were taken."""
     p = os.path.join(ROOT, "profiles", "fast_stage_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload:
+    if d.get("kernel_code_hash") != code_hash or d.get("workload") != workload:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -231,8 +226,11 @@ def plain_leg(torch, mri, I, config, steps, warmup, block, kernel_name):
     achieved = fps * cfg.n_sub * N / avg_launch_s / 1e12
     workload = (f"mri_fast_stage rk4 {cfg.grid[0]}^3 cells S={mech.n_species} "
                 f"R={mech.n_reactions} n_sub={cfg.n_sub}")
+    traffic = None
+    if kernel != mri.KERNEL_GENERIC:
+        traffic = load_traffic(workload, m.code_hash(mri.FAST_RK4, tb.n_gamma, block or 128))
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=load_traffic(workload),
+                frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=traffic,
                 kernel="mri_spec_main (RK4, specialized)" if kernel != mri.KERNEL_GENERIC
                 else "k_gen_rk4 (generic)",
                 flops_per_cell_substep=fps, avg_launch_ms=round(avg_launch_s * 1e3, 4))

@@ -716,6 +716,22 @@ mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int b
     return st;
 }
 
+mri_status mri_mech_code_hash(mri_mech *m, int method, int n_poly, int block_size,
+                              uint64_t *hash)
+{
+    if (!hash) return fail(MRI_EINVAL, "hash is NULL");
+    mri_status st = mri_mech_specialize_method(m, method, n_poly, block_size, 0, nullptr);
+    if (st != MRI_OK) return st;
+    std::lock_guard<std::mutex> lk(m->mu);
+    uint64_t h = 1469598103934665603ull;        // FNV-1a, 64 bit
+    for (char c : m->last_code) {
+        h ^= (uint64_t)(unsigned char)c;
+        h *= 1099511628211ull;
+    }
+    *hash = h;
+    return MRI_OK;
+}
+
 mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *code_bytes)
 {
     // the RK4 kernel with a constant forcing term (the explicit MIS/MRI-GARK case)

@@ -95,6 +95,7 @@ _SIGS = {
     "mri_mech_state_width": (_i, [_vp]),
     "mri_mech_specialize": (_i, [_vp, _i, _i, C.POINTER(_sz)]),
     "mri_mech_specialize_method": (_i, [_vp, _i, _i, _i, _i, C.POINTER(_sz)]),
+    "mri_mech_code_hash": (_i, [_vp, _i, _i, _i, C.POINTER(C.c_uint64)]),
     "mri_table_create": (_i, [C.POINTER(mri_table_desc), C.POINTER(_vp)]),
     "mri_table_destroy": (None, [_vp]),
     "mri_fast_stage": (_i, [_vp, C.POINTER(mri_fast_opts), _i, _i, _vp, _vp, _i, _vp, _d, _vp,
@@ -209,6 +210,12 @@ class Mech:
             _check(lib.mri_mech_specialize_method(self.h, int(method), int(n_poly), block_size,
                                                   int(load), C.byref(nb)))
         return nb.value
+
+    def code_hash(self, method=0, n_poly=1, block_size=128):
+        """Hex FNV-1a hash of the specialized kernel's code object (no GPU needed)."""
+        h = C.c_uint64(0)
+        _check(lib.mri_mech_code_hash(self.h, int(method), int(n_poly), block_size, C.byref(h)))
+        return f"{h.value:016x}"
 
     def __del__(self, _destroy=lib.mri_mech_destroy, _null=C.c_void_p):
         if getattr(self, "h", None) and self.h.value:

@@ -223,3 +223,12 @@ def test_adaptive_run_validation(mri):
     assert rc == mri.MRI_OK and st.t == 1e-6 and st.accepted == 0
     need = mri.mri_adaptive_workspace_bytes(m, t, 512, 512)
     assert need >= mri.mri_workspace_bytes(m, t, 512, 512) + 2 * 8 * 10 * 512
+
+
+def test_code_hash_identifies_the_compiled_kernel(mri):
+    m = mri.Mech(I.make_mechanism(0))
+    h1 = m.code_hash(mri.FAST_RK4, 1, 128)
+    assert h1 == m.code_hash(mri.FAST_RK4, 1, 128)            # deterministic
+    assert h1 != m.code_hash(mri.FAST_RK4, 2, 128)
+    assert h1 != m.code_hash(mri.FAST_HEUN, 1, 128)
+    assert h1 != mri.Mech(I.make_mechanism(1)).code_hash(mri.FAST_RK4, 1, 128)
