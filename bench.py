@@ -119,7 +119,7 @@ def batch_leg(torch, mri, I, repeats=3):
     """Batched uneven reactor sets: 1000 sets, log-uniform sizes, adaptive
     Zonneveld 4(3) at tol 1e-8, one persistent work-queue launch per run."""
     sizes, off, y_host, Ls = I.batch_workload()
-    mech = I.make_mechanism(2)
+    mech = I.make_mechanism(I.SETS1000)
     m = mri.Mech(mech)
     opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
                          max_steps=2000)
@@ -160,22 +160,22 @@ def batch_leg(torch, mri, I, repeats=3):
                               flops_per_attempted_step=fpa))
 
 
-WORKLOADS = {
-    1: "plain FP64 explicit MRI-GARK (MIS-KW3) slow steps, 64^3 cells, 21 species / 84 "
+DESCRIPTIONS = {
+    "field64_s21": "plain FP64 explicit MRI-GARK (MIS-KW3) slow steps, 64^3 cells, 21 species / 84 "
        "reactions, RK4 50 substeps/stage, H = 1e-7 s, advection-diffusion slow RHS",
-    3: "plain FP64 explicit MRI-GARK (MIS-KW3) slow step, 128^3 cells, 53 species / 325 "
+    "field128_s53": "plain FP64 explicit MRI-GARK (MIS-KW3) slow step, 128^3 cells, 53 species / 325 "
        "reactions, RK4 100 substeps/stage, H = 5e-8 s, advection-diffusion slow RHS",
 }
 
 
-def plain_leg(torch, mri, I, config, steps, warmup, block, kernel_name):
+def plain_leg(torch, mri, I, workload, steps, warmup, block, kernel_name):
     """K timed MRI slow steps of a field workload (W untimed before), wall time
     from events around the whole steps, fast-stage kernel time from libmri's
     per-launch events on the launch stream."""
-    cfg = I.CONFIGS[config]
-    mech = I.make_mechanism(config)
+    cfg = I.WORKLOADS[workload]
+    mech = I.make_mechanism(workload)
     tb = I.table_mis_kw3()
-    y_host = I.initial_state(config)
+    y_host = I.initial_state(workload)
     n, ld = y_host.shape
     N = cfg.n_cells
     kernel = dict(auto=mri.KERNEL_AUTO, specialized=mri.KERNEL_SPECIALIZED,
@@ -196,7 +196,7 @@ def plain_leg(torch, mri, I, config, steps, warmup, block, kernel_name):
         mri.mri_slow_step(m, t, opts, mri.ADVDIFF_RHS, params, k * cfg.H, cfg.H, N, ld, y, ws,
                           status)
 
-    print(f"# config {config}: warmup {warmup} steps", file=sys.stderr, flush=True)
+    print(f"# {workload}: warmup {warmup} steps", file=sys.stderr, flush=True)
     for k in range(warmup):
         step(k)
     torch.cuda.synchronize()
@@ -216,7 +216,7 @@ def plain_leg(torch, mri, I, config, steps, warmup, block, kernel_name):
     fast_ms, n_launch = mri.timing_read(reset=True)
     mri.timing_enable(False)
     n_bad = mri.mri_status_count(status, N)
-    print(f"# config {config}: timed {steps} steps: {wall_ms:.1f} ms, fast kernels "
+    print(f"# {workload}: timed {steps} steps: {wall_ms:.1f} ms, fast kernels "
           f"{fast_ms:.1f} ms over {n_launch} launches, flagged cells {n_bad}", file=sys.stderr,
           flush=True)
     stages_per_step = tb.s - 1
@@ -235,7 +235,7 @@ def plain_leg(torch, mri, I, config, steps, warmup, block, kernel_name):
                 else "k_gen_rk4 (generic)",
                 flops_per_cell_substep=fps, avg_launch_ms=round(avg_launch_s * 1e3, 4))
     return dict(value=round(value, 1), ms_per_step=round(wall_ms / steps, 3), roofline=roof,
-                config=dict(workload=WORKLOADS[config], cells=N,
+                config=dict(workload=DESCRIPTIONS[workload], cells=N,
                             stages_per_step=stages_per_step, n_sub=cfg.n_sub,
                             flagged_cells=n_bad))
 
@@ -254,7 +254,7 @@ def surrogate_leg(train_steps, n_samples):
     res = S.train(data, steps=train_steps, batch=TRAIN_BATCH, log=log,
                   log_every=max(1, train_steps // 8))
     del data
-    ev = S.evaluate_stage(res["params"], res["stats"], config=4, gate_tol=1e-4, log=log)
+    ev = S.evaluate_stage(res["params"], res["stats"], workload=I.FIELD128, gate_tol=1e-4, log=log)
     t_inf_s = ev["infer_ms"] * 1e-3
     achieved = ev["cells"] * MLP_FLOPS / t_inf_s / 1e12
     ev.update(
@@ -315,16 +315,16 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes_per_dispatch=2 ** 30, dispatches=3)), flush=True)
         return
-    plain = plain_leg(torch, mri, I, 1, args.steps, args.warmup, args.block, args.kernel)
+    plain = plain_leg(torch, mri, I, I.FIELD64, args.steps, args.warmup, args.block, args.kernel)
     out = dict(metric=METRIC, value=plain["value"], unit="cell-stages/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=plain["ms_per_step"],
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
                data="synthetic", config=plain["config"], roofline=plain["roofline"])
     if not args.no_large:
         print("# large-mechanism leg", file=sys.stderr, flush=True)
-        big = plain_leg(torch, mri, I, 3, 1, 1, args.block, args.kernel)
-        cfg3 = I.CONFIGS[3]
-        rhs_rate = 4 * cfg3.n_sub * big["value"]          # 4 RHS per RK4 substep
+        big = plain_leg(torch, mri, I, I.LARGE128, 1, 1, args.block, args.kernel)
+        large = I.WORKLOADS[I.LARGE128]
+        rhs_rate = 4 * large.n_sub * big["value"]          # 4 RHS per RK4 substep
         out["large_mechanism"] = dict(
             value=big["value"], unit="cell-stages/s", ms_per_step=big["ms_per_step"], steps=1,
             warmup=1, config=big["config"], roofline=big["roofline"],
@@ -347,11 +347,11 @@ def main():
     if not args.no_cpu_baseline:
         # forcing of the first stage of one slow step, from the oracle's own slow RHS
         from oracle import oracle as O
-        cfg, tb = I.CONFIGS[1], I.table_mis_kw3()
-        y_host = I.initial_state(1)
+        cfg, tb = I.WORKLOADS[I.FIELD64], I.table_mis_kw3()
+        y_host = I.initial_state(I.FIELD64)
         rho = O.advdiff(y_host, cfg.grid)[None]
         Ls = [float((tb.c[i] - tb.c[i - 1]) * cfg.H) for i in range(1, tb.s)]
-        out["cpu_baseline"] = cpu_baseline(I.make_mechanism(1), y_host, rho, Ls, cfg.n_sub)
+        out["cpu_baseline"] = cpu_baseline(I.make_mechanism(I.FIELD64), y_host, rho, Ls, cfg.n_sub)
     print(json.dumps(out), flush=True)
 
 

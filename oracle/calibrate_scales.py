@@ -46,22 +46,22 @@ def spectral_radii(orc, y, n_cells, chunk=8192):
     return np.concatenate(out)
 
 
-def calibrate(config: int, sample: int | None, traj_sample: int = 1024):
-    cfg = I.CONFIGS[config]
-    mech = I.make_mechanism(config, with_scale=False)
+def calibrate(workload: str, sample: int | None, traj_sample: int = 1024):
+    cfg = I.WORKLOADS[workload]
+    mech = I.make_mechanism(workload, with_scale=False)
     orc = O.Oracle(mech)
-    y = I.initial_state(config)
+    y = I.initial_state(workload)
     n_cells = cfg.n_cells
     idx = np.arange(n_cells)
     if sample and sample < n_cells:
         idx = np.sort(np.random.Generator(np.random.PCG64(7)).choice(n_cells, sample, replace=False))
     ys = np.ascontiguousarray(y[:, idx])
     rho = spectral_radii(orc, ys, idx.size)
-    h_max = I.longest_substep(config)
+    h_max = I.longest_substep(workload)
     s0 = TARGET / (h_max * rho.max())
     s, hist = s0, []
     for _ in range(12):
-        worst = trajectory_h_rho(config, mech.with_scale(s), n_sample=traj_sample)
+        worst = trajectory_h_rho(workload, mech.with_scale(s), n_sample=traj_sample)
         hist.append((s, worst))
         if worst <= TARGET * 1.0001:
             break
@@ -73,12 +73,12 @@ def calibrate(config: int, sample: int | None, traj_sample: int = 1024):
                 target_h_rho=TARGET)
 
 
-def trajectory_h_rho(config, mech, n_sample):
+def trajectory_h_rho(workload, mech, n_sample):
     """Max h*rho(J_F) over stage starts and run end of the full fast-only run."""
-    cfg = I.CONFIGS[config]
+    cfg = I.WORKLOADS[workload]
     tb = I.table_mis_kw3()
     orc = O.Oracle(mech)
-    y = I.initial_state(config)
+    y = I.initial_state(workload)
     idx = np.linspace(0, cfg.n_cells - 1, min(n_sample, cfg.n_cells)).astype(np.int64)
     ys = np.ascontiguousarray(y[:, idx])
     n = idx.size
@@ -92,7 +92,7 @@ def trajectory_h_rho(config, mech, n_sample):
                                               O.rk4_opts(cfg.n_sub))
             if (st != 0).any():
                 return float("inf")
-    h_max = I.longest_substep(config)
+    h_max = I.longest_substep(workload)
     return max(worst, h_max * spectral_radii(orc, ys, n).max())
 
 
@@ -101,9 +101,10 @@ def main():
     ap.add_argument("--sample", type=int, default=65536)
     args = ap.parse_args()
     res = {}
-    for mc in (0, 1, 3):
-        res[str(mc)] = calibrate(mc, args.sample)
-        print(mc, res[str(mc)], flush=True)
+    # the three mechanisms (the other workloads reuse the 64^3 one)
+    for mc in (I.SMALL, I.FIELD64, I.LARGE128):
+        res[mc] = calibrate(mc, args.sample)
+        print(mc, res[mc], flush=True)
     out = dict(
         note="global rate scale per mechanism; written by oracle/calibrate_scales.py",
         scales=res)

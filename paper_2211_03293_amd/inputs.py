@@ -20,7 +20,8 @@ are not available and are not reproduced; these synthetic inputs stand in):
   literal generators give rate constants up to 1e27 s^-1, which no explicit
   method can integrate at the stated step sizes.  s is stored in
   rate_scales.json (written by oracle/calibrate_scales.py).
-* Seeds: numpy PCG64 with seed = 1000 * config + purpose, purpose in
+* Seeds: numpy PCG64 with seed = 1000 * seed_base + purpose (seed_base is a
+  fixed small integer per workload, below), purpose in
   {0 mechanism, 1 initial state, 2 forcing, 3 set sizes, 4 MLP init, 5 split}.
 """
 from __future__ import annotations
@@ -40,16 +41,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SCALES_PATH = os.path.join(_HERE, "rate_scales.json")
 
 
-def rng_for(config: int, purpose: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(1000 * config + purpose))
-
-
 # ----------------------------------------------------------------------------
-# Workload configurations
+# Workloads
 # ----------------------------------------------------------------------------
 @dataclass(frozen=True)
-class Config:
-    index: int
+class Workload:
+    name: str
+    seed_base: int              # seeds are 1000 * seed_base + purpose
     n_species: int
     n_reactions: int
     n_elements: int
@@ -59,22 +57,33 @@ class Config:
     H: float                    # slow step [s]
     n_sub: int                  # RK4 substeps per fast stage
     n_slow_steps: int
-    mech_config: int            # which config's mechanism (seed) is used
+    mech_of: str                # workload whose mechanism (seed) is used
     note: str = ""
 
 
-CONFIGS = {
-    0: Config(0, 9, 21, 2, 3, None, 512, 1e-6, 20, 1, 0,
-              "parity: 512 independent cells, Gaussian slow tendencies"),
-    1: Config(1, 21, 84, 3, 2, (64, 64, 64), 64 ** 3, 1e-7, 50, 10, 1,
-              "plain throughput: 64^3 periodic fields, advection-diffusion slow side"),
-    2: Config(2, 21, 84, 3, 2, None, 0, 1e-7, 0, 1, 1,
-              "batched uneven reactor sets, adaptive Zonneveld 4(3)"),
-    3: Config(3, 53, 325, 3, 3, (128, 128, 128), 128 ** 3, 5e-8, 100, 1, 3,
-              "large mechanism: 128^3 fields"),
-    4: Config(4, 21, 84, 3, 2, (128, 128, 128), 128 ** 3, 1e-7, 50, 1, 1,
-              "surrogate: 128^3 fields, mechanism of config 1"),
+# workload names: cell layout and size, then species count
+SMALL = "cells512_s9"           # 512 independent cells, 9 species / 21 reactions
+FIELD64 = "field64_s21"         # 64^3 periodic fields, 21 species / 84 reactions
+SETS1000 = "sets1000_s21"       # 1000 uneven reactor sets, 21 species / 84 reactions
+LARGE128 = "field128_s53"       # 128^3 periodic fields, 53 species / 325 reactions
+FIELD128 = "field128_s21"       # 128^3 periodic fields, 21 species / 84 reactions
+
+WORKLOADS = {
+    SMALL: Workload(SMALL, 0, 9, 21, 2, 3, None, 512, 1e-6, 20, 1, SMALL,
+                    "parity: 512 independent cells, Gaussian slow tendencies"),
+    FIELD64: Workload(FIELD64, 1, 21, 84, 3, 2, (64, 64, 64), 64 ** 3, 1e-7, 50, 10, FIELD64,
+                      "plain throughput: 64^3 periodic fields, advection-diffusion slow side"),
+    SETS1000: Workload(SETS1000, 2, 21, 84, 3, 2, None, 0, 1e-7, 0, 1, FIELD64,
+                       "batched uneven reactor sets, adaptive Zonneveld 4(3)"),
+    LARGE128: Workload(LARGE128, 3, 53, 325, 3, 3, (128, 128, 128), 128 ** 3, 5e-8, 100, 1,
+                       LARGE128, "large mechanism: 128^3 fields"),
+    FIELD128: Workload(FIELD128, 4, 21, 84, 3, 2, (128, 128, 128), 128 ** 3, 1e-7, 50, 1, FIELD64,
+                       "surrogate: 128^3 fields, mechanism of the 64^3 workload"),
 }
+
+
+def rng_for(workload: str, purpose: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(1000 * WORKLOADS[workload].seed_base + purpose))
 
 # Slow-side constants for the field workloads (u in m/s, D in m^2/s, dx in m).
 ADVDIFF = dict(u=(10.0, 10.0, 10.0), D=1e-5, dx=1e-4)
@@ -226,10 +235,9 @@ def _balanced_reactions(comp: np.ndarray):
     return cands
 
 
-def make_mechanism(config: int, with_scale: bool = True) -> Mechanism:
-    cfg = CONFIGS[config]
-    mc = cfg.mech_config
-    base = CONFIGS[mc]
+def make_mechanism(workload: str, with_scale: bool = True) -> Mechanism:
+    mc = WORKLOADS[workload].mech_of
+    base = WORKLOADS[mc]
     rng = rng_for(mc, 0)
     S, R, E = base.n_species, base.n_reactions, base.n_elements
     comp = _lattice_species(E, base.n_max, S, rng)
@@ -269,7 +277,7 @@ def make_mechanism(config: int, with_scale: bool = True) -> Mechanism:
         lnA=np.log(A), beta=beta, theta=Ea / R_CAL,
         g_a=g_a, g_b=g_b, W=W_g * 1e-3, cv=cv,
         composition=comp.astype(np.int32), rho=1.0, T_ref=298.15, rate_scale=1.0,
-        meta=dict(config=mc, seed=1000 * mc + 0, atomic_masses_g=m.tolist(),
+        meta=dict(workload=mc, seed=1000 * base.seed_base + 0, atomic_masses_g=m.tolist(),
                   n_candidates=len(cands)),
     )
     if with_scale:
@@ -279,17 +287,17 @@ def make_mechanism(config: int, with_scale: bool = True) -> Mechanism:
     return mech
 
 
-def load_rate_scale(mech_config: int):
+def load_rate_scale(mech_of: str):
     if not os.path.exists(SCALES_PATH):
         return None
     with open(SCALES_PATH) as f:
         d = json.load(f)
-    v = d.get("scales", {}).get(str(mech_config))
+    v = d.get("scales", {}).get(mech_of)
     return None if v is None else float(v["s"])
 
 
-def longest_substep(config: int, table: Table | None = None) -> float:
-    cfg = CONFIGS[config]
+def longest_substep(workload: str, table: Table | None = None) -> float:
+    cfg = WORKLOADS[workload]
     table = table or table_mis_kw3()
     dc = np.diff(table.c)
     return float(dc.max() * cfg.H / cfg.n_sub)
@@ -334,12 +342,12 @@ def _smooth_periodic_field(grid, rng, n_modes: int = 8, kmax: int = 4) -> np.nda
     return f.reshape(-1)
 
 
-def field_state(config: int, grid=None) -> np.ndarray:
+def field_state(workload: str, grid=None) -> np.ndarray:
     """Smooth random periodic fields: Y = softmax of S fields, T = 1500 + 500 f."""
-    cfg = CONFIGS[config]
+    cfg = WORKLOADS[workload]
     grid = grid or cfg.grid
     S = cfg.n_species
-    rng = rng_for(config, 1)
+    rng = rng_for(workload, 1)
     N = int(np.prod(grid))
     ld = pad_ld(N)
     logits = np.stack([2.0 * _smooth_periodic_field(grid, rng) for _ in range(S)])
@@ -353,27 +361,29 @@ def field_state(config: int, grid=None) -> np.ndarray:
     return y
 
 
-def initial_state(config: int) -> np.ndarray:
-    cfg = CONFIGS[config]
+def initial_state(workload: str) -> np.ndarray:
+    cfg = WORKLOADS[workload]
     if cfg.grid is None:
-        return independent_cells(cfg.n_cells, cfg.n_species, rng_for(config, 1))
-    return field_state(config)
+        return independent_cells(cfg.n_cells, cfg.n_species, rng_for(workload, 1))
+    return field_state(workload)
 
 
-def gaussian_xi(config: int, n_stages: int, n_comp: int, ld: int) -> np.ndarray:
-    """Standard normal draws xi[j][comp][cell] for the config-0 slow tendencies.
+def gaussian_xi(workload: str, n_stages: int, n_comp: int, ld: int) -> np.ndarray:
+    """Standard normal draws xi[j][comp][cell] for the 512-cell workload's slow
+    tendencies.
 
     The tendencies are r_j = 1e-3 * |f^F(y0)| * xi_j; the magnitude |f^F(y0)|
     is evaluated by whichever side consumes these draws.
     """
-    return rng_for(config, 2).standard_normal((n_stages, n_comp, ld))
+    return rng_for(workload, 2).standard_normal((n_stages, n_comp, ld))
 
 
 # ----------------------------------------------------------------------------
-# Batched uneven reactor sets (config 2)
+# Batched uneven reactor sets
 # ----------------------------------------------------------------------------
-def set_sizes(n_sets: int = 1000, lo: int = 64, hi: int = 65536, config: int = 2) -> np.ndarray:
-    rng = rng_for(config, 3)
+def set_sizes(n_sets: int = 1000, lo: int = 64, hi: int = 65536,
+              workload: str = SETS1000) -> np.ndarray:
+    rng = rng_for(workload, 3)
     u = rng.uniform(math.log(lo), math.log(hi), size=n_sets)
     return np.floor(np.exp(u)).astype(np.int64).clip(lo, hi)
 
@@ -401,16 +411,16 @@ def mechanism_arrays(m: Mechanism) -> dict:
     )
 
 
-def batch_workload(n_sets: int = 1000, config: int = 2):
+def batch_workload(n_sets: int = 1000, workload: str = SETS1000):
     """Uneven reactor sets: sizes log-uniform in [64, 65536], every cell drawn
     like the independent-cell workload (T ~ U[1000, 2000] K, Y ~ Dirichlet(1)),
     and one fast stage per set whose length cycles through the three stage
     lengths dc_i H of the MIS-KW3 table (H = 1e-7 s).  No slow tendencies are
     stated for this workload: the stage is unforced (n_poly = 0)."""
-    cfg = CONFIGS[config]
-    sizes = set_sizes(n_sets, config=config)
+    cfg = WORKLOADS[workload]
+    sizes = set_sizes(n_sets, workload=workload)
     off = set_offsets(sizes)
-    y = independent_cells(int(off[-1]), CONFIGS[cfg.mech_config].n_species, rng_for(config, 1))
+    y = independent_cells(int(off[-1]), WORKLOADS[cfg.mech_of].n_species, rng_for(workload, 1))
     dc = np.diff(table_mis_kw3().c)
     L = np.array([dc[i % dc.size] * cfg.H for i in range(n_sets)])
     return sizes, off, y, L

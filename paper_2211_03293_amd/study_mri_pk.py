@@ -40,7 +40,7 @@ METHODS = (("Heun", 2), ("Bogacki-Shampine", 3), ("RK4", 4), ("Cash-Karp", 5))
 def _fields(n_side):
     """The 64^3 workload's initial fields on an n_side^3 periodic grid."""
     grid = (n_side, n_side, n_side)
-    return I.field_state(1, grid), grid
+    return I.field_state(I.FIELD64, grid), grid
 
 
 def run(torch, m, t, y_host, grid, method, k, H):
@@ -86,7 +86,7 @@ def main(argv=None):
     import torch
     assert torch.cuda.is_available(), "the study runs on a GPU"
     torch.cuda.set_device(0)
-    mech = I.make_mechanism(1)
+    mech = I.make_mechanism(I.FIELD64)
     m = mri.Mech(mech)
     if len(args.k) not in (1, len(METHODS)):
         ap.error(f"--k takes 1 or {len(METHODS)} values")

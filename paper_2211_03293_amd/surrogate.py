@@ -40,16 +40,16 @@ class StageData:
         self.n = L.numel()
 
 
-def generate_stage_data(n_full=1_000_000, config=1, seed=None, log=print):
-    """Full- and half-stage samples from the config's MRI run (n_full full-stage
+def generate_stage_data(n_full=1_000_000, workload=I.FIELD64, seed=None, log=print):
+    """Full- and half-stage samples from the workload's MRI run (n_full full-stage
     samples spread evenly over all fast stages, plus 2 n_full half-stage ones)."""
     torch = _torch()
-    cfg = I.CONFIGS[config]
-    mech = I.make_mechanism(config)
+    cfg = I.WORKLOADS[workload]
+    mech = I.make_mechanism(workload)
     tb = I.table_mis_kw3()
     m, t = mri.Mech(mech), mri.Table(tb)
     m.specialize(128, load=True)
-    y_host = I.initial_state(config)
+    y_host = I.initial_state(workload)
     n, ld = y_host.shape
     N = cfg.n_cells
     y = torch.as_tensor(y_host, device="cuda")
@@ -57,7 +57,7 @@ def generate_stage_data(n_full=1_000_000, config=1, seed=None, log=print):
     rho = torch.empty((1, n, ld), dtype=torch.float64, device="cuda")
     params = mri.advdiff_params(cfg.grid, n)
     gen = torch.Generator(device="cpu")
-    gen.manual_seed(1000 * config + 5 if seed is None else seed)
+    gen.manual_seed(1000 * I.WORKLOADS[workload].seed_base + 5 if seed is None else seed)
     n_stages = cfg.n_slow_steps * (tb.s - 1)
     per = int(math.ceil(n_full / n_stages))
     buf = {k: [] for k in ("Y0", "RHO", "L", "Y1")}
@@ -187,15 +187,15 @@ def stage_error(y_pred, y_ref, n_species, floor=1e-8):
     return ((y_pred - y_ref).abs() / torch.maximum(y_ref.abs(), fl)).amax(0)
 
 
-def stage_inputs(config=4, stage=1):
-    """State, forcing and stage length of one fast stage of the config's first
+def stage_inputs(workload=I.FIELD128, stage=1):
+    """State, forcing and stage length of one fast stage of the workload's first
     slow step (slow RHS by the advection-diffusion kernel, forcing assembly by
     libmri), as device tensors."""
     torch = _torch()
-    cfg = I.CONFIGS[config]
+    cfg = I.WORKLOADS[workload]
     tb = I.table_mis_kw3()
     t = mri.Table(tb)
-    y_host = I.initial_state(config)
+    y_host = I.initial_state(workload)
     n, ld = y_host.shape
     N = cfg.n_cells
     y = torch.as_tensor(y_host, device="cuda")
@@ -211,16 +211,16 @@ def stage_inputs(config=4, stage=1):
     return y, rho, L, N, ld
 
 
-def evaluate_stage(params, stats, config=4, gate_tol=1e-4, repeats=3, log=print):
+def evaluate_stage(params, stats, workload=I.FIELD128, gate_tol=1e-4, repeats=3, log=print):
     """Gated surrogate stage against the plain FP64 stage on every cell of the
-    config's first fast stage: fallback fraction, false accepts, error of the
+    workload's first fast stage: fallback fraction, false accepts, error of the
     accepted cells, wall times and the fused inference kernel time."""
     torch = _torch()
-    cfg = I.CONFIGS[config]
-    mech = I.make_mechanism(config)
+    cfg = I.WORKLOADS[workload]
+    mech = I.make_mechanism(workload)
     m = mri.Mech(mech)
     m.specialize(128, load=True)
-    y, rho, L, N, ld = stage_inputs(config)
+    y, rho, L, N, ld = stage_inputs(workload)
     opts = mri.fast_opts(n_sub=cfg.n_sub)
     ref = torch.empty_like(y)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

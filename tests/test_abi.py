@@ -42,7 +42,7 @@ def test_abi_version(mri):
 
 
 def test_mech_validation(mri):
-    m = I.make_mechanism(0)
+    m = I.make_mechanism(I.SMALL)
     bad = I.Mechanism(**{**m.__dict__})
     bad.reactants = m.reactants.copy()
     bad.reactants[3, 1] = m.n_species          # index out of range
@@ -83,7 +83,7 @@ def test_table_validation(mri):
 
 
 def test_fast_stage_rejects_bad_arguments_without_device(mri):
-    m = mri.Mech(I.make_mechanism(0))
+    m = mri.Mech(I.make_mechanism(I.SMALL))
     ok = mri.fast_opts(n_sub=4)
     L = mri.lib
 
@@ -113,7 +113,7 @@ def test_fast_stage_rejects_bad_arguments_without_device(mri):
 
 
 def test_slow_step_and_batch_validation(mri):
-    m = mri.Mech(I.make_mechanism(0))
+    m = mri.Mech(I.make_mechanism(I.SMALL))
     t = mri.Table(I.table_mis_kw3())
     L = mri.lib
     opts = mri.fast_opts(n_sub=4)
@@ -147,15 +147,15 @@ def test_linear_mode_validation(mri):
     assert rc == mri.MRI_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("config", [0, 1])
-def test_specialized_kernels_compile_for_gfx950(mri, config):
-    m = mri.Mech(I.make_mechanism(config))
+@pytest.mark.parametrize("workload", [I.SMALL, I.FIELD64])
+def test_specialized_kernels_compile_for_gfx950(mri, workload):
+    m = mri.Mech(I.make_mechanism(workload))
     nbytes = m.specialize(128, load=False)
     assert nbytes > 1000
 
 
 def test_specialized_kernels_compile_for_every_fast_method(mri):
-    m = mri.Mech(I.make_mechanism(0))
+    m = mri.Mech(I.make_mechanism(I.SMALL))
     for meth in (mri.FAST_RK4, mri.FAST_ZONNEVELD43, mri.FAST_HEUN, mri.FAST_BS3,
                  mri.FAST_CK5):
         for n_poly in (0, 2):
@@ -163,7 +163,7 @@ def test_specialized_kernels_compile_for_every_fast_method(mri):
     with pytest.raises(mri.MriError):
         m.specialize(64, load=False, method=9)
     with pytest.raises(mri.MriError, match="24 species"):
-        mri.Mech(I.make_mechanism(3)).specialize(64, load=False, method=mri.FAST_CK5)
+        mri.Mech(I.make_mechanism(I.LARGE128)).specialize(64, load=False, method=mri.FAST_CK5)
     with pytest.raises(mri.MriError):
         m.specialize(64, load=False, method=mri.FAST_HEUN, n_poly=5)
 
@@ -178,11 +178,11 @@ def test_cash_karp_limits(mri):
         return L.mri_fast_stage(m.h, C.byref(o), 0, 0, None, None, 0, None, 1e-7, None, None,
                                 None)
 
-    small = mri.Mech(I.make_mechanism(0))
+    small = mri.Mech(I.make_mechanism(I.SMALL))
     assert call(small) == mri.MRI_OK
     assert call(small, kernel=mri.KERNEL_GENERIC) == mri.MRI_OK
     assert call(small, kernel=mri.KERNEL_SPECIALIZED) == mri.MRI_OK
-    large = mri.Mech(I.make_mechanism(3))
+    large = mri.Mech(I.make_mechanism(I.LARGE128))
     assert large.n - 1 > 24
     assert call(large) == mri.MRI_EUNSUPPORTED
     assert "24 species" in mri.last_error()
@@ -193,7 +193,7 @@ def test_cash_karp_limits(mri):
 def test_adaptive_run_validation(mri):
     """Invalid adaptive options fail before any device work; an empty batch
     reaches t_end without a device."""
-    m = mri.Mech(I.make_mechanism(0))
+    m = mri.Mech(I.make_mechanism(I.SMALL))
     t = mri.Table(I.table_mis_kw3())
     L = mri.lib
     fo = mri.fast_opts(n_sub=4)
@@ -226,9 +226,9 @@ def test_adaptive_run_validation(mri):
 
 
 def test_code_hash_identifies_the_compiled_kernel(mri):
-    m = mri.Mech(I.make_mechanism(0))
+    m = mri.Mech(I.make_mechanism(I.SMALL))
     h1 = m.code_hash(mri.FAST_RK4, 1, 128)
     assert h1 == m.code_hash(mri.FAST_RK4, 1, 128)            # deterministic
     assert h1 != m.code_hash(mri.FAST_RK4, 2, 128)
     assert h1 != m.code_hash(mri.FAST_HEUN, 1, 128)
-    assert h1 != mri.Mech(I.make_mechanism(1)).code_hash(mri.FAST_RK4, 1, 128)
+    assert h1 != mri.Mech(I.make_mechanism(I.FIELD64)).code_hash(mri.FAST_RK4, 1, 128)

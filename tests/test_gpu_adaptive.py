@@ -76,11 +76,11 @@ def test_adaptive_chemistry_advection_diffusion_matches_oracle(torch, mri, O):
     substeps per stage at H0 = 2e-7 (50 at 1e-7); the first attempt is rejected."""
     grid = (8, 6, 4)
     N = int(np.prod(grid))
-    mech = I.make_mechanism(1)
+    mech = I.make_mechanism(I.FIELD64)
     S = mech.n_species
     orc = O.Oracle(mech)
     tb = I.table_mis_kw3()
-    y0 = I.field_state(1, grid)
+    y0 = I.field_state(I.FIELD64, grid)
     n, ld = y0.shape
     H0, T = 2e-7, 4e-7
     rtol, atol_Y, atol_T = 1e-5, 1e-9, 1e-3

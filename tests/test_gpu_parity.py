@@ -43,22 +43,23 @@ def _dev(torch, a, dtype=None):
     return T.as_tensor(np.ascontiguousarray(a), dtype=dtype or T.float64, device="cuda")
 
 
-def _config0_forcing(O, orc, y0, n_stages=3):
-    """Config-0 slow tendencies r_j = 1e-3 |f^F(y0)| xi_j (oracle supplies |f^F|)."""
+def _small_forcing(O, orc, y0, n_stages=3):
+    """Slow tendencies of the 512-cell workload, r_j = 1e-3 |f^F(y0)| xi_j (the
+    oracle supplies |f^F|)."""
     fF = orc.rhs_soa(y0)
-    xi = I.gaussian_xi(0, n_stages, y0.shape[0], y0.shape[1])
+    xi = I.gaussian_xi(I.SMALL, n_stages, y0.shape[0], y0.shape[1])
     return 1e-3 * np.abs(fF)[None] * xi
 
 
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("n_poly", [1, 2, 3])
-def test_rk4_stage_config0(torch, mri, O, kernel, n_poly):
-    mech = I.make_mechanism(0)
+def test_rk4_stage_small(torch, mri, O, kernel, n_poly):
+    mech = I.make_mechanism(I.SMALL)
     orc = O.Oracle(mech)
-    y0 = I.initial_state(0)
+    y0 = I.initial_state(I.SMALL)
     n, ld = y0.shape
-    F = _config0_forcing(O, orc, y0)
+    F = _small_forcing(O, orc, y0)
     rho = np.stack([F[k] / (k + 1) for k in range(n_poly)])     # polynomial forcing terms
     L, n_sub = (5.0 / 12.0) * 1e-6, 20
     ref, st_o, _, _ = orc.fast_stage_soa(y0, rho, L, O.rk4_opts(n_sub))
@@ -72,7 +73,7 @@ def test_rk4_stage_config0(torch, mri, O, kernel, n_poly):
     mri.mri_fast_stage(m, opts, 512, ld, yd, out, n_poly, _dev(torch, rho), L, st, steps)
     torch.cuda.synchronize()
     e = assert_parity(out.cpu().numpy(), ref, mech.n_species, what=f"{kernel} np={n_poly}")
-    print(f"rk4 config0 {kernel} n_poly={n_poly}: max rel err {e:.2e}")
+    print(f"rk4 small {kernel} n_poly={n_poly}: max rel err {e:.2e}")
     assert np.all(st.cpu().numpy()[:512] == 0)
     assert np.all(steps.cpu().numpy()[:512] == n_sub)
 
@@ -80,7 +81,7 @@ def test_rk4_stage_config0(torch, mri, O, kernel, n_poly):
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_ragged_tail_and_in_place(torch, mri, O, kernel):
     """517 cells in ld = 576: the padding stays untouched; y_out may alias y_in."""
-    mech = I.make_mechanism(1)
+    mech = I.make_mechanism(I.FIELD64)
     orc = O.Oracle(mech)
     rng = np.random.Generator(np.random.PCG64(77))
     y0 = I.independent_cells(517, mech.n_species, rng, ld=576)
@@ -102,12 +103,12 @@ def test_ragged_tail_and_in_place(torch, mri, O, kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_zonneveld_stage_config0(torch, mri, O, kernel):
-    mech = I.make_mechanism(0)
+def test_zonneveld_stage_small(torch, mri, O, kernel):
+    mech = I.make_mechanism(I.SMALL)
     orc = O.Oracle(mech)
-    y0 = I.initial_state(0)
+    y0 = I.initial_state(I.SMALL)
     n, ld = y0.shape
-    F = _config0_forcing(O, orc, y0)
+    F = _small_forcing(O, orc, y0)
     rho = F[:1]
     L = (5.0 / 12.0) * 1e-6
     zo = O.zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
@@ -148,17 +149,17 @@ TABLES = {"MIS-KW3": I.table_mis_kw3, "ERK33a": I.table_erk33a, "ERK45a": I.tabl
 
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("table_name", list(TABLES))
-def test_mri_slow_step_config0(torch, mri, O, kernel, table_name):
-    """One explicit MRI-GARK step of config 0 (H = 1e-6, RK4 with 20 substeps per
-    stage), slow evaluations given as the config's Gaussian tendencies (one per
+def test_mri_slow_step_small(torch, mri, O, kernel, table_name):
+    """One explicit MRI-GARK step of the 512-cell workload (H = 1e-6, RK4 with 20
+    substeps per stage), slow evaluations given as its Gaussian tendencies (one per
     new slow stage: 3 for the 4-stage tables, 5 for ERK45a)."""
     tb = TABLES[table_name]()
     ns = tb.s - 1
-    mech = I.make_mechanism(0)
+    mech = I.make_mechanism(I.SMALL)
     orc = O.Oracle(mech)
-    y0 = I.initial_state(0)
+    y0 = I.initial_state(I.SMALL)
     n, ld = y0.shape
-    F = _config0_forcing(O, orc, y0, n_stages=ns)
+    F = _small_forcing(O, orc, y0, n_stages=ns)
     ref, st_o, steps_o, n_slow = orc.mri_step_given(tb, O.rk4_opts(20), F, y0, 1e-6)
     assert n_slow == ns and np.all(st_o[:512] == 0)
     m, t = mri.Mech(mech), mri.Table(tb)
@@ -181,12 +182,12 @@ def test_mri_slow_step_config0(torch, mri, O, kernel, table_name):
 
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_mri_slow_steps_advdiff_small_grid(torch, mri, O, kernel):
-    """Config-1 physics on a 12 x 10 x 8 periodic grid: two MRI steps with the
+    """The 64^3 workload's physics on a 12 x 10 x 8 periodic grid: two MRI steps with the
     advection-diffusion slow RHS, H = 1e-7, RK4 with 50 substeps per stage."""
     grid = (12, 10, 8)
-    mech = I.make_mechanism(1)
+    mech = I.make_mechanism(I.FIELD64)
     orc = O.Oracle(mech)
-    y0 = I.field_state(1, grid=grid)
+    y0 = I.field_state(I.FIELD64, grid=grid)
     n, ld = y0.shape
     N = int(np.prod(grid))
     tb = I.table_mis_kw3()
@@ -246,15 +247,15 @@ def _erk_methods(O, mri, method):
 
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("method", ["heun", "bs3", "ck5"])
-def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
+def test_fixed_step_methods_stage_small(torch, mri, O, kernel, method):
     """Heun, Bogacki-Shampine and Cash-Karp fast stages (the order-2, 3 and 5
     fast methods of the MRI-P(k) family) against the oracle's general explicit
     RK stage with its own tableaus."""
-    mech = I.make_mechanism(0)
+    mech = I.make_mechanism(I.SMALL)
     orc = O.Oracle(mech)
-    y0 = I.initial_state(0)
+    y0 = I.initial_state(I.SMALL)
     n, ld = y0.shape
-    F = _config0_forcing(O, orc, y0)
+    F = _small_forcing(O, orc, y0)
     rho = np.stack([F[k] / (k + 1) for k in range(2)])
     L, n_sub = (5.0 / 12.0) * 1e-6, 20
     om, gm = _erk_methods(O, mri, method)
@@ -268,7 +269,7 @@ def test_fixed_step_methods_stage_config0(torch, mri, O, kernel, method):
     mri.mri_fast_stage(m, opts, 512, ld, yd, out, 2, _dev(torch, rho), L, None, steps)
     torch.cuda.synchronize()
     e = assert_parity(out.cpu().numpy(), ref, mech.n_species, what=f"{method} {kernel}")
-    print(f"{method} config0 {kernel}: max rel err {e:.2e}")
+    print(f"{method} small {kernel}: max rel err {e:.2e}")
     assert np.all(steps.cpu().numpy()[:512] == n_sub)
 
 
@@ -308,8 +309,8 @@ def test_mri_order_with_low_order_fast_methods(torch, mri, O, method, order):
 
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_determinism_and_fault_isolation(torch, mri, O, kernel):
-    mech = I.make_mechanism(0)
-    y0 = I.initial_state(0)
+    mech = I.make_mechanism(I.SMALL)
+    y0 = I.initial_state(I.SMALL)
     n, ld = y0.shape
     m = mri.Mech(mech)
     opts = mri.fast_opts(n_sub=20, kernel=_kernel(mri, kernel))

@@ -111,7 +111,7 @@ def test_adam_step(torch, mri):
 
 
 def _cells(torch, mri, n_cells, seed):
-    mech = I.make_mechanism(1)
+    mech = I.make_mechanism(I.FIELD64)
     rng = np.random.Generator(np.random.PCG64(seed))
     y = I.independent_cells(n_cells, mech.n_species, rng)
     rho = (rng.normal(size=(1, *y.shape)) * 1e3)
@@ -229,11 +229,11 @@ def test_trained_network_gain(torch, mri):
     data = S.generate_stage_data(n_full=200_000, log=print)
     res = S.train(data, steps=4000, batch=4096, log=print, log_every=2000)
     del data
-    cfg = I.CONFIGS[4]
-    mech = I.make_mechanism(4)
+    cfg = I.WORKLOADS[I.FIELD128]
+    mech = I.make_mechanism(I.FIELD128)
     m = mri.Mech(mech)
     m.specialize(128, load=True)
-    y, rho, L, N, ld = S.stage_inputs(4)
+    y, rho, L, N, ld = S.stage_inputs(I.FIELD128)
     opts = mri.fast_opts(n_sub=cfg.n_sub)
     ref = torch.empty_like(y)
     mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)

@@ -37,15 +37,15 @@ def _sample(N, k, seed=5):
     return np.unique(np.concatenate([idx, [0, N - 1]]))
 
 
-@pytest.mark.parametrize("config", [1, 4])
-def test_fullsize_fields_first_stage_sampled(torch, mri, O, config):
-    """First fast stage of an MIS-KW3 step on the full 64^3 (config 1) or 128^3
-    (config 4) field, in the benchmark's launch configuration; the slow
+@pytest.mark.parametrize("workload", [I.FIELD64, I.FIELD128])
+def test_fullsize_fields_first_stage_sampled(torch, mri, O, workload):
+    """First fast stage of an MIS-KW3 step on the full 64^3 or 128^3 field
+    (21 species), in the benchmark's launch configuration; the slow
     tendency F_1 = f^S(y0) is compared on the whole grid, the stage on sampled
     cells."""
-    cfg = I.CONFIGS[config]
-    mech = I.make_mechanism(config)
-    y0 = I.initial_state(config)
+    cfg = I.WORKLOADS[workload]
+    mech = I.make_mechanism(workload)
+    y0 = I.initial_state(workload)
     n, ld = y0.shape
     N = cfg.n_cells
     F_ora = O.advdiff(y0, cfg.grid)
@@ -74,16 +74,16 @@ def test_fullsize_fields_first_stage_sampled(torch, mri, O, config):
     ref, st_o, _, _ = orc.fast_stage_soa(np.ascontiguousarray(y0[:, cells]),
                                          np.ascontiguousarray(rho[:, :, cells]), L,
                                          O.rk4_opts(cfg.n_sub))
-    e = assert_parity(out.cpu().numpy()[:, cells], ref, mech.n_species, what=f"config {config}")
-    print(f"config {config} full size, 514 sampled cells: max rel err {e:.2e}")
+    e = assert_parity(out.cpu().numpy()[:, cells], ref, mech.n_species, what=workload)
+    print(f"{workload} full size, 514 sampled cells: max rel err {e:.2e}")
 
 
 def test_large_mechanism_fullsize_sampled(torch, mri, O):
     """53 species / 325 reactions on 128^3 cells, RK4 with 100 substeps, first
     stage of the H = 5e-8 step; sampled cells against the oracle."""
-    cfg = I.CONFIGS[3]
-    mech = I.make_mechanism(3)
-    y0 = I.initial_state(3)
+    cfg = I.WORKLOADS[I.LARGE128]
+    mech = I.make_mechanism(I.LARGE128)
+    y0 = I.initial_state(I.LARGE128)
     n, ld = y0.shape
     N = cfg.n_cells
     F_ora = O.advdiff(y0, cfg.grid)
@@ -103,15 +103,15 @@ def test_large_mechanism_fullsize_sampled(torch, mri, O):
     ref, _, _, _ = orc.fast_stage_soa(np.ascontiguousarray(y0[:, cells]),
                                       np.ascontiguousarray(rho[:, :, cells]), L,
                                       O.rk4_opts(cfg.n_sub))
-    e = assert_parity(out.cpu().numpy()[:, cells], ref, mech.n_species, what="config 3")
-    print(f"config 3 full size, sampled cells: max rel err {e:.2e}")
+    e = assert_parity(out.cpu().numpy()[:, cells], ref, mech.n_species, what=I.LARGE128)
+    print(f"{I.LARGE128} full size, sampled cells: max rel err {e:.2e}")
 
 
 def _batch_inputs(n_sets, lo, hi, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     sizes = np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi), n_sets))).astype(np.int64)
     off = I.set_offsets(sizes)
-    mech = I.make_mechanism(2)
+    mech = I.make_mechanism(I.SETS1000)
     y = I.independent_cells(int(off[-1]), mech.n_species, rng)
     L = rng.uniform(0.3, 1.0, n_sets) * 1e-7
     return mech, off, y, L, rng
@@ -168,8 +168,8 @@ def test_slow_step_graph_capture_replays(torch, mri, O):
     """A captured MRI slow step replays to the eager result on every replay,
     with eager work and synchronizations between replays."""
     grid = (16, 16, 8)
-    mech = I.make_mechanism(1)
-    y0 = I.field_state(1, grid=grid)
+    mech = I.make_mechanism(I.FIELD64)
+    y0 = I.field_state(I.FIELD64, grid=grid)
     n, ld = y0.shape
     N = int(np.prod(grid))
     m, t = mri.Mech(mech), mri.Table(I.table_mis_kw3())
@@ -202,7 +202,7 @@ def test_batch_fullsize_sampled(torch, mri, O):
     """The full batched workload (1000 uneven sets, ~1e7 cells) in one persistent
     launch; sampled cells of every size class against the oracle."""
     sizes, off, y, Ls = I.batch_workload()
-    mech = I.make_mechanism(2)
+    mech = I.make_mechanism(I.SETS1000)
     n, ld = y.shape
     ntot = int(off[-1])
     m = mri.Mech(mech)

@@ -5,10 +5,10 @@ import pytest
 from paper_2211_03293_amd import inputs as I
 
 
-@pytest.mark.parametrize("config", [0, 1, 3])
-def test_mechanism_structure(config):
-    m = I.make_mechanism(config)
-    cfg = I.CONFIGS[config]
+@pytest.mark.parametrize("workload", [I.SMALL, I.FIELD64, I.LARGE128])
+def test_mechanism_structure(workload):
+    m = I.make_mechanism(workload)
+    cfg = I.WORKLOADS[workload]
     assert (m.n_species, m.n_reactions) == (cfg.n_species, cfg.n_reactions)
     comp = m.composition
     assert len({tuple(r) for r in comp}) == m.n_species            # distinct species
@@ -32,21 +32,21 @@ def test_mechanism_structure(config):
 
 
 def test_seeded_reproducibility():
-    a, b = I.make_mechanism(1), I.make_mechanism(1)
+    a, b = I.make_mechanism(I.FIELD64), I.make_mechanism(I.FIELD64)
     np.testing.assert_array_equal(a.lnA, b.lnA)
-    np.testing.assert_array_equal(I.initial_state(0), I.initial_state(0))
+    np.testing.assert_array_equal(I.initial_state(I.SMALL), I.initial_state(I.SMALL))
 
 
 def test_independent_cells():
-    y = I.initial_state(0)
-    S = I.CONFIGS[0].n_species
+    y = I.initial_state(I.SMALL)
+    S = I.WORKLOADS[I.SMALL].n_species
     np.testing.assert_allclose(y[:S].sum(0), 1.0, atol=1e-15)
     assert y[S].min() >= 1000 and y[S].max() <= 2000
 
 
 def test_field_state_small_grid():
-    y = I.field_state(1, grid=(8, 8, 8))
-    S = I.CONFIGS[1].n_species
+    y = I.field_state(I.FIELD64, grid=(8, 8, 8))
+    S = I.WORKLOADS[I.FIELD64].n_species
     np.testing.assert_allclose(y[:S].sum(0), 1.0, atol=1e-14)
     assert y[S].min() >= 1000 - 1e-9 and y[S].max() <= 2000 + 1e-9
 

@@ -12,8 +12,8 @@ from paper_2211_03293_amd import inputs as I
 R_GAS = 8.314462618
 
 
-def _cell(config, i=0, seed=21):
-    m = I.make_mechanism(config)
+def _cell(workload, i=0, seed=21):
+    m = I.make_mechanism(workload)
     y = I.independent_cells(8, m.n_species, np.random.Generator(np.random.PCG64(seed)), ld=8)
     return m, y[:, i].copy()
 
@@ -21,7 +21,7 @@ def _cell(config, i=0, seed=21):
 def test_relaxation_to_equilibrium(oracle_mod):
     """A long fast-only integration ends where every reaction satisfies
     ln Q_j = -Delta G_j(T)/(R T) (mass-action equilibrium)."""
-    m = I.make_mechanism(0)
+    m = I.make_mechanism(I.SMALL)
     # narrow rates and |Delta G/RT| ~ 1 so that an explicit adaptive run reaches
     # equilibrium in a few thousand steps
     m.lnA[:] = np.log(3e9)
@@ -48,9 +48,9 @@ def test_relaxation_to_equilibrium(oracle_mod):
 
 
 def test_brute_force_refinement_converges_at_order_4(oracle_mod):
-    m, v0 = _cell(0)
+    m, v0 = _cell(I.SMALL)
     orc = oracle_mod.Oracle(m)
-    cfg = I.CONFIGS[0]
+    cfg = I.WORKLOADS[I.SMALL]
     L = (5.0 / 12.0) * cfg.H
     rho = np.zeros((1, v0.size))
     sols = [orc.rk4_stage(v0, rho, L, cfg.n_sub * 2 ** k)[0] for k in range(6)]
@@ -58,15 +58,15 @@ def test_brute_force_refinement_converges_at_order_4(oracle_mod):
     errs = [np.abs(s - ref).max() for s in sols[:3]]
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 3.7) and np.all(rates < 4.4), rates
-    # the config's n_sub result agrees with the refined limit to the RK4 error
+    # the workload's n_sub result agrees with the refined limit to the RK4 error
     rel = np.abs(sols[0] - ref) / np.maximum(np.abs(ref), 1e-12)
     assert rel.max() < 1e-4
 
 
 def test_energy_drift_scales_as_h4(oracle_mod):
-    m, v0 = _cell(0, i=4)
+    m, v0 = _cell(I.SMALL, i=4)
     orc = oracle_mod.Oracle(m)
-    L = (5.0 / 12.0) * I.CONFIGS[0].H
+    L = (5.0 / 12.0) * I.WORKLOADS[I.SMALL].H
     E0 = orc.energy(v0)
     drifts = []
     for n_sub in (5, 10, 20, 40):
@@ -81,10 +81,10 @@ def test_mri_step_keeps_linear_invariants(oracle_mod):
     """With mass-sum-free slow tendencies, sum_k Y_k is conserved by the whole MRI
     step (RK methods preserve linear invariants), and so is each element total
     when the slow tendencies are zero."""
-    cfg = I.CONFIGS[0]
-    m = I.make_mechanism(0)
+    cfg = I.WORKLOADS[I.SMALL]
+    m = I.make_mechanism(I.SMALL)
     orc = oracle_mod.Oracle(m)
-    y0 = I.initial_state(0)[:, :64].copy()
+    y0 = I.initial_state(I.SMALL)[:, :64].copy()
     S = m.n_species
     rng = np.random.Generator(np.random.PCG64(2))
     F = rng.normal(size=(3, S + 1, 64)) * 1e3
@@ -104,19 +104,19 @@ def test_mri_step_keeps_linear_invariants(oracle_mod):
     assert np.abs(y2[S] - y0[S]).max() > 10.0
 
 
-def test_stored_rate_scale_config0_reproduces(oracle_mod):
-    """The stored scale for the config-0 mechanism keeps h*rho(J_F) <= 0.5 at
-    every stage start of the config-0 run (the calibration criterion)."""
+def test_stored_rate_scale_of_the_512_cell_workload_reproduces(oracle_mod):
+    """The stored scale for the 9-species mechanism keeps h*rho(J_F) <= 0.5 at
+    every stage start of the 512-cell run (the calibration criterion)."""
     with open(I.SCALES_PATH) as f:
-        stored = json.load(f)["scales"]["0"]
+        stored = json.load(f)["scales"][I.SMALL]
     from oracle import calibrate_scales as cal
-    m = I.make_mechanism(0)
+    m = I.make_mechanism(I.SMALL)
     assert m.rate_scale == pytest.approx(stored["s"], rel=0)
-    worst = cal.trajectory_h_rho(0, m, n_sample=512)
+    worst = cal.trajectory_h_rho(I.SMALL, m, n_sample=512)
     assert worst <= 0.5 * 1.0001
     # and the unscaled initial-state spectral radius matches the stored value
-    m0 = I.make_mechanism(0, with_scale=False)
-    rho = cal.spectral_radii(oracle_mod.Oracle(m0), I.initial_state(0), 512)
+    m0 = I.make_mechanism(I.SMALL, with_scale=False)
+    rho = cal.spectral_radii(oracle_mod.Oracle(m0), I.initial_state(I.SMALL), 512)
     assert rho.max() == pytest.approx(stored["rho_max_unscaled"], rel=1e-6)
 
 
@@ -126,11 +126,11 @@ def test_mri_order_four_on_nonlinear_chemistry_with_advection_diffusion(oracle_m
     decade and the slow error is resolved) as the fast part, 2nd-order
     advection-diffusion on a 4^3 periodic grid as the slow part; self-
     convergence against 64 steps, fast stages resolved with 32 RK4 substeps."""
-    mech = I.make_mechanism(1)
+    mech = I.make_mechanism(I.FIELD64)
     mech = mech.with_scale(mech.rate_scale * 1e-3)
     orc = oracle_mod.Oracle(mech)
     grid = (4, 4, 4)
-    y0 = I.field_state(1, grid)
+    y0 = I.field_state(I.FIELD64, grid)
     T_end = 2e-6
 
     def run(n):
