@@ -224,11 +224,11 @@ def plain_leg(torch, mri, I, workload, steps, warmup, block, kernel_name):
     fps = flops_per_substep(mech.n_species, mech.n_reactions, n_poly=1)
     avg_launch_s = fast_ms * 1e-3 / max(1, n_launch)
     achieved = fps * cfg.n_sub * N / avg_launch_s / 1e12
-    workload = (f"mri_fast_stage rk4 {cfg.grid[0]}^3 cells S={mech.n_species} "
-                f"R={mech.n_reactions} n_sub={cfg.n_sub}")
+    traffic_key = (f"mri_fast_stage rk4 {cfg.grid[0]}^3 cells S={mech.n_species} "
+                   f"R={mech.n_reactions} n_sub={cfg.n_sub}")
     traffic = None
     if kernel != mri.KERNEL_GENERIC:
-        traffic = load_traffic(workload, m.code_hash(mri.FAST_RK4, tb.n_gamma, block or 128))
+        traffic = load_traffic(traffic_key, m.code_hash(mri.FAST_RK4, tb.n_gamma, block or 128))
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=traffic,
                 kernel="mri_spec_main (RK4, specialized)" if kernel != mri.KERNEL_GENERIC

@@ -283,8 +283,11 @@ int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int 
                         mri_stream_t stream);
 
 /* Diagnostic: y[i] = 2^x[i] (device arrays, n elements) with the device
-   exponential the fast-stage kernels use, for accuracy tests. */
+   exponential of the generic fast-stage kernels, for accuracy tests. */
 mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t stream);
+/* The same with the table-driven exponential of the specialized kernels
+   (2^(j/256) table plus a degree-4 polynomial; |x| < 1022). */
+mri_status mri_selftest_exp2_t256(const double *x, double *y, int n, mri_stream_t stream);
 
 /* Counts cells with (status & mask) != 0; synchronizes the stream. */
 mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, int64_t *n_bad,

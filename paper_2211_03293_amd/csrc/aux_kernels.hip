@@ -101,6 +101,20 @@ __global__ void __launch_bounds__(256) k_exp2(const double *__restrict__ x, doub
     if (i < n) y[i] = mri_exp2(x[i]);
 }
 
+__constant__ double exp2_tab_src[256] = MRI_EXP2_T256;
+
+// 2^x by the table-driven exponential of the specialized kernels (u = 256 x is
+// exact), with the table staged in LDS as those kernels do
+__global__ void __launch_bounds__(256) k_exp2_t256(const double *__restrict__ x,
+                                                  double *__restrict__ y, int n)
+{
+    __shared__ double tab[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) tab[i] = exp2_tab_src[i];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = mri_exp2_t256(256.0 * x[i], tab);
+}
+
 __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -224,6 +238,13 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, h
 {
     const int block = 64;
     hipLaunchKernelGGL(k_fill_u64, dim3((n + block - 1) / block), dim3(block), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp2_t256(const double *x, double *y, int n, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(k_exp2_t256, dim3((n + block - 1) / block), dim3(block), 0, s, x, y, n);
     return hipGetLastError();
 }
 

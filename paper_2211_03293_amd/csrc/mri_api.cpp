@@ -291,6 +291,10 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     if (const char *g = std::getenv("MRI_SPEC_GROUP"))   // tuning knob
         group = std::max(1, std::atoi(g));
     std::string tune = "#define MRI_GROUP " + std::to_string(group) + "\n";
+    if (const char *w = std::getenv("MRI_SPEC_WPE"))     // tuning knob: waves per SIMD
+        tune += "#define MRI_WPE " + std::to_string(std::max(1, std::min(4, std::atoi(w)))) + "\n";
+    if (const char *e = std::getenv("MRI_SPEC_EXP_TABLE"))   // tuning knob: 0 / 1
+        tune += std::string("#define MRI_EXP_TABLE ") + (std::atoi(e) ? "1" : "0") + "\n";
     if (kind == 3 || kind == 4) tune += erk_defs(erk_coef(kind == 3 ? MRI_FAST_HEUN : MRI_FAST_BS3));
     if (kind == 5) tune += erk_full_defs(erk_full_ck5());
     std::string src = m->defs + tune + "#define WG " + std::to_string(wg) + "\n#define MRI_KIND " +
@@ -1068,6 +1072,14 @@ mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t str
     if (n < 0 || (n > 0 && (!x || !y))) return fail(MRI_EINVAL, "bad arguments");
     if (n == 0) return MRI_OK;
     HIP_TRY(launch_exp2(x, y, n, (hipStream_t)stream));
+    return MRI_OK;
+}
+
+mri_status mri_selftest_exp2_t256(const double *x, double *y, int n, mri_stream_t stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(MRI_EINVAL, "bad arguments");
+    if (n == 0) return MRI_OK;
+    HIP_TRY(launch_exp2_t256(x, y, n, (hipStream_t)stream));
     return MRI_OK;
 }
 

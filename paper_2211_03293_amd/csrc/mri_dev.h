@@ -97,4 +97,5 @@ hipError_t launch_step_err(int n, int t_comp, int n_cells, int ld, const double 
                            double *part_w2, long long *part_steps, hipStream_t s);
 hipError_t launch_status_merge(int n_cells, const int32_t *st_a, const int32_t *st_b,
                                int32_t *status_out, hipStream_t s);
+hipError_t launch_exp2_t256(const double *x, double *y, int n, hipStream_t s);
 hipError_t launch_exp2(const double *x, double *y, int n, hipStream_t s);

@@ -110,6 +110,7 @@ _SIGS = {
     "mri_advdiff_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
     "mri_linear_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
     "mri_selftest_exp2": (_i, [_vp, _vp, _i, _vp]),
+    "mri_selftest_exp2_t256": (_i, [_vp, _vp, _i, _vp]),
     "mri_status_count": (_i, [_vp, _i, C.c_int32, C.POINTER(C.c_int64), _vp]),
     "mri_get_counters": (None, [C.POINTER(mri_counters)]),
     "mri_reset_counters": (None, []),
@@ -313,6 +314,10 @@ def mri_adaptive_run(mech: Mech, table: Table, opts, aopts, f_slow, user, t0, t_
 
 def mri_selftest_exp2(x, y, stream=None):
     _check(lib.mri_selftest_exp2(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
+
+
+def mri_selftest_exp2_t256(x, y, stream=None):
+    _check(lib.mri_selftest_exp2_t256(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
 
 
 def mri_status_count(status, n_cells, mask=0xFF, stream=None):

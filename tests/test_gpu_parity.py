@@ -339,23 +339,27 @@ def test_determinism_and_fault_isolation(torch, mri, O, kernel):
     assert mri.mri_status_count(torch.as_tensor(sc, device="cuda"), 512) == 2
 
 
-def test_device_exp2_accuracy(torch, mri):
-    """The kernels' 2^t (Taylor series of exp(f ln 2) after range reduction)
-    against numpy's exp2 over the exponent range the kernels use."""
+@pytest.mark.parametrize("variant", ["polynomial", "table"])
+def test_device_exp2_accuracy(torch, mri, variant):
+    """The kernels' 2^t against numpy's exp2 over the exponent range the kernels
+    use: the generic kernels' degree-11 polynomial on [-1/2, 1/2] and the
+    specialized kernels' 2^(j/256) table with a degree-4 polynomial."""
+    fn = mri.mri_selftest_exp2 if variant == "polynomial" else mri.mri_selftest_exp2_t256
     rng = np.random.Generator(np.random.PCG64(8))
     x = np.concatenate([rng.uniform(-1000, 1000, 200000), rng.uniform(-1, 1, 100000),
                         np.arange(-60, 61, 0.5), [0.0, -0.0, 1e-300, 0.49999999999999994,
                                                   -0.5, 0.5, 1021.9]])
     xd = torch.as_tensor(x, device="cuda")
     yd = torch.empty_like(xd)
-    mri.mri_selftest_exp2(xd, yd)
+    fn(xd, yd)
     torch.cuda.synchronize()
     y = yd.cpu().numpy()
     ref = np.exp2(x)
     ulp = np.spacing(np.abs(ref))
     err = np.abs(y - ref) / ulp
+    print(f"exp2 {variant}: max {err.max():.2f} ulp, mean {err.mean():.3f}")
     assert err.max() <= 2.0, (err.max(), x[np.argmax(err)])
-    nan = mri.mri_selftest_exp2
+    nan = fn
     xn = torch.tensor([np.nan], dtype=torch.float64, device="cuda")
     yn = torch.empty_like(xn)
     nan(xn, yn)
