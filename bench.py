@@ -244,6 +244,7 @@ def surrogate_leg(train_steps, n_samples):
     """Learned surrogate: stage data from the 64^3 workload's plain runs, training
     with libmri's BF16 MFMA kernels, then the gated stage (tolerance 1e-4) on the
     first fast stage of the 128^3 workload against the plain FP64 stage."""
+    from paper_2211_03293_amd import inputs as I
     from paper_2211_03293_amd import surrogate as S
 
     def log(msg):
