@@ -365,3 +365,82 @@ def test_device_exp2_accuracy(torch, mri, variant):
     nan(xn, yn)
     torch.cuda.synchronize()
     assert np.isnan(yn.item())
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_zonneveld_step_cap_flags_cells(torch, mri, O, kernel):
+    """A cap of 12 accepted steps per cell-stage (every cell needs at least 10,
+    the first step being L/10): every cell that needs more is flagged MAXSTEPS
+    (173 of 512 cells), cells within the cap are not, and the accepted-step
+    counts equal the oracle's.  Cells that finish end at t = L and meet the
+    1e-10 bar.  A capped cell stops at the time its 12 accepted steps reach;
+    those steps come from the embedded error estimate, a difference of
+    near-equal terms on which the device and the oracle agree only to about
+    1e-16 / tol = 1e-8 relative, so the stopping times and hence the capped
+    states agree to about that (checked at 1e-6)."""
+    mech = I.make_mechanism(I.SMALL)
+    orc = O.Oracle(mech)
+    y0 = I.initial_state(I.SMALL)
+    n, ld = y0.shape
+    rho = _small_forcing(O, orc, y0)[:1]
+    L = (5.0 / 12.0) * 1e-6
+    zo = O.zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=12)
+    ref, st_o, acc_o, _ = orc.fast_stage_soa(y0, rho, L, zo)
+    capped = (st_o[:512] & O.ST_MAXSTEPS) != 0
+    assert 0 < capped.sum() < 512
+    m = mri.Mech(mech)
+    yd = _dev(torch, y0)
+    out = torch.empty_like(yd)
+    st = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+    opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
+                         max_steps=12, kernel=_kernel(mri, kernel))
+    mri.mri_fast_stage(m, opts, 512, ld, yd, out, 1, _dev(torch, rho), L, st, steps)
+    torch.cuda.synchronize()
+    st_g = st.cpu().numpy()[:512]
+    tie = ((st_g | st_o[:512]) & mri.CELL_NEARTIE) != 0
+    ok = ~tie
+    np.testing.assert_array_equal((st_g[ok] & mri.CELL_MAXSTEPS) != 0, capped[ok])
+    np.testing.assert_array_equal(steps.cpu().numpy()[:512][ok], acc_o[:512][ok])
+    got = out.cpu().numpy()
+    assert_parity(got, ref, mech.n_species, cells=np.nonzero(ok & ~capped)[0],
+                  what=f"finished cells {kernel}")
+    e = assert_parity(got, ref, mech.n_species, cells=np.nonzero(ok & capped)[0], tol=1e-6,
+                      what=f"capped cells {kernel}")
+    print(f"capped cells: max rel difference {e:.2e}")
+    print(f"step cap {kernel}: {capped.sum()} of 512 cells capped, near ties {tie.sum()}")
+
+
+def test_checkpoint_resume_is_bitwise(torch, mri, tmp_path):
+    """The whole integration state is the SoA array and the time: six MRI steps
+    straight through equal three steps, a save to disk, a load into fresh
+    device memory and three more steps, bit for bit."""
+    grid = (12, 10, 8)
+    mech = I.make_mechanism(I.FIELD64)
+    y0 = I.field_state(I.FIELD64, grid=grid)
+    n, ld = y0.shape
+    N = int(np.prod(grid))
+    m, t = mri.Mech(mech), mri.Table(I.table_mis_kw3())
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    params = mri.advdiff_params(grid, n)
+    opts = mri.fast_opts(n_sub=50)
+    H = 1e-7
+
+    def steps(y, k0, k1):
+        for k in range(k0, k1):
+            mri.mri_slow_step(m, t, opts, mri.ADVDIFF_RHS, params, k * H, H, N, ld, y, ws)
+        torch.cuda.synchronize()
+
+    a = _dev(torch, y0)
+    steps(a, 0, 6)
+    b = _dev(torch, y0)
+    steps(b, 0, 3)
+    path = tmp_path / "state.npz"
+    np.savez(path, y=b.cpu().numpy(), t=3 * H, step=3)
+    del b
+    ck = np.load(path)
+    c = _dev(torch, ck["y"])
+    steps(c, int(ck["step"]), 6)
+    assert float(ck["t"]) == 3 * H
+    assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
