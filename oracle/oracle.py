@@ -25,15 +25,25 @@ GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-f
 ST_NONFINITE, ST_MAXSTEPS, ST_TRANGE, ST_NEARTIE = 1, 2, 4, 8
 
 
+# MRI_ORACLE_SANITIZE=1 builds and loads a separate copy instrumented with
+# AddressSanitizer and UndefinedBehaviorSanitizer (run Python with
+# LD_PRELOAD=$(gcc -print-file-name=libasan.so) ASAN_OPTIONS=detect_leaks=0).
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
+
+
 def build(force: bool = False) -> str:
     srcs = [s for s in _SRC if os.path.exists(s)]
-    stale = force or not os.path.exists(_LIB) or any(
-        os.path.getmtime(s) > os.path.getmtime(_LIB) for s in srcs)
+    san = os.environ.get("MRI_ORACLE_SANITIZE") == "1"
+    path = _LIB.replace(".so", "_san.so") if san else _LIB
+    stale = force or not os.path.exists(path) or any(
+        os.path.getmtime(s) > os.path.getmtime(path) for s in srcs)
     if stale:
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, *srcs, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        tmp = path + f".tmp{os.getpid()}"
+        flags = GCC_FLAGS + (SAN_FLAGS if san else [])
+        subprocess.check_call(["gcc", *flags, "-o", tmp, *srcs, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
 class Mech(C.Structure):
