@@ -266,7 +266,8 @@ mri_status mri_adaptive_run(const mri_mech *m, const mri_table *t, const mri_fas
 /* Built-in slow RHS: 2nd-order centred advection-diffusion on a periodic grid
    (Sec. 3, eq. problem2 transport terms; Sec. 3.1 second-order stencils) for
    every component: f = -u . grad(phi) + D lap(phi).  Cell index
-   (z*ny + y)*nx + x; n_cells must equal nx*ny*nz.  Pass a pointer to this
+   (z*ny + y)*nx + x; n_cells must equal nx*ny*nz, ny and nz at most 65535
+   (the callback returns nonzero otherwise).  Pass a pointer to this
    struct as `user` with mri_advdiff_slow_rhs as the callback. */
 typedef struct {
     int nx, ny, nz;

@@ -33,34 +33,37 @@ __global__ void __launch_bounds__(256)
 // f = -u . grad(phi) + D lap(phi), 2nd-order centred, periodic; one thread per
 // (component, cell).  Neighbour reads hit L2 / L1: x neighbours are
 // contiguous, y and z neighbours are one row / plane away.
+// One thread per cell (x across the lanes, the row and plane from the block
+// indices: no integer division), looping over the components; x-neighbours
+// come from the same row, y- and z-neighbours from rows the neighbouring blocks
+// also read (L2 hits).
 __global__ void __launch_bounds__(256)
     k_advdiff(int nx, int ny, int nz, int n_comp, int ld, double ux, double uy, double uz,
               double D, double dx, const double *__restrict__ y, double *__restrict__ fy)
 {
-    const long long ncell = (long long)nx * ny * nz;
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncell * n_comp) return;
-    const int comp = (int)(g / ncell);
-    const long long cell = g - (long long)comp * ncell;
-    const int x = (int)(cell % nx);
-    const int yy = (int)((cell / nx) % ny);
-    const int z = (int)(cell / ((long long)nx * ny));
-    const double *p = y + (size_t)comp * ld;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const int yy = blockIdx.y, z = blockIdx.z;
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = yy == 0 ? ny - 1 : yy - 1, yp = yy == ny - 1 ? 0 : yy + 1;
     const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-    const long long row = (long long)nx, plane = (long long)nx * ny;
+    const long long row = nx, plane = (long long)nx * ny;
     const long long base = (long long)z * plane + (long long)yy * row;
-    const double c0 = p[base + x];
-    const double pxm = p[base + xm], pxp = p[base + xp];
-    const double pym = p[(long long)z * plane + (long long)ym * row + x];
-    const double pyp = p[(long long)z * plane + (long long)yp * row + x];
-    const double pzm = p[(long long)zm * plane + (long long)yy * row + x];
-    const double pzp = p[(long long)zp * plane + (long long)yy * row + x];
+    const long long o_ym = (long long)z * plane + (long long)ym * row + x;
+    const long long o_yp = (long long)z * plane + (long long)yp * row + x;
+    const long long o_zm = (long long)zm * plane + (long long)yy * row + x;
+    const long long o_zp = (long long)zp * plane + (long long)yy * row + x;
     const double inv2dx = 1.0 / (2.0 * dx), invdx2 = 1.0 / (dx * dx);
-    const double adv = (ux * (pxp - pxm) + uy * (pyp - pym) + uz * (pzp - pzm)) * inv2dx;
-    const double lap = (pxp + pxm + pyp + pym + pzp + pzm - 6.0 * c0) * invdx2;
-    fy[(size_t)comp * ld + cell] = fma(D, lap, -adv);
+    for (int comp = 0; comp < n_comp; ++comp) {
+        const double *p = y + (size_t)comp * ld;
+        const double c0 = p[base + x];
+        const double pxm = p[base + xm], pxp = p[base + xp];
+        const double pym = p[o_ym], pyp = p[o_yp];
+        const double pzm = p[o_zm], pzp = p[o_zp];
+        const double adv = (ux * (pxp - pxm) + uy * (pyp - pym) + uz * (pzp - pzm)) * inv2dx;
+        const double lap = (pxp + pxm + pyp + pym + pzp + pzm - 6.0 * c0) * invdx2;
+        fy[(size_t)comp * ld + base + x] = fma(D, lap, -adv);
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -209,10 +212,10 @@ hipError_t launch_forcing(long long n_elem, int n_gamma, int nj, const double *F
 hipError_t launch_advdiff(int nx, int ny, int nz, int n_comp, int ld, const double *u,
                           double D, double dx, const double *y, double *fy, hipStream_t s)
 {
-    const int block = 256;
-    const long long total = (long long)nx * ny * nz * n_comp;
-    hipLaunchKernelGGL(k_advdiff, dim3((unsigned)((total + block - 1) / block)), dim3(block), 0, s,
-                       nx, ny, nz, n_comp, ld, u[0], u[1], u[2], D, dx, y, fy);
+    if (ny > 65535 || nz > 65535) return hipErrorInvalidValue;
+    const int block = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
+    hipLaunchKernelGGL(k_advdiff, dim3((unsigned)((nx + block - 1) / block), ny, nz), dim3(block), 0,
+                       s, nx, ny, nz, n_comp, ld, u[0], u[1], u[2], D, dx, y, fy);
     return hipGetLastError();
 }
 

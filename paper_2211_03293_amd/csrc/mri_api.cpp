@@ -1049,6 +1049,7 @@ int mri_advdiff_slow_rhs(double t, const double *y, double *fy, int n_cells, int
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->n_comp < 1) return -2;
     if ((long long)p->nx * p->ny * p->nz != n_cells || ld < n_cells) return -3;
     if (!(p->dx > 0.0)) return -4;
+    if (p->ny > 65535 || p->nz > 65535) return -6;
     if (launch_advdiff(p->nx, p->ny, p->nz, p->n_comp, ld, p->u, p->D, p->dx, y, fy,
                        (hipStream_t)stream) != hipSuccess)
         return -5;
