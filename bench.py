@@ -35,6 +35,10 @@ METRIC = "cell fast-stage solves/s: FP64 plain vs surrogate+fallback at 1e-4 rel
 PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 PEAK_BF16_TFLOPS = 2500.0         # MI355X dense BF16 MFMA
 MLP_FLOPS = 2 * (89 * 256 + 256 * 256 + 256 * 256 + 256 * 22)   # one inference, 89 -> 22
+# MFMA work the fused kernel executes per inference: the padded 96 -> 32 network;
+# rocprofv3's SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512 per dispatch equals this times
+# the cell count
+MLP_FLOPS_EXECUTED = 2 * (96 * 256 + 256 * 256 + 256 * 256 + 256 * 32)
 TRAIN_BATCH = 8192
 F_EXP, F_LOG, F_DIV = 22, 22, 10  # flops charged per FP64 exp / log / divide
 
@@ -63,17 +67,17 @@ def flops_per_zv_attempt(S: int, R: int) -> int:
     return 5 * rhs + 5 * n * 8 + 15 * n + 2 * n + 2 * F_EXP
 
 
-def load_traffic(workload: str, code_hash: str):
-    """HBM bytes per launch measured with rocprofv3 counters for the kernel
-    whose code object hashes to code_hash, or None when the compiled kernel
-    changed since the counters were taken."""
+def load_counters(workload: str, code_hash: str):
+    """rocprofv3 counter figures per launch (HBM bytes, FP64 counter flops) for
+    the kernel whose code object hashes to code_hash, or None when the compiled
+    kernel changed since the counters were taken."""
     p = os.path.join(ROOT, "profiles", "fast_stage_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_code_hash") != code_hash or d.get("workload") != workload:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def _cpu_model():
@@ -226,11 +230,18 @@ def plain_leg(torch, mri, I, workload, steps, warmup, block, kernel_name):
     achieved = fps * cfg.n_sub * N / avg_launch_s / 1e12
     traffic_key = (f"mri_fast_stage rk4 {cfg.grid[0]}^3 cells S={mech.n_species} "
                    f"R={mech.n_reactions} n_sub={cfg.n_sub}")
-    traffic = None
+    ctr = None
     if kernel != mri.KERNEL_GENERIC:
-        traffic = load_traffic(traffic_key, m.code_hash(mri.FAST_RK4, tb.n_gamma, block or 128))
+        ctr = load_counters(traffic_key, m.code_hash(mri.FAST_RK4, tb.n_gamma, block or 128))
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=traffic,
+                frac=round(achieved / PEAK_FP64_TFLOPS, 4),
+                traffic=ctr.get("hbm_bytes_per_launch") if ctr else None,
+                # the same launch time against the FP64 instructions the counters
+                # saw (the algorithmic count charges 22 flops per exponential)
+                frac_counters=(round(ctr["counter_fp64_flops_per_launch"] / avg_launch_s / 1e12
+                                     / PEAK_FP64_TFLOPS, 4)
+                               if ctr and "counter_fp64_flops_per_launch" in ctr else None),
+                mcell_substep_per_s=round(N * cfg.n_sub / avg_launch_s / 1e6, 1),
                 kernel="mri_spec_main (RK4, specialized)" if kernel != mri.KERNEL_GENERIC
                 else "k_gen_rk4 (generic)",
                 flops_per_cell_substep=fps, avg_launch_ms=round(avg_launch_s * 1e3, 4))
@@ -271,7 +282,9 @@ def surrogate_leg(train_steps, n_samples):
         inferences_per_s=round(ev["cells"] / t_inf_s, 1),
         roofline=dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_BF16_TFLOPS,
                       unit="TFLOP/s", frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
-                      kernel="k_infer (fused 4-layer BF16 MFMA)", flops_per_inference=MLP_FLOPS),
+                      kernel="k_infer (fused 4-layer BF16 MFMA)", flops_per_inference=MLP_FLOPS,
+                      frac_counters=round(ev["cells"] * MLP_FLOPS_EXECUTED / t_inf_s / 1e12
+                                          / PEAK_BF16_TFLOPS, 4)),
         seconds_total=round(time.perf_counter() - t0, 1))
     return ev
 
