@@ -96,6 +96,7 @@ bool finite_all(const double *p, int n)
 struct SpecKernel {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
+    size_t code_bytes = 0;      // size of the code object it was loaded from
 };
 
 inline int spec_key(int wg, int kind, int np) { return (wg << 8) | (kind << 4) | np; }
@@ -346,6 +347,7 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     ++c_spec;
     if (!load) return MRI_OK;
     SpecKernel sk;
+    sk.code_bytes = m->last_code.size();
     HIP_TRY(hipModuleLoadData(&sk.mod, m->last_code.data()));
     HIP_TRY(hipModuleGetFunction(&sk.fn, sk.mod, "mri_spec_main"));
     *out = sk;
@@ -692,8 +694,8 @@ void mri_mech_destroy(mri_mech *m)
 
 int mri_mech_state_width(const mri_mech *m) { return m ? m->n : -1; }
 
-mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int block_size,
-                                      int load, size_t *code_bytes)
+// Validation shared by the specialization entry points.
+static mri_status check_spec_request(const mri_mech *m, int method, int n_poly, int block_size)
 {
     if (!m) return fail(MRI_EINVAL, "mech is NULL");
     if (m->kind != 0) return fail(MRI_EUNSUPPORTED, "linear test mode has no specialization");
@@ -704,13 +706,21 @@ mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int b
     if (n_poly < 0 || n_poly > 4) return fail(MRI_EINVAL, "n_poly must be in [0, 4]");
     if (method == MRI_FAST_CK5 && m->S > GEN_NMAX_SMALL)
         return fail(MRI_EUNSUPPORTED, "Cash-Karp 5 supports at most %d species", GEN_NMAX_SMALL);
+    return MRI_OK;
+}
+
+mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int block_size,
+                                      int load, size_t *code_bytes)
+{
+    mri_status cs = check_spec_request(m, method, n_poly, block_size);
+    if (cs != MRI_OK) return cs;
     const int kind = spec_kind(method);
     if (load) {
         hipFunction_t fn = nullptr;
         mri_status st = spec_get(m, block_size, kind, n_poly, &fn);
         if (st != MRI_OK) return st;
         std::lock_guard<std::mutex> lk(m->mu);
-        if (code_bytes) *code_bytes = m->last_code.size();
+        if (code_bytes) *code_bytes = m->spec.at(spec_key(block_size, kind, n_poly)).code_bytes;
         return MRI_OK;
     }
     std::lock_guard<std::mutex> lk(m->mu);
@@ -724,9 +734,14 @@ mri_status mri_mech_code_hash(mri_mech *m, int method, int n_poly, int block_siz
                               uint64_t *hash)
 {
     if (!hash) return fail(MRI_EINVAL, "hash is NULL");
-    mri_status st = mri_mech_specialize_method(m, method, n_poly, block_size, 0, nullptr);
+    mri_status st = check_spec_request(m, method, n_poly, block_size);
     if (st != MRI_OK) return st;
+    // compile and hash under one lock so that a concurrent compilation cannot
+    // interleave
     std::lock_guard<std::mutex> lk(m->mu);
+    SpecKernel unused;
+    st = spec_compile(m, block_size, spec_kind(method), n_poly, 0, &unused);
+    if (st != MRI_OK) return st;
     uint64_t h = 1469598103934665603ull;        // FNV-1a, 64 bit
     for (char c : m->last_code) {
         h ^= (uint64_t)(unsigned char)c;
