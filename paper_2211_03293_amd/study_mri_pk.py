@@ -16,6 +16,9 @@ MRI-2(8), MRI-3(4), MRI-4(8) and MRI-5(4) the most efficient pairings).
 
 --table erk45a replaces the 3rd-order MIS-KW3 slow table by the 4th-order
 explicit MRI-GARK table (Sec. 2.1: explicit MRI-GARK methods reach order 4).
+--adaptive TOL ... adds runs whose slow step is chosen by step doubling
+(mri_adaptive_run, rtol = TOL, atol_Y = 1e-3 TOL, atol_T = 1e-3 TOL K) from
+H0 = the largest H, each fast method keeping the fast step of H0.
 
     python -m paper_2211_03293_amd.study_mri_pk [--cells-per-side 32] [--k 16]
     python -m paper_2211_03293_amd.study_mri_pk --k 8 4 8 4 --H 2.5e-8 1.25e-8 6.25e-9
@@ -63,6 +66,24 @@ def run(torch, m, t, y_host, grid, method, k, H):
     return y.cpu().numpy()[:, :N], dt, bad
 
 
+def run_adaptive(torch, m, t, y_host, grid, method, k, H0, tol, order):
+    n, ld = y_host.shape
+    N = int(np.prod(grid))
+    y = torch.as_tensor(y_host, device="cuda")
+    ws = torch.empty(mri.mri_adaptive_workspace_bytes(m, t, N, ld) // 8 + 1,
+                     dtype=torch.float64, device="cuda")
+    status = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    aopts = mri.adapt_opts(tol, 1e-3 * tol, 1e-3 * tol, H0, order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mri.mri_adaptive_run(m, t, mri.fast_opts(method=method, n_sub=k), aopts,
+                              mri.ADVDIFF_RHS, mri.advdiff_params(grid, n), 0.0, T_END, N, ld, y,
+                              ws, status)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return y.cpu().numpy()[:, :N], dt, mri.mri_status_count(status, N), st
+
+
 def errors(y, ref, n_species):
     """(max absolute mass-fraction error, max relative temperature error, max
     relative state error with the mass-fraction floor 1e-8) over all cells."""
@@ -82,6 +103,8 @@ def main(argv=None):
     ap.add_argument("--H", type=float, nargs="+", default=[1e-7, 5e-8, 2.5e-8, 1.25e-8])
     ap.add_argument("--table", choices=("kw3", "erk45a"), default="kw3",
                     help="slow table: MIS-KW3 (order 3) or MRI-GARK-ERK45a (order 4)")
+    ap.add_argument("--adaptive", type=float, nargs="*", default=[],
+                    help="tolerances of adaptive slow-step runs")
     args = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available(), "the study runs on a GPU"
@@ -117,6 +140,16 @@ def main(argv=None):
                   f"rel {e[2]:.3e}" + (" rates " + " ".join(f"{r:.2f}" for r in rate)
                                       if rate else "") + f"  {dt * 1e3:.1f} ms  flagged {bad}",
                   flush=True)
+    order = 3 if args.table == "kw3" else 4
+    for (name, P), meth, k in zip(METHODS, fast, ks):
+        for tol in args.adaptive:
+            y, dt, bad, st = run_adaptive(torch, m, t, y0, grid, meth, k, max(args.H), tol, order)
+            e = errors(y, ref, mech.n_species)
+            rows.append(dict(method=name, P=P, k=k, adaptive_tol=tol, err_Y_abs=e[0],
+                             err_T_rel=e[1], err_rel=e[2], seconds=dt, flagged=bad, **st))
+            print(f"MRI-{P}({k}) {name:17s} adaptive tol {tol:.0e}: |dY| {e[0]:.3e}  "
+                  f"dT/T {e[1]:.3e}  {st['accepted']} accepted / {st['rejected']} rejected, "
+                  f"last H {st['H_last']:.2e}  {dt * 1e3:.1f} ms  flagged {bad}", flush=True)
     print(json.dumps(dict(study=f"MRI-P(k) convergence, {tb.name} slow, 21 species / 84 "
                                 f"reactions, {args.cells_per_side}^3 cells, t = {T_END}",
                           rows=rows)))
