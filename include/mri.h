@@ -119,9 +119,10 @@ mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *co
    terms (0..4); mri_mech_specialize is the RK4 kernel with one term. */
 mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int block_size,
                                       int load, size_t *code_bytes);
-/* 64-bit FNV-1a hash of that kernel's code object (compiled, not loaded; no GPU
-   needed): identifies the exact machine code, e.g. to tell whether profiler
-   counters taken earlier still describe the kernel. */
+/* 64-bit FNV-1a hash of that kernel's machine code and constant data (the
+   .text and .rodata sections of its code object; compiled, not loaded, no GPU
+   needed): identifies the exact code the GPU runs, e.g. to tell whether
+   profiler counters taken earlier still describe the kernel. */
 mri_status mri_mech_code_hash(mri_mech *m, int method, int n_poly, int block_size,
                               uint64_t *hash);
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <elf.h>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -694,6 +696,62 @@ void mri_mech_destroy(mri_mech *m)
 
 int mri_mech_state_width(const mri_mech *m) { return m ? m->n : -1; }
 
+// FNV-1a (64 bit) over the bytes the GPU executes: the .text and .rodata
+// sections of the ELF code object (machine code, kernel descriptors, constant
+// tables).  The rest of the object carries a compilation-unit id that hipRTC
+// derives from the source text, so comments would otherwise change the hash.
+// Falls back to the whole object if the ELF headers do not parse.
+static uint64_t code_hash_bytes(const std::vector<char> &co)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const char *p, size_t n) {
+        for (size_t i = 0; i < n; ++i) {
+            h ^= (uint64_t)(unsigned char)p[i];
+            h *= 1099511628211ull;
+        }
+    };
+    const size_t size = co.size();
+    Elf64_Ehdr eh;
+    bool ok = size >= sizeof(eh);
+    if (ok) {
+        std::memcpy(&eh, co.data(), sizeof(eh));
+        ok = std::memcmp(eh.e_ident, ELFMAG, SELFMAG) == 0 && eh.e_ident[EI_CLASS] == ELFCLASS64 &&
+             eh.e_shentsize == sizeof(Elf64_Shdr) && eh.e_shstrndx < eh.e_shnum &&
+             eh.e_shoff <= size && (size - eh.e_shoff) / sizeof(Elf64_Shdr) >= eh.e_shnum;
+    }
+    int found = 0;
+    if (ok) {
+        auto shdr = [&](int i) {
+            Elf64_Shdr sh;
+            std::memcpy(&sh, co.data() + eh.e_shoff + (size_t)i * sizeof(Elf64_Shdr), sizeof(sh));
+            return sh;
+        };
+        const Elf64_Shdr strs = shdr(eh.e_shstrndx);
+        ok = strs.sh_offset <= size && strs.sh_size <= size - strs.sh_offset;
+        for (int i = 0; ok && i < eh.e_shnum; ++i) {
+            const Elf64_Shdr sh = shdr(i);
+            if (sh.sh_name >= strs.sh_size || sh.sh_type == SHT_NOBITS) continue;
+            const char *name = co.data() + strs.sh_offset + sh.sh_name;
+            const size_t room = strs.sh_size - sh.sh_name;
+            const bool text = strncmp(name, ".text", room) == 0;
+            const bool ro = strncmp(name, ".rodata", room) == 0;
+            if (!text && !ro) continue;
+            if (sh.sh_offset > size || sh.sh_size > size - sh.sh_offset) {
+                ok = false;
+                break;
+            }
+            mix(name, text ? 5 : 7);
+            mix(co.data() + sh.sh_offset, sh.sh_size);
+            ++found;
+        }
+    }
+    if (!ok || found == 0) {
+        h = 1469598103934665603ull;
+        mix(co.data(), size);
+    }
+    return h;
+}
+
 // Validation shared by the specialization entry points.
 static mri_status check_spec_request(const mri_mech *m, int method, int n_poly, int block_size)
 {
@@ -742,12 +800,7 @@ mri_status mri_mech_code_hash(mri_mech *m, int method, int n_poly, int block_siz
     SpecKernel unused;
     st = spec_compile(m, block_size, spec_kind(method), n_poly, 0, &unused);
     if (st != MRI_OK) return st;
-    uint64_t h = 1469598103934665603ull;        // FNV-1a, 64 bit
-    for (char c : m->last_code) {
-        h ^= (uint64_t)(unsigned char)c;
-        h *= 1099511628211ull;
-    }
-    *hash = h;
+    *hash = code_hash_bytes(m->last_code);
     return MRI_OK;
 }
 
