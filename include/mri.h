@@ -284,11 +284,13 @@ int mri_advdiff_slow_rhs(double t, const double *y, double *fy, int n_cells, int
 int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
                         mri_stream_t stream);
 
-/* Diagnostic: y[i] = 2^x[i] (device arrays, n elements) with the device
-   exponential of the generic fast-stage kernels, for accuracy tests. */
+/* Diagnostic: y[i] = 2^x[i] (device arrays, n elements) with the polynomial
+   exponential of the specialized kernels that run one wave per SIMD, for
+   accuracy tests. */
 mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t stream);
-/* The same with the table-driven exponential of the specialized kernels
-   (2^(j/256) table plus a degree-4 polynomial; |x| < 1022). */
+/* The same with the table-driven exponential of the specialized kernels that
+   run two waves per SIMD (2^(j/256) table plus a degree-4 polynomial;
+   |x| < 1022). */
 mri_status mri_selftest_exp2_t256(const double *x, double *y, int n, mri_stream_t stream);
 
 /* Counts cells with (status & mask) != 0; synchronizes the stream. */
