@@ -33,36 +33,77 @@ __global__ void __launch_bounds__(256)
 // f = -u . grad(phi) + D lap(phi), 2nd-order centred, periodic; one thread per
 // (component, cell).  Neighbour reads hit L2 / L1: x neighbours are
 // contiguous, y and z neighbours are one row / plane away.
-// One thread per cell (x across the lanes, the row and plane from the block
-// indices: no integer division), looping over the components; x-neighbours
-// come from the same row, y- and z-neighbours from rows the neighbouring blocks
-// also read (L2 hits).
-__global__ void __launch_bounds__(256)
+// 2.5D blocking: a block owns a tile of ADV_TX x ADV_TY cells of one component
+// and marches through ADV_TZ planes of z, each thread keeping the z-1, z and
+// z+1 values of its column in registers; the x- and y-neighbours of the
+// current plane come from an LDS tile with a one-cell halo (periodic wrap), so
+// every value is read from memory about once.  The arithmetic is that of the
+// plain 7-point formula, term for term.
+// Tile shape measured on MI355X (64^3 x 22 / 128^3 x 54 fields): 8 rows x 4
+// planes 22.1 / 472 us; 4 x 16: 25.9 / 505; 8 x 16: 24.9 / 492; 8 x 32: 40.6
+// / 527 -- short z marches keep more blocks in flight.
+#ifndef MRI_ADV_TY
+#define MRI_ADV_TY 8
+#endif
+#ifndef MRI_ADV_TZ
+#define MRI_ADV_TZ 4
+#endif
+constexpr int ADV_TX = 64, ADV_TY = MRI_ADV_TY, ADV_TZ = MRI_ADV_TZ;
+
+__global__ void __launch_bounds__(ADV_TX *ADV_TY)
     k_advdiff(int nx, int ny, int nz, int n_comp, int ld, double ux, double uy, double uz,
               double D, double dx, const double *__restrict__ y, double *__restrict__ fy)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    const int yy = blockIdx.y, z = blockIdx.z;
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = yy == 0 ? ny - 1 : yy - 1, yp = yy == ny - 1 ? 0 : yy + 1;
-    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    __shared__ double tile[ADV_TY + 2][ADV_TX + 2];
+    const int tx = threadIdx.x % ADV_TX, ty = threadIdx.x / ADV_TX;
+    const int x0 = blockIdx.x * ADV_TX, y0 = blockIdx.y * ADV_TY;
+    const int nzc = (nz + ADV_TZ - 1) / ADV_TZ;
+    const int comp = blockIdx.z / nzc, z0 = (blockIdx.z % nzc) * ADV_TZ;
+    const int z1 = min(nz, z0 + ADV_TZ);
+    const int x = x0 + tx, yy = y0 + ty;
+    const bool in = x < nx && yy < ny;
+    const double *p = y + (size_t)comp * ld;
     const long long row = nx, plane = (long long)nx * ny;
-    const long long base = (long long)z * plane + (long long)yy * row;
-    const long long o_ym = (long long)z * plane + (long long)ym * row + x;
-    const long long o_yp = (long long)z * plane + (long long)yp * row + x;
-    const long long o_zm = (long long)zm * plane + (long long)yy * row + x;
-    const long long o_zp = (long long)zp * plane + (long long)yy * row + x;
     const double inv2dx = 1.0 / (2.0 * dx), invdx2 = 1.0 / (dx * dx);
-    for (int comp = 0; comp < n_comp; ++comp) {
-        const double *p = y + (size_t)comp * ld;
-        const double c0 = p[base + x];
-        const double pxm = p[base + xm], pxp = p[base + xp];
-        const double pym = p[o_ym], pyp = p[o_yp];
-        const double pzm = p[o_zm], pzp = p[o_zp];
-        const double adv = (ux * (pxp - pxm) + uy * (pyp - pym) + uz * (pzp - pzm)) * inv2dx;
-        const double lap = (pxp + pxm + pyp + pym + pzp + pzm - 6.0 * c0) * invdx2;
-        fy[(size_t)comp * ld + base + x] = fma(D, lap, -adv);
+    // halo cells of the tile: x halo (2 per tile row), y halo (2 per tile column)
+    const int xm = x0 == 0 ? nx - 1 : x0 - 1;
+    const int ym = y0 == 0 ? ny - 1 : y0 - 1;
+    auto at = [&](int z, int yy_, int x_) { return p[(long long)z * plane + (long long)yy_ * row + x_]; };
+    double pzm = 0.0, c0 = 0.0, pzp = 0.0;
+    if (in) {
+        pzm = at(z0 == 0 ? nz - 1 : z0 - 1, yy, x);
+        c0 = at(z0, yy, x);
+    }
+    for (int z = z0; z < z1; ++z) {
+        const int zp = z == nz - 1 ? 0 : z + 1;
+        if (in) {
+            pzp = at(zp, yy, x);
+            tile[ty + 1][tx + 1] = c0;   // cells outside the grid would overwrite a halo
+        }
+        // x halo: the wrapped neighbours of the tile's first and last column
+        if (tx < 2 && y0 + ty < ny) {
+            const int lastx = min(ADV_TX, nx - x0);     // columns present in this tile
+            const int hx = tx == 0 ? xm : (x0 + lastx == nx ? 0 : x0 + lastx);
+            tile[ty + 1][tx == 0 ? 0 : lastx + 1] = at(z, y0 + ty, hx);
+        }
+        // y halo: the wrapped neighbours of the tile's first and last row
+        if (ty < 2 && x < nx) {
+            const int lasty = min(ADV_TY, ny - y0);
+            const int hy = ty == 0 ? ym : (y0 + lasty == ny ? 0 : y0 + lasty);
+            tile[ty == 0 ? 0 : lasty + 1][tx + 1] = at(z, hy, x);
+        }
+        __syncthreads();
+        if (in) {
+            const double pxm = tile[ty + 1][tx], pxp = tile[ty + 1][tx + 2];
+            const double pym = tile[ty][tx + 1], pyp = tile[ty + 2][tx + 1];
+            const double adv = (ux * (pxp - pxm) + uy * (pyp - pym) + uz * (pzp - pzm)) * inv2dx;
+            const double lap = (pxp + pxm + pyp + pym + pzp + pzm - 6.0 * c0) * invdx2;
+            fy[(size_t)comp * ld + (long long)z * plane + (long long)yy * row + x] =
+                fma(D, lap, -adv);
+        }
+        __syncthreads();
+        pzm = c0;
+        c0 = pzp;
     }
 }
 
@@ -212,10 +253,13 @@ hipError_t launch_forcing(long long n_elem, int n_gamma, int nj, const double *F
 hipError_t launch_advdiff(int nx, int ny, int nz, int n_comp, int ld, const double *u,
                           double D, double dx, const double *y, double *fy, hipStream_t s)
 {
-    if (ny > 65535 || nz > 65535) return hipErrorInvalidValue;
-    const int block = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
-    hipLaunchKernelGGL(k_advdiff, dim3((unsigned)((nx + block - 1) / block), ny, nz), dim3(block), 0,
-                       s, nx, ny, nz, n_comp, ld, u[0], u[1], u[2], D, dx, y, fy);
+    const long long gz = (long long)n_comp * ((nz + ADV_TZ - 1) / ADV_TZ);
+    const long long gy = (ny + ADV_TY - 1) / ADV_TY;
+    if (gz > 65535 || gy > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_advdiff, dim3((unsigned)((nx + ADV_TX - 1) / ADV_TX), (unsigned)gy,
+                                       (unsigned)gz),
+                       dim3(ADV_TX * ADV_TY), 0, s, nx, ny, nz, n_comp, ld, u[0], u[1], u[2], D,
+                       dx, y, fy);
     return hipGetLastError();
 }
 

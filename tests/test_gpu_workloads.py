@@ -239,3 +239,29 @@ def test_batch_fullsize_sampled(torch, mri, O):
     useful, issued = plan.lane_stats()
     print(f"batch {ntot} cells: {len(ok)} sampled cells match, lane utilization "
           f"{useful / issued:.3f}, tile {plan.tile()}")
+
+
+@pytest.mark.parametrize("grid", [(13, 7, 19), (64, 5, 33), (130, 9, 3), (1, 1, 17)])
+def test_advdiff_slow_rhs_odd_grids(torch, mri, O, grid):
+    """The blocked advection-diffusion stencil against the oracle's on grids
+    that leave partial tiles in every direction (and degenerate 1-cell
+    directions), every cell and component."""
+    n = 5
+    N = int(np.prod(grid))
+    ld = I.pad_ld(N)
+    rng = np.random.Generator(np.random.PCG64(17))
+    y0 = np.zeros((n, ld))
+    y0[:, :N] = rng.uniform(-1.0, 1.0, (n, N))
+    F_ora = O.advdiff(y0, grid)
+    yd = torch.as_tensor(y0, device="cuda")
+    Fd = torch.full_like(yd, 7.0)
+    params = mri.advdiff_params(grid, n)
+    rc = mri.lib.mri_advdiff_slow_rhs(0.0, yd.data_ptr(), Fd.data_ptr(), N, ld,
+                                      C.cast(C.pointer(params), C.c_void_p).value,
+                                      torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rc == 0
+    F_gpu = Fd.cpu().numpy()
+    scale = 30.0 / 2e-4 + 12e-5 / 1e-8
+    assert np.all(np.abs(F_gpu[:, :N] - F_ora[:, :N]) <= 1e-13 * scale)
+    assert np.all(F_gpu[:, N:] == 7.0)          # nothing written past the grid
