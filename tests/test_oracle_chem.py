@@ -152,3 +152,32 @@ def test_isothermal_single_reaction_closed_form(oracle_mod):
     C_end = out[:4] * 1e-3 / (W * 1e3)
     np.testing.assert_allclose(C_end, [a - x, a - x, c + x, c + x], rtol=1e-9)
     assert out[4] == T
+
+
+def test_fd_jacobian_of_a_linear_rhs_is_its_matrix(oracle_mod):
+    """Central differences are exact for f = A v (up to rounding): the oracle's
+    Jacobian returns A itself, row i = d f_i / d y_j (A is not symmetric, so a
+    transposed layout fails)."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    A = rng.normal(size=(5, 5))
+    orc = oracle_mod.Oracle(A_fast=A)
+    J = orc.jacobian(rng.uniform(0.5, 2.0, 5))
+    np.testing.assert_allclose(J, A, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("workload", [I.SMALL, I.FIELD64])
+def test_fd_jacobian_matches_directional_derivative(oracle_mod, workload):
+    """J delta equals (f(y + e delta) - f(y - e delta)) / (2 e) for a random
+    direction delta (the chemistry Jacobian's columns and their scaling)."""
+    mech = I.make_mechanism(workload)
+    orc = oracle_mod.Oracle(mech)
+    rng = np.random.Generator(np.random.PCG64(43))
+    y = I.independent_cells(1, mech.n_species, rng, ld=1)[:, 0]
+    n = y.size
+    J = orc.jacobian(y)
+    d = rng.normal(size=n) * np.abs(y) * 1e-2
+    d[-1] = 1.0                                   # a temperature component in K
+    for e in (1e-4, 1e-5):
+        fd = (orc.rhs(y + e * d) - orc.rhs(y - e * d)) / (2 * e)
+        scale = np.abs(J) @ np.abs(d) + 1e-300
+        assert np.all(np.abs(J @ d - fd) <= 1e-4 * scale + 1e-12 * np.abs(fd).max())
