@@ -321,10 +321,19 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     // Machine LICM would hoist every materialized 64-bit coefficient of the
     // straight-line rate code out of the substep loop and exhaust the register
     // file; rematerializing them next to their use is far cheaper.
-    const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=fast",
-                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                          "-mllvm", "-disable-machine-licm"};
-    const hiprtcResult rc = hiprtcCompileProgram(prog, 10, opts);
+    std::vector<std::string> extra;   // tuning knob: extra backend options, "-mllvm X" each
+    if (const char *e = std::getenv("MRI_SPEC_LLVM_OPTS")) {
+        std::istringstream in(e);
+        for (std::string w; in >> w;) {
+            extra.push_back("-mllvm");
+            extra.push_back(w);
+        }
+    }
+    std::vector<const char *> opts = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=fast",
+                                      "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                                      "-mllvm", "-disable-machine-licm"};
+    for (const std::string &w : extra) opts.push_back(w.c_str());
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
     const int key = spec_key(wg, kind, np);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
