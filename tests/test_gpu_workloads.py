@@ -78,6 +78,39 @@ def test_fullsize_fields_first_stage_sampled(torch, mri, O, workload):
     print(f"{workload} full size, 514 sampled cells: max rel err {e:.2e}")
 
 
+@pytest.mark.parametrize("method", ["heun", "bs3", "ck5"])
+def test_fullsize_64cube_other_fast_methods_sampled(torch, mri, O, method):
+    """The first stage of the 64^3 workload with the other fixed-step fast
+    methods of the MRI-P(k) family, on all 262,144 cells with the 50 substeps
+    of the benchmark; sampled cells against the oracle's general explicit RK
+    stage."""
+    om, gm = {"heun": (O.ERK_HEUN, mri.FAST_HEUN), "bs3": (O.ERK_BS3, mri.FAST_BS3),
+              "ck5": (O.ERK_CK5, mri.FAST_CK5)}[method]
+    cfg = I.WORKLOADS[I.FIELD64]
+    mech = I.make_mechanism(I.FIELD64)
+    y0 = I.initial_state(I.FIELD64)
+    n, ld = y0.shape
+    N = cfg.n_cells
+    tb = I.table_mis_kw3()
+    L = (tb.c[1] - tb.c[0]) * cfg.H
+    rho = (tb.gamma[0, 1, 0] / (tb.c[1] - tb.c[0])) * O.advdiff(y0, cfg.grid)[None]
+    m = mri.Mech(mech)
+    yd = torch.as_tensor(y0, device="cuda")
+    out = torch.empty_like(yd)
+    st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    mri.mri_fast_stage(m, mri.fast_opts(method=gm, n_sub=cfg.n_sub), N, ld, yd, out, 1,
+                       torch.as_tensor(rho, device="cuda"), L, st)
+    torch.cuda.synchronize()
+    assert mri.mri_status_count(st, N) == 0
+    cells = _sample(N, 256)
+    ref, st_o, _, _ = O.Oracle(mech).fast_stage_soa(
+        np.ascontiguousarray(y0[:, cells]), np.ascontiguousarray(rho[:, :, cells]), L,
+        O.erk_opts(om, cfg.n_sub))
+    assert np.all(st_o[:cells.size] == 0)
+    e = assert_parity(out.cpu().numpy()[:, cells], ref, mech.n_species, what=method)
+    print(f"{method} 64^3 full size, {cells.size} sampled cells: max rel err {e:.2e}")
+
+
 def test_large_mechanism_fullsize_sampled(torch, mri, O):
     """53 species / 325 reactions on 128^3 cells, RK4 with 100 substeps, first
     stage of the H = 5e-8 step; sampled cells against the oracle."""
