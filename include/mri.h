@@ -285,8 +285,8 @@ int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int 
                         mri_stream_t stream);
 
 /* Diagnostic: y[i] = 2^x[i] (device arrays, n elements) with the polynomial
-   exponential of the specialized kernels that run one wave per SIMD, for
-   accuracy tests. */
+   exponential of the generic kernels and of the specialized kernels that run
+   one wave per SIMD, for accuracy tests. */
 mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t stream);
 /* The same with the table-driven exponential of the specialized kernels that
    run two waves per SIMD (2^(j/256) table plus a degree-4 polynomial;

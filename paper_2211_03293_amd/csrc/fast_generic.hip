@@ -8,8 +8,11 @@
 // input stay in VGPRs with compile-time-bounded loops (NMAX).
 //
 // Rate evaluation: see mri_dev.h (kappa and Z factorization of
-// k_f C_a C_b - k_r C_c C_d, R + S exponentials per RHS).
+// k_f C_a C_b - k_r C_c C_d, R + S exponentials per RHS), in base 2 with the
+// polynomial 2^t of mri_math.h (the host scales the exponent coefficients by
+// log2 e when it copies the mechanism to the device).
 #include "mri_dev.h"
+#include "mri_math.h"
 
 namespace {
 
@@ -43,6 +46,11 @@ __device__ __forceinline__ LdsView stage_mechanism(const GenMech &gm)
     return v;
 }
 
+__device__ __forceinline__ void lds_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // Species rates (left in Wd, already multiplied by W/rho) and the temperature
 // rate for the stage input whose mass fractions the caller stored in the Z
 // columns and whose temperature is T.  Z is overwritten with the factors Z_k.
@@ -51,14 +59,14 @@ __device__ __forceinline__ double gen_rhs(const LdsView &m, int S, int R, double
                                           int lane)
 {
     const double invT = 1.0 / T;
-    const double lnT = log(T);
+    const double l2T = log2(T);
     double den = 0.0;
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
         if (k < S) {
             const double *p = m.sp + k * GEN_SP_STRIDE;
             const double Yk = m.Z[k * 64 + lane];
-            m.Z[k * 64 + lane] = (Yk * p[0]) * exp(fma(p[2], invT, p[3]));
+            m.Z[k * 64 + lane] = (Yk * p[0]) * mri_exp2(fma(p[2], invT, p[3]));
             m.Wd[k * 64 + lane] = 0.0;
             den = fma(Yk, p[5], den);
         }
@@ -68,12 +76,16 @@ __device__ __forceinline__ double gen_rhs(const LdsView &m, int S, int R, double
         const uint32_t id = m.rxi[j];
         const int a = (id & 255u) * 64 + lane, b = ((id >> 8) & 255u) * 64 + lane;
         const int c = ((id >> 16) & 255u) * 64 + lane, d = (id >> 24) * 64 + lane;
-        const double kap = exp(fma(-th, invT, fma(be, lnT, lna)));
+        const double kap = mri_exp2(fma(-th, invT, fma(be, l2T, lna)));
         const double q = kap * fma(-m.Z[c], m.Z[d], m.Z[a] * m.Z[b]);
-        m.Wd[a] -= q;
-        m.Wd[b] -= q;
-        m.Wd[c] += q;
-        m.Wd[d] += q;
+        // LDS atomic adds (no return): the four updates need no read-modify-
+        // write round trip, so consecutive reactions do not wait on each
+        // other; a lane's adds to its own column land in program order, giving
+        // the same sums as plain updates.
+        lds_add(&m.Wd[a], -q);
+        lds_add(&m.Wd[b], -q);
+        lds_add(&m.Wd[c], q);
+        lds_add(&m.Wd[d], q);
     }
     double num = 0.0;
     const double dT = T - T_ref;

@@ -397,11 +397,24 @@ static mri_status ensure_device(mri_mech *m)
         return MRI_OK;
     }
     if (m->d_sp) return MRI_OK;
-    HIP_TRY(hipMalloc(&m->d_sp, sizeof(double) * m->sp.size()));
-    HIP_TRY(hipMalloc(&m->d_rx, sizeof(double) * m->rx.size()));
+    // the generic kernels evaluate their exponentials in base 2: the exponent
+    // coefficients (species a/R and b/R, reaction ln A' and theta') go to the
+    // device multiplied by log2(e); beta multiplies log2(T) there instead of ln(T)
+    const double log2e = 1.4426950408889634074;
+    std::vector<double> sp2 = m->sp, rx2 = m->rx;
+    for (int k = 0; k < m->S; ++k) {
+        sp2[(size_t)k * GEN_SP_STRIDE + 2] *= log2e;
+        sp2[(size_t)k * GEN_SP_STRIDE + 3] *= log2e;
+    }
+    for (int j = 0; j < m->R; ++j) {
+        rx2[3 * (size_t)j] *= log2e;
+        rx2[3 * (size_t)j + 2] *= log2e;
+    }
+    HIP_TRY(hipMalloc(&m->d_sp, sizeof(double) * sp2.size()));
+    HIP_TRY(hipMalloc(&m->d_rx, sizeof(double) * rx2.size()));
     HIP_TRY(hipMalloc(&m->d_rxi, sizeof(uint32_t) * m->rxi.size()));
-    HIP_TRY(hipMemcpy(m->d_sp, m->sp.data(), sizeof(double) * m->sp.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(m->d_rx, m->rx.data(), sizeof(double) * m->rx.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_sp, sp2.data(), sizeof(double) * sp2.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_rx, rx2.data(), sizeof(double) * rx2.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(m->d_rxi, m->rxi.data(), sizeof(uint32_t) * m->rxi.size(),
                       hipMemcpyHostToDevice));
     m->gm = GenMech{m->S, m->R, m->d_sp, m->d_rx, m->d_rxi, m->T_ref};

@@ -15,7 +15,9 @@
 // Reaction block rx[j*3 + i]: 0 ln A' = ln A - BR_a - BR_b, 1 beta,
 //   2 theta' = theta + AR_a + AR_b, so that
 //   kappa_j = exp(ln A' + beta ln T - theta'/T) = k_f exp(-(g_a + g_b)/(R T)).
-// rxi[j] = a | b << 8 | c << 16 | d << 24.
+// rxi[j] = a | b << 8 | c << 16 | d << 24.  The device copy the generic
+// kernels read holds AR, BR, ln A' and theta' multiplied by log2(e) (base-2
+// exponentials; beta then multiplies log2 T).
 struct GenMech {
     int S, R;
     const double *sp;

@@ -341,10 +341,10 @@ def test_determinism_and_fault_isolation(torch, mri, O, kernel):
 
 @pytest.mark.parametrize("variant", ["polynomial", "table"])
 def test_device_exp2_accuracy(torch, mri, variant):
-    """The specialized kernels' two 2^t against numpy's exp2 over the exponent
-    range the kernels use: the degree-11 polynomial on [-1/2, 1/2] (kernels at
-    one wave per SIMD) and the 2^(j/256) table with a degree-4 polynomial
-    (kernels at two waves per SIMD)."""
+    """The kernels' two 2^t against numpy's exp2 over the exponent range the
+    kernels use: the degree-11 polynomial on [-1/2, 1/2] (generic kernels and
+    specialized kernels at one wave per SIMD) and the 2^(j/256) table with a
+    degree-4 polynomial (specialized kernels at two waves per SIMD)."""
     fn = mri.mri_selftest_exp2 if variant == "polynomial" else mri.mri_selftest_exp2_t256
     rng = np.random.Generator(np.random.PCG64(8))
     x = np.concatenate([rng.uniform(-1000, 1000, 200000), rng.uniform(-1, 1, 100000),
