@@ -347,9 +347,11 @@ def test_device_exp2_accuracy(torch, mri, variant):
     degree-4 polynomial (specialized kernels at two waves per SIMD)."""
     fn = mri.mri_selftest_exp2 if variant == "polynomial" else mri.mri_selftest_exp2_t256
     rng = np.random.Generator(np.random.PCG64(8))
+    # grid of step 1/16384 on [-4, 4]: every table entry and every rounding
+    # tie of the table index (x an odd multiple of 1/512) in both signs
     x = np.concatenate([rng.uniform(-1000, 1000, 200000), rng.uniform(-1, 1, 100000),
-                        np.arange(-60, 61, 0.5), [0.0, -0.0, 1e-300, 0.49999999999999994,
-                                                  -0.5, 0.5, 1021.9]])
+                        np.arange(-60, 61, 0.5), np.arange(-65536, 65537) / 16384.0,
+                        [0.0, -0.0, 1e-300, 0.49999999999999994, -0.5, 0.5, 1021.9]])
     xd = torch.as_tensor(x, device="cuda")
     yd = torch.empty_like(xd)
     fn(xd, yd)
@@ -360,12 +362,15 @@ def test_device_exp2_accuracy(torch, mri, variant):
     err = np.abs(y - ref) / ulp
     print(f"exp2 {variant}: max {err.max():.2f} ulp, mean {err.mean():.3f}")
     assert err.max() <= 2.0, (err.max(), x[np.argmax(err)])
-    nan = fn
-    xn = torch.tensor([np.nan], dtype=torch.float64, device="cuda")
-    yn = torch.empty_like(xn)
-    nan(xn, yn)
+    # NaN propagates; results beyond the double range saturate
+    xs = torch.tensor([np.nan, 1100.0, 5000.0, -1100.0, -5000.0], dtype=torch.float64,
+                      device="cuda")
+    ys = torch.empty_like(xs)
+    fn(xs, ys)
     torch.cuda.synchronize()
-    assert np.isnan(yn.item())
+    ys = ys.cpu().numpy()
+    assert np.isnan(ys[0])
+    assert np.all(ys[1:3] == np.inf) and np.all(ys[3:] == 0.0), ys
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
