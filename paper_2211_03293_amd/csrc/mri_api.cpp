@@ -360,7 +360,11 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     SpecKernel sk;
     sk.code_bytes = m->last_code.size();
     HIP_TRY(hipModuleLoadData(&sk.mod, m->last_code.data()));
-    HIP_TRY(hipModuleGetFunction(&sk.fn, sk.mod, "mri_spec_main"));
+    const hipError_t ge = hipModuleGetFunction(&sk.fn, sk.mod, "mri_spec_main");
+    if (ge != hipSuccess) {
+        (void)hipModuleUnload(sk.mod);
+        return fail(MRI_EHIP, "hipModuleGetFunction failed: %s", hipGetErrorString(ge));
+    }
     *out = sk;
     return MRI_OK;
 }
@@ -560,6 +564,16 @@ struct mri_batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> graph_key;
+    // releases whatever a partial creation or a run allocated
+    ~mri_batch_plan()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (d_off) (void)hipFree(d_off);
+        if (d_L) (void)hipFree(d_L);
+        if (d_counters) (void)hipFree(d_counters);
+    }
 };
 
 mri_status mri_internal_fast_stage(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
@@ -1231,17 +1245,7 @@ mri_status mri_batch_plan_create(const mri_mech *mc, const mri_fast_opts *opts, 
     return MRI_OK;
 }
 
-void mri_batch_plan_destroy(mri_batch_plan *p)
-{
-    if (!p) return;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    if (p->d_off) (void)hipFree(p->d_off);
-    if (p->d_L) (void)hipFree(p->d_L);
-    if (p->d_counters) (void)hipFree(p->d_counters);
-    delete p;
-}
+void mri_batch_plan_destroy(mri_batch_plan *p) { delete p; }
 
 mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_blocks)
 {
@@ -1315,9 +1319,17 @@ static mri_status batch_tune(mri_batch_plan *p, const double *yin, double *yout,
     int k = 1;
     while (k < p->n_sets && p->off[k] < target) ++k;
     const long long n_sample = p->off[k];
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    struct Events {   // destroyed on every return path
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events()
+        {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    HIP_TRY(hipEventCreate(&ev.e0));
+    HIP_TRY(hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     float best = 1e30f;
     p->tune_log.clear();
     for (int wg : {64, 128, 256}) {
@@ -1345,8 +1357,6 @@ static mri_status batch_tune(mri_batch_plan *p, const double *yin, double *yout,
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     p->tuned = true;
     return MRI_OK;
 }
