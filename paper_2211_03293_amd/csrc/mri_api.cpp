@@ -128,6 +128,15 @@ struct mri_mech {
     std::map<int, SpecKernel> spec;    // by spec_key
     std::map<int, std::string> spec_fail;
     std::vector<char> last_code;       // code object of the last compilation
+    ~mri_mech()
+    {
+        for (auto &kv : spec)
+            if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
+        if (d_sp) (void)hipFree(d_sp);
+        if (d_rx) (void)hipFree(d_rx);
+        if (d_rxi) (void)hipFree(d_rxi);
+        if (d_A) (void)hipFree(d_A);
+    }
 };
 
 struct mri_table {
@@ -718,17 +727,7 @@ mri_status mri_mech_create_linear(int n, const double *A, mri_mech **out)
     return MRI_OK;
 }
 
-void mri_mech_destroy(mri_mech *m)
-{
-    if (!m) return;
-    for (auto &kv : m->spec)
-        if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
-    if (m->d_sp) (void)hipFree(m->d_sp);
-    if (m->d_rx) (void)hipFree(m->d_rx);
-    if (m->d_rxi) (void)hipFree(m->d_rxi);
-    if (m->d_A) (void)hipFree(m->d_A);
-    delete m;
-}
+void mri_mech_destroy(mri_mech *m) { delete m; }
 
 int mri_mech_state_width(const mri_mech *m) { return m ? m->n : -1; }
 

@@ -44,12 +44,31 @@ struct mri_mlp {
     size_t part_elems = 0;
     int step = 0;
     int last_batch = 0;
+    // releases whatever a partial creation allocated
+    ~mri_mlp()
+    {
+        for (void *q : {(void *)p, (void *)g, (void *)m1, (void *)m2, (void *)pq, (void *)dZ,
+                        (void *)dA, (void *)dZq, (void *)part})
+            if (q) (void)hipFree(q);
+        for (auto *z : Z)
+            if (z) (void)hipFree(z);
+        for (auto *a : A)
+            if (a) (void)hipFree(a);
+    }
 };
 
 struct mri_surrogate {
     uint16_t *W[4] = {};
     float *b[4] = {};
     double *stats = nullptr;
+    ~mri_surrogate()
+    {
+        for (int l = 0; l < 4; ++l) {
+            if (W[l]) (void)hipFree(W[l]);
+            if (b[l]) (void)hipFree(b[l]);
+        }
+        if (stats) (void)hipFree(stats);
+    }
 };
 
 extern "C" {
@@ -110,18 +129,7 @@ mri_status mri_mlp_create(int n_layers, const int *widths, const float *params, 
     return MRI_OK;
 }
 
-void mri_mlp_destroy(mri_mlp *m)
-{
-    if (!m) return;
-    for (void *p : {(void *)m->p, (void *)m->g, (void *)m->m1, (void *)m->m2, (void *)m->pq,
-                    (void *)m->dZ, (void *)m->dA, (void *)m->dZq, (void *)m->part})
-        if (p) (void)hipFree(p);
-    for (auto *z : m->Z)
-        if (z) (void)hipFree(z);
-    for (auto *a : m->A)
-        if (a) (void)hipFree(a);
-    delete m;
-}
+void mri_mlp_destroy(mri_mlp *m) { delete m; }
 
 int64_t mri_mlp_param_count(const mri_mlp *m) { return m ? m->n_params : -1; }
 
@@ -296,16 +304,7 @@ mri_status mri_surrogate_create(const int *widths, const float *params, const do
     return MRI_OK;
 }
 
-void mri_surrogate_destroy(mri_surrogate *s)
-{
-    if (!s) return;
-    for (int l = 0; l < 4; ++l) {
-        if (s->W[l]) (void)hipFree(s->W[l]);
-        if (s->b[l]) (void)hipFree(s->b[l]);
-    }
-    if (s->stats) (void)hipFree(s->stats);
-    delete s;
-}
+void mri_surrogate_destroy(mri_surrogate *s) { delete s; }
 
 mri_status mri_surrogate_infer(const mri_surrogate *s, int n_cells, int ld, const double *y_in,
                                double *y_out, int n_poly, const double *rho, double L, int half,
