@@ -157,12 +157,18 @@ def last_error() -> str:
     return lib.mri_last_error().decode()
 
 
-def _ptr(t):
-    """Device (or host) address of a tensor / array, None for None."""
+def _ptr(t, dtype=None):
+    """Device address of a tensor, None for None.  Every array these entry
+    points take through here is device memory: a host array or a tensor of
+    another element type would be read or written out of bounds by a kernel,
+    so both are refused here (ValueError / TypeError)."""
     if t is None:
         return None
-    if isinstance(t, np.ndarray):
-        return t.ctypes.data
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"expected a device tensor, got {type(t).__name__}"
+                         + (f" on {t.device}" if hasattr(t, "device") else ""))
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise TypeError(f"expected a {dtype} tensor, got {t.dtype}")
     return t.data_ptr()
 
 
@@ -247,8 +253,9 @@ def fast_opts(method=FAST_RK4, n_sub=1, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max
 
 def mri_fast_stage(mech: Mech, opts, n_cells, ld, y_in, y_out, n_poly, rho_poly, L,
                    status_out=None, steps_out=None, stream=None):
-    _check(lib.mri_fast_stage(mech.h, C.byref(opts), n_cells, ld, _ptr(y_in), _ptr(y_out), n_poly,
-                              _ptr(rho_poly), float(L), _ptr(status_out), _ptr(steps_out),
+    _check(lib.mri_fast_stage(mech.h, C.byref(opts), n_cells, ld, _ptr(y_in, "float64"),
+                              _ptr(y_out, "float64"), n_poly, _ptr(rho_poly, "float64"), float(L),
+                              _ptr(status_out, "int32"), _ptr(steps_out, "int32"),
                               _stream(stream)))
 
 
@@ -278,8 +285,9 @@ def mri_slow_step(mech: Mech, table: Table, opts, f_slow, user, t0, H, n_cells, 
         user_p = user
     nbytes = ws.numel() * ws.element_size()
     _check(lib.mri_slow_step(mech.h, table.h, C.byref(opts), f_slow, user_p, float(t0), float(H),
-                             n_cells, ld, _ptr(y), _ptr(ws), nbytes, _ptr(status_out),
-                             _ptr(steps_out), _stream(stream)))
+                             n_cells, ld, _ptr(y, "float64"), _ptr(ws), nbytes,
+                             _ptr(status_out, "int32"), _ptr(steps_out, "int32"),
+                             _stream(stream)))
 
 
 def adapt_opts(rtol, atol_Y, atol_T, H0, order, H_min=0.0, H_max=0.0, max_attempts=10000,
@@ -307,8 +315,8 @@ def mri_adaptive_run(mech: Mech, table: Table, opts, aopts, f_slow, user, t0, t_
     st = mri_adapt_stats()
     nbytes = ws.numel() * ws.element_size()
     _check(lib.mri_adaptive_run(mech.h, table.h, C.byref(opts), C.byref(aopts), f_slow, user_p,
-                                float(t0), float(t_end), n_cells, ld, _ptr(y), _ptr(ws), nbytes,
-                                _ptr(status_out), C.byref(st), _stream(stream)))
+                                float(t0), float(t_end), n_cells, ld, _ptr(y, "float64"), _ptr(ws),
+                                nbytes, _ptr(status_out, "int32"), C.byref(st), _stream(stream)))
     return {f: getattr(st, f) for f, _ in mri_adapt_stats._fields_}
 
 

@@ -232,3 +232,29 @@ def test_code_hash_identifies_the_compiled_kernel(mri):
     assert h1 != m.code_hash(mri.FAST_RK4, 2, 128)
     assert h1 != m.code_hash(mri.FAST_HEUN, 1, 128)
     assert h1 != mri.Mech(I.make_mechanism(I.FIELD64)).code_hash(mri.FAST_RK4, 1, 128)
+
+
+def test_binding_refuses_host_and_mistyped_arrays(mri):
+    """The binding passes device addresses only: a host tensor or array, or a
+    device tensor of another element type, is refused before the library is
+    called (a kernel would read it out of bounds)."""
+    import torch
+
+    m = mri.Mech(I.make_mechanism(I.SMALL))
+    opts = mri.fast_opts(n_sub=1)
+    y = torch.zeros((10, 8), dtype=torch.float64)
+    with pytest.raises(ValueError, match="device tensor"):
+        mri.mri_fast_stage(m, opts, 8, 8, y, y, 0, None, 1e-9)
+    with pytest.raises(ValueError, match="device tensor"):
+        mri.mri_fast_stage(m, opts, 8, 8, y.numpy(), y.numpy(), 0, None, 1e-9)
+
+    class DeviceF32:                     # stands in for a float32 device tensor
+        is_cuda = True
+        dtype = torch.float32
+
+        def data_ptr(self):
+            return 0
+
+    with pytest.raises(TypeError, match="float64"):
+        mri._ptr(DeviceF32(), "float64")
+    assert mri._ptr(None, "float64") is None
