@@ -36,37 +36,50 @@ def O():
     return O
 
 
-def test_adaptive_linear_two_rate_matches_oracle(torch, mri, O):
+# (slow table, its order, fast method): the 3rd- and 4th-order tables with
+# fixed-step fast methods of orders 3 to 5
+LINEAR_CASES = [("kw3", 3, "rk4"), ("kw3", 3, "bs3"), ("erk45a", 4, "rk4"), ("erk45a", 4, "ck5")]
+
+
+@pytest.mark.parametrize("table,order,method", LINEAR_CASES)
+def test_adaptive_linear_two_rate_matches_oracle(torch, mri, O, table, order, method):
     A_F = np.array([[-6.0, 5.0], [-5.0, -4.0]])
     A_S = np.array([[0.3, 1.0], [-1.2, 0.2]])
-    tb = I.table_mis_kw3()
+    tb = I.table_mis_kw3() if table == "kw3" else I.table_erk45a()
     orc = O.Oracle(A_fast=A_F)
     H0, n_sub, T = 0.7, 64, 0.7
+    ora_opts = {"rk4": O.rk4_opts, "bs3": lambda k: O.erk_opts(O.ERK_BS3, k),
+                "ck5": lambda k: O.erk_opts(O.ERK_CK5, k)}[method]
+    dev_method = {"rk4": mri.FAST_RK4, "bs3": mri.FAST_BS3, "ck5": mri.FAST_CK5}[method]
 
     def step(y, t, H):
-        out, st, _, _ = orc.mri_step_linear(tb, O.rk4_opts(O.fixed_substeps(n_sub, H, H0)), A_S,
+        out, st, _, _ = orc.mri_step_linear(tb, ora_opts(O.fixed_substeps(n_sub, H, H0)), A_S,
                                             y[:, 0], H, t=t)
         return out, st
 
     y0 = np.array([[1.0], [0.5]])
-    ref, st_o, hist = O.adaptive_run(step, y0, 0.0, T, 3, 1e-8, 1e-8, 1e-8, H0)
+    ref, st_o, hist = O.adaptive_run(step, y0, 0.0, T, order, 1e-8, 1e-8, 1e-8, H0)
+    errs = np.array([e for _, _, e, _ in hist])
+    assert np.all(np.abs(errs - 1.0) > 0.2), errs       # no decision near a tie
     mF, mS, t = mri.Mech(A_linear=A_F), mri.Mech(A_linear=A_S), mri.Table(tb)
     yd = torch.as_tensor(np.repeat(y0, 64, axis=1), device="cuda")
     ws = torch.empty(mri.mri_adaptive_workspace_bytes(mF, t, 64, 64) // 8 + 1,
                      dtype=torch.float64, device="cuda")
-    st = mri.mri_adaptive_run(mF, t, mri.fast_opts(n_sub=n_sub),
-                              mri.adapt_opts(1e-8, 1e-8, 1e-8, H0, 3), mri.LINEAR_RHS, mS, 0.0, T,
-                              64, 64, yd, ws)
+    st = mri.mri_adaptive_run(mF, t, mri.fast_opts(method=dev_method, n_sub=n_sub),
+                              mri.adapt_opts(1e-8, 1e-8, 1e-8, H0, order), mri.LINEAR_RHS, mS,
+                              0.0, T, 64, 64, yd, ws)
     got = yd.cpu().numpy()
-    print(f"linear: {st}")
+    print(f"linear {table} {method}: {st}")
     assert (st["accepted"], st["rejected"]) == (st_o["accepted"], st_o["rejected"])
     assert st["rejected"] >= 1 and st["t"] == T
     assert st["H_last"] == pytest.approx(st_o["H_last"], rel=1e-5)
     np.testing.assert_allclose(got[:, 0], ref[:, 0], rtol=1e-10)
     assert np.all(got == got[:, :1])
     assert np.abs(got[:, 0] - expm((A_F + A_S) * T) @ y0[:, 0]).max() < 1e-6
-    # fixed-step fast work: the two half steps of every accepted attempt
-    exp_fast = sum(2 * 3 * O.fixed_substeps(n_sub, H / 2, H0) for _, H, _, a in hist if a)
+    # fixed-step fast work: the fast stages of the two half steps of every
+    # accepted attempt
+    n_fast = int(np.count_nonzero(np.diff(np.asarray(tb.c)) > 0))
+    exp_fast = sum(2 * n_fast * O.fixed_substeps(n_sub, H / 2, H0) for _, H, _, a in hist if a)
     assert st["fast_steps"] == 64 * exp_fast
 
 
