@@ -29,6 +29,8 @@
  *     comp 0..S-1 the mass fractions Y_k and comp S the temperature T [K];
  *     ld >= n_cells is the leading dimension.  Forcing coefficients are
  *     rho_poly[k * n * ld + comp * ld + cell], k = 0..n_poly-1, n = S + 1.
+ *     Size limits (MRI_EINVAL beyond them): n * ld <= 2^31 - 1 elements per
+ *     array and ld <= 2^31 - 1024 cells.
  *   - All compute calls are asynchronous on the given stream (a hipStream_t
  *     passed as void*; NULL = the legacy default stream).  Per-cell errors
  *     detected on the device are written to the optional status array as the

@@ -235,7 +235,7 @@ hipError_t launch_status_merge(int n_cells, const int32_t *st_a, const int32_t *
                                int32_t *status_out, hipStream_t s)
 {
     const int block = 256;
-    hipLaunchKernelGGL(k_status_merge, dim3((n_cells + block - 1) / block), dim3(block), 0, s,
+    hipLaunchKernelGGL(k_status_merge, dim3((unsigned)(((long long)n_cells + block - 1) / block)), dim3(block), 0, s,
                        n_cells, st_a, st_b, status_out);
     return hipGetLastError();
 }
@@ -267,7 +267,7 @@ hipError_t launch_lin_apply(int n, const double *A, int n_cells, int ld, const d
                             double *fy, hipStream_t s)
 {
     const int block = 256;
-    hipLaunchKernelGGL(k_lin_apply, dim3((n_cells + block - 1) / block), dim3(block), 0, s, n, A,
+    hipLaunchKernelGGL(k_lin_apply, dim3((unsigned)(((long long)n_cells + block - 1) / block)), dim3(block), 0, s, n, A,
                        n_cells, ld, y, fy);
     return hipGetLastError();
 }
@@ -276,7 +276,7 @@ hipError_t launch_status_count(const int32_t *status, int n_cells, int32_t mask,
                                unsigned long long *count, hipStream_t s)
 {
     const int block = 256;
-    hipLaunchKernelGGL(k_status_count, dim3((n_cells + block - 1) / block), dim3(block), 0, s,
+    hipLaunchKernelGGL(k_status_count, dim3((unsigned)(((long long)n_cells + block - 1) / block)), dim3(block), 0, s,
                        status, n_cells, mask, count);
     return hipGetLastError();
 }
@@ -284,20 +284,20 @@ hipError_t launch_status_count(const int32_t *status, int n_cells, int32_t mask,
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s)
 {
     const int block = 64;
-    hipLaunchKernelGGL(k_fill_u64, dim3((n + block - 1) / block), dim3(block), 0, s, p, n, v);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)(((long long)n + block - 1) / block)), dim3(block), 0, s, p, n, v);
     return hipGetLastError();
 }
 
 hipError_t launch_exp2_t256(const double *x, double *y, int n, hipStream_t s)
 {
     const int block = 256;
-    hipLaunchKernelGGL(k_exp2_t256, dim3((n + block - 1) / block), dim3(block), 0, s, x, y, n);
+    hipLaunchKernelGGL(k_exp2_t256, dim3((unsigned)(((long long)n + block - 1) / block)), dim3(block), 0, s, x, y, n);
     return hipGetLastError();
 }
 
 hipError_t launch_exp2(const double *x, double *y, int n, hipStream_t s)
 {
     const int block = 256;
-    hipLaunchKernelGGL(k_exp2, dim3((n + block - 1) / block), dim3(block), 0, s, x, y, n);
+    hipLaunchKernelGGL(k_exp2, dim3((unsigned)(((long long)n + block - 1) / block)), dim3(block), 0, s, x, y, n);
     return hipGetLastError();
 }

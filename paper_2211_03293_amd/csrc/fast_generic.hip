@@ -563,7 +563,7 @@ hipError_t launch_gen_rk4(const GenMech &gm, const ErkCoef &e, int block, int n_
                           double L, int n_sub, int *status, int *steps, int accumulate,
                           hipStream_t s)
 {
-    const dim3 grid((n_cells + block - 1) / block);
+    const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
     if (gm.S <= GEN_NMAX_SMALL) {
         GEN_DISPATCH_NP(k_gen_rk4, GEN_NMAX_SMALL, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
@@ -579,7 +579,7 @@ hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, cons
                          double *yout, int n_poly, const double *rho, double L, ZvOpts o,
                          int *status, int *steps, int accumulate, hipStream_t s)
 {
-    const dim3 grid((n_cells + block - 1) / block);
+    const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
     if (gm.S <= GEN_NMAX_SMALL) {
         GEN_DISPATCH_NP(k_gen_zv, GEN_NMAX_SMALL, gm, n_cells, ld, yin, yout, rho, L, o, status,
@@ -596,7 +596,7 @@ hipError_t launch_gen_erk(const GenMech &gm, const ErkFull &e, int block, int n_
                           double L, int n_sub, int *status, int *steps, int accumulate,
                           hipStream_t s)
 {
-    const dim3 grid((n_cells + block - 1) / block);
+    const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     if (gm.S > GEN_NMAX_SMALL || e.s < 1 || e.s > ERK_SMAX) return hipErrorInvalidValue;
     const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
     GEN_DISPATCH_NP(k_gen_erk, GEN_NMAX_SMALL, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
@@ -611,7 +611,7 @@ hipError_t launch_lin_erk(int n, const double *A, const ErkFull &e, int n_cells,
 {
     if (n > 16 || e.s < 1 || e.s > ERK_SMAX) return hipErrorInvalidValue;
     const int block = 256;
-    const dim3 grid((n_cells + block - 1) / block);
+    const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     switch (n_poly) {
     case 0:
         hipLaunchKernelGGL(k_lin_erk<0>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,
@@ -643,7 +643,7 @@ hipError_t launch_lin_rk4(int n, const double *A, const ErkCoef &e, int n_cells,
                           hipStream_t s)
 {
     const int block = 256;
-    const dim3 grid((n_cells + block - 1) / block);
+    const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     switch (n_poly) {
     case 0:
         hipLaunchKernelGGL(k_lin_rk4<0>, grid, dim3(block), 0, s, n, A, e, n_cells, ld, yin, yout,

@@ -33,6 +33,9 @@ extern const char mri_spec_abi_src[];
 extern const char mri_math_src[];
 
 thread_local std::string g_err;
+// Cell counts and leading dimensions stay below 2^31 - 1024 so that a kernel's
+// block index times block size (at most 1024) never leaves the int range.
+constexpr long long kMaxCells = (1ll << 31) - 1024;
 
 mri_status mri_fail(mri_status st, const char *fmt, ...)
 {
@@ -893,6 +896,7 @@ mri_status mri_fast_stage(const mri_mech *mc, const mri_fast_opts *opts, int n_c
     mri_status st = check_opts(m, opts);
     if (st != MRI_OK) return st;
     if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     if ((long long)ld * m->n > (1ll << 31) - 1)
         return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
     if (n_poly < 0 || n_poly > 4) return fail(MRI_EINVAL, "n_poly must be in [0, 4]");
@@ -909,6 +913,7 @@ mri_status mri_workspace_bytes(const mri_mech *m, const mri_table *t, int n_cell
 {
     if (!m || !t || !bytes) return fail(MRI_EINVAL, "NULL argument");
     if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     *bytes = sizeof(double) * (size_t)m->n * (size_t)ld * (size_t)(t->s - 1 + t->ng);
     return MRI_OK;
 }
@@ -924,6 +929,7 @@ mri_status mri_slow_step(const mri_mech *mc, const mri_table *t, const mri_fast_
     if (st != MRI_OK) return st;
     if (!f_slow) return fail(MRI_EINVAL, "slow RHS callback is NULL");
     if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     if ((long long)ld * m->n > (1ll << 31) - 1)
         return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
     if (!(H > 0.0) || !std::isfinite(H) || !std::isfinite(t0))
@@ -1014,6 +1020,7 @@ mri_status mri_adaptive_run(const mri_mech *mc, const mri_table *t, const mri_fa
     if (!std::isfinite(t0) || !std::isfinite(t_end) || !(t_end > t0))
         return fail(MRI_EINVAL, "need finite t0 < t_end");
     if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     if ((long long)ld * m->n > (1ll << 31) - 1)
         return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
     size_t need = 0, base = 0;
@@ -1191,7 +1198,8 @@ mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, in
                             mri_stream_t stream)
 {
     if (!n_bad) return fail(MRI_EINVAL, "n_bad is NULL");
-    if (n_cells < 0) return fail(MRI_EINVAL, "n_cells < 0");
+    if (n_cells < 0 || n_cells > kMaxCells)
+        return fail(MRI_EINVAL, "need 0 <= n_cells <= 2^31 - 1024");
     *n_bad = 0;
     if (n_cells == 0) return MRI_OK;
     if (!status) return fail(MRI_EINVAL, "status is NULL");
@@ -1367,6 +1375,7 @@ extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, doubl
 {
     if (!p) return fail(MRI_EINVAL, "plan is NULL");
     if (ld < p->n_total) return fail(MRI_EINVAL, "ld < total cells");
+    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     if (ld * (int64_t)p->mech->n > (1ll << 31) - 1)
         return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
     if (n_poly < 0 || n_poly > 4 || (n_poly > 0 && !rho_poly))

@@ -312,6 +312,7 @@ mri_status mri_surrogate_infer(const mri_surrogate *s, int n_cells, int ld, cons
 {
     if (!s) return fail(MRI_EINVAL, "surrogate is NULL");
     if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > (1ll << 31) - 1024) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     if (n_poly < 0 || n_poly > 3 || (n_poly > 0 && !rho)) return fail(MRI_EINVAL, "bad n_poly");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(MRI_EINVAL, "L must be positive");
     if (half < 0 || half > 2) return fail(MRI_EINVAL, "half must be 0, 1 or 2");
@@ -343,6 +344,7 @@ mri_status mri_surrogate_stage(const mri_surrogate *s, const mri_mech *mech,
         return fail(MRI_EUNSUPPORTED, "the surrogate is built for 21-species mechanisms");
     if (!(gate_tol >= 0.0)) return fail(MRI_EINVAL, "gate_tol must be >= 0");
     if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > (1ll << 31) - 1024) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     if (n_poly < 0 || n_poly > 3 || (n_poly > 0 && !rho)) return fail(MRI_EINVAL, "bad n_poly");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(MRI_EINVAL, "L must be positive");
     size_t need = 0;

@@ -147,6 +147,27 @@ def test_linear_mode_validation(mri):
     assert rc == mri.MRI_EUNSUPPORTED
 
 
+def test_size_limits(mri):
+    """A one-component state may use ld up to 2^31 - 1024 cells (n * ld <=
+    2^31 - 1 elements is not the binding limit there): beyond it the block
+    index arithmetic of the kernels would leave the int range, so the call is
+    refused before any device work; so is a status count of that size."""
+    L = mri.lib
+    m = mri.Mech(A_linear=np.eye(1))
+    rk4 = mri.fast_opts(n_sub=1)
+    big = (1 << 31) - 1000
+    assert L.mri_fast_stage(m.h, C.byref(rk4), big, big, 1, 1, 0, None, 1.0, None, None,
+                            None) == mri.MRI_EINVAL
+    assert "2^31 - 1024" in mri.last_error()
+    n = C.c_int64(0)
+    assert L.mri_status_count(1, big, 0xFF, C.byref(n), None) == mri.MRI_EINVAL
+    chem = mri.Mech(I.make_mechanism(I.SMALL))         # n = 10: n * ld is the limit
+    ld = (1 << 31) // 10 + 1
+    assert L.mri_fast_stage(chem.h, C.byref(rk4), ld, ld, 1, 1, 0, None, 1.0, None, None,
+                            None) == mri.MRI_EINVAL
+    assert "n * ld" in mri.last_error()
+
+
 @pytest.mark.parametrize("workload", [I.SMALL, I.FIELD64])
 def test_specialized_kernels_compile_for_gfx950(mri, workload):
     m = mri.Mech(I.make_mechanism(workload))
