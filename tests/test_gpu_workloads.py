@@ -300,15 +300,17 @@ def test_advdiff_slow_rhs_odd_grids(torch, mri, O, grid):
     assert np.all(F_gpu[:, N:] == 7.0)          # nothing written past the grid
 
 
-def test_maximum_size_stage_sampled(torch, mri, O):
+@pytest.mark.parametrize("kernel,method", [("specialized", "rk4"), ("generic", "rk4"),
+                                           ("specialized", "zonneveld")])
+def test_maximum_size_stage_sampled(torch, mri, O, kernel, method):
     """The largest state the boundary takes for the 9-species mechanism:
     n * ld = 10 x 209,715,200 elements (16.8 GB per array, 98% of the
     2^31 - 1 limit), a ragged n_cells = ld - 37, two forcing terms (their
-    array spans 4.2e9 elements, indexed past 2^31 and 2^32 bytes), the
-    specialized RK4 kernel.  The state repeats 1,024 seeded cells; sampled
-    cells across the whole range, the last ones included, match the oracle
-    at 1e-10, every processed cell reports status 0, and the cells past
-    n_cells are left untouched."""
+    array spans 4.2e9 elements, indexed past 2^31), RK4 on both kernels and
+    the adaptive Zonneveld pair.  The state repeats 1,024 seeded cells;
+    sampled cells across the whole range, the last ones included, match the
+    oracle at 1e-10, every processed cell reports status 0, and the cells
+    past n_cells are left untouched."""
     free, _ = torch.cuda.mem_get_info()
     if free < 80 * 2**30:
         pytest.skip(f"needs 80 GiB of free device memory ({free / 2**30:.0f} GiB)")
@@ -322,24 +324,36 @@ def test_maximum_size_stage_sampled(torch, mri, O):
     xi = rng.standard_normal((2, n, 1024))
     rho_small = 1e-3 * np.abs(fF)[None] * xi
     L, n_sub = (5.0 / 12.0) * 1e-6, 20
-    ref, st_o, _, _ = orc.fast_stage_soa(y_small, rho_small, L, O.rk4_opts(n_sub))
-    assert np.all(st_o == 0)
+    if method == "rk4":
+        ora_opts, opts = O.rk4_opts(n_sub), mri.fast_opts(n_sub=n_sub)
+    else:
+        ora_opts = O.zonneveld_opts(rtol=1e-6, atol_Y=1e-10, atol_T=1e-6, max_steps=2000)
+        opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-6, atol_Y=1e-10, atol_T=1e-6,
+                             max_steps=2000)
+    opts.kernel = mri.KERNEL_SPECIALIZED if kernel == "specialized" else mri.KERNEL_GENERIC
+    ref, st_o, _, _ = orc.fast_stage_soa(y_small, rho_small, L, ora_opts)
+    tie = mri.CELL_NEARTIE           # adaptive accept decisions within rounding of the bound
+    assert np.all((st_o & ~tie) == 0)
     ld = 1024 * 204800
     assert n * ld <= 2**31 - 1 and n * ld > 0.97 * 2**31
     N = ld - 37
-    print(f"max size: n {n}, ld {ld}, n_cells {N}", flush=True)
+    print(f"max size {kernel} {method}: n {n}, ld {ld}, n_cells {N}", flush=True)
     yd = torch.as_tensor(y_small, device="cuda").repeat(1, ld // 1024)
     rhod = torch.as_tensor(rho_small, device="cuda").repeat(1, 1, ld // 1024)
     out = torch.full((n, ld), -1.0, dtype=torch.float64, device="cuda")
     st = torch.full((ld,), 7, dtype=torch.int32, device="cuda")
     m = mri.Mech(mech)
-    mri.mri_fast_stage(m, mri.fast_opts(n_sub=n_sub, kernel=mri.KERNEL_SPECIALIZED), N, ld, yd,
-                       out, 2, rhod, L, st)
+    mri.mri_fast_stage(m, opts, N, ld, yd, out, 2, rhod, L, st)
     torch.cuda.synchronize()
-    assert mri.mri_status_count(st, N) == 0
+    assert mri.mri_status_count(st, N, mask=0xFF & ~tie) == 0
     assert bool((st[N:] == 7).all()) and bool((out[:, N:] == -1.0).all())
     cells = np.unique(np.concatenate([_sample(N, 4096, seed=9),
                                       np.arange(N - 64, N), np.arange(0, 64)]))
-    got = out[:, torch.as_tensor(cells, device="cuda")].cpu().numpy()
-    e = assert_parity(got, np.ascontiguousarray(ref[:, cells % 1024]), S, what="max size")
-    print(f"max size: {cells.size} sampled cells, max rel err {e:.2e}", flush=True)
+    idx = torch.as_tensor(cells, device="cuda")
+    got, st_g = out[:, idx].cpu().numpy(), st[idx].cpu().numpy()
+    ok = ((st_g | st_o[cells % 1024]) & tie) == 0
+    assert ok.mean() > 0.95
+    e = assert_parity(got[:, ok], np.ascontiguousarray(ref[:, cells[ok] % 1024]), S,
+                      what=f"max size {kernel} {method}")
+    print(f"max size {kernel} {method}: {ok.sum()} of {cells.size} sampled cells compared "
+          f"(near ties excluded), max rel err {e:.2e}", flush=True)
