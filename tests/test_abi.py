@@ -279,3 +279,29 @@ def test_binding_refuses_host_and_mistyped_arrays(mri):
     with pytest.raises(TypeError, match="float64"):
         mri._ptr(DeviceF32(), "float64")
     assert mri._ptr(None, "float64") is None
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding raises ImportError at import: there
+    is no CPU fallback for any entry point."""
+    import subprocess
+    import sys
+
+    env = dict(os.environ, MRI_LIB_PATH=str(tmp_path / "absent" / "libmri.so"))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", "import paper_2211_03293_amd.mri"], cwd=root,
+                       env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "is missing" in r.stderr
+
+
+def test_product_package_does_not_use_the_oracle():
+    """The oracle is test infrastructure: no module of the package imports it."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2211_03293_amd")
+    pat = re.compile(r"^\s*(from\s+oracle\b|import\s+oracle\b|from\s+\.\.?oracle\b)", re.M)
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                with open(os.path.join(dirpath, f)) as fh:
+                    assert not pat.search(fh.read()), f
