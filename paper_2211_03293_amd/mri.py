@@ -370,9 +370,11 @@ class BatchPlan:
     def run(self, y_in, y_out, ld, n_poly, rho_poly, L_per_set, status_out=None, steps_out=None,
             stream=None):
         L = _f64(L_per_set)
-        _check(lib.mri_batch_run(self.h, _ptr(y_in), _ptr(y_out), int(ld), n_poly, _ptr(rho_poly),
-                                 L.ctypes.data_as(C.POINTER(C.c_double)), _ptr(status_out),
-                                 _ptr(steps_out), _stream(stream)))
+        _check(lib.mri_batch_run(self.h, _ptr(y_in, "float64"), _ptr(y_out, "float64"), int(ld),
+                                 n_poly, _ptr(rho_poly, "float64"),
+                                 L.ctypes.data_as(C.POINTER(C.c_double)),
+                                 _ptr(status_out, "int32"), _ptr(steps_out, "int32"),
+                                 _stream(stream)))
 
     def tile(self):
         b, n = C.c_int(0), C.c_int(0)

@@ -357,3 +357,65 @@ def test_maximum_size_stage_sampled(torch, mri, O, kernel, method):
                       what=f"max size {kernel} {method}")
     print(f"max size {kernel} {method}: {ok.sum()} of {cells.size} sampled cells compared "
           f"(near ties excluded), max rel err {e:.2e}", flush=True)
+
+
+def test_batch_maximum_size_sampled(torch, mri, O):
+    """The batched work queue at the largest state the boundary takes for the
+    21-species mechanism: n * ld = 22 x 97,612,800 elements (within 2,047 of
+    2^31 - 1), 2,000 reactor sets of uneven size over n_cells = ld - 37, four
+    stage lengths, adaptive Zonneveld 4(3) at tol 1e-8.  The state repeats
+    1,024 seeded cells; sampled cells (set boundaries and the last cells
+    included) match the oracle off near-tie decisions, no cell reports an
+    error, and the padding is untouched."""
+    free, _ = torch.cuda.mem_get_info()
+    if free < 48 * 2**30:
+        pytest.skip(f"needs 48 GiB of free device memory ({free / 2**30:.0f} GiB)")
+    mech = I.make_mechanism(I.SETS1000)
+    S = mech.n_species
+    n = S + 1
+    rng = np.random.Generator(np.random.PCG64(41))
+    y_small = I.independent_cells(1024, S, rng, ld=1024)
+    L_vals = np.array([0.3, 0.5, 0.7, 1.0]) * 1e-7
+    orc = O.Oracle(mech)
+    zo = O.zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
+    ref4, st4 = [], []
+    for L in L_vals:
+        r, s, _, _ = orc.fast_stage_soa(y_small, np.zeros((1, n, 1024)), L, zo)
+        ref4.append(r)
+        st4.append(s)
+    ref4, st4 = np.stack(ref4), np.stack(st4)
+    tie = mri.CELL_NEARTIE
+    assert np.all((st4 & ~tie) == 0)
+    ld = 1024 * 95325
+    assert n * ld <= 2**31 - 1 and 2**31 - 1 - n * ld < 2048
+    N = ld - 37
+    w = np.exp(rng.uniform(np.log(1e3), np.log(1e5), 2000))
+    sizes = np.floor(w / w.sum() * N).astype(np.int64)
+    sizes[-1] += N - sizes.sum()
+    off = I.set_offsets(sizes)
+    assert off[-1] == N and np.all(sizes > 0)
+    L_set = L_vals[np.arange(2000) % 4]
+    print(f"batch max size: n {n}, ld {ld}, n_cells {N}, 2000 sets", flush=True)
+    yd = torch.as_tensor(y_small, device="cuda").repeat(1, ld // 1024)
+    out = torch.full((n, ld), -1.0, dtype=torch.float64, device="cuda")
+    st = torch.full((ld,), 7, dtype=torch.int32, device="cuda")
+    m = mri.Mech(mech)
+    opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
+                         max_steps=2000)
+    plan = mri.BatchPlan(m, opts, off)
+    plan.run(yd, out, ld, 0, None, L_set, st)
+    torch.cuda.synchronize()
+    assert mri.mri_status_count(st, N, mask=0xFF & ~tie) == 0
+    assert bool((st[N:] == 7).all()) and bool((out[:, N:] == -1.0).all())
+    edges = np.concatenate([off[1:40] - 1, off[1:40], off[-40:-1] - 1, off[-40:-1]])
+    cells = np.unique(np.concatenate([_sample(N, 4096, seed=13), edges, np.arange(N - 64, N)]))
+    idx = torch.as_tensor(cells, device="cuda")
+    got, st_g = out[:, idx].cpu().numpy(), st[idx].cpu().numpy()
+    li = (np.searchsorted(off, cells, side="right") - 1) % 4
+    ref = ref4[li, :, cells % 1024].T
+    ok = ((st_g | st4[li, cells % 1024]) & tie) == 0
+    assert ok.mean() > 0.95
+    e = assert_parity(got[:, ok], np.ascontiguousarray(ref[:, ok]), S, what="batch max size")
+    wg, nb = plan.tile()
+    print(f"batch max size: {ok.sum()} of {cells.size} sampled cells compared, max rel err "
+          f"{e:.2e}, tile {wg}x{nb}", flush=True)
