@@ -197,6 +197,35 @@ def test_batch_work_queue_parity(torch, mri, O, n_poly):
     assert 0 < useful <= issued
 
 
+def test_batch_result_is_independent_of_the_tile(torch, mri, O):
+    """Each cell is integrated by one lane from start to finish, so the batched
+    results do not depend on how the queue hands cells out: tiles of 64 and 256
+    lanes per block (and the autotuned one) give bitwise equal states, status
+    bits and step counts."""
+    mech, off, y, Ls, rng = _batch_inputs(40, 64, 3000, seed=23)
+    n, ld = y.shape
+    ntot = int(off[-1])
+    m = mri.Mech(mech)
+    yd = torch.as_tensor(y, device="cuda")
+    res = []
+    for block in (64, 256, 0):
+        opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
+                             max_steps=2000, block_size=block)
+        plan = mri.BatchPlan(m, opts, off)
+        out = torch.zeros_like(yd)
+        st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+        steps = torch.zeros(ld, dtype=torch.int32, device="cuda")
+        plan.run(yd, out, ld, 0, None, Ls, st, steps)
+        torch.cuda.synchronize()
+        res.append((out.cpu().numpy()[:, :ntot], st.cpu().numpy()[:ntot],
+                    steps.cpu().numpy()[:ntot], plan.tile()))
+    print(f"batch tiles {[r[3] for r in res]}, {ntot} cells")
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0])
+        assert np.array_equal(r[1], res[0][1]) and np.array_equal(r[2], res[0][2])
+    assert res[0][3][0] == 64 and res[1][3][0] == 256
+
+
 def test_slow_step_graph_capture_replays(torch, mri, O):
     """A captured MRI slow step replays to the eager result on every replay,
     with eager work and synchronizations between replays."""
