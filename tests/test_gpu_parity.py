@@ -102,6 +102,36 @@ def test_ragged_tail_and_in_place(torch, mri, O, kernel):
     assert np.array_equal(yd.cpu().numpy(), got)
 
 
+@pytest.mark.parametrize("method", ["rk4", "zonneveld"])
+def test_stage_result_is_independent_of_the_block_size(torch, mri, method):
+    """One lane integrates one cell with the same arithmetic whatever the block
+    size the kernel is compiled for: blocks of 64, 128 and 256 lanes give
+    bitwise equal states, status bits and step counts (specialized kernels)."""
+    mech = I.make_mechanism(I.SMALL)
+    y0 = I.initial_state(I.SMALL)
+    n, ld = y0.shape
+    m = mri.Mech(mech)
+    yd = _dev(torch, y0)
+    rho = torch.zeros((1, n, ld), dtype=torch.float64, device="cuda")
+    res = []
+    for block in (64, 128, 256):
+        if method == "rk4":
+            opts = mri.fast_opts(n_sub=20, kernel=mri.KERNEL_SPECIALIZED, block_size=block)
+        else:
+            opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8,
+                                 atol_T=1e-5, kernel=mri.KERNEL_SPECIALIZED, block_size=block)
+        out = torch.empty_like(yd)
+        st = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+        steps = torch.zeros((ld,), dtype=torch.int32, device="cuda")
+        mri.mri_fast_stage(m, opts, 512, ld, yd, out, 1, rho, (5.0 / 12.0) * 1e-6, st, steps)
+        torch.cuda.synchronize()
+        res.append((out.cpu().numpy()[:, :512], st.cpu().numpy()[:512],
+                    steps.cpu().numpy()[:512]))
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0])
+        assert np.array_equal(r[1], res[0][1]) and np.array_equal(r[2], res[0][2])
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_zonneveld_stage_small(torch, mri, O, kernel):
     mech = I.make_mechanism(I.SMALL)
