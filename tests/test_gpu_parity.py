@@ -133,6 +133,33 @@ def test_stage_result_is_independent_of_the_block_size(torch, mri, method):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
+def test_stage_on_a_side_stream(torch, mri, kernel):
+    """Every call runs on the stream it is given: a stage enqueued on a side
+    stream (default priority) behind a copy into its input on that stream sees
+    the copied input, and equals bitwise the same stage on the current stream."""
+    mech = I.make_mechanism(I.SMALL)
+    y0 = I.initial_state(I.SMALL)
+    n, ld = y0.shape
+    m = mri.Mech(mech)
+    src = _dev(torch, y0)
+    rho = torch.zeros((1, n, ld), dtype=torch.float64, device="cuda")
+    opts = mri.fast_opts(n_sub=20, kernel=_kernel(mri, kernel))
+    L = (5.0 / 12.0) * 1e-6
+    ref = torch.empty_like(src)
+    mri.mri_fast_stage(m, opts, 512, ld, src, ref, 1, rho, L)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    yin = torch.zeros_like(src)
+    out = torch.full_like(src, -1.0)
+    side.wait_stream(torch.cuda.current_stream())     # the two fills above come first
+    with torch.cuda.stream(side):
+        yin.copy_(src)                       # ordered before the stage on `side`
+        mri.mri_fast_stage(m, opts, 512, ld, yin, out, 1, rho, L, stream=side)
+    side.synchronize()
+    assert torch.equal(out[:, :512], ref[:, :512])
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 def test_zonneveld_stage_small(torch, mri, O, kernel):
     mech = I.make_mechanism(I.SMALL)
     orc = O.Oracle(mech)
