@@ -305,3 +305,33 @@ def test_product_package_does_not_use_the_oracle():
             if f.endswith(".py"):
                 with open(os.path.join(dirpath, f)) as fh:
                     assert not pat.search(fh.read()), f
+
+
+def test_concurrent_specialization_of_one_handle(mri):
+    """A handle may be shared by threads: concurrent run-time compilations of
+    one mechanism (serialized inside the library) all succeed and produce the
+    same code object."""
+    import threading
+
+    m = mri.Mech(I.make_mechanism(I.SMALL))
+    out, errs = [], []
+
+    def work(method):
+        try:
+            out.append((method, m.code_hash(method, 1, 64)))
+        except Exception as e:           # noqa: BLE001 - reported below
+            errs.append(e)
+
+    threads = [threading.Thread(target=work, args=(meth,))
+               for meth in (mri.FAST_RK4, mri.FAST_HEUN, mri.FAST_RK4, mri.FAST_HEUN)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=600)
+    assert not errs, errs
+    assert len(out) == 4
+    by_method = {}
+    for meth, h in out:
+        by_method.setdefault(meth, set()).add(h)
+    assert all(len(v) == 1 for v in by_method.values()), by_method
+    assert by_method[mri.FAST_RK4] != by_method[mri.FAST_HEUN]
