@@ -197,6 +197,50 @@ def test_batch_work_queue_parity(torch, mri, O, n_poly):
     assert 0 < useful <= issued
 
 
+def test_batch_with_empty_sets(torch, mri, O):
+    """Empty reactor sets (first, last and in between) take no cells and shift
+    nothing: every non-empty set matches the oracle with its own stage length;
+    a plan whose sets are all empty runs as a no-op."""
+    sizes = np.array([0, 100, 0, 0, 257, 64, 0, 1, 0], dtype=np.int64)
+    off = I.set_offsets(sizes)
+    ntot = int(off[-1])
+    mech = I.make_mechanism(I.SETS1000)
+    rng = np.random.Generator(np.random.PCG64(29))
+    y = I.independent_cells(ntot, mech.n_species, rng)
+    n, ld = y.shape
+    Ls = rng.uniform(0.3, 1.0, sizes.size) * 1e-7
+    orc = O.Oracle(mech)
+    zo = O.zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
+    ref = np.zeros_like(y)
+    st_o = np.zeros(ld, dtype=np.int32)
+    for k in range(sizes.size):
+        a, b = off[k], off[k + 1]
+        if b > a:
+            o, st, _, _ = orc.fast_stage_soa(np.ascontiguousarray(y[:, a:b]),
+                                             np.zeros((1, n, b - a)), Ls[k], zo)
+            ref[:, a:b], st_o[a:b] = o, st
+    m = mri.Mech(mech)
+    opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
+                         max_steps=2000)
+    yd = torch.as_tensor(y, device="cuda")
+    out = torch.full_like(yd, -1.0)
+    st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    mri.BatchPlan(m, opts, off).run(yd, out, ld, 0, None, Ls, st)
+    torch.cuda.synchronize()
+    st_g = st.cpu().numpy()[:ntot]
+    tie = ((st_g | st_o[:ntot]) & mri.CELL_NEARTIE) != 0
+    assert tie.sum() <= 2
+    assert np.all((st_g & ~mri.CELL_NEARTIE) == 0)
+    assert_parity(out.cpu().numpy(), ref, mech.n_species, cells=np.nonzero(~tie)[0],
+                  what="empty sets")
+    assert bool((out[:, ntot:] == -1.0).all())
+    empty = mri.BatchPlan(m, opts, np.zeros(4, dtype=np.int64))
+    out2 = torch.full_like(yd, -1.0)
+    empty.run(yd, out2, ld, 0, None, np.full(3, 1e-7))
+    torch.cuda.synchronize()
+    assert bool((out2 == -1.0).all())
+
+
 def test_batch_result_is_independent_of_the_tile(torch, mri, O):
     """Each cell is integrated by one lane from start to finish, so the batched
     results do not depend on how the queue hands cells out: tiles of 64 and 256
