@@ -295,7 +295,9 @@ mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t str
    |x| < 1022). */
 mri_status mri_selftest_exp2_t256(const double *x, double *y, int n, mri_stream_t stream);
 
-/* Counts cells with (status & mask) != 0; synchronizes the stream. */
+/* Counts cells with (status & mask) != 0; synchronizes the stream.  Uses one
+   device counter per GPU, allocated on the first call there and kept until the
+   process ends; concurrent calls take turns. */
 mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, int64_t *n_bad,
                             mri_stream_t stream);
 

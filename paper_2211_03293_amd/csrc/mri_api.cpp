@@ -1204,14 +1204,22 @@ mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, in
     if (n_cells == 0) return MRI_OK;
     if (!status) return fail(MRI_EINVAL, "status is NULL");
     hipStream_t s = (hipStream_t)stream;
-    unsigned long long *d = nullptr;
-    HIP_TRY(hipMalloc(&d, sizeof(unsigned long long)));
+    // one device counter per GPU, allocated on the first call there and kept
+    // until the process ends; the lock spans the whole (synchronizing) call, so
+    // concurrent calls take turns instead of sharing the counter
+    static std::mutex mu;
+    static unsigned long long *counter[64] = {};
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MRI_EUNSUPPORTED, "device index %d", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!counter[dev]) HIP_TRY(hipMalloc(&counter[dev], sizeof(unsigned long long)));
+    unsigned long long *d = counter[dev];
     unsigned long long h = 0;
     hipError_t e = launch_fill_u64(d, 1, 0ull, s);
     if (e == hipSuccess) e = launch_status_count(status, n_cells, mask, d, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d);
     if (e != hipSuccess) return fail(MRI_EHIP, "status count failed: %s", hipGetErrorString(e));
     *n_bad = (int64_t)h;
     return MRI_OK;
