@@ -218,6 +218,28 @@ mri_status mri_slow_step(const mri_mech *m, const mri_table *t, const mri_fast_o
                          int32_t *steps_out, mri_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph        */
+/* capture, tight serving loops, harnesses that forbid hipMalloc): the slow    */
+/* step of mri_slow_step with no workspace argument.  The slow evaluations and */
+/* forcing planes live in a device array inside the library of                 */
+/* MRI_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends); a step     */
+/* needs 8 n ld (s - 1 + n_gamma) bytes of it (MRI_EINVAL beyond, e.g. n = 22  */
+/* with MIS-KW3 up to ld = 381,300 cells).  The call allocates nothing: the    */
+/* fast-stage kernel must already be set up on the device by one earlier       */
+/* mri_fast_stage or mri_slow_step with the same options and number of forcing */
+/* terms (MRI_EINVAL otherwise).  Every call on a GPU shares that GPU's array: */
+/* calls that overlap on one GPU (other streams or threads) race.  Each plane  */
+/* is written before it is read, so no content carries over between calls.    */
+/* The slow RHS callback receives pointers into the array.                     */
+/* ------------------------------------------------------------------------- */
+#define MRI_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+size_t mri_noalloc_scratch_bytes(void);
+mri_status mri_slow_step_noalloc(const mri_mech *m, const mri_table *t,
+                                 const mri_fast_opts *opts, mri_slow_rhs f_slow, void *user,
+                                 double t0, double H, int n_cells, int ld, double *y,
+                                 int32_t *status_out, int32_t *steps_out, mri_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Adaptive slow steps (Sec. 7 names adaptive step control as the way to spare */
 /* users the manual choice of fast and slow step sizes).  Integrates y in place */
 /* from t0 to t_end with mri_slow_step, choosing H by step doubling: an attempt */

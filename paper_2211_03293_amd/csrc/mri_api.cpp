@@ -600,6 +600,83 @@ mri_status mri_internal_fast_stage(mri_mech *m, const mri_fast_opts *o, int n_ce
 int mri_internal_state_width(const mri_mech *m) { return m ? m->n : -1; }
 int mri_internal_is_chem(const mri_mech *m) { return m && m->kind == 0; }
 
+// The Sec. 2.1 step after validation: F [s-1][n][ld] and rho [ng][n][ld] are
+// device buffers the caller provides.  With timed = 0 no event is recorded
+// around the fast stages (the path that must not create or allocate anything).
+mri_status mri_internal_slow_step(mri_mech *m, const mri_table *t, const mri_fast_opts *opts,
+                                  mri_slow_rhs f_slow, void *user, double t0, double H,
+                                  int n_cells, int ld, double *y, double *F, double *rho,
+                                  int32_t *status_out, int32_t *steps_out, int timed,
+                                  hipStream_t s)
+{
+    const size_t vec = (size_t)m->n * ld;
+    const int s_ = t->s, ng = t->ng;
+    mri_stream_t stream = (mri_stream_t)s;
+    mri_status st = MRI_OK;
+    // step 1: Y_1 = y_n; F_1 = f^S(t_n, Y_1)
+    int rc = f_slow(t0, y, F, n_cells, ld, user, stream);
+    if (rc != 0) return fail(MRI_EINVAL, "slow RHS callback returned %d", rc);
+    ++c_slow;
+    for (int i = 1; i < s_; ++i) {
+        const double dc = t->c[i] - t->c[i - 1];
+        const double L = dc * H;
+        // step 2a: forcing coefficients from F_j, j < i
+        ForcingCoef coef{};
+        for (int k = 0; k < ng; ++k)
+            for (int j = 0; j < i; ++j) coef.c[k * 8 + j] = t->gamma[((size_t)k * s_ + i) * s_ + j] / dc;
+        HIP_TRY(launch_forcing((long long)vec, ng, i, F, (long long)vec, coef, rho, s));
+        // steps 2b-2c: fast IVP over the stage, in place
+        st = timed ? fast_stage_impl(m, opts, n_cells, ld, y, y, ng, rho, L, status_out,
+                                     steps_out, i > 1 ? 1 : 0, s)
+                   : fast_stage_launch(m, opts, n_cells, ld, y, y, ng, rho, L, status_out,
+                                       steps_out, i > 1 ? 1 : 0, s);
+        if (st != MRI_OK) return st;
+        if (i < s_ - 1) {
+            rc = f_slow(t0 + t->c[i] * H, y, F + (size_t)i * vec, n_cells, ld, user, stream);
+            if (rc != 0) return fail(MRI_EINVAL, "slow RHS callback returned %d", rc);
+            ++c_slow;
+        }
+    }
+    // step 3: y_(n+1) = Y_s (already in y)
+    return MRI_OK;
+}
+
+// Whether a fast stage with these options would have to create device state
+// first (copy the mechanism, compile or load a specialized kernel).
+bool mri_internal_stage_needs_setup(mri_mech *m, const mri_fast_opts *o, int n_poly)
+{
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (m->kind == 1) return m->d_A == nullptr;
+    if (!m->d_sp) return true;
+    if (o->kernel == MRI_KERNEL_GENERIC) return false;
+    const int wg = o->block_size ? o->block_size : default_block(MRI_KERNEL_SPECIALIZED);
+    const int key = spec_key(wg, spec_kind(o->method), n_poly);
+    auto it = m->spec.find(key);
+    if (it != m->spec.end() && it->second.fn) return false;
+    // automatic selection falls back to the generic kernel after a failed compilation
+    return !(o->kernel == MRI_KERNEL_AUTO && m->spec_fail.count(key));
+}
+
+mri_status mri_internal_check_slow_step(const mri_mech *m, const mri_table *t,
+                                        const mri_fast_opts *opts, mri_slow_rhs f_slow,
+                                        double t0, double H, int n_cells, int ld)
+{
+    if (!m || !t) return fail(MRI_EINVAL, "mech or table is NULL");
+    mri_status st = check_opts(m, opts);
+    if (st != MRI_OK) return st;
+    if (!f_slow) return fail(MRI_EINVAL, "slow RHS callback is NULL");
+    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
+    if ((long long)ld * m->n > (1ll << 31) - 1)
+        return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
+    if (!(H > 0.0) || !std::isfinite(H) || !std::isfinite(t0))
+        return fail(MRI_EINVAL, "H must be positive and finite");
+    return MRI_OK;
+}
+
+int mri_internal_table_stages(const mri_table *t) { return t ? t->s : 0; }
+int mri_internal_table_terms(const mri_table *t) { return t ? t->ng : 0; }
+
 extern "C" {
 
 int mri_abi_version(void) { return MRI_ABI_VERSION; }
@@ -924,51 +1001,19 @@ mri_status mri_slow_step(const mri_mech *mc, const mri_table *t, const mri_fast_
                          int32_t *steps_out, mri_stream_t stream)
 {
     mri_mech *m = const_cast<mri_mech *>(mc);
-    if (!m || !t) return fail(MRI_EINVAL, "mech or table is NULL");
-    mri_status st = check_opts(m, opts);
+    mri_status st = mri_internal_check_slow_step(m, t, opts, f_slow, t0, H, n_cells, ld);
     if (st != MRI_OK) return st;
-    if (!f_slow) return fail(MRI_EINVAL, "slow RHS callback is NULL");
-    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
-    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
-    if ((long long)ld * m->n > (1ll << 31) - 1)
-        return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
-    if (!(H > 0.0) || !std::isfinite(H) || !std::isfinite(t0))
-        return fail(MRI_EINVAL, "H must be positive and finite");
     size_t need = 0;
     mri_workspace_bytes(m, t, n_cells, ld, &need);
     if (n_cells == 0) return MRI_OK;
     if (!y) return fail(MRI_EINVAL, "y is NULL");
     if (!ws || ws_bytes < need)
         return fail(MRI_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, need);
-    hipStream_t s = (hipStream_t)stream;
     const size_t vec = (size_t)m->n * ld;
     double *F = (double *)ws;                       // [s-1][n][ld]
     double *rho = F + (size_t)(t->s - 1) * vec;     // [ng][n][ld]
-    const int s_ = t->s, ng = t->ng;
-    // step 1: Y_1 = y_n; F_1 = f^S(t_n, Y_1)
-    int rc = f_slow(t0, y, F, n_cells, ld, user, stream);
-    if (rc != 0) return fail(MRI_EINVAL, "slow RHS callback returned %d", rc);
-    ++c_slow;
-    for (int i = 1; i < s_; ++i) {
-        const double dc = t->c[i] - t->c[i - 1];
-        const double L = dc * H;
-        // step 2a: forcing coefficients from F_j, j < i
-        ForcingCoef coef{};
-        for (int k = 0; k < ng; ++k)
-            for (int j = 0; j < i; ++j) coef.c[k * 8 + j] = t->gamma[((size_t)k * s_ + i) * s_ + j] / dc;
-        HIP_TRY(launch_forcing((long long)vec, ng, i, F, (long long)vec, coef, rho, s));
-        // steps 2b-2c: fast IVP over the stage, in place
-        st = fast_stage_impl(m, opts, n_cells, ld, y, y, ng, rho, L, status_out, steps_out,
-                             i > 1 ? 1 : 0, s);
-        if (st != MRI_OK) return st;
-        if (i < s_ - 1) {
-            rc = f_slow(t0 + t->c[i] * H, y, F + (size_t)i * vec, n_cells, ld, user, stream);
-            if (rc != 0) return fail(MRI_EINVAL, "slow RHS callback returned %d", rc);
-            ++c_slow;
-        }
-    }
-    // step 3: y_(n+1) = Y_s (already in y)
-    return MRI_OK;
+    return mri_internal_slow_step(m, t, opts, f_slow, user, t0, H, n_cells, ld, y, F, rho,
+                                  status_out, steps_out, 1, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

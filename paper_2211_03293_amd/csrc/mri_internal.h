@@ -13,6 +13,23 @@ mri_status mri_internal_fast_stage(mri_mech *m, const mri_fast_opts *o, int n_ce
                                    const double *yin, double *yout, int n_poly, const double *rho,
                                    double L, int32_t *status, int32_t *steps, hipStream_t s);
 int mri_internal_state_width(const mri_mech *m);
+// Argument checks of mri_slow_step (everything but y and the workspace).
+mri_status mri_internal_check_slow_step(const mri_mech *m, const mri_table *t,
+                                        const mri_fast_opts *opts, mri_slow_rhs f_slow,
+                                        double t0, double H, int n_cells, int ld);
+// One slow step (Sec. 2.1) on validated arguments with caller-provided slow
+// evaluations F [s-1][n][ld] and forcing rho [n_gamma][n][ld]; timed = 0 records
+// no events.
+mri_status mri_internal_slow_step(mri_mech *m, const mri_table *t, const mri_fast_opts *opts,
+                                  mri_slow_rhs f_slow, void *user, double t0, double H,
+                                  int n_cells, int ld, double *y, double *F, double *rho,
+                                  int32_t *status_out, int32_t *steps_out, int timed,
+                                  hipStream_t s);
+// True when a fast stage with these options would first copy the mechanism to
+// the device or compile / load a specialized kernel.
+bool mri_internal_stage_needs_setup(mri_mech *m, const mri_fast_opts *o, int n_poly);
+int mri_internal_table_stages(const mri_table *t);
+int mri_internal_table_terms(const mri_table *t);
 int mri_internal_is_chem(const mri_mech *m);
 
 #define MRI_HIP_TRY(expr)                                                                  \

@@ -103,6 +103,9 @@ _SIGS = {
     "mri_workspace_bytes": (_i, [_vp, _vp, _i, _i, C.POINTER(_sz)]),
     "mri_slow_step": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), _vp, _vp, _d, _d, _i, _i, _vp,
                            _vp, _sz, _vp, _vp, _vp]),
+    "mri_slow_step_noalloc": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), _vp, _vp, _d, _d, _i, _i,
+                                   _vp, _vp, _vp, _vp]),
+    "mri_noalloc_scratch_bytes": (_sz, []),
     "mri_adaptive_workspace_bytes": (_i, [_vp, _vp, _i, _i, C.POINTER(_sz)]),
     "mri_adaptive_run": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), C.POINTER(mri_adapt_opts), _vp,
                               _vp, _d, _d, _i, _i, _vp, _vp, _sz, _vp,
@@ -288,6 +291,25 @@ def mri_slow_step(mech: Mech, table: Table, opts, f_slow, user, t0, H, n_cells, 
                              n_cells, ld, _ptr(y, "float64"), _ptr(ws), nbytes,
                              _ptr(status_out, "int32"), _ptr(steps_out, "int32"),
                              _stream(stream)))
+
+
+def mri_slow_step_noalloc(mech: Mech, table: Table, opts, f_slow, user, t0, H, n_cells, ld, y,
+                          status_out=None, steps_out=None, stream=None):
+    """mri_slow_step without a workspace (the library's own device array)."""
+    if isinstance(user, C.Structure):
+        user_p = C.cast(C.pointer(user), C.c_void_p).value
+    elif isinstance(user, Mech):
+        user_p = user.h.value
+    else:
+        user_p = user
+    _check(lib.mri_slow_step_noalloc(mech.h, table.h, C.byref(opts), f_slow, user_p, float(t0),
+                                     float(H), n_cells, ld, _ptr(y, "float64"),
+                                     _ptr(status_out, "int32"), _ptr(steps_out, "int32"),
+                                     _stream(stream)))
+
+
+def mri_noalloc_scratch_bytes():
+    return int(lib.mri_noalloc_scratch_bytes())
 
 
 def adapt_opts(rtol, atol_Y, atol_T, H0, order, H_min=0.0, H_max=0.0, max_attempts=10000,
