@@ -396,6 +396,18 @@ def _mlp_setup():
     return L
 
 
+# rounding points of the bfloat16-emulating mode (mlp_oracle.c ORA_R_*)
+R_INPUT, R_WEIGHT, R_ACC, R_BIAS, R_SUM, R_ACT, R_GRAD = 1, 2, 4, 8, 16, 32, 64
+R_ALL = 127
+
+
+def _mode(bf16):
+    """True: every rounding point of the GPU; False: FP64; an int: that set."""
+    if bf16 is True:
+        return R_ALL
+    return int(bf16 or 0)
+
+
 def mlp_param_count(widths):
     return sum(widths[l + 1] * widths[l] + widths[l + 1] for l in range(len(widths) - 1))
 
@@ -419,7 +431,7 @@ def mlp_forward(widths, params, X, bf16=False, cache=False):
     Z = np.zeros(nz) if cache else None
     A = np.zeros(max(na, 1)) if cache else None
     L.ora_mlp_forward(len(widths) - 1, _p(w, C.c_int32), _p(p), batch, _p(X), _p(Y),
-                      _p(Z) if cache else None, _p(A) if cache else None, int(bf16))
+                      _p(Z) if cache else None, _p(A) if cache else None, _mode(bf16))
     return (Y, Z, A) if cache else Y
 
 
@@ -430,7 +442,7 @@ def mlp_loss_grad(widths, params, X, T, bf16=False):
     X, T = _f64(X), _f64(T)
     g = np.zeros(p.size)
     loss = L.ora_mlp_loss_grad(len(widths) - 1, _p(w, C.c_int32), _p(p), X.shape[0], _p(X),
-                               _p(T), _p(g), int(bf16))
+                               _p(T), _p(g), _mode(bf16))
     return loss, g
 
 
@@ -449,3 +461,72 @@ def silu(z):
 
 def silu_grad(z):
     return _mlp_setup().ora_silu_grad(float(z))
+
+
+# ---------------------------------------------------------------------------
+# Learned fast-stage surrogate (mlp_oracle.c ora_sur_*)
+# ---------------------------------------------------------------------------
+def sur_n_features(S):
+    return int(lib().ora_sur_n_features(int(S)))
+
+
+def _soa(a):
+    return _f64(a)
+
+
+def sur_stats(S, Y0, RHO, Lv, Y1, Yb=None):
+    """Standardization statistics [x_mean, x_inv_std, y_mean, y_inv_std, y_std]
+    of the samples (columns of the SoA arrays; RHO [n_poly][n][ld])."""
+    Y0, Y1, Lv = _soa(Y0), _soa(Y1), _soa(Lv)
+    RHO = _soa(RHO)
+    N, ld = Lv.size, Y0.shape[1]
+    F, n = sur_n_features(S), S + 1
+    stats = np.zeros(2 * F + 3 * n)
+    lib().ora_sur_stats(int(S), C.c_long(N), C.c_long(ld), _p(Y0), RHO.shape[0], _p(RHO), _p(Lv),
+                        _p(_soa(Yb)) if Yb is not None else None, _p(Y1), _p(stats))
+    return stats
+
+
+def sur_featurize(S, Y0, RHO, Lv, stats, kpad=96, Yb=None, Y1=None):
+    """Standardized feature rows [N][kpad] (FP64) and, given Y1, standardized
+    targets [N][n] (corrections from Yb, default Y0)."""
+    Y0, Lv, RHO = _soa(Y0), _soa(Lv), _soa(RHO)
+    N, ld = Lv.size, Y0.shape[1]
+    X = np.zeros((N, kpad))
+    T = np.zeros((N, S + 1)) if Y1 is not None else None
+    lib().ora_sur_featurize(int(S), C.c_long(N), C.c_long(ld), _p(Y0), RHO.shape[0], _p(RHO),
+                            _p(Lv), _p(_soa(Yb)) if Yb is not None else None,
+                            _p(_soa(Y1)) if Y1 is not None else None, _p(_f64(stats)), int(kpad),
+                            _p(X), _p(T) if T is not None else None)
+    return (X, T) if Y1 is not None else X
+
+
+def sur_infer(S, widths, params, stats, Y, RHO, L, N=None, base=None, bf16=True, want_z=False):
+    """The surrogate's prediction on the first N cells of Y [n][ld] (forcing
+    RHO [n_poly][n][ld], stage length L), applied to `base` (default Y)."""
+    Y, RHO = _soa(Y), _soa(RHO)
+    n, ld = Y.shape
+    N = ld if N is None else N
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    out = np.zeros_like(Y)
+    Z = np.zeros((N, n)) if want_z else None
+    lib().ora_sur_infer(int(S), C.c_long(N), C.c_long(ld), _p(Y), RHO.shape[0], _p(RHO),
+                        C.c_double(L), _p(_soa(base)) if base is not None else None,
+                        len(widths) - 1, _p(w, C.c_int32), _p(_f64(params)), _p(_f64(stats)),
+                        _mode(bf16), _p(out), _p(Z) if want_z else None)
+    return (out, Z) if want_z else out
+
+
+def sur_gate(S, Y0, RHO, L, Vc, Vh, Vn, rich, tol, N=None, status_c=None):
+    """Residual check of the surrogate: (G [N], accept [N] as bool)."""
+    Y0, RHO, Vc, Vh, Vn = _soa(Y0), _soa(RHO), _soa(Vc), _soa(Vh), _soa(Vn)
+    ld = Y0.shape[1]
+    N = ld if N is None else N
+    G = np.zeros(N)
+    acc = np.zeros(N, dtype=np.int32)
+    st = np.ascontiguousarray(status_c, dtype=np.int32) if status_c is not None else None
+    lib().ora_sur_gate(int(S), C.c_long(N), C.c_long(ld), _p(Y0), RHO.shape[0], _p(RHO),
+                       C.c_double(L), _p(Vc), _p(Vh), _p(Vn),
+                       _p(st, C.c_int32) if st is not None else None, C.c_double(rich),
+                       C.c_double(tol), _p(G), _p(acc, C.c_int32))
+    return G, acc.astype(bool)

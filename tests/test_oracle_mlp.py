@@ -84,3 +84,50 @@ def test_bf16_mode_tracks_fp64_mode(oracle_mod):
     _, g64 = O.mlp_loss_grad(widths, p, X, T)
     _, g16 = O.mlp_loss_grad(widths, p, X, T, bf16=True)
     assert np.linalg.norm(g16 - g64) / np.linalg.norm(g64) < 5e-2
+
+
+def test_bf16_mode_rounding_points_hand_computed(oracle_mod):
+    """A 2-2-1 network whose output, worked out by hand, moves when any single
+    rounding point of the bfloat16 mode is switched off.
+
+    Hidden pre-activations are near 64, where SiLU(z) = z / (1 + e^-z) equals z
+    in double precision (e^-64 < 2^-53), so every step is exact dyadic
+    arithmetic.  bfloat16 spacing in [64, 128) is 1/2, FP32 spacing 2^-17.
+      x = (1 + 2^-8 + 2^-10, 1) -> bf16 (1 + 2^-7, 1)
+      W1 = [[64.375, 0], [0, 64]] -> bf16 [[64.5, 0], [0, 64]],  b1 = (1/4, 0)
+      z1 = 64.5 (1 + 2^-7) + 1/4 = 65.25390625 -> bf16 65.5 (above the midpoint
+           65.25 between 65 and 65.5);  z2 = 64 -> 64
+      W2 = [[1, 2^-30]], b2 = 2^-18 + 2^-44 (the 2^-44 is below FP32
+      resolution at 2^-18 but above FP64 resolution at 65.5)
+      acc = 65.5 + 2^-24 -> FP32 65.5;  b2 -> FP32 2^-18;
+      65.5 + 2^-18 is half an FP32 ulp above 65.5: ties to even -> y = 65.5.
+    With one rounding point off:
+      input   z1 = 64.5 (1 + 2^-8 + 2^-10) + 1/4 = 65.0649... -> 65   -> y = 65
+      weight  z1 = 64.375 (1 + 2^-7) + 1/4 = 65.1279...      -> 65   -> y = 65
+      act     h1 = 65.25390625 (no bf16), tie again rounds to even -> y = 65.25390625
+      acc     65.5 + 2^-24 + 2^-18 above the tie            -> y = 65.5 + 2^-17
+      bias    65.5 + 2^-18 + 2^-44 above the tie            -> y = 65.5 + 2^-17
+      sum     65.5 + 2^-18 kept in FP64                     -> y = 65.5 + 2^-18
+    """
+    O = oracle_mod
+    widths = [2, 2, 1]
+    W1 = np.array([[64.375, 0.0], [0.0, 64.0]])
+    b1 = np.array([0.25, 0.0])
+    W2 = np.array([[1.0, 2.0 ** -30]])
+    b2 = np.array([2.0 ** -18 + 2.0 ** -44])
+    p = O.mlp_pack([W1, W2], [b1, b2])
+    X = np.array([[1.0 + 2.0 ** -8 + 2.0 ** -10, 1.0]])
+    expect = {
+        O.R_ALL: 65.5,
+        O.R_ALL & ~O.R_INPUT: 65.0,
+        O.R_ALL & ~O.R_WEIGHT: 65.0,
+        O.R_ALL & ~O.R_ACT: 65.25390625,
+        O.R_ALL & ~O.R_ACC: 65.5 + 2.0 ** -17,
+        O.R_ALL & ~O.R_BIAS: 65.5 + 2.0 ** -17,
+        O.R_ALL & ~O.R_SUM: 65.5 + 2.0 ** -18,
+    }
+    for mode, want in expect.items():
+        got = O.mlp_forward(widths, p, X, bf16=mode)[0, 0]
+        assert got == want, (mode, got, want)
+    # True selects every rounding point
+    assert O.mlp_forward(widths, p, X, bf16=True)[0, 0] == 65.5
