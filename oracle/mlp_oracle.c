@@ -344,24 +344,29 @@ void ora_sur_infer(int S, long N, long ld, const double *Y, int n_poly, const do
                    const double *params, const double *stats, int mode, double *OUT, double *Z)
 {
     const int n = S + 1, F = ora_sur_n_features(S), kin = widths[0];
-    double *f = (double *)malloc(sizeof(double) * (size_t)F);
-    double *x = (double *)malloc(sizeof(double) * (size_t)kin);
-    double *z = (double *)malloc(sizeof(double) * (size_t)n);
     if (!B) B = Y;
-    for (long i = 0; i < N; ++i) {
-        sur_raw_features(S, ld, i, Y, n_poly, RHO, L, f);
-        for (int k = 0; k < kin; ++k)
-            x[k] = (k < F) ? f32((f[k] - stats[k]) * stats[F + k], mode & ORA_R_INPUT) : 0.0;
-        ora_mlp_forward(n_layers, widths, params, 1, x, z, NULL, NULL, mode);
-        for (int c = 0; c < n; ++c) {
-            const double d = stats[2 * F + c] + stats[2 * F + 2 * n + c] * z[c];
-            OUT[(size_t)c * ld + i] = sur_apply(S, c, B[(size_t)c * ld + i], d);
-            if (Z) Z[(size_t)i * n + c] = z[c];
+    /* cells are independent; the threads only shorten the CPU timing */
+#pragma omp parallel
+    {
+        double *f = (double *)malloc(sizeof(double) * (size_t)F);
+        double *x = (double *)malloc(sizeof(double) * (size_t)kin);
+        double *z = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(dynamic, 64)
+        for (long i = 0; i < N; ++i) {
+            sur_raw_features(S, ld, i, Y, n_poly, RHO, L, f);
+            for (int k = 0; k < kin; ++k)
+                x[k] = (k < F) ? f32((f[k] - stats[k]) * stats[F + k], mode & ORA_R_INPUT) : 0.0;
+            ora_mlp_forward(n_layers, widths, params, 1, x, z, NULL, NULL, mode);
+            for (int c = 0; c < n; ++c) {
+                const double d = stats[2 * F + c] + stats[2 * F + 2 * n + c] * z[c];
+                OUT[(size_t)c * ld + i] = sur_apply(S, c, B[(size_t)c * ld + i], d);
+                if (Z) Z[(size_t)i * n + c] = z[c];
+            }
         }
+        free(f);
+        free(x);
+        free(z);
     }
-    free(f);
-    free(x);
-    free(z);
 }
 
 /*

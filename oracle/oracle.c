@@ -19,7 +19,8 @@
  *   Zonneveld 4(3) adaptive integration over one fast stage
  *   the explicit MRI-GARK slow step (Sec. 2.1 algorithm, steps 1-3)
  *   the 2nd-order centred periodic advection-diffusion slow RHS (Sec. 3.1)
- *   a finite-difference Jacobian of f^F (stiffness calibration / monitor)
+ *   a finite-difference Jacobian of f^F (stiffness calibration) and a
+ *     Gershgorin bound of its species block (stiffness monitor)
  *   an MLP forward/backward in FP64 and in a BF16-emulating mode
  */
 #include <math.h>
@@ -122,6 +123,64 @@ void ora_chem_rhs_parts(const ora_mech *m, const double *y, double *ydot,
     if (wdot_out) memcpy(wdot_out, wdot, sizeof(double) * S);
     free(C);
     free(wdot);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stiffness monitor: an upper bound of the spectral radius of the species    */
+/* block of the chemistry Jacobian at fixed T (the stability statements of    */
+/* the fast methods, Sec. 5.2, compare h times the fastest rate with the      */
+/* method's stability interval).  In concentration variables -- a similarity */
+/* transform of the mass-fraction variables (Y_k = C_k W_k / rho), so the     */
+/* same eigenvalues -- d(omega_k)/d(C_l) = sum_j nu_kj dq_j/dC_l with          */
+/* dq_j/dC_a = kf C_b, dq_j/dC_b = kf C_a, dq_j/dC_c = -kr C_d,               */
+/* dq_j/dC_d = -kr C_c; by the triangle inequality every absolute row sum is  */
+/* at most B_k = sum_j |nu_kj| w_j, w_j = kf (C_a + C_b) + kr (C_c + C_d),     */
+/* and the spectral radius is at most max_k B_k (Gershgorin).                 */
+/* ------------------------------------------------------------------------ */
+double ora_stiff_bound(const ora_mech *m, const double *y)
+{
+    const int S = m->S, R = m->R;
+    double *kf = (double *)malloc(sizeof(double) * R);
+    double *kr = (double *)malloc(sizeof(double) * R);
+    double *C = (double *)malloc(sizeof(double) * S);
+    double *B = (double *)malloc(sizeof(double) * S);
+    double *ydot = (double *)malloc(sizeof(double) * (S + 1));
+    ora_chem_rhs_parts(m, y, ydot, kf, kr, NULL, NULL);
+    const double rho_cgs = m->rho * 1e-3;
+    for (int k = 0; k < S; ++k) {
+        C[k] = rho_cgs * y[k] / (m->W[k] * 1e3);
+        B[k] = 0.0;
+    }
+    for (int j = 0; j < R; ++j) {
+        int a = m->reac[2 * j], b = m->reac[2 * j + 1];
+        int c = m->prod[2 * j], d = m->prod[2 * j + 1];
+        double w = kf[j] * (C[a] + C[b]) + kr[j] * (C[c] + C[d]);
+        B[a] += w;          /* one term per occurrence: |nu| = 2 when a = b */
+        B[b] += w;
+        B[c] += w;
+        B[d] += w;
+    }
+    double bmax = 0.0;
+    for (int k = 0; k < S; ++k)
+        if (B[k] > bmax) bmax = B[k];
+    free(kf);
+    free(kr);
+    free(C);
+    free(B);
+    free(ydot);
+    return bmax;
+}
+
+void ora_stiff_bound_soa(const ora_mech *m, int n_cells, int ld, const double *y, double *out)
+{
+    const int n = m->S + 1;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n_cells; ++i) {
+        double *v = (double *)malloc(sizeof(double) * n);
+        for (int c = 0; c < n; ++c) v[c] = y[(size_t)c * ld + i];
+        out[i] = ora_stiff_bound(m, v);
+        free(v);
+    }
 }
 
 void ora_chem_rhs(const ora_mech *m, const double *y, double *ydot)

@@ -157,6 +157,17 @@ class Oracle:
         return J
 
     # ---- one fast stage ----------------------------------------------------
+    def stiff_bound(self, y):
+        """Upper bound of the spectral radius of the species Jacobian (1/s) of one
+        cell (state y) or of every column of an SoA array."""
+        y = _f64(y)
+        self.L.ora_stiff_bound.restype = C.c_double
+        if y.ndim == 1:
+            return self.L.ora_stiff_bound(C.byref(self.m), _p(y))
+        out = np.zeros(y.shape[1])
+        self.L.ora_stiff_bound_soa(C.byref(self.m), y.shape[1], y.shape[1], _p(y), _p(out))
+        return out
+
     def rk4_stage(self, y, rho_poly, L, n_sub):
         """Single cell; rho_poly [n_poly][n]."""
         y = _f64(y)
@@ -530,3 +541,29 @@ def sur_gate(S, Y0, RHO, L, Vc, Vh, Vn, rich, tol, N=None, status_c=None):
                        _p(st, C.c_int32) if st is not None else None, C.c_double(rich),
                        C.c_double(tol), _p(G), _p(acc, C.c_int32))
     return G, acc.astype(bool)
+
+
+def sur_stage(orc, widths, params, stats, y, rho, L, n_coarse, n_fine, tol, N=None, bf16=True):
+    """The gated surrogate stage composed from the oracle's steps: RK4 stages
+    with n_coarse and n_coarse/2 substeps, the network's correction of the
+    first, the residual check against their Richardson extrapolation (RK4:
+    1/15), and the plain RK4 stage with n_fine substeps for every rejected
+    cell.  Returns (out [n][N], accept [N], G [N], status of the plain stage
+    [N])."""
+    y, rho = _f64(y), _f64(rho)
+    N = y.shape[1] if N is None else N
+    S = y.shape[0] - 1
+    vc, sc, _, _ = orc.fast_stage_soa(y, rho, L, rk4_opts(n_coarse), N)
+    vh, sh, _, _ = orc.fast_stage_soa(y, rho, L, rk4_opts(n_coarse // 2), N)
+    vn = sur_infer(S, widths, params, stats, y, rho, L, N=N, base=vc, bf16=bf16)
+    G, acc = sur_gate(S, y, rho, L, vc, vh, vn, 1.0 / 15.0, tol, N=N, status_c=(sc | sh)[:N])
+    out = vn[:, :N].copy()
+    sf = np.zeros(N, dtype=np.int32)
+    rej = np.nonzero(~acc)[0]
+    if rej.size:
+        yr = np.ascontiguousarray(y[:, rej])
+        rr = np.ascontiguousarray(rho[:, :, rej])
+        fine, s_f, _, _ = orc.fast_stage_soa(yr, rr, L, rk4_opts(n_fine))
+        out[:, rej] = fine
+        sf[rej] = s_f
+    return out, acc, G, sf

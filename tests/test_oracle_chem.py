@@ -181,3 +181,43 @@ def test_fd_jacobian_matches_directional_derivative(oracle_mod, workload):
         fd = (orc.rhs(y + e * d) - orc.rhs(y - e * d)) / (2 * e)
         scale = np.abs(J) @ np.abs(d) + 1e-300
         assert np.all(np.abs(J @ d - fd) <= 1e-4 * scale + 1e-12 * np.abs(fd).max())
+
+
+def test_stiffness_bound_single_reaction_is_the_spectral_radius(oracle_mod):
+    """One reversible reaction A + B <=> C + D: the species Jacobian (at fixed T)
+    is the rank-one nu (grad q)^T, whose only nonzero eigenvalue is nu . grad q
+    = -(kf C_b + kf C_a + kr C_d + kr C_c); the Gershgorin bound equals its
+    magnitude, and so does the finite-difference Jacobian's leading eigenvalue."""
+    W = [0.012, 0.044, 0.040, 0.016]
+    mech = _one_reaction_mech(math.log(3e12), 0.5, 4000.0, [-1e4, 2e4, -5e4, 1e4],
+                              [-20.0, 10.0, 5.0, -30.0], W, [1000.0, 1500.0, 800.0, 2000.0])
+    orc = oracle_mod.Oracle(mech)
+    y = np.array([0.3, 0.2, 0.4, 0.1, 1500.0])
+    d = orc.rhs_parts(y)
+    C = 1e-3 * y[:4] / (np.array(W) * 1e3)
+    kf, kr = d["kf"][0], d["kr"][0]
+    w = kf * (C[0] + C[1]) + kr * (C[2] + C[3])
+    assert orc.stiff_bound(y) == pytest.approx(w, rel=1e-14)
+    J = orc.jacobian(y)[:4, :4]
+    ev = np.linalg.eigvals(J)
+    lead = ev[np.argmax(np.abs(ev))]
+    assert lead.real == pytest.approx(-w, rel=1e-5) and abs(lead.imag) <= 1e-6 * w
+
+
+@pytest.mark.parametrize("workload", [I.SMALL, I.FIELD64])
+def test_stiffness_bound_dominates_the_spectral_radius(oracle_mod, workload):
+    """On random cells of the workload mechanisms the bound is at least the
+    spectral radius of the species block of the finite-difference Jacobian."""
+    mech = I.make_mechanism(workload)
+    orc = oracle_mod.Oracle(mech)
+    y = _states(mech, 24, 44)
+    S = mech.n_species
+    b = orc.stiff_bound(y)
+    ratios = []
+    for i in range(y.shape[1]):
+        assert b[i] == orc.stiff_bound(y[:, i])
+        J = orc.jacobian(y[:, i])[:S, :S]
+        rho = np.abs(np.linalg.eigvals(J)).max()
+        assert b[i] >= rho * (1 - 1e-5), (i, b[i], rho)
+        ratios.append(b[i] / rho)
+    print(f"{workload}: bound / spectral radius in [{min(ratios):.2f}, {max(ratios):.2f}]")
