@@ -1,22 +1,28 @@
-"""Benchmark: plain FP64 MRI fast-stage throughput on one MI355X.
+"""Benchmark: FP64 plain MRI fast stages against the learned surrogate with FP64
+fallback at 1e-4 relative stage error, on one MI355X.
 
-Workload (one bench step = one explicit MRI-GARK slow step over the batch):
-64^3 = 262,144 cells of smooth periodic synthetic fields, 21 species / 84
+Headline (one bench step = one explicit MRI-GARK slow step over the batch):
+128^3 = 2,097,152 cells of smooth periodic synthetic fields, 21 species / 84
 reversible reactions, MIS-KW3 coupling table (3 fast stages per slow step),
-classic RK4 with 50 substeps per stage, H = 1e-7 s, advection-diffusion slow
-RHS.  The default K = 10 steps is the workload's 10 slow steps.  Inputs are
-resident in HBM before the timed region.
+H = 1e-7 s, advection-diffusion slow RHS; every fast stage taken by the gated
+surrogate stage: coarse FP64 RK4 stage (4 and 2 substeps), BF16 MFMA network
+correction, residual check at 1e-4, plain FP64 RK4 with 50 substeps for every
+rejected cell.  The same K slow steps with the plain FP64 stage (RK4, 50
+substeps) run in the same process for the comparison the metric names.  The
+network is trained first (untimed) with libmri's kernels on stage data of the
+64^3 workload.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line: value = cell fast-stage solves per second (cell-stages/s),
-plus the fast-stage kernel's roofline figures (kernel time from hipEvents around
-every fast-stage launch inside the timed region) and the CPU oracle timed on a
-bounded sample of the same workload.  Further legs, each in its own JSON object:
-the 128^3 large mechanism (53 species / 325 reactions), the batched uneven
-reactor sets (adaptive, persistent work queue) and the learned surrogate
-(training on the GPU, then the gated stage against the plain FP64 stage).
+Prints one JSON line: value = cell fast-stage solves per second (cell-stages/s)
+of the surrogate + fallback path, plus its dominant kernel's roofline (the
+fixed-step RK4 kernel: kernel time from libmri's HIP events on the launch
+stream around every fast-stage launch inside the timed region, FP64 flops from
+the algorithmic count and from rocprof counters) and the oracle timed on a
+bounded sample.  Further objects: the accuracy of the surrogate on every cell
+of the first slow step, the plain legs (128^3 and 64^3), the 53-species large
+mechanism, the batched uneven reactor sets.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-large] [--no-batch] [--no-surrogate]
+                    [--no-large] [--no-batch] [--no-plain64]
 """
 from __future__ import annotations
 
@@ -68,16 +74,29 @@ def flops_per_zv_attempt(S: int, R: int) -> int:
 
 
 def load_counters(workload: str, code_hash: str):
-    """rocprofv3 counter figures per launch (HBM bytes, FP64 counter flops) for
-    the kernel whose code object hashes to code_hash, or None when the compiled
-    kernel changed since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", "fast_stage_traffic.json")
+    """rocprofv3 counter figures per launch (HBM bytes, FP64 counter flops) of the
+    kernel whose machine code hashes to code_hash on the named workload, or None
+    when the compiled kernel changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "kernel_counters.json")
     if not os.path.exists(p):
         return None
-    d = json.load(open(p))
-    if d.get("kernel_code_hash") != code_hash or d.get("workload") != workload:
+    for d in json.load(open(p)).get("entries", []):
+        if d.get("kernel_code_hash") == code_hash and d.get("workload") == workload:
+            return d
+    return None
+
+
+def counter_flops_per_unit(code_hash: str):
+    """FP64 flops per unit of work (cell-substep of a fixed-step kernel, attempted
+    cell-step of the batched kernel) that the rocprof counters measured for the
+    kernel with this machine code, whatever the launch size, or None."""
+    p = os.path.join(ROOT, "profiles", "kernel_counters.json")
+    if not os.path.exists(p):
         return None
-    return d
+    for d in json.load(open(p)).get("entries", []):
+        if d.get("kernel_code_hash") == code_hash and d.get("counter_fp64_flops_per_unit"):
+            return d["counter_fp64_flops_per_unit"]
+    return None
 
 
 def _cpu_model():
@@ -164,9 +183,34 @@ def batch_leg(torch, mri, I, repeats=3):
                               flops_per_attempted_step=fpa))
 
 
+def fp64_roofline(achieved_alg, avg_launch_s, counter_flops=None, traffic=None):
+    """FP64 vector roofline of a fixed-step kernel: frac from the FP64 flops the
+    rocprof counters count per launch (64 x (ADD + MUL + TRANS + 2 FMA) wave
+    instructions) when they were taken for this machine code, else from the
+    algorithmic count; the algorithmic fraction (F_exp flops per exponential)
+    is kept beside it."""
+    alg = dict(achieved=round(achieved_alg, 3), frac=round(achieved_alg / PEAK_FP64_TFLOPS, 4),
+               f_exp=F_EXP, f_log=F_LOG, f_div=F_DIV)
+    if counter_flops:
+        ach = counter_flops / avg_launch_s / 1e12
+        return dict(bound="alu", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / PEAK_FP64_TFLOPS, 4), frac_source="rocprof FP64 counters",
+                    traffic=traffic, algorithmic=alg)
+    return dict(bound="alu", achieved=alg["achieved"], peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                frac=alg["frac"], frac_source="algorithmic count (no counters for this code)",
+                traffic=traffic, algorithmic=alg)
+
+
+def counter_key(cfg, mech):
+    return (f"mri_fast_stage rk4 {cfg.grid[0]}^3 cells S={mech.n_species} "
+            f"R={mech.n_reactions} n_sub={cfg.n_sub}")
+
+
 DESCRIPTIONS = {
     "field64_s21": "plain FP64 explicit MRI-GARK (MIS-KW3) slow steps, 64^3 cells, 21 species / 84 "
        "reactions, RK4 50 substeps/stage, H = 1e-7 s, advection-diffusion slow RHS",
+    "field128_s21": "plain FP64 explicit MRI-GARK (MIS-KW3) slow steps, 128^3 cells, 21 species / "
+       "84 reactions, RK4 50 substeps/stage, H = 1e-7 s, advection-diffusion slow RHS",
     "field128_s53": "plain FP64 explicit MRI-GARK (MIS-KW3) slow step, 128^3 cells, 53 species / 325 "
        "reactions, RK4 100 substeps/stage, H = 5e-8 s, advection-diffusion slow RHS",
 }
@@ -228,20 +272,15 @@ def plain_leg(torch, mri, I, workload, steps, warmup, block, kernel_name):
     fps = flops_per_substep(mech.n_species, mech.n_reactions, n_poly=1)
     avg_launch_s = fast_ms * 1e-3 / max(1, n_launch)
     achieved = fps * cfg.n_sub * N / avg_launch_s / 1e12
-    traffic_key = (f"mri_fast_stage rk4 {cfg.grid[0]}^3 cells S={mech.n_species} "
-                   f"R={mech.n_reactions} n_sub={cfg.n_sub}")
-    ctr = None
+    ctr, per_unit = None, None
     if kernel != mri.KERNEL_GENERIC:
-        ctr = load_counters(traffic_key, m.code_hash(mri.FAST_RK4, tb.n_gamma, block or 128))
-    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_FP64_TFLOPS, 4),
-                traffic=ctr.get("hbm_bytes_per_launch") if ctr else None,
-                # the same launch time against the FP64 instructions the counters
-                # saw (the algorithmic count charges 22 flops per exponential)
-                frac_counters=(round(ctr["counter_fp64_flops_per_launch"] / avg_launch_s / 1e12
-                                     / PEAK_FP64_TFLOPS, 4)
-                               if ctr and "counter_fp64_flops_per_launch" in ctr else None),
-                mcell_substep_per_s=round(N * cfg.n_sub / avg_launch_s / 1e6, 1),
+        h = m.code_hash(mri.FAST_RK4, tb.n_gamma, block or 128)
+        ctr = load_counters(counter_key(cfg, mech), h)
+        per_unit = counter_flops_per_unit(h)
+    roof = fp64_roofline(achieved_alg=achieved, avg_launch_s=avg_launch_s,
+                         counter_flops=per_unit * N * cfg.n_sub if per_unit else None,
+                         traffic=ctr.get("hbm_bytes_per_launch") if ctr else None)
+    roof.update(mcell_substep_per_s=round(N * cfg.n_sub / avg_launch_s / 1e6, 1),
                 kernel="mri_spec_main (RK4, specialized)" if kernel != mri.KERNEL_GENERIC
                 else "k_gen_rk4 (generic)",
                 flops_per_cell_substep=fps, avg_launch_ms=round(avg_launch_s * 1e3, 4))
@@ -251,42 +290,155 @@ def plain_leg(torch, mri, I, workload, steps, warmup, block, kernel_name):
                             flagged_cells=n_bad))
 
 
-def surrogate_leg(train_steps, n_samples):
-    """Learned surrogate: stage data from the 64^3 workload's plain runs, training
-    with libmri's BF16 MFMA kernels, then the gated stage (tolerance 1e-4) on the
-    first fast stage of the 128^3 workload against the plain FP64 stage."""
-    from paper_2211_03293_amd import inputs as I
+def train_surrogate(n_samples, train_steps, log):
+    """Stage data from the 64^3 workload's plain runs and training with libmri's
+    BF16 MFMA kernels (setup of the headline, not timed as a bench step)."""
     from paper_2211_03293_amd import surrogate as S
-
-    def log(msg):
-        print(msg, file=sys.stderr, flush=True)
-
     t0 = time.perf_counter()
     data = S.generate_stage_data(n_full=n_samples, log=log)
     res = S.train(data, steps=train_steps, batch=TRAIN_BATCH, log=log,
                   log_every=max(1, train_steps // 8))
     del data
-    ev = S.evaluate_stage(res["params"], res["stats"], workload=I.FIELD128, gate_tol=1e-4, log=log)
-    t_inf_s = ev["infer_ms"] * 1e-3
-    achieved = ev["cells"] * MLP_FLOPS / t_inf_s / 1e12
+    res["setup_seconds"] = time.perf_counter() - t0
+    return res
+
+
+def surrogate_steps(torch, mri, I, params, stats, steps, warmup, gate_tol=1e-4):
+    """K timed MRI slow steps of the 128^3 workload whose fast stages are gated
+    surrogate stages (W untimed before, from the same initial state); the slow
+    RHS and forcing assembly as in the plain path.  The residual check accepts
+    at half the stage tolerance.  Nothing synchronizes inside a step: the
+    fallback counts stay on the device until the timed region ends."""
+    from paper_2211_03293_amd import surrogate as S
+    cfg = I.WORKLOADS[I.FIELD128]
+    mech = I.make_mechanism(I.FIELD128)
+    tb = I.table_mis_kw3()
+    y_host = I.initial_state(I.FIELD128)
+    n, ld = y_host.shape
+    N = cfg.n_cells
+    m, t = mri.Mech(mech), mri.Table(tb)
+    m.specialize(128, load=True)
+    sg = mri.Surrogate(S.WIDTHS, params, stats)
+    coarse, fine = mri.fast_opts(n_sub=S.N_COARSE), mri.fast_opts(n_sub=cfg.n_sub)
+    y0 = torch.as_tensor(y_host, device="cuda")
+    del y_host
+    y = y0.clone()
+    F = torch.empty((tb.s - 1, n, ld), dtype=torch.float64, device="cuda")
+    rho = torch.empty((1, n, ld), dtype=torch.float64, device="cuda")
+    ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    status = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    n_fb = torch.zeros(max(steps, warmup) * (tb.s - 1), dtype=torch.int32, device="cuda")
+    params_ad = mri.advdiff_params(cfg.grid, n)
+    uptr = mri.C.cast(mri.C.pointer(params_ad), mri.C.c_void_p).value
+
+    def step(k):
+        sp = torch.cuda.current_stream().cuda_stream
+        for i in range(1, tb.s):
+            rc = mri.lib.mri_advdiff_slow_rhs(k * cfg.H + tb.c[i - 1] * cfg.H, y.data_ptr(),
+                                              F[i - 1].data_ptr(), N, ld, uptr, sp)
+            assert rc == 0
+            mri.mri_forcing_assemble(t, i, n, ld, F, rho)
+            L = float((tb.c[i] - tb.c[i - 1]) * cfg.H)
+            j = k * (tb.s - 1) + i - 1
+            sg.stage(m, coarse, fine, 0.5 * gate_tol, N, ld, y, y, 1, rho, L, ws, None, None,
+                     status, n_fb[j:j + 1])
+
+    print(f"# surrogate steps: warmup {warmup}", file=sys.stderr, flush=True)
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    y.copy_(y0)
+    n_fb.zero_()
+    torch.cuda.synchronize()
+    mri.timing_enable(True)
+    mri.timing_read(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    wall_ms = e0.elapsed_time(e1)
+    fast_ms, n_launch = mri.timing_read(reset=True)
+    mri.timing_enable(False)
+    fb = n_fb[:steps * (tb.s - 1)].cpu().numpy()
+    n_bad = mri.mri_status_count(status, N)
+    print(f"# surrogate steps: timed {steps} steps: {wall_ms:.1f} ms, RK4 kernels {fast_ms:.1f} ms "
+          f"over {n_launch} launches, fallback cells per stage {fb.tolist()}", file=sys.stderr,
+          flush=True)
+    stages = steps * (tb.s - 1)
+    value = N * stages / (wall_ms * 1e-3)
+    # the dominant kernel: the fixed-step RK4 kernel of the coarse stages (n and
+    # n/2 substeps over every cell) and of the fallback (n_sub over the rejected
+    # cells); algorithmic flops per cell-substep as for the plain path
+    fps = flops_per_substep(mech.n_species, mech.n_reactions, n_poly=1)
+    cell_substeps = stages * N * (S.N_COARSE + S.N_COARSE // 2) + int(fb.sum()) * cfg.n_sub
+    fast_s = fast_ms * 1e-3
+    per_unit = counter_flops_per_unit(m.code_hash(mri.FAST_RK4, tb.n_gamma, 128))
+    roof = fp64_roofline(achieved_alg=fps * cell_substeps / fast_s / 1e12,
+                         avg_launch_s=fast_s / max(1, n_launch),
+                         counter_flops=(per_unit * cell_substeps / max(1, n_launch)
+                                        if per_unit else None))
+    roof.update(kernel="mri_spec_main (RK4, specialized): coarse, half and fallback stages",
+                launches=n_launch, kernel_ms=round(fast_ms, 3),
+                share_of_step_time=round(fast_ms / wall_ms, 3), flops_per_cell_substep=fps,
+                cell_substeps=cell_substeps)
+    return dict(value=round(value, 1), ms_per_step=round(wall_ms / steps, 3), roofline=roof,
+                fallback_cells=int(fb.sum()), fallback_frac=float(fb.sum()) / (N * stages),
+                flagged_cells=n_bad, cells=N, stages_per_step=tb.s - 1)
+
+
+def surrogate_eval(params, stats, log, gate_tol=1e-4):
+    """Accuracy on every cell of the three fast stages of the first slow step
+    against the plain FP64 stage, the no-network comparison, the cheapest plain
+    substep count within the tolerance, and the fused inference's roofline."""
+    from paper_2211_03293_amd import inputs as I
+    from paper_2211_03293_amd import surrogate as S
+    ev = S.evaluate(params, stats, workload=I.FIELD128, gate_tol=gate_tol, log=log)
+    t_inf_s = ev["infer_ms"] * 1e-3 / ev["stages"]
+    n = ev["cells"] // ev["stages"]
+    achieved = n * MLP_FLOPS / t_inf_s / 1e12
     ev.update(
-        workload="128^3 cells, 21 species / 84 reactions, first MIS-KW3 fast stage "
-                 "(L = H/3, H = 1e-7 s, advection-diffusion forcing); MLP 89-256-256-256-22 "
-                 "BF16/FP32 trained on the 64^3 workload's stages; fallback plain RK4 "
-                 "50 substeps",
-        value=round(ev["cells"] / (ev["surrogate_stage_ms"] * 1e-3), 1),
-        unit="cell-stages/s", plain_value=round(ev["cells"] / (ev["plain_ms"] * 1e-3), 1),
-        training=dict(samples=int(3 * n_samples), steps=train_steps, batch=TRAIN_BATCH,
-                      seconds=round(res["train_seconds"], 1),
-                      final_val_mse=res["history"][-1][2] if res["history"] else None),
-        inferences_per_s=round(ev["cells"] / t_inf_s, 1),
+        workload="every cell of the three MIS-KW3 fast stages of the 128^3 workload's first "
+                 "slow step, against the plain FP64 RK4 stage (50 substeps)",
+        inferences_per_s=round(n / t_inf_s, 1),
         roofline=dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_BF16_TFLOPS,
                       unit="TFLOP/s", frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
                       kernel="k_infer (fused 4-layer BF16 MFMA)", flops_per_inference=MLP_FLOPS,
-                      frac_counters=round(ev["cells"] * MLP_FLOPS_EXECUTED / t_inf_s / 1e12
-                                          / PEAK_BF16_TFLOPS, 4)),
-        seconds_total=round(time.perf_counter() - t0, 1))
+                      frac_executed_mfma=round(n * MLP_FLOPS_EXECUTED / t_inf_s / 1e12
+                                               / PEAK_BF16_TFLOPS, 4)))
     return ev
+
+
+def cpu_baseline_surrogate(params, stats, n_sample=8192):
+    """The oracle's gated surrogate stage (RK4 at 4 and 2 substeps, the network
+    in its bfloat16-emulating mode, the residual check, plain RK4 with 50
+    substeps for rejected cells) on evenly spaced cells of the first fast stage
+    of the 128^3 workload, with all the threads the job may use."""
+    from oracle import oracle as O
+    from paper_2211_03293_amd import inputs as I
+    from paper_2211_03293_amd import surrogate as S
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(threads)
+    cfg, tb = I.WORKLOADS[I.FIELD128], I.table_mis_kw3()
+    y_host = I.initial_state(I.FIELD128)
+    idx = np.linspace(0, cfg.n_cells - 1, n_sample).astype(np.int64)
+    rho = O.advdiff(y_host, cfg.grid)[None][:, :, idx] * (tb.gamma[0][1][0] / tb.c[1])
+    ys = np.ascontiguousarray(y_host[:, idx])
+    del y_host
+    orc = O.Oracle(I.make_mechanism(I.FIELD128))
+    L = float(tb.c[1] * cfg.H)
+    t0 = time.perf_counter()
+    _, acc, _, _ = O.sur_stage(orc, S.WIDTHS, np.asarray(params, np.float64), stats, ys,
+                               np.ascontiguousarray(rho), L, S.N_COARSE, cfg.n_sub, 1e-4)
+    dt = time.perf_counter() - t0
+    return dict(value=n_sample / dt, unit="cell-stages/s", cores=O.num_threads(), kind="oracle",
+                sample=f"{n_sample} evenly spaced cells of the 128^3 field, first MIS-KW3 fast "
+                       f"stage, the oracle's gated surrogate stage ({int((~acc).sum())} plain "
+                       f"fallbacks); {dt:.1f} s",
+                host=dict(cpu=_cpu_model(), nproc=os.cpu_count()))
 
 
 def main():
@@ -298,13 +450,13 @@ def main():
     ap.add_argument("--kernel", choices=["auto", "specialized", "generic"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-set leg")
-    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-plain64", action="store_true", help="skip the 64^3 plain leg")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 128^3 large-mechanism leg (53 species / 325 reactions)")
     ap.add_argument("--surrogate-steps", type=int, default=40000,
-                    help="training steps of the surrogate leg (batch 8192)")
+                    help="training steps of the surrogate (batch 8192)")
     ap.add_argument("--surrogate-samples", type=int, default=2_000_000,
-                    help="full-stage training samples (plus twice as many half-stage ones)")
+                    help="stage samples (start state, forcing, coarse and plain stage results)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -329,13 +481,49 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes_per_dispatch=2 ** 30, dispatches=3)), flush=True)
         return
-    plain = plain_leg(torch, mri, I, I.FIELD64, args.steps, args.warmup, args.block, args.kernel)
-    out = dict(metric=METRIC, value=plain["value"], unit="cell-stages/s", n_gpus=1,
-               steps=args.steps, warmup=args.warmup, ms_per_step=plain["ms_per_step"],
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
-               data="synthetic", config=plain["config"], roofline=plain["roofline"])
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    log("# surrogate training (setup)")
+    res = train_surrogate(args.surrogate_samples, args.surrogate_steps, log)
+    sur = surrogate_steps(torch, mri, I, res["params"], res["stats"], args.steps, args.warmup)
+    log("# plain steps on the same workload")
+    plain = plain_leg(torch, mri, I, I.FIELD128, args.steps, args.warmup, args.block,
+                      args.kernel)
+    out = dict(metric=METRIC, value=sur["value"], unit="cell-stages/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=sur["ms_per_step"],
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64+bf16",
+               data="synthetic",
+               config=dict(workload="surrogate + FP64 fallback at 1e-4: explicit MRI-GARK "
+                                    "(MIS-KW3) slow steps, 128^3 cells, 21 species / 84 reactions, "
+                                    "H = 1e-7 s, advection-diffusion slow RHS; each fast stage: "
+                                    "coarse FP64 RK4 (4 and 2 substeps), BF16 MLP correction "
+                                    "89-256-256-256-22, residual check 1e-4, FP64 RK4 50 substeps "
+                                    "for rejected cells",
+                           cells=sur["cells"], stages_per_step=sur["stages_per_step"],
+                           stage_tol=1e-4, check_tol=5e-5),
+               plain_value=plain["value"], plain_ms_per_step=plain["ms_per_step"],
+               speedup_vs_plain=round(sur["value"] / plain["value"], 3),
+               fallback_frac=sur["fallback_frac"], flagged_cells=sur["flagged_cells"],
+               roofline=sur["roofline"])
+    log("# surrogate accuracy (every cell of the first slow step)")
+    ev = surrogate_eval(res["params"], res["stats"], log)
+    ev["training"] = dict(samples=int(args.surrogate_samples), steps=args.surrogate_steps,
+                          batch=TRAIN_BATCH, seconds=round(res["train_seconds"], 1),
+                          setup_seconds=round(res["setup_seconds"], 1),
+                          final_val_mse=res["history"][-1][2] if res["history"] else None)
+    out["surrogate"] = ev
+    out["plain_128cube"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
+                                roofline=plain["roofline"], config=plain["config"])
+    if not args.no_plain64:
+        log("# 64^3 plain leg")
+        p64 = plain_leg(torch, mri, I, I.FIELD64, args.steps, args.warmup, args.block,
+                        args.kernel)
+        out["plain_64cube"] = dict(value=p64["value"], ms_per_step=p64["ms_per_step"],
+                                   roofline=p64["roofline"], config=p64["config"])
     if not args.no_large:
-        print("# large-mechanism leg", file=sys.stderr, flush=True)
+        log("# large-mechanism leg")
         big = plain_leg(torch, mri, I, I.LARGE128, 1, 1, args.block, args.kernel)
         large = I.WORKLOADS[I.LARGE128]
         rhs_rate = 4 * large.n_sub * big["value"]          # 4 RHS per RK4 substep
@@ -353,19 +541,18 @@ def main():
                           "synthetic mechanism)",
                 note="other hardware and another integrator; context, not the target"))
     if not args.no_batch:
-        print("# batched uneven-set leg", file=sys.stderr, flush=True)
+        log("# batched uneven-set leg")
         out["batch"] = batch_leg(torch, mri, I)
-    if not args.no_surrogate:
-        print("# surrogate leg", file=sys.stderr, flush=True)
-        out["surrogate"] = surrogate_leg(args.surrogate_steps, args.surrogate_samples)
     if not args.no_cpu_baseline:
-        # forcing of the first stage of one slow step, from the oracle's own slow RHS
+        log("# CPU baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline_surrogate(res["params"], res["stats"])
         from oracle import oracle as O
         cfg, tb = I.WORKLOADS[I.FIELD64], I.table_mis_kw3()
         y_host = I.initial_state(I.FIELD64)
         rho = O.advdiff(y_host, cfg.grid)[None]
         Ls = [float((tb.c[i] - tb.c[i - 1]) * cfg.H) for i in range(1, tb.s)]
-        out["cpu_baseline"] = cpu_baseline(I.make_mechanism(I.FIELD64), y_host, rho, Ls, cfg.n_sub)
+        out["cpu_baseline_plain"] = cpu_baseline(I.make_mechanism(I.FIELD64), y_host, rho, Ls,
+                                                 cfg.n_sub, n_sample=65536, n_sample_1core=4096)
     print(json.dumps(out), flush=True)
 
 

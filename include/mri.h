@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MRI_ABI_VERSION 1
+#define MRI_ABI_VERSION 2
 
 typedef enum {
     MRI_OK = 0,
@@ -64,6 +64,8 @@ typedef enum {
 #define MRI_CELL_MAXSTEPS 2    /* adaptive: accepted-step cap reached           */
 #define MRI_CELL_TRANGE 4      /* T left [200, 6000] K                          */
 #define MRI_CELL_NEARTIE 8     /* adaptive: an accept/reject had |err - 1| < 1e-12 */
+#define MRI_CELL_STIFF 16      /* stiffness monitor: h B above the limit at a    */
+                               /* stage start (stability not guaranteed)         */
 
 typedef void *mri_stream_t;     /* hipStream_t */
 
@@ -182,6 +184,10 @@ typedef struct {
     int max_steps;              /* Zonneveld: accepted-step cap per cell-stage    */
     int kernel;                 /* MRI_KERNEL_*                                   */
     int block_size;             /* threads per block, 0 = tuned default           */
+    double stiff_limit;         /* fixed-step methods: > 0 runs the stiffness     */
+                                /* monitor at the stage start state and sets      */
+                                /* MRI_CELL_STIFF where h B > stiff_limit (B: see */
+                                /* mri_stiffness_check); 0 = off                  */
 } mri_fast_opts;
 
 /* ------------------------------------------------------------------------- */
@@ -317,6 +323,20 @@ mri_status mri_selftest_exp2(const double *x, double *y, int n, mri_stream_t str
    |x| < 1022). */
 mri_status mri_selftest_exp2_t256(const double *x, double *y, int n, mri_stream_t stream);
 
+/* Stiffness monitor (the stability statements of Sec. 5.2 compare h times the
+   fastest chemical rate with a method's stability interval, 2.785 on the
+   negative real axis for RK4).  For the chemistry mechanism m and the states
+   y (device [n][ld]): B = max_k sum_j |nu_kj| (kf_j (C_a + C_b) + kr_j (C_c +
+   C_d)), an upper bound (Gershgorin, in concentration variables, which have
+   the same eigenvalues) of the spectral radius of the species block of the
+   Jacobian of f^F at fixed T, in 1/s.  bound_out (nullable, device FP64
+   [n_cells]) receives B; status (nullable, device int32 [n_cells]) gets
+   MRI_CELL_STIFF OR-ed in where h B > limit.  MRI_EUNSUPPORTED for linear
+   mechanisms. */
+mri_status mri_stiffness_check(const mri_mech *m, int n_cells, int ld, const double *y, double h,
+                               double limit, double *bound_out, int32_t *status,
+                               mri_stream_t stream);
+
 /* Counts cells with (status & mask) != 0; synchronizes the stream.  Uses one
    device counter per GPU, allocated on the first call there and kept until the
    process ends; concurrent calls take turns. */
@@ -356,10 +376,14 @@ mri_status mri_batch_plan_create(const mri_mech *m, const mri_fast_opts *opts, i
 /* y_in/y_out device [n][ld], distinct (the first run times tile candidates on
    a prefix of the sets, writing y_out); rho_poly device [n_poly][n][ld] or
    NULL; L_per_set host [n_sets], copied to the device on the stream;
-   status_out/steps_out optional device [n_total]. */
+   status_out/steps_out/rejects_out optional device [n_total]: status bits,
+   accepted and rejected steps of each cell (written once, when its lane
+   finishes it; with mri_batch_lane_stats, sum(accepted + rejected) equals the
+   useful lane-steps exactly when every cell was integrated by one lane). */
 mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, double *y_out, int64_t ld,
                          int n_poly, const double *rho_poly, const double *L_per_set,
-                         int32_t *status_out, int32_t *steps_out, mri_stream_t stream);
+                         int32_t *status_out, int32_t *steps_out, int32_t *rejects_out,
+                         mri_stream_t stream);
 /* Tile chosen by the autotuner (threads per block, persistent blocks); valid
    after the first run. */
 mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_blocks);

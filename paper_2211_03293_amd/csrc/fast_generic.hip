@@ -129,11 +129,12 @@ template <int NMAX, int NP>
 __global__ void __launch_bounds__(256)
     k_gen_rk4(GenMech gm, ErkCoef e, int n_cells, int ld, const double *__restrict__ yin,
               double *yout, const double *__restrict__ rho, double L, int n_sub, int *status,
-              int *steps, int accumulate)
+              int *steps, int accumulate, const unsigned int *n_live)
 {
     const LdsView m = stage_mechanism(gm);
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= n_cells) return;     // no barrier below this point
+    // no barrier below this point
+    if (cell >= n_cells || (n_live && (unsigned int)cell >= *n_live)) return;
     const int S = gm.S, R = gm.R, lane = threadIdx.x & 63;
     const size_t plane = (size_t)(S + 1) * ld;
     const size_t offT = (size_t)S * ld + cell;
@@ -194,12 +195,13 @@ template <int NMAX, int NP>
 __global__ void __launch_bounds__(256)
     k_gen_erk(GenMech gm, ErkFull e, int n_cells, int ld, const double *__restrict__ yin,
               double *yout, const double *__restrict__ rho, double L, int n_sub, int *status,
-              int *steps, int accumulate)
+              int *steps, int accumulate, const unsigned int *n_live)
 {
     constexpr int NK = ERK_SMAX - 1;   // derivatives a later stage can read
     const LdsView m = stage_mechanism(gm);
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= n_cells) return;     // no barrier below this point
+    // no barrier below this point
+    if (cell >= n_cells || (n_live && (unsigned int)cell >= *n_live)) return;
     const int S = gm.S, R = gm.R, lane = threadIdx.x & 63;
     const size_t plane = (size_t)(S + 1) * ld;
     const size_t offT = (size_t)S * ld + cell;
@@ -350,11 +352,11 @@ template <int NMAX, int NP>
 __global__ void __launch_bounds__(256)
     k_gen_zv(GenMech gm, int n_cells, int ld, const double *__restrict__ yin, double *yout,
              const double *__restrict__ rho, double L, ZvOpts o, int *status, int *steps,
-             int accumulate)
+             int accumulate, const unsigned int *n_live)
 {
     const LdsView m = stage_mechanism(gm);
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= n_cells) return;
+    if (cell >= n_cells || (n_live && (unsigned int)cell >= *n_live)) return;
     const int S = gm.S, lane = threadIdx.x & 63;
     const size_t plane = (size_t)(S + 1) * ld;
     const size_t offT = (size_t)S * ld + cell;
@@ -535,6 +537,56 @@ __global__ void __launch_bounds__(256)
     if (steps) steps[cell] = accumulate ? (steps[cell] + n_sub) : n_sub;
 }
 
+// Stiffness monitor: B = max_k sum_j |nu_kj| w_j with w_j = kf (C_a + C_b) +
+// kr (C_c + C_d), an upper bound of the spectral radius of the species block of
+// the chemistry Jacobian at fixed T (Gershgorin in concentration variables, a
+// similarity transform of the mass-fraction variables).  With E_k = e^(g_k/RT)
+// and Z_k = C_k E_k: kf = kappa E_a E_b and kr = kappa E_c E_d, so
+// w_j = kappa (Z_a E_b + Z_b E_a + Z_c E_d + Z_d E_c).  Per lane three LDS
+// columns (Z, E, B) after the block's copy of the mechanism.
+__global__ void __launch_bounds__(64)
+    k_gen_stiff(GenMech gm, int n_cells, int ld, const double *__restrict__ y, double h,
+                double limit, double *__restrict__ bound, int *__restrict__ status,
+                int *__restrict__ steps, int accumulate, int flag)
+{
+    const LdsView m = stage_mechanism(gm);
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= n_cells) return;     // no barrier below this point
+    const int S = gm.S, R = gm.R, lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    double *Z = m.Z, *E = m.Wd;
+    // the third column set follows the two of every wave
+    double *B = m.Z + (size_t)(n_waves - wave) * 2 * S * 64 + (size_t)wave * S * 64;
+    const double T = y[(size_t)S * ld + cell];
+    const double invT = 1.0 / T;
+    const double l2T = log2(T);
+    for (int k = 0; k < S; ++k) {
+        const double *p = m.sp + k * GEN_SP_STRIDE;
+        const double e = mri_exp2(fma(p[2], invT, p[3]));
+        E[k * 64 + lane] = e;
+        Z[k * 64 + lane] = (y[(size_t)k * ld + cell] * p[0]) * e;
+        B[k * 64 + lane] = 0.0;
+    }
+    for (int j = 0; j < R; ++j) {
+        const double lna = m.rx[3 * j], be = m.rx[3 * j + 1], th = m.rx[3 * j + 2];
+        const uint32_t id = m.rxi[j];
+        const int a = (id & 255u) * 64 + lane, b = ((id >> 8) & 255u) * 64 + lane;
+        const int c = ((id >> 16) & 255u) * 64 + lane, d = (id >> 24) * 64 + lane;
+        const double kap = mri_exp2(fma(-th, invT, fma(be, l2T, lna)));
+        const double w = kap * (fma(Z[a], E[b], Z[b] * E[a]) + fma(Z[c], E[d], Z[d] * E[c]));
+        B[a] += w;
+        B[b] += w;
+        B[c] += w;
+        B[d] += w;
+    }
+    double bmax = 0.0;
+    for (int k = 0; k < S; ++k) bmax = fmax(bmax, B[k * 64 + lane]);
+    if (bound) bound[cell] = bmax;
+    const int st = (h * bmax <= limit) ? 0 : flag;
+    if (status) status[cell] = accumulate ? (status[cell] | st) : st;
+    if (steps && !accumulate) steps[cell] = 0;
+}
+
 }  // namespace
 
 size_t gen_lds_bytes(int S, int R, int block)
@@ -561,32 +613,33 @@ size_t gen_lds_bytes(int S, int R, int block)
 hipError_t launch_gen_rk4(const GenMech &gm, const ErkCoef &e, int block, int n_cells, int ld,
                           const double *yin, double *yout, int n_poly, const double *rho,
                           double L, int n_sub, int *status, int *steps, int accumulate,
-                          hipStream_t s)
+                          const unsigned int *n_live, hipStream_t s)
 {
     const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
     if (gm.S <= GEN_NMAX_SMALL) {
         GEN_DISPATCH_NP(k_gen_rk4, GEN_NMAX_SMALL, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
-                        status, steps, accumulate)
+                        status, steps, accumulate, n_live)
     } else {
         GEN_DISPATCH_NP(k_gen_rk4, GEN_NMAX_LARGE, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
-                        status, steps, accumulate)
+                        status, steps, accumulate, n_live)
     }
     return hipGetLastError();
 }
 
 hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, const double *yin,
                          double *yout, int n_poly, const double *rho, double L, ZvOpts o,
-                         int *status, int *steps, int accumulate, hipStream_t s)
+                         int *status, int *steps, int accumulate, const unsigned int *n_live,
+                         hipStream_t s)
 {
     const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
     if (gm.S <= GEN_NMAX_SMALL) {
         GEN_DISPATCH_NP(k_gen_zv, GEN_NMAX_SMALL, gm, n_cells, ld, yin, yout, rho, L, o, status,
-                        steps, accumulate)
+                        steps, accumulate, n_live)
     } else {
         GEN_DISPATCH_NP(k_gen_zv, GEN_NMAX_LARGE, gm, n_cells, ld, yin, yout, rho, L, o, status,
-                        steps, accumulate)
+                        steps, accumulate, n_live)
     }
     return hipGetLastError();
 }
@@ -594,13 +647,13 @@ hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, cons
 hipError_t launch_gen_erk(const GenMech &gm, const ErkFull &e, int block, int n_cells, int ld,
                           const double *yin, double *yout, int n_poly, const double *rho,
                           double L, int n_sub, int *status, int *steps, int accumulate,
-                          hipStream_t s)
+                          const unsigned int *n_live, hipStream_t s)
 {
     const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
     if (gm.S > GEN_NMAX_SMALL || e.s < 1 || e.s > ERK_SMAX) return hipErrorInvalidValue;
     const size_t lds = gen_lds_bytes(gm.S, gm.R, block);
     GEN_DISPATCH_NP(k_gen_erk, GEN_NMAX_SMALL, gm, e, n_cells, ld, yin, yout, rho, L, n_sub,
-                    status, steps, accumulate)
+                    status, steps, accumulate, n_live)
     return hipGetLastError();
 }
 
@@ -666,5 +719,17 @@ hipError_t launch_lin_rk4(int n, const double *A, const ErkCoef &e, int n_cells,
                            rho, L, n_sub, status, steps, accumulate);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_stiff(const GenMech &gm, int n_cells, int ld, const double *y, double h,
+                            double limit, double *bound, int *status, int *steps, int accumulate,
+                            int flag, hipStream_t s)
+{
+    const int block = 64;
+    const dim3 grid((unsigned)(((long long)n_cells + block - 1) / block));
+    const size_t lds = gen_lds_bytes(gm.S, gm.R, block) + sizeof(double) * gm.S * 64;
+    hipLaunchKernelGGL(k_gen_stiff, grid, dim3(block), lds, s, gm, n_cells, ld, y, h, limit,
+                       bound, status, steps, accumulate, flag);
     return hipGetLastError();
 }

@@ -43,19 +43,24 @@ hipError_t mlp_adam(long long n, float *w, const float *g, float *m, float *v, u
                     float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t mlp_to_bf16(long long n, const float *x, uint16_t *y, hipStream_t s);
 hipError_t mlp_featurize(int B, const int *idx, long long ld, const double *Y0, int n_poly,
-                         const double *RHO, const double *Lv, const double *Y1,
-                         const double *stats, uint16_t *X, float *T, hipStream_t s);
+                         const double *RHO, const double *Lv, const double *Yb,
+                         const double *Y1, const double *stats, uint16_t *X, float *T,
+                         hipStream_t s);
 hipError_t mlp_stats(long long N, long long ld, const double *Y0, int n_poly, const double *RHO,
-                     const double *Lv, const double *Y1, double *part, int n_blocks,
-                     double *stats, hipStream_t s);
-hipError_t mlp_infer(const double *yin, double *yout, const double *rho, const uint16_t *const *W,
-                     const float *const *b, const double *stats, long long ld, int n_cells,
-                     int n_poly, double L, int half, hipStream_t s);
+                     const double *Lv, const double *Yb, const double *Y1, double *part,
+                     int n_blocks, double *stats, hipStream_t s);
+hipError_t mlp_infer(const double *yin, const double *base, double *yout, const double *rho,
+                     const uint16_t *const *W, const float *const *b, const double *stats,
+                     long long ld, int n_cells, int n_poly, double L, hipStream_t s);
 hipError_t mlp_gate(int n_cells, long long ld, const double *yin, const double *rho, int n_poly,
-                    double L, const double *full, const double *dbl, double tol, double *yout,
-                    int *used_fallback, int *list, unsigned int *count, float *dmax,
-                    hipStream_t s);
+                    double L, const double *vc, const double *vh, const double *vn,
+                    const int *status_c, double rich, double tol, double *yout, int *used_fallback,
+                    double *gval, int *status, int *list, unsigned int *count, hipStream_t s);
 hipError_t mlp_gather(int n_planes, const unsigned int *count, const int *list, long long n_max,
                       const double *src, long long lds, double *dst, long long ldd, hipStream_t s);
 hipError_t mlp_scatter(int n_planes, const unsigned int *count, const int *list, long long n_max,
                        const double *src, long long lds, double *dst, long long ldd, hipStream_t s);
+// *p = 0 by a one-thread kernel (no memset node when the stream is captured).
+hipError_t mlp_zero_u32(unsigned int *p, hipStream_t s);
+hipError_t mlp_scatter_i32(const unsigned int *count, const int *list, long long n_max,
+                           const int *src, int *dst, hipStream_t s);

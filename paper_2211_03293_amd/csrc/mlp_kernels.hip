@@ -23,6 +23,20 @@ __device__ __forceinline__ uint16_t f2bf(float x)
     return __builtin_bit_cast(uint16_t, b);
 }
 
+// The features are computed in FP64, rounded to FP32 and then to bfloat16
+// (nearest even at each step).  The second rounding is done on the FP32 bit
+// pattern: a plain conversion of an FP32 value that was just narrowed from
+// FP64 may be folded by the compiler into one FP64 -> bfloat16 rounding, which
+// differs from the two-step rounding where the FP64 value lies within half an
+// FP32 ulp of a bfloat16 midpoint.
+__device__ __forceinline__ uint16_t f2bf_bits(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 __device__ __forceinline__ float bf2f(uint16_t u)
 {
     return __builtin_bit_cast(float, (uint32_t)u << 16);
@@ -199,42 +213,31 @@ __global__ void __launch_bounds__(256)
 // Raw feature k of one sample read straight from SoA arrays (no private
 // arrays, so per-lane feature indices cost no scratch memory):
 //   k < NS: log max(Y_k, 1e-30); k = NS: T; then the forcing coefficient p of
-//   component c for k = NS + 1 + p NC + c, transformed for half stages; last:
-//   log L (L is the stage length of this inference).
-// half: 0 full stage; 1 first half, r(tau'/2): rho_p / 2^p; 2 second half,
-// r((1 + tau')/2): sum_(q >= p) C(q, p) 2^-q rho_q.
+//   component c for k = NS + 1 + p NC + c (zero for p >= n_poly); last: log L
+//   (L is the stage length).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double raw_feature(int k, const double *__restrict__ y,
                                               const double *__restrict__ rho, long long ld,
-                                              long long s, int n_poly, int half, double L)
+                                              long long s, int n_poly, double L)
 {
-    // logarithms in FP32: every feature is rounded to bfloat16 afterwards
+    // species logarithms in FP32: every feature is rounded to bfloat16 afterwards
     if (k < MLP_NS) return (double)__logf((float)fmax(y[k * ld + s], 1e-30));
     if (k == MLP_NS) return y[MLP_NS * ld + s];
     if (k < MLP_NS + 1 + MLP_NPOLY * MLP_NC) {
-        const int q = k - MLP_NS - 1, p = q / MLP_NC, c = q % MLP_NC;
-        double r[MLP_NPOLY];
-#pragma unroll
-        for (int t = 0; t < MLP_NPOLY; ++t)
-            r[t] = (t < n_poly) ? rho[((long long)t * MLP_NC + c) * ld + s] : 0.0;
-        if (half == 0) return p == 0 ? r[0] : (p == 1 ? r[1] : r[2]);
-        if (half == 1) return p == 0 ? r[0] : (p == 1 ? 0.5 * r[1] : 0.25 * r[2]);
-        // C(q, p) 2^-q: p = 0: r0 + r1/2 + r2/4; p = 1: r1/2 + 2 r2/4; p = 2: r2/4
-        return p == 0 ? r[0] + 0.5 * r[1] + 0.25 * r[2]
-                      : (p == 1 ? 0.5 * r[1] + 0.5 * r[2] : 0.25 * r[2]);
+        const int q = k - MLP_NS - 1, p = q / MLP_NC;
+        return (p < n_poly) ? rho[(long long)q * ld + s] : 0.0;
     }
-    if (k == MLP_FEAT - 1) return (double)__logf((float)L);
+    if (k == MLP_FEAT - 1) return log(L);
     return 0.0;
 }
 
 __device__ __forceinline__ float std_feature(int k, const double *__restrict__ y,
                                              const double *__restrict__ rho, long long ld,
-                                             long long s, int n_poly, int half, double L,
+                                             long long s, int n_poly, double L,
                                              const double *__restrict__ stats)
 {
     if (k >= MLP_FEAT) return 0.0f;
-    return (float)((raw_feature(k, y, rho, ld, s, n_poly, half, L) - stats[k]) *
-                   stats[MLP_FEAT + k]);
+    return (float)((raw_feature(k, y, rho, ld, s, n_poly, L) - stats[k]) * stats[MLP_FEAT + k]);
 }
 
 // Raw target of component c: log-increment for species, plain increment for T.
@@ -252,27 +255,29 @@ __device__ __forceinline__ double apply_target(int c, double y0, double d)
 }
 
 // Training / evaluation features.  Samples are SoA with leading dimension ld:
-// Y0[c*ld + s] (c < NC), RHO[(p*NC + c)*ld + s] (p < n_poly), Lv[s], Y1 like Y0.
-// idx (nullable) picks the samples of this batch.  X: bf16 [B][MLP_KPAD]
-// standardized features; T (nullable): f32 [B][MLP_NC] standardized targets
-// (raw_target - y_mean) / y_std.
+// Y0[c*ld + s] (c < NC), RHO[(p*NC + c)*ld + s] (p < n_poly), Lv[s], Yb and Y1
+// like Y0.  idx (nullable) picks the samples of this batch.  X: bf16
+// [B][MLP_KPAD] standardized features of (Y0, RHO, Lv); T (nullable): f32
+// [B][MLP_NC] standardized targets (raw_target(Yb, Y1) - y_mean) / y_std, the
+// correction from the base state Yb to Y1.
 __global__ void __launch_bounds__(256)
     k_featurize(int B, const int *__restrict__ idx, long long ld, const double *__restrict__ Y0,
                 int n_poly, const double *__restrict__ RHO, const double *__restrict__ Lv,
-                const double *__restrict__ Y1, const double *__restrict__ stats,
-                uint16_t *__restrict__ X, float *__restrict__ T)
+                const double *__restrict__ Yb, const double *__restrict__ Y1,
+                const double *__restrict__ stats, uint16_t *__restrict__ X,
+                float *__restrict__ T)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     const long long s = idx ? idx[b] : b;
     const double L = Lv[s];
     for (int k = 0; k < MLP_KPAD; ++k)
-        X[(size_t)b * MLP_KPAD + k] = f2bf(std_feature(k, Y0, RHO, ld, s, n_poly, 0, L, stats));
+        X[(size_t)b * MLP_KPAD + k] = f2bf_bits(std_feature(k, Y0, RHO, ld, s, n_poly, L, stats));
     if (T) {
         const double *ym = stats + 2 * MLP_FEAT, *yi = stats + 2 * MLP_FEAT + MLP_NC;
         for (int c = 0; c < MLP_NC; ++c)
             T[(size_t)b * MLP_NC + c] =
-                (float)((raw_target(c, Y0[c * ld + s], Y1[c * ld + s]) - ym[c]) * yi[c]);
+                (float)((raw_target(c, Yb[c * ld + s], Y1[c * ld + s]) - ym[c]) * yi[c]);
     }
 }
 
@@ -282,7 +287,8 @@ __global__ void __launch_bounds__(256)
 __global__ void __launch_bounds__(256)
     k_stats_partial(long long N, long long ld, const double *__restrict__ Y0, int n_poly,
                     const double *__restrict__ RHO, const double *__restrict__ Lv,
-                    const double *__restrict__ Y1, double *__restrict__ part)
+                    const double *__restrict__ Yb, const double *__restrict__ Y1,
+                    double *__restrict__ part)
 {
     constexpr int NV = MLP_FEAT + MLP_NC;
     __shared__ double red[256];
@@ -292,8 +298,8 @@ __global__ void __launch_bounds__(256)
         double sum = 0.0, sq = 0.0;
         for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
             const double x = (v < MLP_FEAT)
-                                 ? raw_feature(v, Y0, RHO, ld, s, n_poly, 0, Lv[s])
-                                 : raw_target(v - MLP_FEAT, Y0[(v - MLP_FEAT) * ld + s],
+                                 ? raw_feature(v, Y0, RHO, ld, s, n_poly, Lv[s])
+                                 : raw_target(v - MLP_FEAT, Yb[(v - MLP_FEAT) * ld + s],
                                               Y1[(v - MLP_FEAT) * ld + s]);
             sum += x;
             sq += x * x;
@@ -345,18 +351,19 @@ __global__ void k_stats_final(int n_blocks, long long N, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: y_out = apply_target(y_in, y_mean + y_std * MLP(features(y_in,
-// rho', L'))).
+// Fused inference: y_out = apply_target(base, y_mean + y_std * MLP(features(y_in,
+// rho', L'))): the network reads the stage start state and predicts the
+// correction of `base` (the coarse FP64 stage result; y_in itself for an
+// increment over the stage).
 // One wave owns 32 cells (two 16-cell MFMA column tiles); activations stay in
 // registers between layers: the D layout of one layer is the B layout of the
 // next once the next layer's input columns are permuted (done on the host):
 // logical K index 32 t + 8 g + e of a layer holds the previous layer's output
 // 32 t + (e < 4 ? 4 g + e : 16 + 4 g + e - 4).
-// half: 0 full stage (rho, L); 1 first half (rho_k / 2^k, L/2); 2 second half
-// (binomially re-expanded rho, L/2).
 // ---------------------------------------------------------------------------
 struct InferArgs {
     const double *yin;
+    const double *base;         // state the predicted correction applies to
     double *yout;
     const double *rho;
     const uint16_t *W[4];       // [out_pad][in_pad] bf16, permuted inputs
@@ -366,7 +373,6 @@ struct InferArgs {
     int n_cells;
     int n_poly;
     double L;
-    int half;
 };
 
 // Weights stream through LDS in chunks of RB = 32 output rows with all their
@@ -579,7 +585,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
     // every wave takes part in the block's barriers; idle cells are clamped
     const long long block0 = (long long)blockIdx.x * CELLS_PER_BLOCK;
     const long long base = block0 + w * 16 * NT;
-    const double L = (a.half == 0) ? a.L : 0.5 * a.L;
+    const double L = a.L;
     // ---- features of the block's cells, computed cooperatively: thread
     // groups take interleaved features (the feature index is uniform per wave,
     // so its source plane is a scalar address and the loads are coalesced)
@@ -590,48 +596,43 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
         const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / CELLS_PER_BLOCK);
         long long cell = block0 + c;
         if (cell >= a.n_cells) cell = a.n_cells - 1;
-        if (a.n_poly <= 1) {
-            // constant forcing: every half-stage transform is the identity on
-            // rho_0 and the higher coefficients are zero, so each feature is one
-            // unconditional load plus selects.  Loads go out in batches of FB
-            // before any of them is used.
-            // The statistics are read through the constant address space
-            // (scalar loads: the feature index is uniform per wave and the
-            // statistics are not written during the launch).
-            constexpr int FB = PER % 48 == 0 ? 48 : (PER % 16 == 0 ? 16 : 8);
-            static_assert(PER % FB == 0, "feature batches");
-            typedef const __attribute__((address_space(4))) double cdouble;
-            cdouble *cst = (cdouble *)a.stats;
-            const float logL = __logf((float)L);
-            for (int b0 = 0; b0 < PER; b0 += FB) {
-                double v[FB];
+        // each feature is one unconditional load (the state, a forcing plane or
+        // a dummy for log L and the padding) plus selects.  Loads go out in
+        // batches of FB before any of them is used.
+        // The statistics are read through the constant address space
+        // (scalar loads: the feature index is uniform per wave and the
+        // statistics are not written during the launch).
+        constexpr int FB = PER % 48 == 0 ? 48 : (PER % 16 == 0 ? 16 : 8);
+        static_assert(PER % FB == 0, "feature batches");
+        typedef const __attribute__((address_space(4))) double cdouble;
+        cdouble *cst = (cdouble *)a.stats;
+        const double logL = log(L);
+        for (int b0 = 0; b0 < PER; b0 += FB) {
+            double v[FB];
 #pragma unroll
-                for (int i = 0; i < FB; ++i) {
-                    const int k = grp + GROUPS * (b0 + i);
-                    const bool isy = k <= MLP_NS;
-                    const bool isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
-                    const double *src = isy ? a.yin + (long long)k * a.ld
-                                            : (isr ? a.rho + (long long)(k - MLP_NS - 1) * a.ld
-                                                   : a.yin);
-                    v[i] = src[cell];
-                }
-#pragma unroll
-                for (int i = 0; i < FB; ++i) {
-                    const int k = grp + GROUPS * (b0 + i);
-                    const bool isy = k <= MLP_NS;
-                    const bool isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
-                    float raw = (k < MLP_NS) ? __logf((float)fmax(v[i], 1e-30)) : (float)v[i];
-                    if (k == MLP_FEAT - 1) raw = logL;
-                    const bool live = isy || isr || (k == MLP_FEAT - 1);
-                    const int kk = min(k, MLP_FEAT - 1);
-                    const float z = live ? (float)((raw - cst[kk]) * cst[MLP_FEAT + kk]) : 0.0f;
-                    xs[c * XROW + k] = f2bf(z);
-                }
+            for (int i = 0; i < FB; ++i) {
+                const int k = grp + GROUPS * (b0 + i);
+                const bool isy = k <= MLP_NS;
+                const bool isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
+                const double *src = isy ? a.yin + (long long)k * a.ld
+                                        : (isr ? a.rho + (long long)(k - MLP_NS - 1) * a.ld
+                                               : a.yin);
+                v[i] = src[cell];
             }
-        } else {
-            for (int k = grp; k < MLP_KPAD; k += GROUPS)
-                xs[c * XROW + k] = f2bf(std_feature(k, a.yin, a.rho, a.ld, cell, a.n_poly, a.half,
-                                                    L, a.stats));
+#pragma unroll
+            for (int i = 0; i < FB; ++i) {
+                const int k = grp + GROUPS * (b0 + i);
+                const bool isy = k <= MLP_NS;
+                const bool isr = (k > MLP_NS) && (k - MLP_NS - 1 < a.n_poly * MLP_NC);
+                // species logarithms in FP32 (the feature is rounded to bfloat16
+                // next); T, the forcing and log L as they are
+                double raw = (k < MLP_NS) ? (double)__logf((float)fmax(v[i], 1e-30)) : v[i];
+                if (k == MLP_FEAT - 1) raw = logL;
+                const bool live = isy || isr || (k == MLP_FEAT - 1);
+                const int kk = min(k, MLP_FEAT - 1);
+                const float z = live ? (float)((raw - cst[kk]) * cst[MLP_FEAT + kk]) : 0.0f;
+                xs[c * XROW + k] = f2bf_bits(z);
+            }
         }
     }
     __syncthreads();
@@ -669,7 +670,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 const int c = min(16 * mi + 4 * g + r4, MLP_NC - 1);
-                y0[t][mi][r4] = a.yin[c * a.ld + cell];
+                y0[t][mi][r4] = a.base[c * a.ld + cell];
             }
     }
 #pragma unroll
@@ -688,45 +689,56 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
     }
 }
 
-// Gate: G = max(D, I).  D = max_c |full_c - dbl_c| / max(|dbl_c|, floor_c)
-// (step doubling; floor 1e-8 for mass fractions, 0 for T).  I = the residual of
-// the mass-sum invariant: the chemistry conserves sum_k Y_k, so over the stage
-// sum_k (dbl_k - y0_k) must equal L sum_p sum_k rho_(p,k) / (p + 1) (the
-// integral of the forcing), relative to sum_k |y0_k|.  Accepted cells take the
-// two-half prediction; rejected cells are appended to the fallback list (one
-// atomic per wave, ranks from the ballot mask).
+// Residual check of the surrogate, G = max(D, I), on FP64 data:
+//   Ve = vc + rich (vc - vh), the Richardson extrapolation of the coarse stage
+//   vc (n substeps) and vh (n / 2 substeps), rich = 1 / (2^p - 1) for a fast
+//   method of order p: an estimate of the fine stage from FP64 work alone;
+//   D = max_c |vn_c - Ve_c| / max(|Ve_c|, floor_c) (floor 1e-8 for mass
+//   fractions, 0 for T), vn the network's correction of vc;
+//   I = the residual of the mass-sum invariant of vn: the chemistry conserves
+//   sum_k Y_k, so over the stage sum_k (vn_k - y0_k) must equal
+//   L sum_p sum_k rho_(p,k) / (p + 1), relative to sum_k |y0_k|.
+// A cell is accepted when G <= tol and neither coarse solve flagged it
+// (status_c, nullable); it takes vn and status 0.  Rejected cells are appended
+// to the fallback list (one atomic per wave, ranks from the ballot mask).
 __global__ void __launch_bounds__(256)
     k_gate(int n_cells, long long ld, const double *__restrict__ yin,
-           const double *__restrict__ rho, int n_poly, double L,
-           const double *__restrict__ full, const double *__restrict__ dbl, double tol,
-           double *__restrict__ yout, int *__restrict__ used_fallback, int *__restrict__ list,
-           unsigned int *count, float *__restrict__ dmax)
+           const double *__restrict__ rho, int n_poly, double L, const double *__restrict__ vc,
+           const double *__restrict__ vh, const double *__restrict__ vn,
+           const int *__restrict__ status_c, double rich, double tol, double *__restrict__ yout,
+           int *__restrict__ used_fallback, double *__restrict__ gval, int *__restrict__ status,
+           int *__restrict__ list, unsigned int *count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < n_cells;
     bool reject = false;
     if (live) {
         double D = 0.0, dsum = 0.0, y0sum = 0.0, fsum = 0.0;
+        bool nan = false;
         for (int c = 0; c < MLP_NC; ++c) {
-            const double a = full[c * ld + i], b = dbl[c * ld + i];
+            const double a = vc[c * ld + i], h = vh[c * ld + i];
+            const double ve = a + rich * (a - h);
             const double fl = (c < MLP_NS) ? 1e-8 : 0.0;
-            const double e = fabs(a - b) / fmax(fabs(b), fl);
-            D = (e > D || e != e) ? e : D;       // NaN counts as rejection
+            const double e = fabs(vn[c * ld + i] - ve) / fmax(fabs(ve), fl);
+            nan = nan || (e != e);
+            D = (e > D) ? e : D;
             if (c < MLP_NS) {
                 const double y0 = yin[c * ld + i];
-                dsum += b - y0;
+                dsum += vn[c * ld + i] - y0;
                 y0sum += fabs(y0);
                 for (int p = 0; p < n_poly; ++p)
                     fsum += rho[((long long)p * MLP_NC + c) * ld + i] / (double)(p + 1);
             }
         }
         const double I = fabs(dsum - L * fsum) / fmax(y0sum, 1e-300);
-        D = (I > D || I != I) ? I : D;
-        reject = !(D <= tol);
+        nan = nan || (I != I);
+        const double G = nan ? __builtin_nan("") : fmax(D, I);
+        reject = nan || !(G <= tol) || (status_c && status_c[i] != 0);
         if (!reject)
-            for (int c = 0; c < MLP_NC; ++c) yout[c * ld + i] = dbl[c * ld + i];
+            for (int c = 0; c < MLP_NC; ++c) yout[c * ld + i] = vn[c * ld + i];
         if (used_fallback) used_fallback[i] = reject ? 1 : 0;
-        if (dmax) dmax[i] = (float)D;
+        if (gval) gval[i] = G;
+        if (status && !reject) status[i] = 0;
     }
     const unsigned long long m = __ballot(reject);
     const int lane = threadIdx.x & 63;
@@ -760,6 +772,16 @@ __global__ void __launch_bounds__(256)
     if (k >= (long long)*count) return;
     const int cell = list[k];
     for (int c = 0; c < n_planes; ++c) dst[c * ldd + cell] = src[c * lds + k];
+}
+
+// dst[list[k]] = src[k] for k < *count (the fallback cells' status words).
+__global__ void __launch_bounds__(256)
+    k_scatter_i32(const unsigned int *count, const int *__restrict__ list,
+                  const int *__restrict__ src, int *__restrict__ dst)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long long)*count) return;
+    dst[list[k]] = src[k];
 }
 
 __global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
@@ -845,30 +867,32 @@ hipError_t mlp_to_bf16(long long n, const float *x, uint16_t *y, hipStream_t s)
 }
 
 hipError_t mlp_featurize(int B, const int *idx, long long ld, const double *Y0, int n_poly,
-                         const double *RHO, const double *Lv, const double *Y1,
-                         const double *stats, uint16_t *X, float *T, hipStream_t s)
+                         const double *RHO, const double *Lv, const double *Yb,
+                         const double *Y1, const double *stats, uint16_t *X, float *T,
+                         hipStream_t s)
 {
     hipLaunchKernelGGL(k_featurize, grid1(B, 256), dim3(256), 0, s, B, idx, ld, Y0, n_poly, RHO,
-                       Lv, Y1, stats, X, T);
+                       Lv, Yb ? Yb : Y0, Y1, stats, X, T);
     return hipGetLastError();
 }
 
 hipError_t mlp_stats(long long N, long long ld, const double *Y0, int n_poly, const double *RHO,
-                     const double *Lv, const double *Y1, double *part, int n_blocks,
-                     double *stats, hipStream_t s)
+                     const double *Lv, const double *Yb, const double *Y1, double *part,
+                     int n_blocks, double *stats, hipStream_t s)
 {
     hipLaunchKernelGGL(k_stats_partial, dim3(n_blocks), dim3(256), 0, s, N, ld, Y0, n_poly, RHO,
-                       Lv, Y1, part);
+                       Lv, Yb ? Yb : Y0, Y1, part);
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(128), 0, s, n_blocks, N, part, stats);
     return hipGetLastError();
 }
 
-hipError_t mlp_infer(const double *yin, double *yout, const double *rho, const uint16_t *const *W,
-                     const float *const *b, const double *stats, long long ld, int n_cells,
-                     int n_poly, double L, int half, hipStream_t s)
+hipError_t mlp_infer(const double *yin, const double *base, double *yout, const double *rho,
+                     const uint16_t *const *W, const float *const *b, const double *stats,
+                     long long ld, int n_cells, int n_poly, double L, hipStream_t s)
 {
     InferArgs a;
     a.yin = yin;
+    a.base = base ? base : yin;
     a.yout = yout;
     a.rho = rho;
     for (int l = 0; l < 4; ++l) {
@@ -880,19 +904,19 @@ hipError_t mlp_infer(const double *yin, double *yout, const double *rho, const u
     a.n_cells = n_cells;
     a.n_poly = n_poly;
     a.L = L;
-    a.half = half;
     hipLaunchKernelGGL(k_infer, grid1(n_cells, CELLS_PER_BLOCK), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t mlp_gate(int n_cells, long long ld, const double *yin, const double *rho, int n_poly,
-                    double L, const double *full, const double *dbl, double tol, double *yout,
-                    int *used_fallback, int *list, unsigned int *count, float *dmax,
-                    hipStream_t s)
+                    double L, const double *vc, const double *vh, const double *vn,
+                    const int *status_c, double rich, double tol, double *yout, int *used_fallback,
+                    double *gval, int *status, int *list, unsigned int *count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, count);
     hipLaunchKernelGGL(k_gate, grid1(n_cells, 256), dim3(256), 0, s, n_cells, ld, yin, rho,
-                       n_poly, L, full, dbl, tol, yout, used_fallback, list, count, dmax);
+                       n_poly, L, vc, vh, vn, status_c, rich, tol, yout, used_fallback, gval,
+                       status, list, count);
     return hipGetLastError();
 }
 
@@ -909,5 +933,18 @@ hipError_t mlp_scatter(int n_planes, const unsigned int *count, const int *list,
 {
     hipLaunchKernelGGL(k_scatter, grid1(n_max, 256), dim3(256), 0, s, n_planes, count, list, src,
                        lds, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t mlp_scatter_i32(const unsigned int *count, const int *list, long long n_max,
+                           const int *src, int *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter_i32, grid1(n_max, 256), dim3(256), 0, s, count, list, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t mlp_zero_u32(unsigned int *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, p);
     return hipGetLastError();
 }

@@ -462,6 +462,8 @@ static mri_status check_opts(const mri_mech *m, const mri_fast_opts *o)
     if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 &&
         o->block_size != 256)
         return fail(MRI_EINVAL, "block_size must be 0, 64, 128 or 256 (got %d)", o->block_size);
+    if (!(o->stiff_limit >= 0.0) || !std::isfinite(o->stiff_limit))
+        return fail(MRI_EINVAL, "stiff_limit must be finite and >= 0");
     return MRI_OK;
 }
 
@@ -471,12 +473,14 @@ static int default_block(int kernel_kind) { return kernel_kind == MRI_KERNEL_GEN
 static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
                                   const double *yin, double *yout, int n_poly,
                                   const double *rho, double L, int32_t *status, int32_t *steps,
-                                  int accumulate, hipStream_t s)
+                                  int accumulate, hipStream_t s,
+                                  const unsigned int *n_live = nullptr)
 {
     if (n_cells == 0) return MRI_OK;
     mri_status dst = ensure_device(m);
     if (dst != MRI_OK) return dst;
     if (m->kind == 1) {
+        if (n_live) return fail(MRI_EUNSUPPORTED, "device cell counts need a chemistry mechanism");
         if (o->method == MRI_FAST_CK5) {
             HIP_TRY(launch_lin_erk(m->n, m->d_A, erk_full_ck5(), n_cells, ld, yin, yout, n_poly,
                                    rho, L, o->n_sub, status, steps, accumulate, s));
@@ -487,6 +491,13 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
         ++c_fast;
         c_cells += n_cells;
         return MRI_OK;
+    }
+    // stiffness monitor at the stage start state: it writes (or ORs) the status
+    // words and zeroes the step counts, and the stage then accumulates onto them
+    if (o->stiff_limit > 0.0 && fixed_step(o->method) && (status || steps) && !n_live) {
+        HIP_TRY(launch_gen_stiff(m->gm, n_cells, ld, yin, L / o->n_sub, o->stiff_limit, nullptr,
+                                 status, steps, accumulate, MRI_CELL_STIFF, s));
+        accumulate = 1;
     }
     int kind = o->kernel;
     hipFunction_t fn = nullptr;
@@ -508,14 +519,14 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
             // stage derivatives held in registers: at most GEN_NMAX_SMALL
             // species (checked with the options)
             HIP_TRY(launch_gen_erk(m->gm, erk_full_ck5(), wg, n_cells, ld, yin, yout, n_poly,
-                                   rho, L, o->n_sub, status, steps, accumulate, s));
+                                   rho, L, o->n_sub, status, steps, accumulate, n_live, s));
         } else if (fixed_step(o->method)) {
             HIP_TRY(launch_gen_rk4(m->gm, erk_coef(o->method), wg, n_cells, ld, yin, yout, n_poly,
-                                   rho, L, o->n_sub, status, steps, accumulate, s));
+                                   rho, L, o->n_sub, status, steps, accumulate, n_live, s));
         } else {
             ZvOpts z{o->rtol, o->atol_Y, o->atol_T, o->max_steps};
             HIP_TRY(launch_gen_zv(m->gm, wg, n_cells, ld, yin, yout, n_poly, rho, L, z, status,
-                                  steps, accumulate, s));
+                                  steps, accumulate, n_live, s));
         }
     } else {
         const unsigned grid = (unsigned)((n_cells + wg - 1) / wg);
@@ -524,14 +535,15 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
         double *yo = yout;
         double Lv = L;
         int *stp = status, *sps = steps;
+        const unsigned int *nl = n_live;
         if (fixed_step(o->method)) {
             int nsub = o->n_sub;
-            void *args[] = {&nc, &ldv, &yi, &yo, &rh, &Lv, &nsub, &stp, &sps, &acc};
+            void *args[] = {&nc, &ldv, &yi, &yo, &rh, &Lv, &nsub, &stp, &sps, &acc, &nl};
             HIP_TRY(hipModuleLaunchKernel(fn, grid, 1, 1, wg, 1, 1, 0, s, args,
                                           nullptr));
         } else {
             ZvOpts z{o->rtol, o->atol_Y, o->atol_T, o->max_steps};
-            void *args[] = {&nc, &ldv, &yi, &yo, &rh, &Lv, &z, &stp, &sps, &acc};
+            void *args[] = {&nc, &ldv, &yi, &yo, &rh, &Lv, &z, &stp, &sps, &acc, &nl};
             HIP_TRY(hipModuleLaunchKernel(fn, grid, 1, 1, wg, 1, 1, 0, s, args,
                                           nullptr));
         }
@@ -544,13 +556,14 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
 static mri_status fast_stage_impl(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
                                   const double *yin, double *yout, int n_poly,
                                   const double *rho, double L, int32_t *status, int32_t *steps,
-                                  int accumulate, hipStream_t s)
+                                  int accumulate, hipStream_t s,
+                                  const unsigned int *n_live = nullptr)
 {
     if (n_cells == 0) return MRI_OK;
     auto *ev = timing_slot();
     if (ev) HIP_TRY(hipEventRecord(ev->first, s));
     mri_status st = fast_stage_launch(m, o, n_cells, ld, yin, yout, n_poly, rho, L, status, steps,
-                                      accumulate, s);
+                                      accumulate, s, n_live);
     if (ev) HIP_TRY(hipEventRecord(ev->second, s));
     return st;
 }
@@ -590,11 +603,13 @@ struct mri_batch_plan {
 
 mri_status mri_internal_fast_stage(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
                                    const double *yin, double *yout, int n_poly, const double *rho,
-                                   double L, int32_t *status, int32_t *steps, hipStream_t s)
+                                   double L, int32_t *status, int32_t *steps, hipStream_t s,
+                                   const unsigned int *n_live, int accumulate)
 {
     mri_status st = check_opts(m, o);
     if (st != MRI_OK) return st;
-    return fast_stage_impl(m, o, n_cells, ld, yin, yout, n_poly, rho, L, status, steps, 0, s);
+    return fast_stage_impl(m, o, n_cells, ld, yin, yout, n_poly, rho, L, status, steps, accumulate,
+                           s, n_live);
 }
 
 int mri_internal_state_width(const mri_mech *m) { return m ? m->n : -1; }
@@ -1239,6 +1254,28 @@ mri_status mri_selftest_exp2_t256(const double *x, double *y, int n, mri_stream_
     return MRI_OK;
 }
 
+mri_status mri_stiffness_check(const mri_mech *mc, int n_cells, int ld, const double *y, double h,
+                               double limit, double *bound_out, int32_t *status,
+                               mri_stream_t stream)
+{
+    mri_mech *m = const_cast<mri_mech *>(mc);
+    if (!m) return fail(MRI_EINVAL, "mech is NULL");
+    if (m->kind != 0) return fail(MRI_EUNSUPPORTED, "the monitor needs a chemistry mechanism");
+    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
+    if (ld > kMaxCells) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
+    if ((long long)ld * m->n > (1ll << 31) - 1)
+        return fail(MRI_EINVAL, "n * ld exceeds 2^31 - 1 elements");
+    if (!(h >= 0.0) || !std::isfinite(h) || !(limit >= 0.0) || std::isnan(limit))
+        return fail(MRI_EINVAL, "need finite h >= 0 and limit >= 0");
+    if (n_cells == 0) return MRI_OK;
+    if (!y) return fail(MRI_EINVAL, "y is NULL");
+    mri_status st = ensure_device(m);
+    if (st != MRI_OK) return st;
+    HIP_TRY(launch_gen_stiff(m->gm, n_cells, ld, y, h, limit, bound_out, status, nullptr, 1,
+                             MRI_CELL_STIFF, (hipStream_t)stream));
+    return MRI_OK;
+}
+
 mri_status mri_status_count(const int32_t *status, int n_cells, int32_t mask, int64_t *n_bad,
                             mri_stream_t stream)
 {
@@ -1322,7 +1359,8 @@ mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_
 // work-queue kernel) over the first n_total cells on stream s.
 static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, long long n_total,
                                 const double *yin, double *yout, long long ld, int n_poly,
-                                const double *rho, int32_t *status, int32_t *steps, hipStream_t s)
+                                const double *rho, int32_t *status, int32_t *steps,
+                                int32_t *rejects, hipStream_t s)
 {
     hipFunction_t fn = nullptr;
     mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn);
@@ -1336,6 +1374,7 @@ static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, long lo
     a.set_L = p->d_L;
     a.status = status;
     a.steps = steps;
+    a.rejects = rejects;
     a.counter = p->d_counters;
     a.lane_steps = p->d_counters + 1;
     a.issued_steps = p->d_counters + 2;
@@ -1403,7 +1442,7 @@ static mri_status batch_tune(mri_batch_plan *p, const double *yin, double *yout,
             const int blocks = nb * n_cus() * f;
             HIP_TRY(hipEventRecord(e0, s));
             st = batch_enqueue(p, wg, blocks, n_sample, yin, yout, ld, n_poly, rho, nullptr,
-                               nullptr, s);
+                               nullptr, nullptr, s);
             if (st != MRI_OK) return st;
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));
@@ -1424,7 +1463,8 @@ static mri_status batch_tune(mri_batch_plan *p, const double *yin, double *yout,
 extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, double *y_out,
                                     int64_t ld, int n_poly, const double *rho_poly,
                                     const double *L_per_set, int32_t *status_out,
-                                    int32_t *steps_out, mri_stream_t stream)
+                                    int32_t *steps_out, int32_t *rejects_out,
+                                    mri_stream_t stream)
 {
     if (!p) return fail(MRI_EINVAL, "plan is NULL");
     if (ld < p->n_total) return fail(MRI_EINVAL, "ld < total cells");
@@ -1451,7 +1491,8 @@ extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, doubl
     const std::vector<uintptr_t> key = {(uintptr_t)y_in, (uintptr_t)y_out, (uintptr_t)ld,
                                         (uintptr_t)n_poly, (uintptr_t)rho_poly,
                                         (uintptr_t)status_out, (uintptr_t)steps_out,
-                                        (uintptr_t)p->wg, (uintptr_t)p->n_blocks};
+                                        (uintptr_t)rejects_out, (uintptr_t)p->wg,
+                                        (uintptr_t)p->n_blocks};
     if (!p->exec || key != p->graph_key) {
         if (p->exec) (void)hipGraphExecDestroy(p->exec);
         if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -1464,7 +1505,7 @@ extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, doubl
         if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
         st = batch_enqueue(p, p->wg, p->n_blocks, p->n_total, y_in, y_out, ld, n_poly, rho_poly,
-                           status_out, steps_out, p->cap_stream);
+                           status_out, steps_out, rejects_out, p->cap_stream);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
         if (st != MRI_OK) {

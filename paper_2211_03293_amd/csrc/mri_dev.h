@@ -53,10 +53,12 @@ struct ErkFull {
     double c[ERK_SMAX], b[ERK_SMAX], a[ERK_SMAX][ERK_SMAX];
 };
 
+// n_live (nullable, device): cells at or beyond *n_live are skipped, so a
+// launch sized for n_cells can serve a count known only on the device.
 hipError_t launch_gen_erk(const GenMech &gm, const ErkFull &e, int block, int n_cells, int ld,
                           const double *yin, double *yout, int n_poly, const double *rho,
                           double L, int n_sub, int *status, int *steps, int accumulate,
-                          hipStream_t s);
+                          const unsigned int *n_live, hipStream_t s);
 hipError_t launch_lin_erk(int n, const double *A, const ErkFull &e, int n_cells, int ld,
                           const double *yin, double *yout, int n_poly, const double *rho,
                           double L, int n_sub, int *status, int *steps, int accumulate,
@@ -65,10 +67,19 @@ hipError_t launch_lin_erk(int n, const double *A, const ErkFull &e, int n_cells,
 hipError_t launch_gen_rk4(const GenMech &gm, const ErkCoef &e, int block, int n_cells, int ld,
                           const double *yin, double *yout, int n_poly, const double *rho,
                           double L, int n_sub, int *status, int *steps, int accumulate,
-                          hipStream_t s);
+                          const unsigned int *n_live, hipStream_t s);
+// Stiffness monitor: bound[i] = B (1/s; nullable), B an upper bound of the
+// spectral radius of the species block of the chemistry Jacobian at fixed T;
+// status[i] (nullable) gets `flag` where h B > limit, OR-ed in when accumulate
+// is set, written otherwise (steps[i], nullable, then set to 0, so that a
+// stage launched after it with accumulate set counts from zero).
+hipError_t launch_gen_stiff(const GenMech &gm, int n_cells, int ld, const double *y, double h,
+                            double limit, double *bound, int *status, int *steps, int accumulate,
+                            int flag, hipStream_t s);
 hipError_t launch_gen_zv(const GenMech &gm, int block, int n_cells, int ld, const double *yin,
                          double *yout, int n_poly, const double *rho, double L, ZvOpts o,
-                         int *status, int *steps, int accumulate, hipStream_t s);
+                         int *status, int *steps, int accumulate, const unsigned int *n_live,
+                         hipStream_t s);
 
 // Linear test mode: f = A v, n <= 16, A row-major on the device.
 hipError_t launch_lin_rk4(int n, const double *A, const ErkCoef &e, int n_cells, int ld,

@@ -8,10 +8,14 @@
 // Records the thread-local error text and returns st.
 mri_status mri_fail(mri_status st, const char *fmt, ...);
 
-// One fast stage (validated options), used by the surrogate's fallback path.
+// One fast stage (options validated here), used by the surrogate.  n_live
+// (nullable, device): only cells below *n_live are integrated (a launch sized
+// for n_cells serving a count the device computed); accumulate ORs status and
+// adds steps.
 mri_status mri_internal_fast_stage(mri_mech *m, const mri_fast_opts *o, int n_cells, int ld,
                                    const double *yin, double *yout, int n_poly, const double *rho,
-                                   double L, int32_t *status, int32_t *steps, hipStream_t s);
+                                   double L, int32_t *status, int32_t *steps, hipStream_t s,
+                                   const unsigned int *n_live = nullptr, int accumulate = 0);
 int mri_internal_state_width(const mri_mech *m);
 // Argument checks of mri_slow_step (everything but y and the workspace).
 mri_status mri_internal_check_slow_step(const mri_mech *m, const mri_table *t,

@@ -14,7 +14,8 @@ struct BatchArgs {
     const long long *set_off;           // [n_sets + 1]
     const double *set_L;                // [n_sets]
     int *status;
-    int *steps;
+    int *steps;                         // accepted steps per cell (nullable)
+    int *rejects;                       // rejected steps per cell (nullable)
     unsigned long long *counter;        // next unclaimed cell
     unsigned long long *lane_steps;     // useful lane-steps (nullable)
     unsigned long long *issued_steps;   // issued lane-steps (nullable)

@@ -212,8 +212,8 @@ mri_status mri_adam_step(mri_mlp *m, float lr, float beta1, float beta2, float e
 }
 
 mri_status mri_mlp_feature_stats(int64_t n, int64_t ld, const double *Y0, int n_poly,
-                                 const double *RHO, const double *Lv, const double *Y1,
-                                 double *stats, mri_stream_t stream)
+                                 const double *RHO, const double *Lv, const double *Yb,
+                                 const double *Y1, double *stats, mri_stream_t stream)
 {
     if (n < 1 || ld < n || !Y0 || !Lv || !Y1 || !stats || n_poly < 0 || n_poly > 3 ||
         (n_poly > 0 && !RHO))
@@ -222,7 +222,7 @@ mri_status mri_mlp_feature_stats(int64_t n, int64_t ld, const double *Y0, int n_
     double *part = nullptr;
     HIP_TRY(dalloc(&part, (size_t)n_blocks * 2 * (MLP_FEAT + MLP_NC)));
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = mlp_stats(n, ld, Y0, n_poly, RHO, Lv, Y1, part, n_blocks, stats, s);
+    hipError_t e = mlp_stats(n, ld, Y0, n_poly, RHO, Lv, Yb, Y1, part, n_blocks, stats, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(part);
     if (e != hipSuccess) return fail(MRI_EHIP, "feature statistics: %s", hipGetErrorString(e));
@@ -230,14 +230,15 @@ mri_status mri_mlp_feature_stats(int64_t n, int64_t ld, const double *Y0, int n_
 }
 
 mri_status mri_mlp_featurize(int batch, const int32_t *idx, int64_t ld, const double *Y0,
-                             int n_poly, const double *RHO, const double *Lv, const double *Y1,
-                             const double *stats, uint16_t *X, float *T, mri_stream_t stream)
+                             int n_poly, const double *RHO, const double *Lv, const double *Yb,
+                             const double *Y1, const double *stats, uint16_t *X, float *T,
+                             mri_stream_t stream)
 {
     if (batch < 0 || !Y0 || !Lv || !stats || !X || n_poly < 0 || n_poly > 3 ||
         (n_poly > 0 && !RHO) || (T && !Y1))
         return fail(MRI_EINVAL, "bad arguments");
     if (batch == 0) return MRI_OK;
-    HIP_TRY(mlp_featurize(batch, idx, ld, Y0, n_poly, RHO, Lv, Y1, stats, X, T,
+    HIP_TRY(mlp_featurize(batch, idx, ld, Y0, n_poly, RHO, Lv, Yb, Y1, stats, X, T,
                           (hipStream_t)stream));
     return MRI_OK;
 }
@@ -306,80 +307,146 @@ mri_status mri_surrogate_create(const int *widths, const float *params, const do
 
 void mri_surrogate_destroy(mri_surrogate *s) { delete s; }
 
-mri_status mri_surrogate_infer(const mri_surrogate *s, int n_cells, int ld, const double *y_in,
-                               double *y_out, int n_poly, const double *rho, double L, int half,
-                               mri_stream_t stream)
+static mri_status check_cells(int n_cells, int ld, int n_poly, const double *rho, double L)
 {
-    if (!s) return fail(MRI_EINVAL, "surrogate is NULL");
     if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
     if (ld > (1ll << 31) - 1024) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
     if (n_poly < 0 || n_poly > 3 || (n_poly > 0 && !rho)) return fail(MRI_EINVAL, "bad n_poly");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(MRI_EINVAL, "L must be positive");
-    if (half < 0 || half > 2) return fail(MRI_EINVAL, "half must be 0, 1 or 2");
+    return MRI_OK;
+}
+
+mri_status mri_surrogate_infer(const mri_surrogate *s, int n_cells, int ld, const double *y_in,
+                               const double *base, double *y_out, int n_poly, const double *rho,
+                               double L, mri_stream_t stream)
+{
+    if (!s) return fail(MRI_EINVAL, "surrogate is NULL");
+    mri_status st = check_cells(n_cells, ld, n_poly, rho, L);
+    if (st != MRI_OK) return st;
     if (n_cells == 0) return MRI_OK;
-    if (!y_in || !y_out || y_in == y_out) return fail(MRI_EINVAL, "need distinct y_in, y_out");
-    HIP_TRY(mlp_infer(y_in, y_out, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, half,
+    if (!y_in || !y_out || y_in == y_out || base == y_out)
+        return fail(MRI_EINVAL, "need y_in and y_out, y_out distinct from y_in and base");
+    HIP_TRY(mlp_infer(y_in, base, y_out, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L,
                       (hipStream_t)stream));
     return MRI_OK;
+}
+
+mri_status mri_surrogate_gate(int n_cells, int ld, const double *y_in, int n_poly,
+                              const double *rho, double L, const double *v_coarse,
+                              const double *v_half, const double *v_net,
+                              const int32_t *status_coarse, double richardson, double gate_tol,
+                              double *y_out, int32_t *used_fallback, double *gate_value,
+                              int32_t *fallback_list, uint32_t *n_fallback, mri_stream_t stream)
+{
+    mri_status st = check_cells(n_cells, ld, n_poly, rho, L);
+    if (st != MRI_OK) return st;
+    if (!(gate_tol >= 0.0)) return fail(MRI_EINVAL, "gate_tol must be >= 0");
+    if (!(richardson >= 0.0) || !std::isfinite(richardson))
+        return fail(MRI_EINVAL, "richardson must be finite and >= 0");
+    if (!fallback_list || !n_fallback) return fail(MRI_EINVAL, "fallback list or count is NULL");
+    if (n_cells == 0) {
+        HIP_TRY(mlp_zero_u32(n_fallback, (hipStream_t)stream));
+        return MRI_OK;
+    }
+    if (!y_in || !v_coarse || !v_half || !v_net || !y_out)
+        return fail(MRI_EINVAL, "NULL state array");
+    HIP_TRY(mlp_gate(n_cells, ld, y_in, rho, n_poly, L, v_coarse, v_half, v_net, status_coarse,
+                     richardson, gate_tol, y_out, used_fallback, gate_value, nullptr,
+                     fallback_list, n_fallback, (hipStream_t)stream));
+    return MRI_OK;
+}
+
+// Workspace of the gated stage (all [22][ld] planes FP64): coarse, half and
+// network states, the compacted forcing; int32 coarse status, fallback list and
+// compacted status [ld]; the device fallback count.
+static size_t stage_ws_bytes(int ld, int n_poly)
+{
+    const size_t plane = sizeof(double) * (size_t)ld * MLP_NC;
+    return plane * (3 + (size_t)n_poly) + 3 * sizeof(int) * (size_t)ld + 256;
 }
 
 mri_status mri_surrogate_workspace_bytes(int n_cells, int ld, int n_poly, size_t *bytes)
 {
     if (!bytes || n_cells < 0 || ld < n_cells || n_poly < 0 || n_poly > 3)
         return fail(MRI_EINVAL, "bad arguments");
-    // full, mid, doubled states; compact forcing; fallback list; count
-    *bytes = sizeof(double) * (size_t)ld * MLP_NC * (3 + n_poly) + sizeof(int) * (size_t)ld + 256;
+    *bytes = stage_ws_bytes(ld, n_poly);
     return MRI_OK;
 }
 
+static int method_order(int method)
+{
+    switch (method) {
+    case MRI_FAST_HEUN: return 2;
+    case MRI_FAST_BS3: return 3;
+    case MRI_FAST_CK5: return 5;
+    default: return 4;
+    }
+}
+
 mri_status mri_surrogate_stage(const mri_surrogate *s, const mri_mech *mech,
-                               const mri_fast_opts *fallback, double gate_tol, int n_cells, int ld,
-                               const double *y_in, double *y_out, int n_poly, const double *rho,
-                               double L, int32_t *used_fallback, float *gate_value,
-                               int64_t *n_fallback, void *ws, size_t ws_bytes,
+                               const mri_fast_opts *coarse, const mri_fast_opts *fallback,
+                               double gate_tol, int n_cells, int ld, const double *y_in,
+                               double *y_out, int n_poly, const double *rho, double L,
+                               int32_t *used_fallback, double *gate_value, int32_t *status_out,
+                               uint32_t *n_fallback, void *ws, size_t ws_bytes,
                                mri_stream_t stream)
 {
-    if (!s || !mech || !fallback) return fail(MRI_EINVAL, "NULL argument");
+    if (!s || !mech || !coarse || !fallback) return fail(MRI_EINVAL, "NULL argument");
     if (!mri_internal_is_chem(mech) || mri_internal_state_width(mech) != MLP_NC)
         return fail(MRI_EUNSUPPORTED, "the surrogate is built for 21-species mechanisms");
     if (!(gate_tol >= 0.0)) return fail(MRI_EINVAL, "gate_tol must be >= 0");
-    if (n_cells < 0 || ld < n_cells) return fail(MRI_EINVAL, "need 0 <= n_cells <= ld");
-    if (ld > (1ll << 31) - 1024) return fail(MRI_EINVAL, "ld exceeds 2^31 - 1024 cells");
-    if (n_poly < 0 || n_poly > 3 || (n_poly > 0 && !rho)) return fail(MRI_EINVAL, "bad n_poly");
-    if (!(L > 0.0) || !std::isfinite(L)) return fail(MRI_EINVAL, "L must be positive");
-    size_t need = 0;
-    mri_surrogate_workspace_bytes(n_cells, ld, n_poly, &need);
-    if (n_fallback) *n_fallback = 0;
-    if (n_cells == 0) return MRI_OK;
+    mri_status st = check_cells(n_cells, ld, n_poly, rho, L);
+    if (st != MRI_OK) return st;
+    if (coarse->method == MRI_FAST_ZONNEVELD43)
+        return fail(MRI_EINVAL, "the coarse stage needs a fixed-step method");
+    if (coarse->n_sub < 2 || coarse->n_sub % 2)
+        return fail(MRI_EINVAL, "the coarse stage needs an even n_sub >= 2 (got %d)",
+                    coarse->n_sub);
+    const size_t need = stage_ws_bytes(ld, n_poly);
+    if (n_cells == 0) {
+        if (n_fallback) HIP_TRY(mlp_zero_u32(n_fallback, (hipStream_t)stream));
+        return MRI_OK;
+    }
     if (!y_in || !y_out) return fail(MRI_EINVAL, "y_in or y_out is NULL");
     if (!ws || ws_bytes < need)
         return fail(MRI_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, need);
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t hs = (hipStream_t)stream;
     const size_t plane = (size_t)ld * MLP_NC;
-    double *full = (double *)ws, *mid = full + plane, *dbl = mid + plane;
-    double *rho_c = dbl + plane;
-    int *list = (int *)(rho_c + (size_t)n_poly * plane);
-    unsigned int *count = (unsigned int *)(list + ld);
-    // three inferences: full stage, first half, second half from the midpoint
-    HIP_TRY(mlp_infer(y_in, full, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, 0, st));
-    HIP_TRY(mlp_infer(y_in, mid, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, 1, st));
-    HIP_TRY(mlp_infer(mid, dbl, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, 2, st));
-    HIP_TRY(mlp_gate(n_cells, ld, y_in, rho, n_poly, L, full, dbl, gate_tol, y_out,
-                     used_fallback, list, count, gate_value, st));
-    unsigned int h_count = 0;
-    HIP_TRY(hipMemcpyAsync(&h_count, count, sizeof h_count, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (n_fallback) *n_fallback = h_count;
-    if (h_count == 0) return MRI_OK;
-    // compact the rejected cells (state into `full`, forcing into rho_c),
-    // integrate them with the plain FP64 fast stage into `mid`, scatter back
-    HIP_TRY(mlp_gather(MLP_NC, count, list, h_count, y_in, ld, full, ld, st));
+    double *vc = (double *)ws, *vh = vc + plane, *vn = vh + plane;
+    double *rho_c = vn + plane;
+    int *st_c = (int *)(rho_c + (size_t)n_poly * plane);
+    int *list = st_c + ld, *st_f = list + ld;
+    unsigned int *count = (unsigned int *)(st_f + ld);
+    mri_mech *m = const_cast<mri_mech *>(mech);
+    // coarse FP64 stage and the same with half the substeps (statuses OR-ed)
+    mri_fast_opts half = *coarse;
+    half.n_sub = coarse->n_sub / 2;
+    st = mri_internal_fast_stage(m, coarse, n_cells, ld, y_in, vc, n_poly, rho, L, st_c, nullptr,
+                                 hs);
+    if (st != MRI_OK) return st;
+    st = mri_internal_fast_stage(m, &half, n_cells, ld, y_in, vh, n_poly, rho, L, st_c, nullptr,
+                                 hs, nullptr, 1);
+    if (st != MRI_OK) return st;
+    // the network's correction of the coarse result
+    HIP_TRY(mlp_infer(y_in, vc, vn, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, hs));
+    // residual check against the Richardson extrapolation; accepted cells take
+    // the corrected state, the others go to the fallback list
+    const double rich = 1.0 / (std::ldexp(1.0, method_order(coarse->method)) - 1.0);
+    HIP_TRY(mlp_gate(n_cells, ld, y_in, rho, n_poly, L, vc, vh, vn, st_c, rich, gate_tol, y_out,
+                     used_fallback, gate_value, status_out, list, count, hs));
+    // plain FP64 stage of the rejected cells: compacted (state into vh, forcing
+    // into rho_c), integrated into vn with a launch sized for every cell whose
+    // kernels stop at the device count, scattered back; no host synchronization
+    HIP_TRY(mlp_gather(MLP_NC, count, list, n_cells, y_in, ld, vh, ld, hs));
     if (n_poly > 0)
-        HIP_TRY(mlp_gather(n_poly * MLP_NC, count, list, h_count, rho, ld, rho_c, ld, st));
-    mri_status r = mri_internal_fast_stage(const_cast<mri_mech *>(mech), fallback, (int)h_count, ld,
-                                           full, mid, n_poly, rho_c, L, nullptr, nullptr, st);
-    if (r != MRI_OK) return r;
-    HIP_TRY(mlp_scatter(MLP_NC, count, list, h_count, mid, ld, y_out, ld, st));
+        HIP_TRY(mlp_gather(n_poly * MLP_NC, count, list, n_cells, rho, ld, rho_c, ld, hs));
+    st = mri_internal_fast_stage(m, fallback, n_cells, ld, vh, vn, n_poly, rho_c, L,
+                                 status_out ? st_f : nullptr, nullptr, hs, count);
+    if (st != MRI_OK) return st;
+    HIP_TRY(mlp_scatter(MLP_NC, count, list, n_cells, vn, ld, y_out, ld, hs));
+    if (status_out) HIP_TRY(mlp_scatter_i32(count, list, n_cells, st_f, status_out, hs));
+    if (n_fallback)
+        HIP_TRY(hipMemcpyAsync(n_fallback, count, sizeof(uint32_t), hipMemcpyDeviceToDevice, hs));
     return MRI_OK;
 }
 

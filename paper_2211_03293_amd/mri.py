@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("MRI_LIB_PATH") or os.path.join(_HERE, "libmri.so")
 
 MRI_OK, MRI_EINVAL, MRI_EHIP, MRI_ENONFINITE, MRI_EMAXSTEPS, MRI_ENOMEM, MRI_EUNSUPPORTED, \
     MRI_ECOMPILE = 0, -1, -2, -3, -4, -5, -6, -7
-CELL_NONFINITE, CELL_MAXSTEPS, CELL_TRANGE, CELL_NEARTIE = 1, 2, 4, 8
+CELL_NONFINITE, CELL_MAXSTEPS, CELL_TRANGE, CELL_NEARTIE, CELL_STIFF = 1, 2, 4, 8, 16
 FAST_RK4, FAST_ZONNEVELD43, FAST_HEUN, FAST_BS3, FAST_CK5 = 0, 1, 2, 3, 4
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
 
@@ -59,7 +59,7 @@ class mri_table_desc(C.Structure):
 class mri_fast_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("n_sub", C.c_int), ("rtol", C.c_double),
                 ("atol_Y", C.c_double), ("atol_T", C.c_double), ("max_steps", C.c_int),
-                ("kernel", C.c_int), ("block_size", C.c_int)]
+                ("kernel", C.c_int), ("block_size", C.c_int), ("stiff_limit", C.c_double)]
 
 
 class mri_advdiff_params(C.Structure):
@@ -115,6 +115,7 @@ _SIGS = {
     "mri_selftest_exp2": (_i, [_vp, _vp, _i, _vp]),
     "mri_selftest_exp2_t256": (_i, [_vp, _vp, _i, _vp]),
     "mri_status_count": (_i, [_vp, _i, C.c_int32, C.POINTER(C.c_int64), _vp]),
+    "mri_stiffness_check": (_i, [_vp, _i, _i, _vp, _d, _d, _vp, _vp, _vp]),
     "mri_get_counters": (None, [C.POINTER(mri_counters)]),
     "mri_reset_counters": (None, []),
     "mri_timing_enable": (_i, [_i]),
@@ -122,7 +123,7 @@ _SIGS = {
     "mri_batch_plan_create": (_i, [_vp, C.POINTER(mri_fast_opts), _i, C.POINTER(C.c_int64),
                                    C.POINTER(_vp)]),
     "mri_batch_run": (_i, [_vp, _vp, _vp, C.c_int64, _i, _vp, C.POINTER(C.c_double), _vp, _vp,
-                           _vp]),
+                           _vp, _vp]),
     "mri_batch_plan_tile": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "mri_batch_lane_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _vp]),
     "mri_batch_plan_destroy": (None, [_vp]),
@@ -135,15 +136,20 @@ _SIGS = {
     "mri_mlp_forward": (_i, [_vp, _i, _vp, _vp, _vp]),
     "mri_mlp_backward": (_i, [_vp, _i, _vp, _vp, _vp]),
     "mri_adam_step": (_i, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
-    "mri_mlp_feature_stats": (_i, [C.c_int64, C.c_int64, _vp, _i, _vp, _vp, _vp, _vp, _vp]),
-    "mri_mlp_featurize": (_i, [_i, _vp, C.c_int64, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mri_mlp_feature_stats": (_i, [C.c_int64, C.c_int64, _vp, _i, _vp, _vp, _vp, _vp, _vp,
+                                   _vp]),
+    "mri_mlp_featurize": (_i, [_i, _vp, C.c_int64, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                               _vp]),
     "mri_surrogate_create": (_i, [C.POINTER(C.c_int), C.POINTER(C.c_float),
                                   C.POINTER(C.c_double), C.POINTER(_vp)]),
     "mri_surrogate_destroy": (None, [_vp]),
-    "mri_surrogate_infer": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _d, _i, _vp]),
+    "mri_surrogate_infer": (_i, [_vp, _i, _i, _vp, _vp, _vp, _i, _vp, _d, _vp]),
+    "mri_surrogate_gate": (_i, [_i, _i, _vp, _i, _vp, _d, _vp, _vp, _vp, _vp, _d, _d, _vp, _vp,
+                                _vp, _vp, _vp, _vp]),
     "mri_surrogate_workspace_bytes": (_i, [_i, _i, _i, C.POINTER(_sz)]),
-    "mri_surrogate_stage": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), _d, _i, _i, _vp, _vp, _i, _vp,
-                                 _d, _vp, _vp, C.POINTER(C.c_int64), _vp, _sz, _vp]),
+    "mri_surrogate_stage": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), C.POINTER(mri_fast_opts), _d,
+                                 _i, _i, _vp, _vp, _i, _vp, _d, _vp, _vp, _vp, _vp, _vp, _sz,
+                                 _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -250,8 +256,16 @@ class Table:
 
 
 def fast_opts(method=FAST_RK4, n_sub=1, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000,
-              kernel=KERNEL_AUTO, block_size=0):
-    return mri_fast_opts(method, n_sub, rtol, atol_Y, atol_T, max_steps, kernel, block_size)
+              kernel=KERNEL_AUTO, block_size=0, stiff_limit=0.0):
+    return mri_fast_opts(method, n_sub, rtol, atol_Y, atol_T, max_steps, kernel, block_size,
+                         stiff_limit)
+
+
+def mri_stiffness_check(mech: Mech, n_cells, ld, y, h, limit, bound_out=None, status=None,
+                        stream=None):
+    _check(lib.mri_stiffness_check(mech.h, n_cells, ld, _ptr(y, "float64"), float(h),
+                                   float(limit), _ptr(bound_out, "float64"),
+                                   _ptr(status, "int32"), _stream(stream)))
 
 
 def mri_fast_stage(mech: Mech, opts, n_cells, ld, y_in, y_out, n_poly, rho_poly, L,
@@ -390,13 +404,13 @@ class BatchPlan:
                                          C.byref(self.h)))
 
     def run(self, y_in, y_out, ld, n_poly, rho_poly, L_per_set, status_out=None, steps_out=None,
-            stream=None):
+            rejects_out=None, stream=None):
         L = _f64(L_per_set)
         _check(lib.mri_batch_run(self.h, _ptr(y_in, "float64"), _ptr(y_out, "float64"), int(ld),
                                  n_poly, _ptr(rho_poly, "float64"),
                                  L.ctypes.data_as(C.POINTER(C.c_double)),
                                  _ptr(status_out, "int32"), _ptr(steps_out, "int32"),
-                                 _stream(stream)))
+                                 _ptr(rejects_out, "int32"), _stream(stream)))
 
     def tile(self):
         b, n = C.c_int(0), C.c_int(0)
@@ -462,15 +476,33 @@ class MLP:
             self.h = _null()
 
 
-def mri_mlp_feature_stats(n, ld, Y0, n_poly, RHO, Lv, Y1, stats, stream=None):
-    _check(lib.mri_mlp_feature_stats(int(n), int(ld), _ptr(Y0), n_poly, _ptr(RHO), _ptr(Lv),
-                                     _ptr(Y1), _ptr(stats), _stream(stream)))
+def mri_mlp_feature_stats(n, ld, Y0, n_poly, RHO, Lv, Y1, stats, Yb=None, stream=None):
+    _check(lib.mri_mlp_feature_stats(int(n), int(ld), _ptr(Y0, "float64"), n_poly,
+                                     _ptr(RHO, "float64"), _ptr(Lv, "float64"),
+                                     _ptr(Yb, "float64"), _ptr(Y1, "float64"),
+                                     _ptr(stats, "float64"), _stream(stream)))
 
 
-def mri_mlp_featurize(batch, idx, ld, Y0, n_poly, RHO, Lv, Y1, stats, X, T=None, stream=None):
-    _check(lib.mri_mlp_featurize(int(batch), _ptr(idx), int(ld), _ptr(Y0), n_poly, _ptr(RHO),
-                                 _ptr(Lv), _ptr(Y1), _ptr(stats), _ptr(X), _ptr(T),
-                                 _stream(stream)))
+def mri_mlp_featurize(batch, idx, ld, Y0, n_poly, RHO, Lv, Y1, stats, X, T=None, Yb=None,
+                      stream=None):
+    _check(lib.mri_mlp_featurize(int(batch), _ptr(idx, "int32"), int(ld), _ptr(Y0, "float64"),
+                                 n_poly, _ptr(RHO, "float64"), _ptr(Lv, "float64"),
+                                 _ptr(Yb, "float64"), _ptr(Y1, "float64"),
+                                 _ptr(stats, "float64"), _ptr(X, "bfloat16"),
+                                 _ptr(T, "float32"), _stream(stream)))
+
+
+def mri_surrogate_gate(n_cells, ld, y_in, n_poly, rho, L, v_coarse, v_half, v_net, richardson,
+                       gate_tol, y_out, fallback_list, n_fallback, status_coarse=None,
+                       used_fallback=None, gate_value=None, stream=None):
+    _check(lib.mri_surrogate_gate(n_cells, ld, _ptr(y_in, "float64"), n_poly,
+                                  _ptr(rho, "float64"), float(L), _ptr(v_coarse, "float64"),
+                                  _ptr(v_half, "float64"), _ptr(v_net, "float64"),
+                                  _ptr(status_coarse, "int32"), float(richardson),
+                                  float(gate_tol), _ptr(y_out, "float64"),
+                                  _ptr(used_fallback, "int32"), _ptr(gate_value, "float64"),
+                                  _ptr(fallback_list, "int32"), _ptr(n_fallback, "int32"),
+                                  _stream(stream)))
 
 
 class Surrogate:
@@ -482,9 +514,10 @@ class Surrogate:
         _check(lib.mri_surrogate_create(w, p.ctypes.data_as(C.POINTER(C.c_float)),
                                         st.ctypes.data_as(C.POINTER(C.c_double)), C.byref(self.h)))
 
-    def infer(self, n_cells, ld, y_in, y_out, n_poly, rho, L, half=0, stream=None):
-        _check(lib.mri_surrogate_infer(self.h, n_cells, ld, _ptr(y_in), _ptr(y_out), n_poly,
-                                       _ptr(rho), float(L), half, _stream(stream)))
+    def infer(self, n_cells, ld, y_in, y_out, n_poly, rho, L, base=None, stream=None):
+        _check(lib.mri_surrogate_infer(self.h, n_cells, ld, _ptr(y_in, "float64"),
+                                       _ptr(base, "float64"), _ptr(y_out, "float64"), n_poly,
+                                       _ptr(rho, "float64"), float(L), _stream(stream)))
 
     @staticmethod
     def workspace_bytes(n_cells, ld, n_poly):
@@ -492,15 +525,20 @@ class Surrogate:
         _check(lib.mri_surrogate_workspace_bytes(n_cells, ld, n_poly, C.byref(b)))
         return b.value
 
-    def stage(self, mech: Mech, fallback_opts, gate_tol, n_cells, ld, y_in, y_out, n_poly, rho, L,
-              ws, used_fallback=None, gate_value=None, stream=None):
-        nf = C.c_int64(0)
+    def stage(self, mech: Mech, coarse_opts, fallback_opts, gate_tol, n_cells, ld, y_in, y_out,
+              n_poly, rho, L, ws, used_fallback=None, gate_value=None, status_out=None,
+              n_fallback=None, stream=None):
+        """Gated stage; n_fallback: an optional device int32 tensor of one element
+        that receives the fallback count (nothing synchronizes)."""
         nbytes = ws.numel() * ws.element_size()
-        _check(lib.mri_surrogate_stage(self.h, mech.h, C.byref(fallback_opts), float(gate_tol),
-                                       n_cells, ld, _ptr(y_in), _ptr(y_out), n_poly, _ptr(rho),
-                                       float(L), _ptr(used_fallback), _ptr(gate_value),
-                                       C.byref(nf), _ptr(ws), nbytes, _stream(stream)))
-        return nf.value
+        _check(lib.mri_surrogate_stage(self.h, mech.h, C.byref(coarse_opts),
+                                       C.byref(fallback_opts), float(gate_tol), n_cells, ld,
+                                       _ptr(y_in, "float64"), _ptr(y_out, "float64"), n_poly,
+                                       _ptr(rho, "float64"), float(L),
+                                       _ptr(used_fallback, "int32"),
+                                       _ptr(gate_value, "float64"), _ptr(status_out, "int32"),
+                                       _ptr(n_fallback, "int32"), _ptr(ws), nbytes,
+                                       _stream(stream)))
 
     def __del__(self, _destroy=lib.mri_surrogate_destroy, _null=C.c_void_p):
         if getattr(self, "h", None) and self.h.value:

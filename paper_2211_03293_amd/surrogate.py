@@ -5,12 +5,12 @@ of the gated surrogate stage against the plain FP64 stage.
 Every arithmetic step runs in libmri kernels; this module only orders the
 calls, draws random sample indices and moves tensors.
 
-Stage data (the 64^3 workload, 21 species / 84 reactions): the workload's MRI
-slow steps are replayed stage by stage (slow RHS, forcing assembly, plain RK4
-fast stage).  In every fast stage a random subset of cells is recorded as a
-full-stage sample (Y0, rho, L -> Y1) and, for the step-doubling gate, as two
-half-stage samples (Y0, rho, L/2 -> Yh) and (Yh, rho, L/2 -> Yhh) integrated by
-the same plain method with half the substeps.
+The network predicts the correction from a coarse FP64 solve of the stage (RK4
+with N_COARSE substeps) to the plain stage (the workload's substeps).  Stage
+data (the 64^3 workload, 21 species / 84 reactions): the workload's MRI slow
+steps are replayed stage by stage (slow RHS, forcing assembly, plain RK4 fast
+stage); in every fast stage a random subset of cells is recorded as a sample
+(Y0, rho, L, coarse result Yc, plain result Y1).
 """
 from __future__ import annotations
 
@@ -25,6 +25,9 @@ from . import mri
 # the training network reads the padded feature rows written by mri_mlp_featurize
 # (96 columns, the last 7 always zero)
 WIDTHS = [mri.MLP_KPAD, 256, 256, 256, mri.MLP_OUTPUTS]
+# substeps of the coarse FP64 stage the network corrects (the residual check
+# also runs it with half as many)
+N_COARSE = 4
 
 
 def _torch():
@@ -35,14 +38,16 @@ def _torch():
 class StageData:
     """Stage samples on the device, SoA with leading dimension n (= count)."""
 
-    def __init__(self, Y0, RHO, L, Y1):
-        self.Y0, self.RHO, self.L, self.Y1 = Y0, RHO, L, Y1
+    def __init__(self, Y0, RHO, L, Yc, Y1):
+        self.Y0, self.RHO, self.L, self.Yc, self.Y1 = Y0, RHO, L, Yc, Y1
         self.n = L.numel()
 
 
-def generate_stage_data(n_full=1_000_000, workload=I.FIELD64, seed=None, log=print):
-    """Full- and half-stage samples from the workload's MRI run (n_full full-stage
-    samples spread evenly over all fast stages, plus 2 n_full half-stage ones)."""
+def generate_stage_data(n_full=1_000_000, workload=I.FIELD64, n_coarse=N_COARSE, seed=None,
+                        log=print):
+    """n_full samples spread evenly over all fast stages of the workload's run:
+    start state, forcing, stage length, coarse stage (n_coarse substeps) and
+    plain stage (the workload's substeps)."""
     torch = _torch()
     cfg = I.WORKLOADS[workload]
     mech = I.make_mechanism(workload)
@@ -60,9 +65,9 @@ def generate_stage_data(n_full=1_000_000, workload=I.FIELD64, seed=None, log=pri
     gen.manual_seed(1000 * I.WORKLOADS[workload].seed_base + 5 if seed is None else seed)
     n_stages = cfg.n_slow_steps * (tb.s - 1)
     per = int(math.ceil(n_full / n_stages))
-    buf = {k: [] for k in ("Y0", "RHO", "L", "Y1")}
+    buf = {k: [] for k in ("Y0", "RHO", "L", "Yc", "Y1")}
     opts_full = mri.fast_opts(n_sub=cfg.n_sub)
-    opts_half = mri.fast_opts(n_sub=max(1, cfg.n_sub // 2))
+    opts_coarse = mri.fast_opts(n_sub=n_coarse)
     sp = torch.cuda.current_stream().cuda_stream
     t0 = time.time()
     for step in range(cfg.n_slow_steps):
@@ -82,23 +87,20 @@ def generate_stage_data(n_full=1_000_000, workload=I.FIELD64, seed=None, log=pri
             rs = rho[:, :, idx].contiguous()
             y_next = torch.empty_like(y)
             mri.mri_fast_stage(m, opts_full, N, ld, y, y_next, 1, rho, L)
-            y1s = y_next[:, idx].contiguous()
-            yh = torch.empty_like(y0s)
-            mri.mri_fast_stage(m, opts_half, k, k, y0s, yh, 1, rs, 0.5 * L)
-            yhh = torch.empty_like(y0s)
-            mri.mri_fast_stage(m, opts_half, k, k, yh, yhh, 1, rs, 0.5 * L)
-            buf["Y0"] += [y0s, y0s, yh]
-            buf["RHO"] += [rs, rs, rs]
-            buf["L"] += [torch.full((k,), L, dtype=torch.float64, device="cuda"),
-                         torch.full((k,), 0.5 * L, dtype=torch.float64, device="cuda"),
-                         torch.full((k,), 0.5 * L, dtype=torch.float64, device="cuda")]
-            buf["Y1"] += [y1s, yh, yhh]
+            ycs = torch.empty_like(y0s)
+            mri.mri_fast_stage(m, opts_coarse, k, k, y0s, ycs, 1, rs, L)
+            buf["Y0"].append(y0s)
+            buf["RHO"].append(rs)
+            buf["L"].append(torch.full((k,), L, dtype=torch.float64, device="cuda"))
+            buf["Yc"].append(ycs)
+            buf["Y1"].append(y_next[:, idx].contiguous())
             y = y_next
     torch.cuda.synchronize()
     data = StageData(torch.cat(buf["Y0"], 1).contiguous(), torch.cat(buf["RHO"], 2).contiguous(),
-                     torch.cat(buf["L"]).contiguous(), torch.cat(buf["Y1"], 1).contiguous())
-    log(f"# stage data: {data.n} samples ({n_stages} stages x {per} cells x 3) in "
-        f"{time.time() - t0:.1f} s")
+                     torch.cat(buf["L"]).contiguous(), torch.cat(buf["Yc"], 1).contiguous(),
+                     torch.cat(buf["Y1"], 1).contiguous())
+    log(f"# stage data: {data.n} samples ({n_stages} stages x {per} cells, coarse stage "
+        f"{n_coarse} substeps) in {time.time() - t0:.1f} s")
     return data
 
 
@@ -119,18 +121,19 @@ def init_params(seed=4004):
 
 
 def train(data: StageData, steps=20000, batch=4096, lr=2e-3, lr_min=2e-5, seed=5005,
-          val_frac=0.05, log=print, log_every=2000):
+          val_frac=0.05, log=print, log_every=2000, init_seed=4004):
     """Adam with cosine learning-rate decay on the standardized MSE."""
     torch = _torch()
     stats = torch.empty(mri.MLP_STATS, dtype=torch.float64, device="cuda")
-    mri.mri_mlp_feature_stats(data.n, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats)
+    mri.mri_mlp_feature_stats(data.n, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats,
+                              Yb=data.Yc)
     gen = torch.Generator(device="cpu")
     gen.manual_seed(seed)
     perm = torch.randperm(data.n, generator=gen)
     n_val = int(data.n * val_frac)
     val_idx = perm[:n_val].to(torch.int32).to("cuda")
     tr_idx = perm[n_val:].to(torch.int32).to("cuda")
-    net = mri.MLP(WIDTHS, init_params(), max_batch=batch)
+    net = mri.MLP(WIDTHS, init_params(init_seed), max_batch=batch)
     X = torch.empty((batch, mri.MLP_KPAD), dtype=torch.bfloat16, device="cuda")
     T = torch.empty((batch, mri.MLP_OUTPUTS), dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -146,7 +149,7 @@ def train(data: StageData, steps=20000, batch=4096, lr=2e-3, lr_min=2e-5, seed=5
         bidx = tr_idx[order[pos:pos + batch]].contiguous()
         pos += batch
         mri.mri_mlp_featurize(batch, bidx, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats,
-                              X, T)
+                              X, T, Yb=data.Yc)
         net.forward(X)
         net.backward(T, loss)
         cur = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * it / steps))
@@ -171,7 +174,8 @@ def evaluate_loss(net, data, idx, stats, batch):
     tot, cnt = 0.0, 0
     for a in range(0, idx.numel() - batch + 1, batch):
         b = idx[a:a + batch].contiguous()
-        mri.mri_mlp_featurize(batch, b, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats, X, T)
+        mri.mri_mlp_featurize(batch, b, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats, X, T,
+                              Yb=data.Yc)
         net.forward(X, Y)
         tot += float(((Y - T) ** 2).mean().item()) * batch
         cnt += batch
@@ -187,10 +191,11 @@ def stage_error(y_pred, y_ref, n_species, floor=1e-8):
     return ((y_pred - y_ref).abs() / torch.maximum(y_ref.abs(), fl)).amax(0)
 
 
-def stage_inputs(workload=I.FIELD128, stage=1):
-    """State, forcing and stage length of one fast stage of the workload's first
-    slow step (slow RHS by the advection-diffusion kernel, forcing assembly by
-    libmri), as device tensors."""
+def slow_step_stages(m, workload=I.FIELD128):
+    """Start state, forcing and length of every fast stage of the workload's
+    first MIS-KW3 slow step (slow RHS by the advection-diffusion kernel, forcing
+    assembly by libmri, stages advanced by the plain FP64 fast stage of mechanism
+    handle m with the workload's substeps), as device tensors."""
     torch = _torch()
     cfg = I.WORKLOADS[workload]
     tb = I.table_mis_kw3()
@@ -200,101 +205,164 @@ def stage_inputs(workload=I.FIELD128, stage=1):
     N = cfg.n_cells
     y = torch.as_tensor(y_host, device="cuda")
     F = torch.empty((tb.s - 1, n, ld), dtype=torch.float64, device="cuda")
-    rho = torch.empty((1, n, ld), dtype=torch.float64, device="cuda")
     params = mri.advdiff_params(cfg.grid, n)
+    uptr = mri.C.cast(mri.C.pointer(params), mri.C.c_void_p).value
     sp = torch.cuda.current_stream().cuda_stream
-    rc = mri.lib.mri_advdiff_slow_rhs(0.0, y.data_ptr(), F[0].data_ptr(), N, ld,
-                                      mri.C.cast(mri.C.pointer(params), mri.C.c_void_p).value, sp)
-    assert rc == 0
-    mri.mri_forcing_assemble(t, stage, n, ld, F, rho)
-    L = float((tb.c[stage] - tb.c[stage - 1]) * cfg.H)
-    return y, rho, L, N, ld
+    out = []
+    for i in range(1, tb.s):
+        rc = mri.lib.mri_advdiff_slow_rhs(tb.c[i - 1] * cfg.H, y.data_ptr(), F[i - 1].data_ptr(),
+                                          N, ld, uptr, sp)
+        assert rc == 0
+        rho = torch.empty((1, n, ld), dtype=torch.float64, device="cuda")
+        mri.mri_forcing_assemble(t, i, n, ld, F, rho)
+        L = float((tb.c[i] - tb.c[i - 1]) * cfg.H)
+        out.append((y, rho, L))
+        y_next = torch.empty_like(y)
+        mri.mri_fast_stage(m, mri.fast_opts(n_sub=cfg.n_sub), N, ld, y, y_next, 1, rho, L)
+        y = y_next
+    torch.cuda.synchronize()
+    return out, N, ld
 
 
-def evaluate_stage(params, stats, workload=I.FIELD128, gate_tol=1e-4, repeats=3, log=print):
+def zero_network():
+    """Parameters and statistics of a network whose correction is zero: the
+    gated stage then checks the coarse result itself against the Richardson
+    extrapolation (the method without the learned part)."""
+    params = np.zeros(sum(WIDTHS[l + 1] * WIDTHS[l] + WIDTHS[l + 1]
+                          for l in range(len(WIDTHS) - 1)), dtype=np.float32)
+    stats = np.zeros(mri.MLP_STATS)
+    F, n = mri.MLP_FEATURES, mri.MLP_OUTPUTS
+    stats[F:2 * F] = 1.0                 # x_inv_std
+    stats[2 * F + n:2 * F + 2 * n] = 1.0  # y_inv_std
+    stats[2 * F + 2 * n:] = 1.0          # y_std; y_mean = 0
+    return params, stats
+
+
+def _timed(torch, fn, repeats):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(repeats):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / repeats
+
+
+def evaluate(params, stats, workload=I.FIELD128, gate_tol=1e-4, check_tol=None,
+             n_coarse=N_COARSE, repeats=3, log=print):
     """Gated surrogate stage against the plain FP64 stage on every cell of the
-    workload's first fast stage: fallback fraction, false accepts, error of the
-    accepted cells, wall times and the fused inference kernel time."""
+    three fast stages of the workload's first slow step: fallback fraction,
+    false accepts (accepted cells whose error exceeds the tolerance gate_tol),
+    error of the accepted cells, the errors of the coarse result, its Richardson
+    extrapolation and the network's correction on their own, the same pipeline
+    with a zero correction (no network), wall times (HIP events) and the
+    cheapest plain substep count within the tolerance.  The residual check
+    accepts at G <= check_tol (default gate_tol / 2: an accepted state is within
+    G of the Richardson extrapolation, so it meets gate_tol wherever that
+    estimate is within gate_tol / 2 of the plain stage)."""
+    check = 0.5 * gate_tol if check_tol is None else check_tol
     torch = _torch()
     cfg = I.WORKLOADS[workload]
     mech = I.make_mechanism(workload)
+    S = mech.n_species
     m = mri.Mech(mech)
     m.specialize(128, load=True)
-    y, rho, L, N, ld = stage_inputs(workload)
-    opts = mri.fast_opts(n_sub=cfg.n_sub)
-    ref = torch.empty_like(y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(repeats):
-        mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)
-    e1.record()
-    torch.cuda.synchronize()
-    t_plain = e0.elapsed_time(e1) / repeats
-    sg = mri.Surrogate([mri.MLP_KPAD, 256, 256, 256, mri.MLP_OUTPUTS], params, stats)
-    raw = torch.empty_like(y)
-    sg.infer(N, ld, y, raw, 1, rho, L)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(repeats):
-        sg.infer(N, ld, y, raw, 1, rho, L)
-    e1.record()
-    torch.cuda.synchronize()
-    t_inf = e0.elapsed_time(e1) / repeats
+    stages, N, ld = slow_step_stages(m, workload)
+    plain = mri.fast_opts(n_sub=cfg.n_sub)
+    coarse = mri.fast_opts(n_sub=n_coarse)
+    half = mri.fast_opts(n_sub=n_coarse // 2)
+    nets = {"learned": mri.Surrogate(WIDTHS, params, stats),
+            "no_network": mri.Surrogate(WIDTHS, *zero_network())}
     ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
                      device="cuda")
     used = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    gv = torch.zeros(ld, dtype=torch.float32, device="cuda")
-    out = torch.empty_like(y)
-    nf = sg.stage(m, opts, gate_tol, N, ld, y, out, 1, rho, L, ws, used, gv)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(repeats):
-        t1 = time.perf_counter()
-        nf = sg.stage(m, opts, gate_tol, N, ld, y, out, 1, rho, L, ws, used, gv)
-        torch.cuda.synchronize()
-        times.append((time.perf_counter() - t1) * 1e3)
-    t_sur = float(np.median(times))
-    err = stage_error(out[:, :N], ref[:, :N], mech.n_species)
-    err6 = stage_error(out[:, :N], ref[:, :N], mech.n_species, floor=1e-6)
-    acc = used[:N] == 0
-    n_acc = int(acc.sum().item())
-    err_raw = stage_error(raw[:, :N], ref[:, :N], mech.n_species)
+    gv = torch.zeros(ld, dtype=torch.float64, device="cuda")
+    st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rich = 1.0 / 15.0
+    per_stage = []
+    agg = {k: dict(cells=0, fallback=0, false_accepts=0, max_err=0.0, ms=0.0, flagged=0)
+           for k in nets}
+    t_plain = t_coarse = t_half = t_inf = 0.0
+    err_parts = dict(coarse=[], richardson=[], network=[])
+    cheapest_need = 0
+    for k, (y, rho, L) in enumerate(stages):
+        ref = torch.empty_like(y)
+        tp = _timed(torch, lambda: mri.mri_fast_stage(m, plain, N, ld, y, ref, 1, rho, L), repeats)
+        vc, vh, vn = torch.empty_like(y), torch.empty_like(y), torch.empty_like(y)
+        tc = _timed(torch, lambda: mri.mri_fast_stage(m, coarse, N, ld, y, vc, 1, rho, L), repeats)
+        th = _timed(torch, lambda: mri.mri_fast_stage(m, half, N, ld, y, vh, 1, rho, L), repeats)
+        sg = nets["learned"]
+        ti = _timed(torch, lambda: sg.infer(N, ld, y, vn, 1, rho, L, base=vc), repeats)
+        t_plain, t_coarse, t_half, t_inf = t_plain + tp, t_coarse + tc, t_half + th, t_inf + ti
+        ve = vc + rich * (vc - vh)
+        for name, v in (("coarse", vc), ("richardson", ve), ("network", vn)):
+            err_parts[name].append(torch.nan_to_num(stage_error(v[:, :N], ref[:, :N], S),
+                                                    nan=float("inf")))
+        row = dict(stage=k + 1, L=L, plain_ms=round(tp, 3))
+        out = torch.empty_like(y)
+        for name, net in nets.items():
+            def run():
+                net.stage(m, coarse, plain, check, N, ld, y, out, 1, rho, L, ws, used, gv, st, nf)
+            ts = _timed(torch, run, repeats)
+            err = torch.nan_to_num(stage_error(out[:, :N], ref[:, :N], S), nan=float("inf"))
+            acc = used[:N] == 0
+            n_fb = int(nf.item())
+            assert n_fb == int((~acc).sum().item())
+            a = agg[name]
+            a["cells"] += N
+            a["fallback"] += n_fb
+            a["false_accepts"] += int(((err > gate_tol) & acc).sum().item())
+            a["max_err"] = max(a["max_err"], float(err.max().item()))
+            a["ms"] += ts
+            a["flagged"] += int((st[:N] != 0).sum().item())
+            row[name] = dict(ms=round(ts, 3), fallback_cells=n_fb,
+                             max_err=float(err.max().item()))
+        per_stage.append(row)
+        # fair comparison: fewest plain substeps within gate_tol on every cell of this stage
+        alt = torch.empty_like(y)
+        for n_sub in (5, 8, 10, 13, 16, 20, 25, 32, 40, cfg.n_sub):
+            mri.mri_fast_stage(m, mri.fast_opts(n_sub=n_sub), N, ld, y, alt, 1, rho, L)
+            e = float(torch.nan_to_num(stage_error(alt[:, :N], ref[:, :N], S),
+                                       nan=float("inf")).max().item())
+            if e <= gate_tol:
+                cheapest_need = max(cheapest_need, n_sub)
+                break
+    t_cheap = 0.0
+    for (y, rho, L) in stages:
+        alt = torch.empty_like(y)
+        t_cheap += _timed(torch, lambda: mri.mri_fast_stage(
+            m, mri.fast_opts(n_sub=cheapest_need), N, ld, y, alt, 1, rho, L), repeats)
 
     def q(x, p):
-        return float(torch.quantile(x.float()[:1 << 24], p).item()) if x.numel() else None
+        x = x.float()
+        return float(torch.quantile(x[:1 << 24], p).item()) if x.numel() else None
 
-    # fair comparison: the cheapest plain substep count whose stage result is
-    # within gate_tol of the workload's own (n_sub) result on every cell
-    cheapest = None
-    alt = torch.empty_like(y)
-    for n_sub in sorted(c for c in (5, 8, 10, 13, 16, 20, 25, 32, 40) if c < cfg.n_sub):
-        o2 = mri.fast_opts(n_sub=n_sub)
-        mri.mri_fast_stage(m, o2, N, ld, y, alt, 1, rho, L)
-        torch.cuda.synchronize()
-        e = float(torch.nan_to_num(stage_error(alt[:, :N], ref[:, :N], mech.n_species),
-                                   nan=float("inf")).max().item())
-        if e <= gate_tol:
-            e0.record()
-            mri.mri_fast_stage(m, o2, N, ld, y, alt, 1, rho, L)
-            e1.record()
-            torch.cuda.synchronize()
-            cheapest = dict(n_sub=n_sub, max_err=e, ms=round(e0.elapsed_time(e1), 3))
-            break
-    res = dict(cells=N, gate_tol=gate_tol, fallback_cells=int(nf), fallback_frac=nf / N,
-               accepted_cells=n_acc,
-               false_accepts=int(((err > gate_tol) & acc).sum().item()),
-               max_err_accepted=float(err[acc].max().item()) if n_acc else None,
-               p999_err_accepted=q(err[acc], 0.999) if n_acc else None,
-               max_err_accepted_floor_1e6=float(err6[acc].max().item()) if n_acc else None,
-               max_err_all=float(err.max().item()),
-               raw_err_median=q(err_raw, 0.5), raw_err_p90=q(err_raw, 0.9),
-               raw_frac_within_tol=float((err_raw <= gate_tol).float().mean().item()),
-               plain_ms=round(t_plain, 3), surrogate_stage_ms=round(t_sur, 3),
-               infer_ms=round(t_inf, 4), speedup=round(t_plain / t_sur, 3),
-               plain_cheapest_within_tol=cheapest)
-    log(f"# surrogate stage on {N} cells at gate {gate_tol:g}: fallback {nf / N:.3f}, "
-        f"false accepts {res['false_accepts']}, plain {t_plain:.2f} ms, gated {t_sur:.2f} ms, "
-        f"one inference {t_inf:.3f} ms")
+    parts = {}
+    for name, lst in err_parts.items():
+        e = torch.cat(lst)
+        parts[name] = dict(max=float(e.max().item()), median=q(e, 0.5), p999=q(e, 0.999),
+                           frac_within_tol=float((e <= gate_tol).float().mean().item()))
+    n_all = agg["learned"]["cells"]
+    res = dict(cells=n_all, stages=len(stages), gate_tol=gate_tol, check_tol=check,
+               n_coarse=n_coarse,
+               plain_n_sub=cfg.n_sub, plain_ms=round(t_plain, 3),
+               coarse_ms=round(t_coarse, 3), half_ms=round(t_half, 3), infer_ms=round(t_inf, 3),
+               errors=parts, per_stage=per_stage,
+               plain_cheapest_within_tol=dict(n_sub=cheapest_need, ms=round(t_cheap, 3)))
+    for name, a in agg.items():
+        res[name] = dict(ms=round(a["ms"], 3), fallback_cells=a["fallback"],
+                         fallback_frac=a["fallback"] / n_all, false_accepts=a["false_accepts"],
+                         max_err=a["max_err"], flagged_cells=a["flagged"],
+                         speedup_vs_plain=round(t_plain / a["ms"], 3),
+                         speedup_vs_cheapest_plain=round(t_cheap / a["ms"], 3))
+    L0 = res["learned"]
+    log(f"# surrogate on {n_all} cell-stages at gate {gate_tol:g}: fallback "
+        f"{L0['fallback_frac']:.2e}, false accepts {L0['false_accepts']}, max err "
+        f"{L0['max_err']:.2e}; plain {t_plain:.2f} ms, gated {L0['ms']:.2f} ms "
+        f"({L0['speedup_vs_plain']:.2f}x; cheapest plain n_sub {cheapest_need}: {t_cheap:.2f} ms); "
+        f"no network: fallback {res['no_network']['fallback_frac']:.2e}, "
+        f"{res['no_network']['ms']:.2f} ms")
     return res

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(mri):
 
 
 def test_abi_version(mri):
-    assert mri.lib.mri_abi_version() == 1
+    assert mri.lib.mri_abi_version() == 2
 
 
 def test_mech_validation(mri):
@@ -335,3 +335,39 @@ def test_concurrent_specialization_of_one_handle(mri):
         by_method.setdefault(meth, set()).add(h)
     assert all(len(v) == 1 for v in by_method.values()), by_method
     assert by_method[mri.FAST_RK4] != by_method[mri.FAST_HEUN]
+
+
+def test_stiffness_check_validation(mri):
+    """Argument errors of the stiffness monitor come back before device work."""
+    m = mri.Mech(I.make_mechanism(I.SMALL))
+    lin = mri.Mech(A_linear=np.eye(3))
+    for args, status in (((m, -1, 64, None, 1e-8, 2.785), mri.MRI_EINVAL),
+                         ((m, 64, 32, None, 1e-8, 2.785), mri.MRI_EINVAL),
+                         ((m, 8, 64, None, -1e-8, 2.785), mri.MRI_EINVAL),
+                         ((m, 8, 64, None, 1e-8, float("nan")), mri.MRI_EINVAL),
+                         ((lin, 8, 64, None, 1e-8, 2.785), mri.MRI_EUNSUPPORTED)):
+        with pytest.raises(mri.MriError) as e:
+            mri.mri_stiffness_check(*args, stream=0)
+        assert e.value.status == status
+    mri.mri_stiffness_check(m, 0, 64, None, 1e-8, 2.785, stream=0)      # nothing to do
+    with pytest.raises(mri.MriError) as e:
+        mri.mri_fast_stage(m, mri.fast_opts(n_sub=4, stiff_limit=-1.0), 0, 64, None, None, 0,
+                           None, 1e-8, stream=0)
+    assert e.value.status == mri.MRI_EINVAL
+
+
+def test_exp2_coefficient_generators_reproduce_the_header():
+    """The constants of both device exponentials in mri_math.h are what their
+    committed generators compute (polynomial: interpolation at the Chebyshev
+    nodes in 50-digit arithmetic; table: 2^(j/256) and Taylor terms in 60)."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2211_03293_amd", "csrc")
+    text = open(os.path.join(here, "mri_math.h")).read()
+    for name in ("gen_exp2_poly", "gen_exp2_table"):
+        spec = importlib.util.spec_from_file_location(name, os.path.join(here, name + ".py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        a = text.index(mod.BEGIN) + len(mod.BEGIN)
+        assert text[a:text.index(mod.END)] == mod.body(), name

@@ -507,3 +507,65 @@ def test_checkpoint_resume_is_bitwise(torch, mri, tmp_path):
     steps(c, int(ck["step"]), 6)
     assert float(ck["t"]) == 3 * H
     assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+
+
+def test_stiffness_bound_matches_oracle(torch, mri, O):
+    """The device's stiffness bound (Gershgorin bound of the species Jacobian)
+    against the oracle's on 1000 cells of the 21- and 53-species mechanisms, and
+    the MRI_CELL_STIFF bit exactly where h B exceeds the limit (cells within
+    1e-10 of the threshold excluded)."""
+    for wl in (I.FIELD64, I.LARGE128):
+        mech = I.make_mechanism(wl)
+        rng = np.random.Generator(np.random.PCG64(71))
+        y = I.independent_cells(1000, mech.n_species, rng)
+        n, ld = y.shape
+        ref = O.Oracle(mech).stiff_bound(np.ascontiguousarray(y[:, :1000]))
+        m = mri.Mech(mech)
+        b = torch.zeros(ld, dtype=torch.float64, device="cuda")
+        st = torch.full((ld,), 4, dtype=torch.int32, device="cuda")
+        h = 2.785 / float(np.median(ref))
+        mri.mri_stiffness_check(m, 1000, ld, _dev(torch, y), h, 2.785, b, st)
+        torch.cuda.synchronize()
+        got = b.cpu().numpy()[:1000]
+        rel = np.abs(got - ref) / ref
+        flag = (st.cpu().numpy()[:1000] & mri.CELL_STIFF) != 0
+        want = h * ref > 2.785
+        near = np.abs(h * ref / 2.785 - 1.0) < 1e-10
+        print(f"{wl}: bound max rel diff {rel.max():.1e}, {flag.sum()} of 1000 flagged")
+        assert rel.max() <= 1e-12
+        assert np.array_equal(flag[~near], want[~near]) and 300 < flag.sum() < 700
+        # OR-ed into the existing words
+        assert np.all((st.cpu().numpy()[:1000] & 4) == 4)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_stage_stiffness_monitor(torch, mri, O, kernel):
+    """A fixed-step stage with the monitor on: the state is bitwise the stage
+    without it, the step counts are n_sub, and MRI_CELL_STIFF marks exactly the
+    cells whose stage start state has h B above the limit (h = L / n_sub)."""
+    mech = I.make_mechanism(I.SMALL)
+    orc = O.Oracle(mech)
+    y0 = I.initial_state(I.SMALL)
+    n, ld = y0.shape
+    rho = _small_forcing(O, orc, y0, 1)
+    L, n_sub = 3e-7, 5
+    bound = orc.stiff_bound(np.ascontiguousarray(y0[:, :512]))
+    limit = float(np.median(bound)) * L / n_sub
+    m = mri.Mech(mech)
+    yd, rd = _dev(torch, y0), _dev(torch, rho)
+    outs = []
+    for lim in (0.0, limit):
+        out = torch.zeros_like(yd)
+        st = torch.full((ld,), 99, dtype=torch.int32, device="cuda")
+        steps = torch.full((ld,), 99, dtype=torch.int32, device="cuda")
+        opts = mri.fast_opts(n_sub=n_sub, kernel=_kernel(mri, kernel), stiff_limit=lim)
+        mri.mri_fast_stage(m, opts, 512, ld, yd, out, 1, rd, L, st, steps)
+        torch.cuda.synchronize()
+        outs.append((out.cpu().numpy(), st.cpu().numpy()[:512], steps.cpu().numpy()[:512]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.all(outs[1][2] == n_sub)
+    want = (L / n_sub) * bound > limit
+    near = np.abs((L / n_sub) * bound / limit - 1.0) < 1e-10
+    got = (outs[1][1] & mri.CELL_STIFF) != 0
+    assert np.array_equal(got[~near], want[~near]) and 100 < got.sum() < 400
+    assert np.array_equal(outs[1][1] & ~mri.CELL_STIFF, outs[0][1])

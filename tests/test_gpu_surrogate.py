@@ -1,6 +1,18 @@
-"""GPU checks of the surrogate: MFMA GEMM layout, forward and gradients against
-the oracle MLP (bfloat16-emulating mode), the fused inference kernel against
-the training forward, Adam, the gate's limiting cases and a short training run."""
+"""GPU checks of the surrogate against the oracle: MFMA GEMM layout, forward and
+gradients (bfloat16-emulating mode), Adam, feature statistics, features and
+targets, the fused inference kernel, the residual check, the whole gated stage
+(element by element), graph capture of the gated stage and a short training run.
+
+Tolerances of the network comparisons come from the two differences between
+the kernels and the oracle's bfloat16 mode: the FP32 accumulation order (MFMA
+tiles against a sequential FP64 sum rounded once) and the bfloat16 roundings
+that it flips (a hidden activation whose exact value lies within the
+accumulation difference of a rounding midpoint moves by one bfloat16 ulp,
+2^-8 relative).  With about 1e-6 relative accumulation difference and 768
+activations per cell, a fraction ~1e-6 / 2^-9 of the activations flip, so
+most cells agree to FP32 rounding and a few move by ~1e-4 of an output's
+scale; norm-wise the outputs and gradients differ by 1e-4 to 4e-4 (measured),
+bounded here by 1e-3."""
 import math
 
 import numpy as np
@@ -76,8 +88,8 @@ def test_mlp_forward_and_gradients_match_oracle(torch, mri, oracle_mod):
     l_o, g_o = O.mlp_loss_grad(widths, p.astype(np.float64), X.astype(np.float64),
                                T.astype(np.float64), bf16=True)
     e_fwd = _relnorm(Y.cpu().numpy(), y_o)
-    assert e_fwd < 5e-3, e_fwd
-    assert loss.item() == pytest.approx(l_o, rel=1e-2)
+    assert e_fwd < 1e-3, e_fwd
+    assert loss.item() == pytest.approx(l_o, rel=1e-3)
     g = net.grads()
     off = 0
     worst = 0.0
@@ -88,7 +100,7 @@ def test_mlp_forward_and_gradients_match_oracle(torch, mri, oracle_mod):
             worst = max(worst, e)
             off += sz
     print(f"forward rel err {e_fwd:.2e}, worst gradient tensor rel err {worst:.2e}")
-    assert worst < 2e-2, worst
+    assert worst < 1e-3, worst
 
 
 def test_adam_step(torch, mri):
@@ -110,173 +122,405 @@ def test_adam_step(torch, mri):
     np.testing.assert_allclose(net.params(), ref, rtol=1e-5, atol=1e-6)
 
 
-def _cells(torch, mri, n_cells, seed):
+def _cells(n_cells, seed, n_poly=1):
+    """Independent cells of the 64^3 workload's mechanism with a random forcing
+    (mass-fraction forcing of zero sum per cell)."""
     mech = I.make_mechanism(I.FIELD64)
     rng = np.random.Generator(np.random.PCG64(seed))
     y = I.independent_cells(n_cells, mech.n_species, rng)
-    rho = (rng.normal(size=(1, *y.shape)) * 1e3)
+    rho = rng.normal(size=(n_poly, *y.shape)) * 1e3
     rho[:, :mech.n_species] -= rho[:, :mech.n_species].mean(axis=1, keepdims=True)
+    rho[:, :, n_cells:] = 0.0
     return mech, y, rho
 
 
-@pytest.mark.parametrize("n_poly", [1, 2])
-def test_fused_inference_matches_training_forward(torch, mri, n_poly):
-    """The fused kernel (activations in registers, permuted inputs) reproduces the
-    training-path forward on the same features, for the full and both half
-    stages; with two forcing terms the half stages see the forcing polynomial
-    re-expanded on each half (first half: r0 + r1 tau/2; second half:
-    r0 + r1/2 + r1 tau/2), which the training path is given explicitly."""
-    widths = [89, 256, 256, 256, 22]
-    Ws, bs, rng = _rand_net(widths, 5)
-    p = _pack(Ws, bs)
-    mech, y, rho1 = _cells(torch, mri, 1000, 6)
-    rho = np.concatenate([rho1, 0.5 * rho1[::-1, ::-1]]) if n_poly == 2 else rho1
-    n, ld = y.shape
-    yd = torch.as_tensor(y, device="cuda")
-    rd = torch.as_tensor(rho, device="cuda")
-    L = 3e-8
-    stats = torch.empty(mri.MLP_STATS, dtype=torch.float64, device="cuda")
-    Lv = torch.full((ld,), L, dtype=torch.float64, device="cuda")
-    mri.mri_mlp_feature_stats(1000, ld, yd, n_poly, rd, Lv, yd, stats)
-    st = stats.cpu().numpy()
-    st[2 * 89 + 2 * 22:] = rng.uniform(0.5, 2.0, 22) * 1e-3      # y_std
-    st[2 * 89:2 * 89 + 22] = rng.normal(size=22) * 1e-4         # y_mean
-    stats = torch.as_tensor(st, device="cuda")
-    sg = mri.Surrogate(widths, p, st)
-    # the training path reads 96 padded feature columns
-    W1p = np.zeros((256, 96), np.float32)
-    W1p[:, :89] = Ws[0]
-    net = mri.MLP([96] + widths[1:], _pack([W1p] + Ws[1:], bs), max_batch=ld)
-    X = torch.empty((ld, 96), dtype=torch.bfloat16, device="cuda")
-    Y = torch.empty((ld, 22), dtype=torch.float32, device="cuda")
-    for half, Lh in ((0, L), (1, 0.5 * L), (2, 0.5 * L)):
-        out = torch.empty_like(yd)
-        sg.infer(1000, ld, yd, out, n_poly, rd, L, half=half)
-        Lv.fill_(Lh)
-        rh = rho.copy()
-        if n_poly == 2 and half == 1:
-            rh[1] = 0.5 * rho[1]
-        elif n_poly == 2 and half == 2:
-            rh[0] = rho[0] + 0.5 * rho[1]
-            rh[1] = 0.5 * rho[1]
-        mri.mri_mlp_featurize(ld, None, ld, yd, n_poly, torch.as_tensor(rh, device="cuda"), Lv,
-                              None, stats, X)
-        net.forward(X, Y)
-        torch.cuda.synchronize()
-        d = st[2 * 89:2 * 89 + 22][:, None] + st[2 * 89 + 44:][:, None] * Y.cpu().numpy().T.astype(np.float64)
-        # species: log-increment of Y + 1e-8; T: plain increment
-        d_out = np.log(np.maximum(out.cpu().numpy()[:22] + 1e-8, 1e-300)) - np.log(np.maximum(y[:22], 0) + 1e-8)
-        d_out[21] = out.cpu().numpy()[21] - y[21]
-        e = _relnorm(d_out[:, :1000], d[:, :1000])
-        print(f"half={half}: fused vs training forward rel err {e:.2e}")
-        assert e < 2e-2
+def _dev(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
 
 
-def test_gate_limits(torch, mri):
-    """gate_tol = 0 sends every cell to the FP64 fallback (bitwise the plain
-    stage); gate_tol = inf accepts every cell (the doubled prediction)."""
-    widths = [89, 256, 256, 256, 22]
-    Ws, bs, rng = _rand_net(widths, 7, scale=0.5)
-    p = _pack(Ws, bs)
-    mech, y, rho = _cells(torch, mri, 700, 8)
-    n, ld = y.shape
+def _bf16_bits(x):
+    return np.ascontiguousarray(np.asarray(x, np.float32)).view(np.uint32) >> 16
+
+
+def test_feature_statistics_match_oracle(torch, mri, oracle_mod):
+    """Device statistics (sums and sums of squares, fixed order) against the
+    oracle's two-pass moments, with a base state for the targets."""
+    O = oracle_mod
+    mech, y0, rho = _cells(3000, 11, n_poly=2)
+    rng = np.random.Generator(np.random.PCG64(12))
+    n, ld = y0.shape
+    N = 3000
+    yb = y0 * (1 + 1e-3 * rng.normal(size=y0.shape))
+    y1 = y0 * (1 + 1e-2 * rng.normal(size=y0.shape))
+    Lv = np.exp(rng.uniform(np.log(2e-8), np.log(4e-8), ld))
+    ref = O.sur_stats(mech.n_species, y0[:, :N], rho[:, :, :N], Lv[:N], y1[:, :N], Yb=yb[:, :N])
+    st = torch.empty(mri.MLP_STATS, dtype=torch.float64, device="cuda")
+    mri.mri_mlp_feature_stats(N, ld, _dev(torch, y0), 2, _dev(torch, rho), _dev(torch, Lv),
+                              _dev(torch, y1), st, Yb=_dev(torch, yb))
+    got = st.cpu().numpy()
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    # the species logarithms are taken in FP32 on the device (the features are
+    # rounded to bfloat16 afterwards): their moments agree to FP32 accuracy,
+    # every other statistic to FP64 rounding of the sums
+    logs = np.zeros(rel.size, dtype=bool)
+    logs[:21] = True
+    logs[89:89 + 21] = True
+    print(f"statistics: max rel diff {rel[~logs].max():.2e} (FP64 features and targets), "
+          f"{rel[logs].max():.2e} (FP32 species logarithms)")
+    assert rel[~logs].max() <= 1e-10
+    assert rel[logs].max() <= 1e-6
+
+
+def test_featurize_rounds_to_nearest_even(torch, mri):
+    """The feature path's FP32 -> bfloat16 conversion rounds to the nearest
+    bfloat16 and breaks exact ties to the even neighbour (features chosen
+    exactly representable in FP32: the temperature feature with mean 0 and
+    inverse standard deviation 1)."""
+    N = 64
+    T = np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), -(1.0 + 3 * 2.0 ** -8),
+                  2.0 + 2.0 ** -7, 1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -8 - 2.0 ** -20,
+                  3.0 + 2.0 ** -7] + [1.5] * (N - 8))
+    want = np.array([1.0, 1.0 + 2.0 ** -6, -1.0, -(1.0 + 2.0 ** -6), 2.0, 1.0 + 2.0 ** -7, 1.0,
+                     3.0] + [1.5] * (N - 8))
+    y = np.zeros((22, N))
+    y[:21] = 1.0 / 21
+    y[21] = T
     st = np.zeros(mri.MLP_STATS)
     st[89:2 * 89] = 1.0
-    st[2 * 89 + 22:2 * 89 + 44] = 1.0
-    st[2 * 89 + 44:] = 1e-6
+    st[2 * 89 + 22:] = 1.0
+    X = torch.empty((N, 96), dtype=torch.bfloat16, device="cuda")
+    mri.mri_mlp_featurize(N, None, N, _dev(torch, y), 0, None, _dev(torch, np.full(N, 1e-8)),
+                          None, _dev(torch, st), X)
+    torch.cuda.synchronize()
+    got = X[:, 21].float().cpu().numpy().astype(np.float64)
+    print("ties:", got[:8].tolist())
+    assert np.array_equal(got, want)
+
+
+def test_featurize_matches_oracle(torch, mri, oracle_mod):
+    """Training features: bitwise equal bfloat16 values except species
+    logarithms within one bfloat16 ulp where the device's FP32 logarithm sits on
+    the other side of a rounding midpoint; targets equal to FP32 rounding."""
+    O = oracle_mod
+    S = 21
+    mech, y0, rho = _cells(4000, 13, n_poly=3)
+    rng = np.random.Generator(np.random.PCG64(14))
+    n, ld = y0.shape
+    N = 4000
+    yb = y0 * (1 + 1e-3 * rng.normal(size=y0.shape))
+    y1 = y0 * (1 + 1e-2 * rng.normal(size=y0.shape))
+    Lv = np.exp(rng.uniform(np.log(2e-8), np.log(4e-8), ld))
+    stats = O.sur_stats(S, y0[:, :N], rho[:, :, :N], Lv[:N], y1[:, :N], Yb=yb[:, :N])
+    X_o, T_o = O.sur_featurize(S, y0[:, :N], rho[:, :, :N], Lv[:N], stats, kpad=96,
+                               Yb=yb[:, :N], Y1=y1[:, :N])
+    X = torch.empty((N, 96), dtype=torch.bfloat16, device="cuda")
+    T = torch.empty((N, 22), dtype=torch.float32, device="cuda")
+    idx = torch.arange(N, dtype=torch.int32, device="cuda")
+    mri.mri_mlp_featurize(N, idx, ld, _dev(torch, y0), 3, _dev(torch, rho), _dev(torch, Lv),
+                          _dev(torch, y1), _dev(torch, stats), X, T, Yb=_dev(torch, yb))
+    torch.cuda.synchronize()
+    xg = _bf16_bits(X.float().cpu().numpy())
+    xo = _bf16_bits(O.bf16_round(X_o.astype(np.float32)))
+    diff = xg != xo
+    cols = np.nonzero(diff.any(axis=0))[0]
+    print(f"features: {int(diff.sum())} of {diff.size} differ (columns {cols.tolist()})")
+    for i, k in zip(*np.nonzero(diff)):
+        if k >= S:
+            print(f"  cell {i} feature {k}: oracle {X_o[i, k]!r} ({np.float32(X_o[i, k]).view(np.uint32):08x})"
+                  f" device {float(X[i, k].float().item())!r}")
+    assert np.all(cols < S)                        # only the FP32 logarithms
+    assert np.all(np.abs(xg[diff].astype(np.int64) - xo[diff].astype(np.int64)) == 1)
+    assert diff.sum() <= 1e-3 * N * S
+    Tg = T.cpu().numpy().astype(np.float64)
+    To = T_o.astype(np.float32).astype(np.float64)
+    ulp = np.spacing(np.abs(To).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(Tg - To) <= 2 * ulp)
+
+
+def _net_and_stats(oracle_mod, seed, y, rho, L, N, y_std):
+    """A random 89-256-256-256-22 network and statistics from the oracle over
+    the cells (the output scale y_std, output means zero)."""
+    widths = [89, 256, 256, 256, 22]
+    Ws, bs, rng = _rand_net(widths, seed)
+    p = _pack(Ws, bs)
+    Lv = np.full(y.shape[1], L)
+    st = oracle_mod.sur_stats(21, y[:, :N], rho[:, :, :N], Lv[:N], y[:, :N])
+    st[2 * 89:2 * 89 + 22] = 0.0
+    st[2 * 89 + 22:2 * 89 + 44] = 1.0 / y_std
+    st[2 * 89 + 44:] = y_std
+    return widths, p, st
+
+
+@pytest.mark.parametrize("n_poly", [1, 2, 3])
+def test_fused_inference_matches_oracle(torch, mri, oracle_mod, n_poly):
+    """The fused kernel (features in LDS, weights streamed, activations in
+    registers, FP64 de-standardization) against the oracle's bfloat16-mode
+    inference, element by element in standardized output units z, on 1000
+    cells (7 full blocks of 128 and a ragged tail) with a base state."""
+    O = oracle_mod
+    N = 1000
+    mech, y, rho = _cells(N, 15 + n_poly, n_poly=n_poly)
+    rng = np.random.Generator(np.random.PCG64(20 + n_poly))
+    n, ld = y.shape
+    base = y * (1 + 1e-3 * rng.normal(size=y.shape))
+    L = 3.3e-8
+    y_std = np.full(22, 1e-3)
+    y_std[21] = 0.5
+    widths, p, st = _net_and_stats(O, 21, y, rho, L, N, y_std)
+    out_o, z_o = O.sur_infer(21, widths, p.astype(np.float64), st, y, rho, L, N=N, base=base,
+                             bf16=True, want_z=True)
+    sg = mri.Surrogate(widths, p, st)
+    out = torch.zeros((n, ld), dtype=torch.float64, device="cuda")
+    sg.infer(N, ld, _dev(torch, y), out, n_poly, _dev(torch, rho), L, base=_dev(torch, base))
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    # standardized output difference: species through log(Y + 1e-8), T plain
+    dz = np.empty((22, N))
+    dz[:21] = (np.log(g[:21, :N] + 1e-8) - np.log(out_o[:21, :N] + 1e-8)) / y_std[:21, None]
+    dz[21] = (g[21, :N] - out_o[21, :N]) / y_std[21]
+    a = np.abs(dz)
+    rel = np.linalg.norm(dz) / np.linalg.norm(z_o)
+    exact = (a.max(axis=0) <= 1e-4).mean()
+    print(f"n_poly {n_poly}: |dz| median {np.median(a):.1e}, p99 {np.quantile(a, 0.99):.1e}, "
+          f"max {a.max():.1e}; norm-wise {rel:.1e}; cells within 1e-4: {exact:.3f}")
+    # measured: norm-wise 1.0e-4, median 4e-13..4e-9, max 7e-4..9e-4, 99% of the
+    # cells within 1e-4 (the rest moved by a flipped bfloat16 activation)
+    assert rel <= 3e-4
+    assert np.median(a) <= 1e-6
+    assert a.max() <= 3e-3
+    assert exact >= 0.97
+    # cells beyond N are not written
+    assert not g[:, N:].any()
+
+
+def _gate_inputs(seed, N=3000, S=21):
+    """Synthetic coarse, half and network states straddling a 1e-4 check:
+    mass-conserving coarse states (the forcing integral added), Richardson
+    corrections and network deviations log-uniform over 1e-7..1e-2, a mass
+    error on every third cell, NaN in a few and coarse flags on a few."""
+    mech, y0, rho = _cells(N, seed, n_poly=2)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    n, ld = y0.shape
+    L = 2.5e-8
+    gain = L * (rho[0] + rho[1] / 2.0)
+
+    def zero_sum(v):
+        v = v.copy()
+        v[:S] -= v[:S].mean(axis=0, keepdims=True)
+        return v
+
+    vc = y0 + gain + zero_sum(1e-3 * rng.normal(size=y0.shape) * np.abs(y0))
+    s1 = np.exp(rng.uniform(np.log(1e-7), np.log(1e-2), ld))
+    vh = vc + zero_sum(s1 * rng.normal(size=y0.shape) * np.abs(vc))
+    ve = vc + (vc - vh) / 15.0
+    s2 = np.exp(rng.uniform(np.log(1e-7), np.log(1e-2), ld))
+    eta = s2 * rng.normal(size=y0.shape) * np.abs(ve)
+    keep = np.arange(ld) % 3 != 0
+    eta[:, keep] = zero_sum(eta)[:, keep]
+    vn = ve + eta
+    vn[5, 17] = np.nan
+    vn[21, 1234] = np.nan
+    status = np.zeros(ld, dtype=np.int32)
+    status[[3, 999, 2500]] = 1
+    for a in (vc, vh, vn):
+        a[:, N:] = 0.0
+    return y0, rho, L, vc, vh, vn, status
+
+
+def test_gate_matches_oracle(torch, mri, oracle_mod):
+    """The residual check: gate values to FP64 rounding, the same accept
+    decisions (cells within 1e-9 of the threshold excluded and counted), the
+    fallback list equal to the rejected set, accepted cells given the network
+    state bitwise and rejected cells left untouched."""
+    O = oracle_mod
+    N, tol, rich = 3000, 1e-4, 1.0 / 15.0
+    y0, rho, L, vc, vh, vn, status = _gate_inputs(31, N)
+    n, ld = y0.shape
+    G_o, acc_o = O.sur_gate(21, y0, rho, L, vc, vh, vn, rich, tol, N=N, status_c=status)
+    d = {k: _dev(torch, v) for k, v in dict(y0=y0, rho=rho, vc=vc, vh=vh, vn=vn).items()}
+    sentinel = -7.0
+    yout = torch.full((n, ld), sentinel, dtype=torch.float64, device="cuda")
+    used = torch.full((ld,), 5, dtype=torch.int32, device="cuda")
+    gv = torch.zeros(ld, dtype=torch.float64, device="cuda")
+    lst = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mri.mri_surrogate_gate(N, ld, d["y0"], 2, d["rho"], L, d["vc"], d["vh"], d["vn"], rich, tol,
+                           yout, lst, cnt, status_coarse=_dev(torch, status, torch.int32),
+                           used_fallback=used, gate_value=gv)
+    torch.cuda.synchronize()
+    G = gv.cpu().numpy()[:N]
+    nan_o = np.isnan(G_o)
+    assert np.array_equal(np.isnan(G), nan_o) and nan_o.sum() == 2
+    fin = ~nan_o
+    # G is a relative error; the kernel may fuse the Richardson and residual
+    # products into FMAs, so G agrees to a few FP64 ulps of the state
+    dG = np.abs(G[fin] - G_o[fin])
+    relG = dG / np.maximum(G_o[fin], 1e-300)
+    assert np.all(dG <= 1e-12 * G_o[fin] + 1e-14)
+    acc = used.cpu().numpy()[:N] == 0
+    near = fin & (np.abs(G_o / tol - 1.0) < 1e-9)
+    print(f"gate: {acc_o.sum()} of {N} accepted by the oracle, {near.sum()} near the threshold, "
+          f"max rel diff of G {relG.max():.1e}")
+    assert 0 < acc_o.sum() < N
+    assert np.array_equal(acc[~near], acc_o[~near])
+    assert not acc[status[:N] != 0].any()
+    k = int(cnt.item())
+    assert k == int((~acc).sum())
+    assert sorted(lst.cpu().numpy()[:k].tolist()) == np.nonzero(~acc)[0].tolist()
+    yo = yout.cpu().numpy()
+    assert np.array_equal(yo[:, :N][:, acc], vn[:, :N][:, acc])
+    assert np.all(yo[:, :N][:, ~acc] == sentinel) and np.all(yo[:, N:] == sentinel)
+
+
+def _oracle_stage(O, mech, widths, p, st, y, rho, L, N, n_coarse, n_fine, tol):
+    return O.sur_stage(O.Oracle(mech), widths, p.astype(np.float64), st, y, rho, L, n_coarse,
+                       n_fine, tol, N=N)
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_gated_stage_matches_oracle(torch, mri, oracle_mod, in_place):
+    """The whole gated stage (coarse FP64 stage at 4 and 2 substeps, network
+    correction, residual check, compacted plain fallback at 50 substeps,
+    scatter) against the oracle's composition of the same steps on 700 cells:
+    same accept decisions away from the threshold, accepted cells within the
+    network tolerance, fallback cells within the parity bound 1e-10 of the
+    oracle's plain stage, status words and the device fallback count."""
+    O = oracle_mod
+    N, L = 700, 1e-7 / 3.0
+    mech, y, rho = _cells(N, 41)
+    n, ld = y.shape
+    y_std = np.full(22, 1e-9)
+    y_std[21] = 1e-6
+    widths, p, st = _net_and_stats(O, 42, y, rho, L, N, y_std)
+    # a threshold between the oracle's gate values of the cells, so that both
+    # outcomes occur
+    _, _, G0, _ = _oracle_stage(O, mech, widths, p, st, y, rho, L, N, 4, 50, 0.0)
+    tol = float(np.nanquantile(G0, 0.5))
+    out_o, acc_o, G_o, sf_o = _oracle_stage(O, mech, widths, p, st, y, rho, L, N, 4, 50, tol)
+    m = mri.Mech(mech)
+    sg = mri.Surrogate(widths, p, st)
+    yd, rd = _dev(torch, y), _dev(torch, rho)
+    out = yd if in_place else torch.zeros_like(yd)
+    ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    used = torch.full((ld,), 5, dtype=torch.int32, device="cuda")
+    gv = torch.zeros(ld, dtype=torch.float64, device="cuda")
+    stt = torch.full((ld,), 99, dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sg.stage(m, mri.fast_opts(n_sub=4), mri.fast_opts(n_sub=50), tol, N, ld, yd, out, 1, rd, L,
+             ws, used, gv, stt, nf)
+    torch.cuda.synchronize()
+    acc = used.cpu().numpy()[:N] == 0
+    near = np.abs(G_o / tol - 1.0) < 1e-4
+    print(f"gated stage: tol {tol:.2e}, oracle accepts {acc_o.sum()} of {N}, "
+          f"{near.sum()} near the threshold")
+    assert np.array_equal(acc[~near], acc_o[~near])
+    assert 0 < acc.sum() < N
+    assert int(nf.item()) == int((~acc).sum())
+    g = out.cpu().numpy()[:, :N]
+    floor = np.full((n, 1), 1e-12)
+    floor[-1] = 0.0
+    err = np.abs(g - out_o) / np.maximum(np.abs(out_o), floor)
+    both = ~near
+    fb = both & ~acc
+    ac = both & acc
+    print(f"max rel err: fallback cells {err[:, fb].max():.2e}, accepted {err[:, ac].max():.2e}")
+    assert err[:, fb].max() <= 1e-10
+    assert err[:, ac].max() <= 1e-9
+    s = stt.cpu().numpy()[:N]
+    assert np.all(s[acc] == 0) and np.array_equal(s[~acc], sf_o[~acc])
+
+
+def test_gated_stage_limits_and_graph_replay(torch, mri, oracle_mod):
+    """gate_tol = 0 sends every cell to the plain fallback (bitwise the plain
+    stage); gate_tol = inf accepts every cell unflagged by the coarse solves
+    (bitwise the network's correction of the coarse stage).  The gated stage
+    needs no host synchronization: captured in a graph and replayed three
+    times, with other device work in between, it reproduces the eager result
+    bitwise every time."""
+    N, L = 700, 2e-8
+    mech, y, rho = _cells(N, 51)
+    n, ld = y.shape
+    y_std = np.full(22, 1e-6)
+    widths, p, st = _net_and_stats(oracle_mod, 52, y, rho, L, N, y_std)
     sg = mri.Surrogate(widths, p, st)
     m = mri.Mech(mech)
-    yd = torch.as_tensor(y, device="cuda")
-    rd = torch.as_tensor(rho, device="cuda")
-    L = 2e-8
-    opts = mri.fast_opts(n_sub=10)
+    yd, rd = _dev(torch, y), _dev(torch, rho)
+    coarse, fine = mri.fast_opts(n_sub=4), mri.fast_opts(n_sub=10)
     plain = torch.empty_like(yd)
-    mri.mri_fast_stage(m, opts, 700, ld, yd, plain, 1, rd, L)
-    ws = torch.empty(mri.Surrogate.workspace_bytes(700, ld, 1) // 8 + 1, dtype=torch.float64,
-                     device="cuda")
-    used = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    out = torch.zeros_like(yd)
-    nf = sg.stage(m, opts, 0.0, 700, ld, yd, out, 1, rd, L, ws, used)
-    torch.cuda.synchronize()
-    assert nf == 700 and int(used[:700].sum().item()) == 700
-    assert torch.equal(out[:, :700], plain[:, :700])
-    out2 = torch.zeros_like(yd)
-    nf = sg.stage(m, opts, float("inf"), 700, ld, yd, out2, 1, rd, L, ws, used)
-    mid = torch.empty_like(yd)
-    dbl = torch.empty_like(yd)
-    sg.infer(700, ld, yd, mid, 1, rd, L, half=1)
-    sg.infer(700, ld, mid, dbl, 1, rd, L, half=2)
-    torch.cuda.synchronize()
-    assert nf == 0 and int(used[:700].sum().item()) == 0
-    assert torch.equal(out2[:, :700], dbl[:, :700])
-    # in place (y_out aliases y_in) gives the same result
-    yy = yd.clone()
-    sg.stage(m, opts, 0.0, 700, ld, yy, yy, 1, rd, L, ws)
-    torch.cuda.synchronize()
-    assert torch.equal(yy[:, :700], plain[:, :700])
-
-
-def test_trained_network_gain(torch, mri):
-    """What training buys, on every cell of the first fast stage of the 128^3
-    workload (errors judged against the plain FP64 stage): the trained network's
-    median stage error is far below the untrained one's; the gated stage at
-    1e-4 returns the plain FP64 result bitwise on every rejected cell and never
-    accepts a cell the gate should not (mass-sum residual and step doubling both
-    within the tolerance); with the gate open it is several times faster than
-    the plain stage at a median error of a few per mille."""
-    from paper_2211_03293_amd import surrogate as S
-    import time
-    data = S.generate_stage_data(n_full=200_000, log=print)
-    res = S.train(data, steps=4000, batch=4096, log=print, log_every=2000)
-    del data
-    cfg = I.WORKLOADS[I.FIELD128]
-    mech = I.make_mechanism(I.FIELD128)
-    m = mri.Mech(mech)
-    m.specialize(128, load=True)
-    y, rho, L, N, ld = S.stage_inputs(I.FIELD128)
-    opts = mri.fast_opts(n_sub=cfg.n_sub)
-    ref = torch.empty_like(y)
-    mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)
-    widths = [mri.MLP_KPAD, 256, 256, 256, mri.MLP_OUTPUTS]
-    med = {}
-    for name, params in (("untrained", S.init_params()), ("trained", res["params"])):
-        sg = mri.Surrogate(widths, params, res["stats"])
-        out = torch.empty_like(y)
-        sg.infer(N, ld, y, out, 1, rho, L)
-        torch.cuda.synchronize()
-        err = S.stage_error(out[:, :N], ref[:, :N], mech.n_species)
-        med[name] = float(torch.median(err).item())
-    print(f"median stage error: untrained {med['untrained']:.3e}, trained {med['trained']:.3e}")
-    assert med["trained"] < 0.1 * med["untrained"]
-    assert med["trained"] < 2e-2
-    sg = mri.Surrogate(widths, res["params"], res["stats"])
+    mri.mri_fast_stage(m, fine, N, ld, yd, plain, 1, rd, L)
+    vc = torch.empty_like(yd)
+    mri.mri_fast_stage(m, coarse, N, ld, yd, vc, 1, rd, L)
+    net = torch.empty_like(yd)
+    sg.infer(N, ld, yd, net, 1, rd, L, base=vc)
     ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
                      device="cuda")
     used = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    gv = torch.zeros(ld, dtype=torch.float32, device="cuda")
-    out = torch.empty_like(y)
-    nf = sg.stage(m, opts, 1e-4, N, ld, y, out, 1, rho, L, ws, used, gv)
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = torch.zeros_like(yd)
+    sg.stage(m, coarse, fine, 0.0, N, ld, yd, out, 1, rd, L, ws, used, n_fallback=nf)
     torch.cuda.synchronize()
-    rej = used[:N] == 1
-    assert int(rej.sum().item()) == nf
-    assert torch.equal(out[:, :N][:, rej], ref[:, :N][:, rej])
-    acc = ~rej
-    assert bool((gv[:N][acc] <= 1e-4).all().item())
-    print(f"gate 1e-4: {nf} of {N} cells fall back to the plain FP64 stage")
-    # gate open: every cell takes the doubled prediction
-    times = {}
-    for name, fn in (("plain", lambda: mri.mri_fast_stage(m, opts, N, ld, y, ref, 1, rho, L)),
-                     ("open gate", lambda: sg.stage(m, opts, float("inf"), N, ld, y, out, 1, rho,
-                                                    L, ws, used, gv))):
-        fn()
+    assert int(nf.item()) == N and int(used[:N].sum().item()) == N
+    assert torch.equal(out[:, :N], plain[:, :N])
+    out2 = torch.zeros_like(yd)
+    sg.stage(m, coarse, fine, float("inf"), N, ld, yd, out2, 1, rd, L, ws, used, n_fallback=nf)
+    torch.cuda.synchronize()
+    k = int(nf.item())
+    acc = used[:N] == 0
+    assert k == int((~acc).sum().item())
+    assert k <= N // 20               # only cells a coarse solve flags
+    assert torch.equal(out2[:, :N][:, acc], net[:, :N][:, acc])
+    # graph capture and replay at a threshold that splits the cells
+    gv = torch.zeros(ld, dtype=torch.float64, device="cuda")
+    sg.stage(m, coarse, fine, float("inf"), N, ld, yd, out2, 1, rd, L, ws, used, gv)
+    torch.cuda.synchronize()
+    tol = float(torch.nanquantile(gv[:N], 0.5).item())
+    eager = torch.zeros_like(yd)
+    sg.stage(m, coarse, fine, tol, N, ld, yd, eager, 1, rd, L, ws, used, n_fallback=nf)
+    torch.cuda.synchronize()
+    n_eager = int(nf.item())
+    graph_out = torch.zeros_like(yd)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sg.stage(m, coarse, fine, tol, N, ld, yd, graph_out, 1, rd, L, ws, used,
+                     n_fallback=nf)
+    torch.cuda.current_stream().wait_stream(s)
+    for r in range(3):
+        graph_out.zero_()
+        nf.zero_()
+        scratch = torch.randn(1 << 20, device="cuda").sum()   # other device work in between
+        g.replay()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fn()
-        torch.cuda.synchronize()
-        times[name] = (time.perf_counter() - t0) * 1e3
-    err = S.stage_error(out[:, :N], ref[:, :N], mech.n_species)
-    med_open = float(torch.median(err).item())
-    print(f"plain {times['plain']:.2f} ms, open gate {times['open gate']:.2f} ms, "
-          f"median error {med_open:.3e}")
-    assert times["open gate"] * 2.0 < times["plain"]
-    assert med_open < 2e-2
+        assert torch.equal(graph_out, eager), f"replay {r}"
+        assert int(nf.item()) == n_eager and float(scratch.item()) == float(scratch.item())
+
+
+def test_trained_network_gain(torch, mri):
+    """What training buys, on every cell of the three fast stages of the 128^3
+    workload's first slow step (errors against the plain FP64 stage of 50
+    substeps): the trained network's correction of the coarse 4-substep stage
+    is far more accurate than an untrained network's; with the check at half
+    the 1e-4 tolerance no accepted cell exceeds 1e-4, with or without the
+    network, and the gated stage is faster than the plain stage.  The same
+    pipeline with a zero correction (no network) is measured beside it."""
+    from paper_2211_03293_amd import surrogate as S
+    data = S.generate_stage_data(n_full=300_000, log=print)
+    res = S.train(data, steps=6000, batch=4096, log=print, log_every=3000)
+    del data
+    ev = S.evaluate(res["params"], res["stats"], workload=I.FIELD128, gate_tol=1e-4, repeats=1,
+                    log=print)
+    ev0 = S.evaluate(S.init_params(), res["stats"], workload=I.FIELD128, gate_tol=1e-4,
+                     repeats=1, log=print)
+    e, e0 = ev["errors"], ev0["errors"]
+    print({k: (v["median"], v["p999"], v["max"]) for k, v in e.items()})
+    print(f"untrained network: median {e0['network']['median']:.2e}; fallback "
+          f"{ev0['learned']['fallback_frac']:.3f}")
+    assert e["network"]["median"] < 0.01 * e0["network"]["median"]
+    assert ev["learned"]["fallback_frac"] < ev0["learned"]["fallback_frac"]
+    for name in ("learned", "no_network"):
+        assert ev[name]["false_accepts"] == 0, name
+        assert ev[name]["max_err"] <= 1e-4, name
+    assert ev["learned"]["speedup_vs_plain"] > 2.0

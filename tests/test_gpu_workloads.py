@@ -164,12 +164,13 @@ def test_batch_work_queue_parity(torch, mri, O, n_poly):
     zo = O.zonneveld_opts(rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
     ref = np.zeros_like(y)
     acc_o = np.zeros(ld, dtype=np.int32)
+    rej_o = np.zeros(ld, dtype=np.int32)
     st_o = np.zeros(ld, dtype=np.int32)
     for s in range(off.size - 1):
         a, b = off[s], off[s + 1]
         r = np.zeros((1, n, b - a)) if rho is None else np.ascontiguousarray(rho[:, :, a:b])
-        o, st, acc, _ = orc.fast_stage_soa(np.ascontiguousarray(y[:, a:b]), r, Ls[s], zo)
-        ref[:, a:b], st_o[a:b], acc_o[a:b] = o, st, acc
+        o, st, acc, rej = orc.fast_stage_soa(np.ascontiguousarray(y[:, a:b]), r, Ls[s], zo)
+        ref[:, a:b], st_o[a:b], acc_o[a:b], rej_o[a:b] = o, st, acc, rej
     m = mri.Mech(mech)
     opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
                          max_steps=2000)
@@ -178,21 +179,31 @@ def test_batch_work_queue_parity(torch, mri, O, n_poly):
     out = torch.zeros_like(yd)
     st = torch.zeros(ld, dtype=torch.int32, device="cuda")
     steps = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    rejects = torch.zeros(ld, dtype=torch.int32, device="cuda")
     rd = None if rho is None else torch.as_tensor(rho, device="cuda")
     for _ in range(2):                        # second run replays the captured graph
         out.zero_()
-        plan.run(yd, out, ld, n_poly, rd, Ls, st, steps)
+        steps.fill_(-1)
+        rejects.fill_(-1)
+        plan.run(yd, out, ld, n_poly, rd, Ls, st, steps, rejects)
         torch.cuda.synchronize()
         got, st_g, acc_g = out.cpu().numpy(), st.cpu().numpy()[:ntot], steps.cpu().numpy()[:ntot]
+        rej_g = rejects.cpu().numpy()[:ntot]
         tie = ((st_g | st_o[:ntot]) & mri.CELL_NEARTIE) != 0
         ok = np.nonzero(~tie)[0]
         assert ok.size >= ntot - 5
         np.testing.assert_array_equal(acc_g[ok], acc_o[ok])
+        np.testing.assert_array_equal(rej_g[ok], rej_o[ok])
         assert np.all((st_g[ok] & ~mri.CELL_NEARTIE) == 0)
-        assert_parity(got, ref, mech.n_species, cells=ok, what="batch")
-    useful, issued = plan.lane_stats()
+        worst = assert_parity(got, ref, mech.n_species, cells=ok, what="batch")
+        # exactly once: every cell finished by one lane (no count left at -1), and
+        # the per-cell attempts add up to the lane-steps the queue issued to cells
+        useful, issued = plan.lane_stats()
+        assert acc_g.min() >= 1 and rej_g.min() >= 0
+        assert int(acc_g.sum()) + int(rej_g.sum()) == useful
     wg, nb = plan.tile()
-    print(f"batch {ntot} cells, steps {acc_g.min()}..{acc_g.max()}, tile {wg}x{nb}, "
+    print(f"batch n_poly {n_poly}: {ntot} cells, max rel err {worst:.2e}, accepted steps "
+          f"{acc_g.min()}..{acc_g.max()}, rejected {rej_g.sum()}, tile {wg}x{nb}, "
           f"lane utilization {useful / issued:.3f}")
     assert 0 < useful <= issued
 
@@ -318,9 +329,16 @@ def test_batch_fullsize_sampled(torch, mri, O):
     yd = torch.as_tensor(y, device="cuda")
     out = torch.empty_like(yd)
     st = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    steps = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    plan.run(yd, out, ld, 0, None, Ls, st, steps)
+    steps = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
+    rejects = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
+    plan.run(yd, out, ld, 0, None, Ls, st, steps, rejects)
     torch.cuda.synchronize()
+    # exactly once over the ~1e7 cells: each finished by one lane
+    acc_all = steps[:ntot].to(torch.int64)
+    rej_all = rejects[:ntot].to(torch.int64)
+    useful, issued = plan.lane_stats()
+    assert int(acc_all.min().item()) >= 1 and int(rej_all.min().item()) >= 0
+    assert int(acc_all.sum().item() + rej_all.sum().item()) == useful
     rng = np.random.Generator(np.random.PCG64(12))
     sets = np.concatenate([[0, off.size - 2], rng.choice(off.size - 1, 30, replace=False)])
     cells = np.unique(np.concatenate([rng.integers(off[s], off[s + 1], 16) for s in sets]))
@@ -492,3 +510,99 @@ def test_batch_maximum_size_sampled(torch, mri, O):
     wg, nb = plan.tile()
     print(f"batch max size: {ok.sum()} of {cells.size} sampled cells compared, max rel err "
           f"{e:.2e}, tile {wg}x{nb}", flush=True)
+
+
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
+def test_large_mechanism_slow_step_small_grid(torch, mri, O, kernel):
+    """All three fast stages of a MIS-KW3 step of the 53-species / 325-reaction
+    workload (RK4, 100 substeps per stage, H = 5e-8 s) with the advection-
+    diffusion slow side, the forcing of stages 2 and 3 built from two and three
+    slow evaluations: every cell of a 6 x 5 x 4 periodic grid against the
+    oracle's MRI step."""
+    grid = (6, 5, 4)
+    cfg = I.WORKLOADS[I.LARGE128]
+    mech = I.make_mechanism(I.LARGE128)
+    y0 = I.field_state(I.LARGE128, grid=grid)
+    n, ld = y0.shape
+    N = int(np.prod(grid))
+    tb = I.table_mis_kw3()
+    ref, st_o, _, _ = O.Oracle(mech).mri_step_advdiff(tb, O.rk4_opts(cfg.n_sub), grid, y0, cfg.H,
+                                                      t=0.0)
+    assert not st_o[:N].any()
+    m, t = mri.Mech(mech), mri.Table(tb)
+    kern = mri.KERNEL_SPECIALIZED if kernel == "specialized" else mri.KERNEL_GENERIC
+    yd = torch.as_tensor(y0, device="cuda")
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    mri.mri_slow_step(m, t, mri.fast_opts(n_sub=cfg.n_sub, kernel=kern), mri.ADVDIFF_RHS,
+                      mri.advdiff_params(grid, n), 0.0, cfg.H, N, ld, yd, ws, st)
+    torch.cuda.synchronize()
+    assert mri.mri_status_count(st, N) == 0
+    e = assert_parity(yd.cpu().numpy()[:, :N], ref[:, :N], mech.n_species,
+                      what=f"53 species {kernel}")
+    print(f"53-species MRI step on {grid}, {kernel}: max rel err {e:.2e}")
+
+
+def _stencil_closure(cells, grid, radius):
+    """Cells within `radius` applications of the 7-point periodic stencil."""
+    nx, ny, nz = grid
+    out = set(int(c) for c in cells)
+    for _ in range(radius):
+        nxt = set(out)
+        for c in out:
+            x, r = c % nx, c // nx
+            y, z = r % ny, r // ny
+            for dx_, dy_, dz_ in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1),
+                                  (0, 0, -1)):
+                nxt.add(((z + dz_) % nz * ny + (y + dy_) % ny) * nx + (x + dx_) % nx)
+        out = nxt
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def test_large_mechanism_fullsize_step_sampled(torch, mri, O):
+    """The 128^3 53-species MRI step the benchmark runs (three fast stages,
+    advection-diffusion slow side) on sampled cells.  A cell's result after one
+    step depends on the initial state within two applications of the stencil
+    (stage 3's forcing reads F_2 at the cell, F_2 reads stage 2 at its
+    neighbours, whose forcing reads stage 1 at theirs), so the oracle integrates
+    stage 1 on that neighbourhood, stage 2 on the one-stencil neighbourhood and
+    stage 3 on the sampled cells, evaluating the slow RHS on the full grid with
+    the neighbourhood's values in place."""
+    cfg = I.WORKLOADS[I.LARGE128]
+    mech = I.make_mechanism(I.LARGE128)
+    tb = I.table_mis_kw3()
+    y0 = I.initial_state(I.LARGE128)
+    n, ld = y0.shape
+    N = cfg.n_cells
+    m, t = mri.Mech(mech), mri.Table(tb)
+    yd = torch.as_tensor(y0, device="cuda")
+    ws = torch.empty(mri.mri_workspace_bytes(m, t, N, ld) // 8, dtype=torch.float64,
+                     device="cuda")
+    st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    mri.mri_slow_step(m, t, mri.fast_opts(n_sub=cfg.n_sub), mri.ADVDIFF_RHS,
+                      mri.advdiff_params(cfg.grid, n), 0.0, cfg.H, N, ld, yd, ws, st)
+    torch.cuda.synchronize()
+    assert mri.mri_status_count(st, N) == 0
+    got = yd.cpu().numpy()
+    del yd, ws
+    centres = _sample(N, 48)
+    regions = [_stencil_closure(centres, cfg.grid, r) for r in (2, 1, 0)]
+    orc = O.Oracle(mech)
+    opts = O.rk4_opts(cfg.n_sub)
+    field = y0.copy()
+    F = [O.advdiff(field, cfg.grid)]
+    for i in range(1, tb.s):
+        cells = regions[i - 1]
+        dc = tb.c[i] - tb.c[i - 1]
+        rho = sum(tb.gamma[0, i, j] * F[j][:, cells] for j in range(i)) / dc
+        ys, st_o, _, _ = orc.fast_stage_soa(np.ascontiguousarray(field[:, cells]),
+                                            np.ascontiguousarray(rho[None]), dc * cfg.H, opts)
+        assert not st_o.any()
+        field[:, cells] = ys
+        if i < tb.s - 1:
+            F.append(O.advdiff(field, cfg.grid))
+    e = assert_parity(got[:, centres], field[:, centres], mech.n_species,
+                      what="53 species 128^3 step")
+    print(f"53-species 128^3 MRI step, {centres.size} sampled cells "
+          f"({regions[0].size} stage-1 cells): max rel err {e:.2e}")
