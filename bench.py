@@ -138,10 +138,13 @@ def cpu_baseline(mech, y_field, rho, L_list, n_sub, n_sample=262144, n_sample_1c
                 host=dict(cpu=_cpu_model(), nproc=os.cpu_count()))
 
 
-def batch_leg(torch, mri, I, repeats=3):
+def batch_leg(torch, mri, I, divergent, repeats=3, per_set_baseline=False):
     """Batched uneven reactor sets: 1000 sets, log-uniform sizes, adaptive
-    Zonneveld 4(3) at tol 1e-8, one persistent work-queue launch per run."""
-    sizes, off, y_host, Ls = I.batch_workload()
+    Zonneveld 4(3) at tol 1e-8, one persistent work-queue launch per run
+    (autotuned tile and register / LDS tiling, captured in a graph).  With
+    per_set_baseline the same sets are also run with one fast-stage launch per
+    set."""
+    sizes, off, y_host, Ls = I.batch_workload(divergent=divergent)
     mech = I.make_mechanism(I.SETS1000)
     m = mri.Mech(mech)
     opts = mri.fast_opts(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
@@ -153,34 +156,73 @@ def batch_leg(torch, mri, I, repeats=3):
     out = torch.empty_like(y)
     st = torch.zeros(ld, dtype=torch.int32, device="cuda")
     steps = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    plan.run(y, out, ld, 0, None, Ls, st, steps)          # tunes the tile, captures the graph
+    rejects = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    t0 = time.perf_counter()
+    plan.run(y, out, ld, 0, None, Ls, st, steps, rejects)   # tunes, captures the graph
     torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(repeats):
-        plan.run(y, out, ld, 0, None, Ls, st, steps)
+        plan.run(y, out, ld, 0, None, Ls, st, steps, rejects)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / repeats
     useful, issued = plan.lane_stats()       # attempted lane-steps of the last run
-    wg, nb = plan.tile()
+    trials, from_cache, choice = plan.tune_log()
     fpa = flops_per_zv_attempt(mech.n_species, mech.n_reactions)
     achieved = useful * fpa / (ms * 1e-3) / 1e12
+    per_unit = counter_flops_per_unit(plan.code_hash(0))
     sv = steps[:ntot].cpu().numpy()
-    n_bad = mri.mri_status_count(st, ntot, mri.CELL_NONFINITE | mri.CELL_MAXSTEPS | mri.CELL_TRANGE)
-    return dict(workload="1000 reactor sets, sizes log-uniform in [64, 65536], 21 species / 84 "
-                         "reactions, one unforced fast stage per set (L cycles through the "
-                         "MIS-KW3 stage lengths, H = 1e-7 s), Zonneveld 4(3) tol 1e-8",
-                cells=ntot, ms_per_run=round(ms, 3), value=round(ntot / (ms * 1e-3), 1),
-                unit="cell-stages/s", accepted_steps=dict(min=int(sv.min()),
-                                                          median=float(np.median(sv)),
-                                                          max=int(sv.max())),
-                lane_utilization=round(useful / max(issued, 1), 4), tile=dict(block=wg, blocks=nb),
-                flagged_cells=n_bad, attempted_steps=int(useful),
-                roofline=dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS,
-                              unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 4),
-                              traffic=None, kernel="mri_spec_main (batched work queue)",
-                              flops_per_attempted_step=fpa))
+    rv = rejects[:ntot].cpu().numpy()
+    n_bad = mri.mri_status_count(st, ntot, mri.CELL_NONFINITE | mri.CELL_TRANGE)
+    n_capped = mri.mri_status_count(st, ntot, mri.CELL_MAXSTEPS)
+    res = dict(workload=("1000 reactor sets, sizes log-uniform in [64, 65536], 21 species / 84 "
+                         "reactions, one unforced fast stage per set, Zonneveld 4(3) tol 1e-8; "
+                         + ("per-set stage lengths log-uniform in [1e-8, 1e-6] s" if divergent
+                            else "L cycles through the MIS-KW3 stage lengths, H = 1e-7 s")),
+               cells=ntot, ms_per_run=round(ms, 3), value=round(ntot / (ms * 1e-3), 1),
+               unit="cell-stages/s",
+               accepted_steps=dict(min=int(sv.min()), median=float(np.median(sv)),
+                                   p99=float(np.quantile(sv, 0.99)), max=int(sv.max())),
+               rejected_steps=int(rv.sum()), capped_cells=n_capped,
+               exactly_once=bool(int(sv.sum()) + int(rv.sum()) == useful),
+               lane_utilization=round(useful / max(issued, 1), 4),
+               tile=dict(block=choice["block_size"], blocks=choice["n_blocks"],
+                         waves_per_simd=choice["waves_per_simd"],
+                         exp_table=choice["exp_table"], sched_window=choice["sched_window"]),
+               tuner=dict(from_cache=from_cache, first_run_s=round(first_s, 2),
+                          trials=[dict(t, ms=round(t["ms"], 3)) for t in trials]),
+               flagged_cells=n_bad, attempted_steps=int(useful),
+               roofline=dict(**fp64_roofline(achieved_alg=achieved, avg_launch_s=ms * 1e-3,
+                                             counter_flops=(per_unit * useful
+                                                            if per_unit else None)),
+                             kernel="mri_spec_main (batched work queue)",
+                             flops_per_attempted_step=fpa))
+    if per_set_baseline:
+        # the same sets, one fast-stage launch per set (Zonneveld kernel,
+        # specialized, default block), sets in order on one stream
+        out2 = torch.empty_like(y)
+
+        def per_set():
+            for s_ in range(off.size - 1):
+                a, b = int(off[s_]), int(off[s_ + 1])
+                mri.mri_fast_stage(m, opts, b - a, ld, y[:, a:], out2[:, a:], 0, None,
+                                   float(Ls[s_]))
+        per_set()
+        torch.cuda.synchronize()
+        e0.record()
+        per_set()
+        e1.record()
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1)
+        res["one_launch_per_set"] = dict(ms_per_run=round(ms1, 3),
+                                         value=round(ntot / (ms1 * 1e-3), 1),
+                                         speedup_of_work_queue=round(ms1 / ms, 3),
+                                         max_rel_diff=float(((out2[:, :ntot] - out[:, :ntot])
+                                                             .abs() / out[:, :ntot].abs()
+                                                             .clamp_min(1e-12)).max().item()))
+    return res
 
 
 def fp64_roofline(achieved_alg, avg_launch_s, counter_flops=None, traffic=None):
@@ -412,7 +454,7 @@ def surrogate_eval(params, stats, log, gate_tol=1e-4):
     return ev
 
 
-def cpu_baseline_surrogate(params, stats, n_sample=8192):
+def cpu_baseline_surrogate(params, stats, n_sample=262144):
     """The oracle's gated surrogate stage (RK4 at 4 and 2 substeps, the network
     in its bfloat16-emulating mode, the residual check, plain RK4 with 50
     substeps for rejected cells) on evenly spaced cells of the first fast stage
@@ -541,8 +583,10 @@ def main():
                           "synthetic mechanism)",
                 note="other hardware and another integrator; context, not the target"))
     if not args.no_batch:
-        log("# batched uneven-set leg")
-        out["batch"] = batch_leg(torch, mri, I)
+        log("# batched uneven-set legs (the standard one tunes; the divergent one takes its "
+            "choice from the tuning cache)")
+        out["batch"] = batch_leg(torch, mri, I, divergent=False)
+        out["batch_divergent"] = batch_leg(torch, mri, I, divergent=True, per_set_baseline=True)
     if not args.no_cpu_baseline:
         log("# CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline_surrogate(res["params"], res["stats"])

@@ -387,6 +387,32 @@ mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, double *y_out, i
 /* Tile chosen by the autotuner (threads per block, persistent blocks); valid
    after the first run. */
 mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_blocks);
+/* The autotuner's trials of the first run (none when the choice came from the
+   tuning cache, *from_cache then 1) and its choice.  Tiling fields: threads
+   per block, persistent blocks, waves per SIMD the register allocation allows
+   (0 = built-in rule), exponential (1 = 2^(j/256) table in LDS, 0 =
+   polynomial, -1 = built-in rule), scheduling window in rate evaluations (0 =
+   built-in), and the trial's time on the tuning prefix.  The tuner times 64 /
+   128 / 256 threads at 1x and 2x the resident grid, then at the best block
+   size the other waves-per-SIMD setting, the other exponential and windows of
+   1 and 4; it caches the choice per mechanism, fast method, forcing terms,
+   tolerances, size class (floor(log2(n_total))) and device architecture in
+   memory and in the file MRI_TUNE_CACHE names ("off": memory only; default
+   $XDG_CACHE_HOME or $HOME/.cache + /libmri/batch_tune.txt).  The choice's ms
+   is its time on the tuning prefix (also when it came from the cache).  The
+   variants with the other exponential round differently: results are bitwise
+   independent of the tile for one variant, not across exponentials. */
+typedef struct {
+    int block_size, n_blocks, waves_per_simd, exp_table, sched_window;
+    float ms;
+} mri_tune_trial;
+mri_status mri_batch_plan_tune_log(const mri_batch_plan *p, int max_entries,
+                                   mri_tune_trial *trials, int *n_entries, int *from_cache,
+                                   mri_tune_trial *choice);
+/* Hash of the machine code of the plan's work-queue kernel (the tile chosen by
+   the first run, else the requested or default block size) for n_poly forcing
+   terms; the same hash as mri_mech_code_hash gives for the other kernels. */
+mri_status mri_batch_plan_code_hash(const mri_batch_plan *p, int n_poly, uint64_t *hash);
 /* Lane utilization of the last run: useful lane-steps (a lane advancing a
    cell) and issued lane-steps (lanes x loop trips).  Synchronizes the stream. */
 mri_status mri_batch_lane_stats(const mri_batch_plan *p, uint64_t *useful, uint64_t *issued,

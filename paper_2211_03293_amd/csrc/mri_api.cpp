@@ -5,6 +5,7 @@
 #include <hip/hiprtc.h>
 
 #include <elf.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <atomic>
@@ -104,7 +105,26 @@ struct SpecKernel {
     size_t code_bytes = 0;      // size of the code object it was loaded from
 };
 
-inline int spec_key(int wg, int kind, int np) { return (wg << 8) | (kind << 4) | np; }
+// Register / LDS tiling choices of a specialized kernel: the waves per SIMD its
+// register allocation must allow, the exponential (2^(j/256) table in LDS or
+// the polynomial), the scheduling window (rate evaluations per scheduling
+// fence); 0 / -1 / 0 select the built-in heuristics of spec_kernels.inc.
+struct SpecVariant {
+    int wpe = 0;
+    int exp_table = -1;
+    int group = 0;
+    bool operator==(const SpecVariant &o) const
+    {
+        return wpe == o.wpe && exp_table == o.exp_table && group == o.group;
+    }
+};
+
+inline uint64_t spec_key(int wg, int kind, int np, const SpecVariant &v = SpecVariant())
+{
+    return (uint64_t)wg << 32 | (uint64_t)kind << 24 | (uint64_t)np << 20 |
+           (uint64_t)(v.wpe & 7) << 16 | (uint64_t)((v.exp_table + 1) & 3) << 12 |
+           (uint64_t)(v.group & 0xff);
+}
 
 std::string hexd(double v)
 {
@@ -128,8 +148,8 @@ struct mri_mech {
     // run-time specialization
     std::mutex mu;
     std::string defs;                  // generated macro block
-    std::map<int, SpecKernel> spec;    // by spec_key
-    std::map<int, std::string> spec_fail;
+    std::map<uint64_t, SpecKernel> spec;    // by spec_key
+    std::map<uint64_t, std::string> spec_fail;
     std::vector<char> last_code;       // code object of the last compilation
     ~mri_mech()
     {
@@ -293,7 +313,8 @@ static std::string erk_defs(const ErkCoef &e)
 
 // Compile the specialized kernel (wg, kind, np); with load != 0 also load it
 // on the current device.  Caller holds m->mu.
-static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, SpecKernel *out)
+static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, SpecKernel *out,
+                               const SpecVariant &var = SpecVariant())
 {
     if (m->defs.empty()) m->defs = make_defs(*m);
     // Scheduling window (rate evaluations per sched barrier): small mechanisms
@@ -305,10 +326,15 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     int group = (m->S >= 40) ? 8 : 2;
     if (const char *g = std::getenv("MRI_SPEC_GROUP"))   // tuning knob
         group = std::max(1, std::atoi(g));
+    if (var.group > 0) group = var.group;
     std::string tune = "#define MRI_GROUP " + std::to_string(group) + "\n";
-    if (const char *w = std::getenv("MRI_SPEC_WPE"))     // tuning knob: waves per SIMD
+    if (var.wpe > 0)
+        tune += "#define MRI_WPE " + std::to_string(std::max(1, std::min(4, var.wpe))) + "\n";
+    else if (const char *w = std::getenv("MRI_SPEC_WPE"))     // tuning knob: waves per SIMD
         tune += "#define MRI_WPE " + std::to_string(std::max(1, std::min(4, std::atoi(w)))) + "\n";
-    if (const char *e = std::getenv("MRI_SPEC_EXP_TABLE"))   // tuning knob: 0 / 1
+    if (var.exp_table >= 0)
+        tune += std::string("#define MRI_EXP_TABLE ") + (var.exp_table ? "1" : "0") + "\n";
+    else if (const char *e = std::getenv("MRI_SPEC_EXP_TABLE"))   // tuning knob: 0 / 1
         tune += std::string("#define MRI_EXP_TABLE ") + (std::atoi(e) ? "1" : "0") + "\n";
     if (kind == 3 || kind == 4) tune += erk_defs(erk_coef(kind == 3 ? MRI_FAST_HEUN : MRI_FAST_BS3));
     if (kind == 5) tune += erk_full_defs(erk_full_ck5());
@@ -346,7 +372,7 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
                                       "-mllvm", "-disable-machine-licm"};
     for (const std::string &w : extra) opts.push_back(w.c_str());
     const hiprtcResult rc = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
-    const int key = spec_key(wg, kind, np);
+    const uint64_t key = spec_key(wg, kind, np, var);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
@@ -381,10 +407,11 @@ static mri_status spec_compile(mri_mech *m, int wg, int kind, int np, int load, 
     return MRI_OK;
 }
 
-static mri_status spec_get(mri_mech *m, int wg, int kind, int np, hipFunction_t *fn)
+static mri_status spec_get(mri_mech *m, int wg, int kind, int np, hipFunction_t *fn,
+                           const SpecVariant &var = SpecVariant())
 {
     std::lock_guard<std::mutex> lk(m->mu);
-    const int key = spec_key(wg, kind, np);
+    const uint64_t key = spec_key(wg, kind, np, var);
     auto it = m->spec.find(key);
     if (it != m->spec.end()) {
         *fn = it->second.fn;
@@ -394,7 +421,7 @@ static mri_status spec_get(mri_mech *m, int wg, int kind, int np, hipFunction_t 
     if (f != m->spec_fail.end())
         return fail(MRI_ECOMPILE, "specialization failed earlier: %s", f->second.c_str());
     SpecKernel sk;
-    mri_status st = spec_compile(m, wg, kind, np, 1, &sk);
+    mri_status st = spec_compile(m, wg, kind, np, 1, &sk, var);
     if (st != MRI_OK) return st;
     m->spec.emplace(key, sk);
     *fn = sk.fn;
@@ -581,8 +608,15 @@ struct mri_batch_plan {
     double *d_L = nullptr;
     unsigned long long *d_counters = nullptr;   // [0] queue, [1] useful, [2] issued
     int wg = 0, n_blocks = 0;                   // tuned tile
-    bool tuned = false;
-    std::vector<std::pair<std::pair<int, int>, float>> tune_log;  // (wg, blocks) -> ms
+    SpecVariant var;                            // tuned register / LDS tiling
+    float tune_ms = 0.0f;                       // timed ms of the choice
+    bool tuned = false, from_cache = false;
+    struct Trial {
+        int wg, blocks;
+        SpecVariant var;
+        float ms;
+    };
+    std::vector<Trial> tune_log;
     // captured launch (counter reset + persistent kernel), replayed while the
     // argument key is unchanged
     hipStream_t cap_stream = nullptr;
@@ -665,7 +699,7 @@ bool mri_internal_stage_needs_setup(mri_mech *m, const mri_fast_opts *o, int n_p
     if (!m->d_sp) return true;
     if (o->kernel == MRI_KERNEL_GENERIC) return false;
     const int wg = o->block_size ? o->block_size : default_block(MRI_KERNEL_SPECIALIZED);
-    const int key = spec_key(wg, spec_kind(o->method), n_poly);
+    const uint64_t key = spec_key(wg, spec_kind(o->method), n_poly);
     auto it = m->spec.find(key);
     if (it != m->spec.end() && it->second.fn) return false;
     // automatic selection falls back to the generic kernel after a failed compilation
@@ -1357,13 +1391,13 @@ mri_status mri_batch_plan_tile(const mri_batch_plan *p, int *block_size, int *n_
 
 // Enqueue one persistent launch (counter reset by a fill kernel, then the
 // work-queue kernel) over the first n_total cells on stream s.
-static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, long long n_total,
-                                const double *yin, double *yout, long long ld, int n_poly,
-                                const double *rho, int32_t *status, int32_t *steps,
-                                int32_t *rejects, hipStream_t s)
+static mri_status batch_enqueue(mri_batch_plan *p, int wg, int n_blocks, const SpecVariant &var,
+                                long long n_total, const double *yin, double *yout,
+                                long long ld, int n_poly, const double *rho, int32_t *status,
+                                int32_t *steps, int32_t *rejects, hipStream_t s)
 {
     hipFunction_t fn = nullptr;
-    mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn);
+    mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn, var);
     if (st != MRI_OK) return st;
     HIP_TRY(launch_fill_u64(p->d_counters, 3, 0ull, s));
     BatchArgs a;
@@ -1396,23 +1430,145 @@ static int n_cus()
     return cus > 0 ? cus : 256;
 }
 
-// Autotuner: time every (threads per block, persistent grid) candidate on a
-// prefix of the sets holding about 1/8 of the cells (at least 64k when
-// available), keep the fastest.  Candidates: 64/128/256 threads per block, grid
-// = 1x or 2x the resident capacity reported by the occupancy query.
+// FNV-1a over a byte string (the mechanism's literal block identifies it).
+static uint64_t fnv1a(const std::string &b)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : b) h = (h ^ c) * 1099511628211ull;
+    return h;
+}
+
+// Tuning results by (mechanism, S, R, fast method, forcing terms, tolerances,
+// size class = floor(log2(cells)), device architecture), in memory and in a
+// text file: MRI_TUNE_CACHE names it
+// ("off" disables it), else $XDG_CACHE_HOME/libmri/batch_tune.txt or
+// $HOME/.cache/libmri/batch_tune.txt.  A line holds the key and the choice:
+// threads per block, grid factor, waves per SIMD, exponential, window, ms.
+struct TuneChoice {
+    int wg = 0, factor = 1;
+    SpecVariant var;
+    float ms = 0.0f;
+};
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneChoice> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_cache_path()
+{
+    if (const char *e = std::getenv("MRI_TUNE_CACHE")) return std::string(e) == "off" ? "" : e;
+    if (const char *x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/libmri/batch_tune.txt";
+    if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/libmri/batch_tune.txt";
+    return "";
+}
+
+static std::string tune_key(const mri_batch_plan *p, int n_poly)
+{
+    char b[256];
+    const mri_mech *m = p->mech;
+    int size_class = 0;
+    while (size_class < 62 && (2ll << size_class) <= p->n_total) ++size_class;
+    snprintf(b, sizeof b, "mech=%016llx S=%d R=%d method=%d np=%d rtol=%a atolY=%a atolT=%a "
+             "max_steps=%d log2cells=%d arch=%s",
+             (unsigned long long)fnv1a(m->defs), m->S, m->R, p->opts.method, n_poly,
+             p->opts.rtol, p->opts.atol_Y, p->opts.atol_T, p->opts.max_steps, size_class,
+             device_arch().c_str());
+    return b;
+}
+
+// Looks a choice up (loading the file on first use); caller holds g_tune_mu.
+static bool tune_lookup(const std::string &key, TuneChoice *c)
+{
+    if (!g_tune_loaded) {
+        g_tune_loaded = true;
+        const std::string path = tune_cache_path();
+        if (!path.empty()) {
+            std::ifstream in(path);
+            for (std::string line; std::getline(in, line);) {
+                const size_t tab = line.find('\t');
+                if (tab == std::string::npos) continue;
+                TuneChoice t;
+                if (sscanf(line.c_str() + tab + 1, "%d %d %d %d %d %f", &t.wg, &t.factor,
+                           &t.var.wpe, &t.var.exp_table, &t.var.group, &t.ms) == 6 &&
+                    (t.wg == 64 || t.wg == 128 || t.wg == 256) && t.factor >= 1 &&
+                    t.factor <= 4)
+                    g_tune[line.substr(0, tab)] = t;
+            }
+        }
+    }
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *c = it->second;
+    return true;
+}
+
+static void tune_store(const std::string &key, const TuneChoice &c)
+{
+    g_tune[key] = c;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        // create the directory chain (best effort; an unwritable cache is skipped)
+        std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    std::ofstream out(path, std::ios::app);
+    if (out)
+        out << key << '\t' << c.wg << ' ' << c.factor << ' ' << c.var.wpe << ' '
+            << c.var.exp_table << ' ' << c.var.group << ' ' << c.ms << '\n';
+}
+
+static mri_status resident_blocks(mri_batch_plan *p, int wg, int n_poly, const SpecVariant &var,
+                                  int *nb)
+{
+    hipFunction_t fn = nullptr;
+    mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn, var);
+    if (st != MRI_OK) return st;
+    int b = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, wg, 0));
+    *nb = std::max(1, b) * n_cus();
+    return MRI_OK;
+}
+
+// Autotuner of the persistent work-queue launch, timed on a prefix of the sets
+// holding about 1/8 of the cells (at least 64k when available):
+//   1. tile: 64 / 128 / 256 threads per block x grid = 1x or 2x the resident
+//      capacity the occupancy query reports, with the built-in tiling;
+//   2. register / LDS tiling at the best block size: the other number of waves
+//      per SIMD (which moves the exponential between its LDS table and the
+//      polynomial), the other exponential alone, and scheduling windows of 1
+//      and 4 rate evaluations, each at both grid factors.
+// The fastest choice is kept and cached (see tune_key); a plan created later
+// with the same key takes it without timing anything.
 static mri_status batch_tune(mri_batch_plan *p, const double *yin, double *yout, long long ld,
                              int n_poly, const double *rho, hipStream_t s)
 {
     if (p->opts.block_size) {
         p->wg = p->opts.block_size;
-        hipFunction_t fn = nullptr;
-        mri_status st = spec_get(p->mech, p->wg, 2, n_poly, &fn);
+        p->var = SpecVariant();
+        mri_status st = resident_blocks(p, p->wg, n_poly, p->var, &p->n_blocks);
         if (st != MRI_OK) return st;
-        int nb = 0;
-        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, p->wg, 0));
-        p->n_blocks = std::max(1, nb) * n_cus();
         p->tuned = true;
         return MRI_OK;
+    }
+    const std::string key = tune_key(p, n_poly);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        TuneChoice c;
+        if (tune_lookup(key, &c)) {
+            int nb = 0;
+            mri_status st = resident_blocks(p, c.wg, n_poly, c.var, &nb);
+            if (st == MRI_OK) {
+                p->wg = c.wg;
+                p->var = c.var;
+                p->n_blocks = nb * c.factor;
+                p->tune_ms = c.ms;
+                p->tuned = p->from_cache = true;
+                p->tune_log.clear();
+                return MRI_OK;
+            }
+        }
     }
     long long target = std::max<long long>(std::min<long long>(p->n_total, 65536), p->n_total / 8);
     int k = 1;
@@ -1428,35 +1584,60 @@ static mri_status batch_tune(mri_batch_plan *p, const double *yin, double *yout,
     } ev;
     HIP_TRY(hipEventCreate(&ev.e0));
     HIP_TRY(hipEventCreate(&ev.e1));
-    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     float best = 1e30f;
+    TuneChoice pick;
     p->tune_log.clear();
-    for (int wg : {64, 128, 256}) {
-        hipFunction_t fn = nullptr;
-        mri_status st = spec_get(p->mech, wg, 2, n_poly, &fn);
-        if (st != MRI_OK) return st;
+    auto trial = [&](int wg, const SpecVariant &var) -> mri_status {
         int nb = 0;
-        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, wg, 0));
-        nb = std::max(1, nb);
+        mri_status st = resident_blocks(p, wg, n_poly, var, &nb);
+        if (st != MRI_OK) return st;
         for (int f : {1, 2}) {
-            const int blocks = nb * n_cus() * f;
-            HIP_TRY(hipEventRecord(e0, s));
-            st = batch_enqueue(p, wg, blocks, n_sample, yin, yout, ld, n_poly, rho, nullptr,
+            HIP_TRY(hipEventRecord(ev.e0, s));
+            st = batch_enqueue(p, wg, nb * f, var, n_sample, yin, yout, ld, n_poly, rho, nullptr,
                                nullptr, nullptr, s);
             if (st != MRI_OK) return st;
-            HIP_TRY(hipEventRecord(e1, s));
-            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventRecord(ev.e1, s));
+            HIP_TRY(hipEventSynchronize(ev.e1));
             float ms = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            p->tune_log.push_back({{wg, blocks}, ms});
+            HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+            p->tune_log.push_back({wg, nb * f, var, ms});
             if (ms < best) {
                 best = ms;
-                p->wg = wg;
-                p->n_blocks = blocks;
+                pick.wg = wg;
+                pick.factor = f;
+                pick.var = var;
+                pick.ms = ms;
             }
         }
+        return MRI_OK;
+    };
+    for (int wg : {64, 128, 256}) {
+        mri_status st = trial(wg, SpecVariant());
+        if (st != MRI_OK) return st;
     }
+    // register / LDS tiling variants at the best block size; a variant the
+    // compiler rejects (e.g. registers that do not fit) is skipped
+    SpecVariant v1, v2, v3, v4;
+    v1.wpe = (p->mech->S < 40) ? 1 : 2;
+    v2.exp_table = 0;
+    v3.group = 1;
+    v4.group = 4;
+    const int wg_best = pick.wg;
+    for (const SpecVariant &v : {v1, v2, v3, v4}) {
+        mri_status st = trial(wg_best, v);
+        if (st == MRI_ECOMPILE) continue;
+        if (st != MRI_OK) return st;
+    }
+    int nb = 0;
+    mri_status st = resident_blocks(p, pick.wg, n_poly, pick.var, &nb);
+    if (st != MRI_OK) return st;
+    p->wg = pick.wg;
+    p->var = pick.var;
+    p->n_blocks = nb * pick.factor;
+    p->tune_ms = pick.ms;
     p->tuned = true;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store(key, pick);
     return MRI_OK;
 }
 
@@ -1489,6 +1670,7 @@ extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, doubl
         if (st != MRI_OK) return st;
     }
     const std::vector<uintptr_t> key = {(uintptr_t)y_in, (uintptr_t)y_out, (uintptr_t)ld,
+                                        (uintptr_t)spec_key(p->wg, 2, n_poly, p->var),
                                         (uintptr_t)n_poly, (uintptr_t)rho_poly,
                                         (uintptr_t)status_out, (uintptr_t)steps_out,
                                         (uintptr_t)rejects_out, (uintptr_t)p->wg,
@@ -1500,12 +1682,12 @@ extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, doubl
         p->graph = nullptr;
         // compile outside the capture
         hipFunction_t fn = nullptr;
-        st = spec_get(p->mech, p->wg, 2, n_poly, &fn);
+        st = spec_get(p->mech, p->wg, 2, n_poly, &fn, p->var);
         if (st != MRI_OK) return st;
         if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        st = batch_enqueue(p, p->wg, p->n_blocks, p->n_total, y_in, y_out, ld, n_poly, rho_poly,
-                           status_out, steps_out, rejects_out, p->cap_stream);
+        st = batch_enqueue(p, p->wg, p->n_blocks, p->var, p->n_total, y_in, y_out, ld, n_poly,
+                           rho_poly, status_out, steps_out, rejects_out, p->cap_stream);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
         if (st != MRI_OK) {
@@ -1520,6 +1702,39 @@ extern "C" mri_status mri_batch_run(mri_batch_plan *p, const double *y_in, doubl
     HIP_TRY(hipGraphLaunch(p->exec, s));
     ++c_fast;
     c_cells += p->n_total;
+    return MRI_OK;
+}
+
+extern "C" mri_status mri_batch_plan_tune_log(const mri_batch_plan *p, int max_entries,
+                                              mri_tune_trial *trials, int *n_entries,
+                                              int *from_cache, mri_tune_trial *choice)
+{
+    if (!p || !n_entries) return fail(MRI_EINVAL, "NULL argument");
+    if (max_entries < 0 || (max_entries > 0 && !trials))
+        return fail(MRI_EINVAL, "bad trial buffer");
+    *n_entries = (int)p->tune_log.size();
+    for (int i = 0; i < std::min(max_entries, *n_entries); ++i) {
+        const auto &t = p->tune_log[i];
+        trials[i] = mri_tune_trial{t.wg, t.blocks, t.var.wpe, t.var.exp_table, t.var.group, t.ms};
+    }
+    if (from_cache) *from_cache = p->from_cache ? 1 : 0;
+    if (choice)
+        *choice = mri_tune_trial{p->wg, p->n_blocks, p->var.wpe, p->var.exp_table, p->var.group,
+                                 p->tune_ms};
+    return MRI_OK;
+}
+
+extern "C" mri_status mri_batch_plan_code_hash(const mri_batch_plan *p, int n_poly,
+                                               uint64_t *hash)
+{
+    if (!p || !hash) return fail(MRI_EINVAL, "NULL argument");
+    if (n_poly < 0 || n_poly > 4) return fail(MRI_EINVAL, "n_poly must be in [0, 4]");
+    const int wg = p->wg ? p->wg : (p->opts.block_size ? p->opts.block_size : 128);
+    std::lock_guard<std::mutex> lk(p->mech->mu);
+    SpecKernel unused;
+    mri_status st = spec_compile(p->mech, wg, 2, n_poly, 0, &unused, p->var);
+    if (st != MRI_OK) return st;
+    *hash = code_hash_bytes(p->mech->last_code);
     return MRI_OK;
 }
 

@@ -411,16 +411,24 @@ def mechanism_arrays(m: Mechanism) -> dict:
     )
 
 
-def batch_workload(n_sets: int = 1000, workload: str = SETS1000):
+def batch_workload(n_sets: int = 1000, workload: str = SETS1000, divergent: bool = False):
     """Uneven reactor sets: sizes log-uniform in [64, 65536], every cell drawn
     like the independent-cell workload (T ~ U[1000, 2000] K, Y ~ Dirichlet(1)),
     and one fast stage per set whose length cycles through the three stage
     lengths dc_i H of the MIS-KW3 table (H = 1e-7 s).  No slow tendencies are
-    stated for this workload: the stage is unforced (n_poly = 0)."""
+    stated for this workload: the stage is unforced (n_poly = 0).
+
+    divergent: the same sets and cells with per-set stage lengths log-uniform
+    in [1e-8, 1e-6] s (the stages of slow steps an adaptive slow controller
+    takes up to about 2.4e-6 s), which spreads the adaptive fast method's
+    accepted steps over 10 to 2,000 per cell."""
     cfg = WORKLOADS[workload]
     sizes = set_sizes(n_sets, workload=workload)
     off = set_offsets(sizes)
     y = independent_cells(int(off[-1]), WORKLOADS[cfg.mech_of].n_species, rng_for(workload, 1))
-    dc = np.diff(table_mis_kw3().c)
-    L = np.array([dc[i % dc.size] * cfg.H for i in range(n_sets)])
+    if divergent:
+        L = np.exp(rng_for(workload, 2).uniform(math.log(1e-8), math.log(1e-6), n_sets))
+    else:
+        dc = np.diff(table_mis_kw3().c)
+        L = np.array([dc[i % dc.size] * cfg.H for i in range(n_sets)])
     return sizes, off, y, L

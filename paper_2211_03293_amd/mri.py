@@ -62,6 +62,11 @@ class mri_fast_opts(C.Structure):
                 ("kernel", C.c_int), ("block_size", C.c_int), ("stiff_limit", C.c_double)]
 
 
+class mri_tune_trial(C.Structure):
+    _fields_ = [("block_size", C.c_int), ("n_blocks", C.c_int), ("waves_per_simd", C.c_int),
+                ("exp_table", C.c_int), ("sched_window", C.c_int), ("ms", C.c_float)]
+
+
 class mri_advdiff_params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("n_comp", C.c_int),
                 ("u", C.c_double * 3), ("D", C.c_double), ("dx", C.c_double)]
@@ -120,6 +125,9 @@ _SIGS = {
     "mri_reset_counters": (None, []),
     "mri_timing_enable": (_i, [_i]),
     "mri_timing_read": (_i, [C.POINTER(C.c_double), C.POINTER(C.c_int64), _i]),
+    "mri_batch_plan_code_hash": (_i, [_vp, _i, C.POINTER(C.c_uint64)]),
+    "mri_batch_plan_tune_log": (_i, [_vp, _i, C.POINTER(mri_tune_trial), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int), C.POINTER(mri_tune_trial)]),
     "mri_batch_plan_create": (_i, [_vp, C.POINTER(mri_fast_opts), _i, C.POINTER(C.c_int64),
                                    C.POINTER(_vp)]),
     "mri_batch_run": (_i, [_vp, _vp, _vp, C.c_int64, _i, _vp, C.POINTER(C.c_double), _vp, _vp,
@@ -416,6 +424,24 @@ class BatchPlan:
         b, n = C.c_int(0), C.c_int(0)
         _check(lib.mri_batch_plan_tile(self.h, C.byref(b), C.byref(n)))
         return b.value, n.value
+
+    def tune_log(self):
+        """(trials, from_cache, choice): the autotuner's timed candidates of the
+        first run and its choice, as dicts."""
+        n, fc, ch = C.c_int(0), C.c_int(0), mri_tune_trial()
+        _check(lib.mri_batch_plan_tune_log(self.h, 0, None, C.byref(n), C.byref(fc),
+                                           C.byref(ch)))
+        buf = (mri_tune_trial * max(1, n.value))()
+        _check(lib.mri_batch_plan_tune_log(self.h, n.value, buf, C.byref(n), None, None))
+
+        def d(t):
+            return {k: getattr(t, k) for k, _ in mri_tune_trial._fields_}
+        return [d(buf[i]) for i in range(n.value)], bool(fc.value), d(ch)
+
+    def code_hash(self, n_poly=0):
+        h = C.c_uint64(0)
+        _check(lib.mri_batch_plan_code_hash(self.h, n_poly, C.byref(h)))
+        return f"{h.value:016x}"
 
     def lane_stats(self, stream=None):
         u, i = C.c_uint64(0), C.c_uint64(0)

@@ -3,7 +3,7 @@ with libmri's own BF16 MFMA forward / backward / Adam kernels, and evaluation
 of the gated surrogate stage against the plain FP64 stage.
 
 Every arithmetic step runs in libmri kernels; this module only orders the
-calls, draws random sample indices and moves tensors.
+calls, draws random sample indices, selects samples and moves tensors.
 
 The network predicts the correction from a coarse FP64 solve of the stage (RK4
 with N_COARSE substeps) to the plain stage (the workload's substeps).  Stage
@@ -120,10 +120,48 @@ def init_params(seed=4004):
     return np.concatenate(out)
 
 
-def train(data: StageData, steps=20000, batch=4096, lr=2e-3, lr_min=2e-5, seed=5005,
-          val_frac=0.05, log=print, log_every=2000, init_seed=4004):
-    """Adam with cosine learning-rate decay on the standardized MSE."""
+def correctable(data: StageData, cap, chunk=65536):
+    """The samples whose correction is at most `cap` relative (log(Y + 1e-8) for
+    the species, T relative): libmri's featurization gives the standardized
+    corrections, which are de-standardized and compared here."""
     torch = _torch()
+    stats = torch.empty(mri.MLP_STATS, dtype=torch.float64, device="cuda")
+    mri.mri_mlp_feature_stats(data.n, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats,
+                              Yb=data.Yc)
+    F, n = mri.MLP_FEATURES, mri.MLP_OUTPUTS
+    y_mean, y_std = stats[2 * F:2 * F + n], stats[2 * F + 2 * n:]
+    X = torch.empty((chunk, mri.MLP_KPAD), dtype=torch.bfloat16, device="cuda")
+    T = torch.empty((chunk, n), dtype=torch.float32, device="cuda")
+    keep = []
+    for a in range(0, data.n, chunk):
+        b = min(data.n, a + chunk)
+        idx = torch.arange(a, b, dtype=torch.int32, device="cuda")
+        mri.mri_mlp_featurize(b - a, idx, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats,
+                              X, T, Yb=data.Yc)
+        raw = T[:b - a].double() * y_std + y_mean
+        raw[:, n - 1] /= data.Y0[n - 1, a:b]
+        keep.append(raw.abs().amax(1) <= cap)
+    return torch.nonzero(torch.cat(keep)).squeeze(1)
+
+
+def subset(data: StageData, idx):
+    return StageData(data.Y0[:, idx].contiguous(), data.RHO[:, :, idx].contiguous(),
+                     data.L[idx].contiguous(), data.Yc[:, idx].contiguous(),
+                     data.Y1[:, idx].contiguous())
+
+
+def train(data: StageData, steps=20000, batch=4096, lr=2e-3, lr_min=2e-5, seed=5005,
+          val_frac=0.05, log=print, log_every=2000, init_seed=4004, max_correction=1e-4):
+    """Adam with cosine learning-rate decay on the standardized MSE, over the
+    samples whose correction is at most max_correction (None: all): a cell the
+    coarse stage misses by more than the stage tolerance needs the network to
+    that tolerance of a large correction and is left to the plain fallback,
+    and the statistics of the remaining corrections set the output scale."""
+    torch = _torch()
+    if max_correction is not None:
+        idx = correctable(data, max_correction)
+        log(f"# training on {idx.numel()} of {data.n} samples (correction <= {max_correction:g})")
+        data = subset(data, idx)
     stats = torch.empty(mri.MLP_STATS, dtype=torch.float64, device="cuda")
     mri.mri_mlp_feature_stats(data.n, data.n, data.Y0, 1, data.RHO, data.L, data.Y1, stats,
                               Yb=data.Yc)

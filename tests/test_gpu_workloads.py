@@ -255,8 +255,11 @@ def test_batch_with_empty_sets(torch, mri, O):
 def test_batch_result_is_independent_of_the_tile(torch, mri, O):
     """Each cell is integrated by one lane from start to finish, so the batched
     results do not depend on how the queue hands cells out: tiles of 64 and 256
-    lanes per block (and the autotuned one) give bitwise equal states, status
-    bits and step counts."""
+    lanes per block give bitwise equal states, status bits and step counts.  The
+    autotuned plan may also pick another register / LDS variant, whose
+    exponential (LDS table or polynomial, each within an ulp of 2^t) rounds
+    differently: its states agree to the parity bound, with the same status
+    bits, and bitwise when it keeps the built-in variant."""
     mech, off, y, Ls, rng = _batch_inputs(40, 64, 3000, seed=23)
     n, ld = y.shape
     ntot = int(off[-1])
@@ -273,12 +276,24 @@ def test_batch_result_is_independent_of_the_tile(torch, mri, O):
         plan.run(yd, out, ld, 0, None, Ls, st, steps)
         torch.cuda.synchronize()
         res.append((out.cpu().numpy()[:, :ntot], st.cpu().numpy()[:ntot],
-                    steps.cpu().numpy()[:ntot], plan.tile()))
-    print(f"batch tiles {[r[3] for r in res]}, {ntot} cells")
-    for r in res[1:]:
-        assert np.array_equal(r[0], res[0][0])
-        assert np.array_equal(r[1], res[0][1]) and np.array_equal(r[2], res[0][2])
+                    steps.cpu().numpy()[:ntot], plan.tile(), plan.tune_log()[2]))
+    choice = res[2][4]
+    print(f"batch tiles {[r[3] for r in res]}, tuned choice {choice}, {ntot} cells")
+    assert np.array_equal(res[1][0], res[0][0])
+    assert np.array_equal(res[1][1], res[0][1]) and np.array_equal(res[1][2], res[0][2])
     assert res[0][3][0] == 64 and res[1][3][0] == 256
+    tuned, ref = res[2], res[0]
+    assert np.array_equal(tuned[1], ref[1])
+    builtin = (choice["waves_per_simd"] == 0 and choice["exp_table"] < 0)
+    if builtin:
+        assert np.array_equal(tuned[0], ref[0]) and np.array_equal(tuned[2], ref[2])
+    else:
+        floor = np.r_[np.full(n - 1, 1e-12), 0.0][:, None]
+        rel = np.abs(tuned[0] - ref[0]) / np.maximum(np.abs(ref[0]), floor)
+        print(f"tuned variant vs built-in: max rel diff {rel.max():.2e}, step counts differ on "
+              f"{int((tuned[2] != ref[2]).sum())} cells")
+        assert rel.max() <= 1e-10
+        assert (tuned[2] != ref[2]).mean() <= 1e-3
 
 
 def test_slow_step_graph_capture_replays(torch, mri, O):
@@ -606,3 +621,46 @@ def test_large_mechanism_fullsize_step_sampled(torch, mri, O):
                       what="53 species 128^3 step")
     print(f"53-species 128^3 MRI step, {centres.size} sampled cells "
           f"({regions[0].size} stage-1 cells): max rel err {e:.2e}")
+
+
+def test_batch_tuner_log_and_cache(torch, mri, O, tmp_path, monkeypatch):
+    """The autotuner times block sizes x grid factors, then register / LDS tiling
+    variants at the best block size, keeps the fastest trial, and caches it: a
+    second plan with the same key takes the choice without timing, and both
+    plans give bitwise equal results that match the oracle on sampled cells."""
+    monkeypatch.setenv("MRI_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    mech, off, y, Ls, rng = _batch_inputs(30, 64, 4000, seed=91)
+    n, ld = y.shape
+    ntot = int(off[-1])
+    m = mri.Mech(mech)
+    # tolerances no other test uses, so that this key is not cached yet
+    zv = dict(method=mri.FAST_ZONNEVELD43, rtol=2e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
+    yd = torch.as_tensor(y, device="cuda")
+    outs, logs = [], []
+    for _ in range(2):
+        plan = mri.BatchPlan(m, mri.fast_opts(**zv), off)
+        out = torch.zeros_like(yd)
+        plan.run(yd, out, ld, 0, None, Ls)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy()[:, :ntot])
+        logs.append(plan.tune_log())
+    (trials, cached1, choice1), (trials2, cached2, choice2) = logs
+    print(f"tuner: {len(trials)} trials, choice {choice1}")
+    assert not cached1 and cached2 and not trials2
+    assert len(trials) >= 6 + 2 and {t["block_size"] for t in trials} == {64, 128, 256}
+    assert any(t["waves_per_simd"] or t["exp_table"] >= 0 or t["sched_window"] for t in trials)
+    best = min(trials, key=lambda t: t["ms"])
+    for k in ("block_size", "n_blocks", "waves_per_simd", "exp_table", "sched_window"):
+        assert choice1[k] == best[k] == choice2[k], k
+    assert np.array_equal(outs[0], outs[1])
+    assert (tmp_path / "tune.txt").read_text().count("\t") >= 1
+    zo = O.zonneveld_opts(rtol=2e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000)
+    orc = O.Oracle(mech)
+    cells = _sample(ntot, 64, seed=92)
+    set_of = np.searchsorted(off, cells, side="right") - 1
+    for c, s in zip(cells, set_of):
+        ref, st_o, _, _ = orc.zonneveld_stage(y[:, c], np.zeros((1, n)), Ls[s], zo)
+        if st_o & mri.CELL_NEARTIE:
+            continue
+        err = np.abs(outs[0][:, c] - ref) / np.maximum(np.abs(ref), np.r_[np.full(n - 1, 1e-12), 0])
+        assert err.max() <= 1e-10, (c, err.max())
