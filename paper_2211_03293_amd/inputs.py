@@ -168,6 +168,55 @@ def table_erk45a() -> Table:
     return Table("MRI-GARK-ERK45a", c, g)
 
 
+@dataclass
+class ImexTable:
+    """Solve-decoupled IMEX-MRI-GARK coupling table (f^S = f^I + f^E).
+
+    gamma[k][i][j] multiplies the implicit slow evaluation f^I(T_j, Y_j) and
+    omega[k][i][j] the explicit one f^E(T_j, Y_j) in the k-th forcing term of
+    stage i; gamma may be nonzero on its diagonal only on stages with
+    c_i = c_(i-1) (the implicit, solve-decoupled stages)."""
+    name: str
+    c: np.ndarray               # [s]
+    gamma: np.ndarray           # [n_gamma][s][s]
+    omega: np.ndarray           # [n_gamma][s][s]
+
+    @property
+    def s(self):
+        return self.c.shape[0]
+
+    @property
+    def n_gamma(self):
+        return self.gamma.shape[0]
+
+
+def table_imex_trap2() -> ImexTable:
+    """2nd-order solve-decoupled IMEX-MRI-GARK table, s = 3, c = (0, 1, 1).
+
+    Stage 2 integrates the fast IVP over the whole step forced by
+    f^I(y_n) + f^E(y_n); stage 3 is the solve-decoupled implicit stage
+    Y_3 = Y_2 + (H/2)(f^I(Y_3) - f^I(Y_1)) + (H/2)(f^E(Y_2) - f^E(Y_1)).
+    With f^F = 0 this is the trapezoidal rule for f^I paired with Heun's
+    method for f^E; with f^S = 0 the exact fast flow."""
+    c = np.array([0.0, 1.0, 1.0])
+    g = np.zeros((1, 3, 3))
+    w = np.zeros((1, 3, 3))
+    g[0, 1, 0] = 1.0
+    g[0, 2, 0] = -0.5
+    g[0, 2, 2] = 0.5
+    w[0, 1, 0] = 1.0
+    w[0, 2, 0] = -0.5
+    w[0, 2, 1] = 0.5
+    return ImexTable("IMEX-MRI-GARK-trap2", c, g, w)
+
+
+# The 64^3 fields with a diffusion coefficient raised so that the diffusion
+# number H D / dx^2 is 1 at H = 1e-7 s: beyond the stability limit of the
+# explicit slow tables (about 0.2 in 3-D for a 3rd-order explicit method), the
+# regime in which the diffusion is taken implicitly.
+ADVDIFF_STIFF = dict(u=(10.0, 10.0, 10.0), D=0.1, dx=1e-4)
+
+
 def table_zero_forcing(c) -> Table:
     """Coupling table with Gamma = 0 (pure fast integration over the stage grid)."""
     c = np.asarray(c, dtype=np.float64)
