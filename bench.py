@@ -19,10 +19,11 @@ stream around every fast-stage launch inside the timed region, FP64 flops from
 the algorithmic count and from rocprof counters) and the oracle timed on a
 bounded sample.  Further objects: the accuracy of the surrogate on every cell
 of the first slow step, the plain legs (128^3 and 64^3), the 53-species large
-mechanism, the batched uneven reactor sets.
+mechanism, the IMEX-MRI-GARK steps with stiff diffusion, the batched uneven
+reactor sets.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-large] [--no-batch] [--no-plain64]
+                    [--no-large] [--no-batch] [--no-plain64] [--no-imex]
 """
 from __future__ import annotations
 
@@ -332,6 +333,99 @@ def plain_leg(torch, mri, I, workload, steps, warmup, block, kernel_name):
                             flagged_cells=n_bad))
 
 
+def imex_leg(torch, mri, I, steps=5, warmup=1):
+    """IMEX-MRI-GARK steps (2nd-order solve-decoupled table: one fast stage over
+    the step, one implicit diffusion stage) on the 64^3 fields with the
+    diffusion number H D / dx^2 = 1, where the explicit MIS-KW3 table diverges;
+    RK4 with 120 substeps (the explicit workload's largest fast step).  Wall
+    time per step, fast-kernel time, conjugate-gradient iterations per solve,
+    and one diffusion solve timed alone for its HBM roofline (algorithmic
+    traffic 11 planes per iteration: the stencil reads p and writes q, the
+    update reads x, p, r, q and writes x, r, the direction update reads r, p
+    and writes p).  The explicit table's first flagged step on the same state
+    plus a 1e-6 K checkerboard is reported beside it."""
+    cfg = I.WORKLOADS[I.FIELD64]
+    P = I.ADVDIFF_STIFF
+    mech = I.make_mechanism(I.FIELD64)
+    N = cfg.n_cells
+    y_host = I.initial_state(I.FIELD64)
+    n, ld = y_host.shape
+    m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+    m.specialize(128, load=True)
+    params = mri.advdiff_params(cfg.grid, n, u=P["u"], D=P["D"], dx=P["dx"])
+    cws = torch.empty(mri.diffusion_solve_workspace_bytes(params, ld), dtype=torch.uint8,
+                      device="cuda")
+    ctx = mri.imex_advdiff(params, cws, cg_rtol=1e-13)
+    ws = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8, device="cuda")
+    y0 = torch.as_tensor(y_host, device="cuda")
+    y = y0.clone()
+    status = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    opts = mri.fast_opts(n_sub=I.IMEX_N_SUB)
+    H = cfg.H
+    for k in range(warmup):
+        mri.mri_imex_slow_step(m, t, opts, ctx, k * H, H, N, ld, y, ws, status_out=status)
+    torch.cuda.synchronize()
+    y.copy_(y0)
+    mri.timing_enable(True)
+    mri.timing_read(reset=True)
+    iters = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        mri.mri_imex_slow_step(m, t, opts, ctx, k * H, H, N, ld, y, ws, status_out=status)
+        iters.append(ctx.cg_iters)
+    e1.record()
+    torch.cuda.synchronize()
+    wall_ms = e0.elapsed_time(e1)
+    fast_ms, n_launch = mri.timing_read(reset=True)
+    mri.timing_enable(False)
+    n_bad = mri.mri_status_count(status, N)
+    # one diffusion solve alone, on the current state, a = H / 2 as in the step
+    r = y.clone()
+    out = torch.empty_like(r)
+    mri.mri_diffusion_solve(ctx, 0.5 * H, r, out, N, ld)
+    torch.cuda.synchronize()
+    e0.record()
+    mri.mri_diffusion_solve(ctx, 0.5 * H, r, out, N, ld)
+    e1.record()
+    torch.cuda.synchronize()
+    solve_ms = e0.elapsed_time(e1)
+    it = ctx.cg_iters
+    bytes_alg = 11 * 8 * n * N * it
+    gbs = bytes_alg / (solve_ms * 1e-3) / 1e9
+    # the explicit table on the same fields with a grid-scale perturbation
+    te = mri.Table(I.table_mis_kw3())
+    wse = torch.empty(mri.mri_workspace_bytes(m, te, N, ld) // 8, dtype=torch.float64,
+                      device="cuda")
+    z, yy, x = np.meshgrid(np.arange(64), np.arange(64), np.arange(64), indexing="ij")
+    ye = y0.clone()
+    ye[-1, :N] += torch.as_tensor(1e-6 * ((-1.0) ** (x + yy + z)).ravel(), device="cuda")
+    ste = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    flagged_at = None
+    for k in range(12):
+        mri.mri_slow_step(m, te, mri.fast_opts(n_sub=cfg.n_sub), mri.ADVDIFF_RHS, params, k * H, H,
+                          N, ld, ye, wse, status_out=ste)
+        if mri.mri_status_count(ste, N) > 0:
+            flagged_at = k + 1
+            break
+    print(f"# imex: {steps} steps {wall_ms:.1f} ms, fast kernels {fast_ms:.1f} ms, CG iterations "
+          f"{iters}, solve {solve_ms:.3f} ms ({gbs:.0f} GB/s algorithmic), explicit flagged at "
+          f"step {flagged_at}", file=sys.stderr, flush=True)
+    return dict(workload="IMEX-MRI-GARK (2nd-order solve-decoupled table) steps, 64^3 cells, 21 "
+                         "species / 84 reactions, H = 1e-7 s, advection explicit, diffusion "
+                         "implicit with D = 0.1 m^2/s (H D / dx^2 = 1), RK4 120 substeps",
+                value=round(N * steps / (wall_ms * 1e-3), 1), unit="cell-steps/s",
+                ms_per_step=round(wall_ms / steps, 3), fast_kernel_ms_per_step=round(
+                    fast_ms / steps, 3), cg_iterations=iters, flagged_cells=n_bad,
+                diffusion_solve=dict(ms=round(solve_ms, 3), iterations=it, cg_rtol=1e-13,
+                                     roofline=dict(bound="hbm", achieved=round(gbs, 1),
+                                                   peak=8000.0, unit="GB/s",
+                                                   frac=round(gbs / 8000.0, 4),
+                                                   bytes_per_iteration=11 * 8 * n * N)),
+                explicit_mis_kw3_first_flagged_step=flagged_at)
+
+
 def train_surrogate(n_samples, train_steps, log):
     """Stage data from the 64^3 workload's plain runs and training with libmri's
     BF16 MFMA kernels (setup of the headline, not timed as a bench step)."""
@@ -493,6 +587,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-set leg")
     ap.add_argument("--no-plain64", action="store_true", help="skip the 64^3 plain leg")
+    ap.add_argument("--no-imex", action="store_true", help="skip the IMEX (stiff diffusion) leg")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 128^3 large-mechanism leg (53 species / 325 reactions)")
     ap.add_argument("--surrogate-steps", type=int, default=40000,
@@ -582,6 +677,9 @@ def main():
                 mechanism="GRI-Mech 3.0, 53 species / 325 reactions (same size as this leg's "
                           "synthetic mechanism)",
                 note="other hardware and another integrator; context, not the target"))
+    if not args.no_imex:
+        log("# IMEX leg (stiff diffusion)")
+        out["imex"] = imex_leg(torch, mri, I)
     if not args.no_batch:
         log("# batched uneven-set legs (the standard one tunes; the divergent one takes its "
             "choice from the tuning cache)")

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MRI_ABI_VERSION 2
+#define MRI_ABI_VERSION 3
 
 typedef enum {
     MRI_OK = 0,
@@ -56,7 +56,8 @@ typedef enum {
     MRI_EMAXSTEPS = -4,     /* reserved for synchronous step-cap reports        */
     MRI_ENOMEM = -5,        /* host or device allocation failed                 */
     MRI_EUNSUPPORTED = -6,  /* valid request outside what this build supports   */
-    MRI_ECOMPILE = -7       /* run-time specialization of a kernel failed        */
+    MRI_ECOMPILE = -7,      /* run-time specialization of a kernel failed        */
+    MRI_ENOCONV = -8        /* an iterative solve missed its tolerance           */
 } mri_status;
 
 /* Per-cell status bits written to status_out arrays. */
@@ -313,6 +314,86 @@ int mri_advdiff_slow_rhs(double t, const double *y, double *fy, int n_cells, int
    (mri_mech_create_linear) passed as `user`. */
 int mri_linear_slow_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
                         mri_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* IMEX-MRI-GARK slow step (Sec. 2.1: the slow operator split as              */
+/* f^S = f^I + f^E, f^I treated implicitly on solve-decoupled stages; Sec. 3.2 */
+/* and Sec. 6 take the diffusion implicitly and the advection explicitly).     */
+/* Table: c[s] nondecreasing with c_1 = 0 and c_s = 1; gamma[k][i][j] weighs   */
+/* the implicit evaluations FI_j = f^I(T_j, Y_j), omega[k][i][j] the explicit  */
+/* ones FE_j = f^E(T_j, Y_j).  A stage with Delta c_i > 0 is a fast stage       */
+/* with forcing r_i(tau) = (1/Delta c_i) sum_k tau^k sum_(j<i) (gamma[k][i][j] */
+/* FI_j + omega[k][i][j] FE_j); a stage with Delta c_i = 0 is solve-decoupled:  */
+/* Y_i = Y_(i-1) + H sum_(j<i) (gbar_ij FI_j + obar_ij FE_j) + H gbar_ii FI_i,  */
+/* gbar_ij = sum_k gamma[k][i][j] / (k + 1) (obar likewise), solved for Y_i.    */
+/* Creation checks: omega strictly lower triangular; gamma lower triangular    */
+/* with its diagonal zero on fast stages; both rows' integral weights sum to   */
+/* Delta c_i (1e-12); at least one fast stage; s <= 13, n_gamma <= 4.          */
+/* ------------------------------------------------------------------------- */
+typedef struct mri_imex_table mri_imex_table;
+typedef struct {
+    int s;                              /* number of stages, 2..13          */
+    int n_gamma;                        /* forcing polynomial terms, 1..4   */
+    const double *c;                    /* host [s]                         */
+    const double *gamma;                /* host [n_gamma][s][s], f^I        */
+    const double *omega;                /* host [n_gamma][s][s], f^E        */
+} mri_imex_table_desc;
+mri_status mri_imex_table_create(const mri_imex_table_desc *desc, mri_imex_table **out);
+void mri_imex_table_destroy(mri_imex_table *t);
+
+/* Implicit solve callback: enqueue on `stream` the solution y of
+   y - a f^I(t, y) = r for the SoA arrays (device [n][ld], cells below
+   n_cells); returns 0 on success, nonzero on failure (the step then returns
+   MRI_ENOCONV). */
+typedef int (*mri_implicit_solve)(double t, double a, const double *r, double *y, int n_cells,
+                                  int ld, void *user, mri_stream_t stream);
+
+/* Workspace: 8 n ld (2 (s - 1) + n_gamma) bytes (the slow evaluations of both
+   partitions and the forcing planes, the first of which also holds the
+   right-hand side of a solve-decoupled stage). */
+mri_status mri_imex_workspace_bytes(const mri_mech *m, const mri_imex_table *t, int n_cells,
+                                    int ld, size_t *bytes);
+/* One IMEX-MRI-GARK step y_n -> y_(n+1) in place.  f_expl, f_impl: slow RHS
+   callbacks as for mri_slow_step; solve_impl: the implicit solve; all three
+   get `user`.  Evaluations per step: s - 1 of each partition; one solve per
+   solve-decoupled stage with gbar_ii != 0.  status_out / steps_out (optional,
+   device [n_cells]) accumulate over the fast stages.  The solve callback may
+   synchronize the stream (the built-in one does). */
+mri_status mri_imex_slow_step(const mri_mech *m, const mri_imex_table *t,
+                              const mri_fast_opts *opts, mri_slow_rhs f_expl,
+                              mri_slow_rhs f_impl, mri_implicit_solve solve_impl, void *user,
+                              double t0, double H, int n_cells, int ld, double *y, void *ws,
+                              size_t ws_bytes, int32_t *status_out, int32_t *steps_out,
+                              mri_stream_t stream);
+
+/* Built-in split of the advection-diffusion operator for the IMEX step (pass
+   a pointer to this struct as `user`): f^E = -u . grad(phi) and f^I =
+   D lap(phi), the two halves of mri_advdiff_slow_rhs's stencil, and the
+   implicit diffusion solve (I - a D lap) y = r by conjugate gradients, one
+   independent CG per component (the operator is symmetric positive definite
+   on the periodic grid, with eigenvalues in [1, 1 + 12 a D / dx^2]), started
+   from y = r and stopped when ||r_c - A y_c||_2 <= cg_rtol ||r_c||_2 for
+   every component c (recursive residual).  Because ||A^-1|| <= 1, the error
+   of every element of y_c is then at most cg_rtol ||r_c||_2.  The solve
+   checks convergence on the host every 8 iterations (synchronizing the
+   stream) and fails after cg_max_iter iterations. */
+typedef struct {
+    mri_advdiff_params grid;            /* grid, n_comp, u, D, dx                */
+    double cg_rtol;                     /* > 0, e.g. 1e-13                       */
+    int cg_max_iter;                    /* >= 1                                  */
+    void *cg_ws;                        /* device, mri_diffusion_solve_workspace */
+    size_t cg_ws_bytes;
+    int cg_iters;                       /* out: iterations of the last solve     */
+    int cg_solves;                      /* out: incremented by every solve       */
+} mri_imex_advdiff;
+mri_status mri_diffusion_solve_workspace_bytes(const mri_advdiff_params *grid, int ld,
+                                               size_t *bytes);
+int mri_advection_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
+                      mri_stream_t stream);
+int mri_diffusion_rhs(double t, const double *y, double *fy, int n_cells, int ld, void *user,
+                      mri_stream_t stream);
+int mri_diffusion_solve(double t, double a, const double *r, double *y, int n_cells, int ld,
+                        void *user, mri_stream_t stream);
 
 /* Diagnostic: y[i] = 2^x[i] (device arrays, n elements) with the polynomial
    exponential of the generic kernels and of the specialized kernels that run

@@ -1464,12 +1464,21 @@ static std::string tune_cache_path()
 static std::string tune_key(const mri_batch_plan *p, int n_poly)
 {
     char b[256];
-    const mri_mech *m = p->mech;
+    mri_mech *m = p->mech;
+    uint64_t defs_hash = 0;
+    {
+        // the literal block is generated on the first compilation; generate it
+        // here when no kernel has been compiled yet, so that the key is the same
+        // before and after
+        std::lock_guard<std::mutex> lk(m->mu);
+        if (m->defs.empty()) m->defs = make_defs(*m);
+        defs_hash = fnv1a(m->defs);
+    }
     int size_class = 0;
     while (size_class < 62 && (2ll << size_class) <= p->n_total) ++size_class;
     snprintf(b, sizeof b, "mech=%016llx S=%d R=%d method=%d np=%d rtol=%a atolY=%a atolT=%a "
              "max_steps=%d log2cells=%d arch=%s",
-             (unsigned long long)fnv1a(m->defs), m->S, m->R, p->opts.method, n_poly,
+             (unsigned long long)defs_hash, m->S, m->R, p->opts.method, n_poly,
              p->opts.rtol, p->opts.atol_Y, p->opts.atol_T, p->opts.max_steps, size_class,
              device_arch().c_str());
     return b;

@@ -215,6 +215,10 @@ def table_imex_trap2() -> ImexTable:
 # explicit slow tables (about 0.2 in 3-D for a 3rd-order explicit method), the
 # regime in which the diffusion is taken implicitly.
 ADVDIFF_STIFF = dict(u=(10.0, 10.0, 10.0), D=0.1, dx=1e-4)
+# RK4 substeps of the one fast stage per step of table_imex_trap2 (it spans the
+# whole step): H / 120 is the largest fast step of the explicit 64^3 workload
+# (MIS-KW3's longest stage, 5H/12, over 50 substeps).
+IMEX_N_SUB = 120
 
 
 def table_zero_forcing(c) -> Table:

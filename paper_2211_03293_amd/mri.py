@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MRI_LIB_PATH") or os.path.join(_HERE, "libmri.so")
 
 MRI_OK, MRI_EINVAL, MRI_EHIP, MRI_ENONFINITE, MRI_EMAXSTEPS, MRI_ENOMEM, MRI_EUNSUPPORTED, \
-    MRI_ECOMPILE = 0, -1, -2, -3, -4, -5, -6, -7
+    MRI_ECOMPILE, MRI_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7, -8
 CELL_NONFINITE, CELL_MAXSTEPS, CELL_TRANGE, CELL_NEARTIE, CELL_STIFF = 1, 2, 4, 8, 16
 FAST_RK4, FAST_ZONNEVELD43, FAST_HEUN, FAST_BS3, FAST_CK5 = 0, 1, 2, 3, 4
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
@@ -62,6 +62,11 @@ class mri_fast_opts(C.Structure):
                 ("kernel", C.c_int), ("block_size", C.c_int), ("stiff_limit", C.c_double)]
 
 
+class mri_imex_table_desc(C.Structure):
+    _fields_ = [("s", C.c_int), ("n_gamma", C.c_int), ("c", C.POINTER(C.c_double)),
+                ("gamma", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double))]
+
+
 class mri_tune_trial(C.Structure):
     _fields_ = [("block_size", C.c_int), ("n_blocks", C.c_int), ("waves_per_simd", C.c_int),
                 ("exp_table", C.c_int), ("sched_window", C.c_int), ("ms", C.c_float)]
@@ -70,6 +75,12 @@ class mri_tune_trial(C.Structure):
 class mri_advdiff_params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("n_comp", C.c_int),
                 ("u", C.c_double * 3), ("D", C.c_double), ("dx", C.c_double)]
+
+
+class mri_imex_advdiff(C.Structure):
+    _fields_ = [("grid", mri_advdiff_params), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int),
+                ("cg_ws", C.c_void_p), ("cg_ws_bytes", C.c_size_t), ("cg_iters", C.c_int),
+                ("cg_solves", C.c_int)]
 
 
 class mri_adapt_opts(C.Structure):
@@ -117,6 +128,16 @@ _SIGS = {
                               C.POINTER(mri_adapt_stats), _vp]),
     "mri_advdiff_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
     "mri_linear_slow_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
+    "mri_imex_table_create": (_i, [C.POINTER(mri_imex_table_desc), C.POINTER(_vp)]),
+    "mri_imex_table_destroy": (None, [_vp]),
+    "mri_imex_workspace_bytes": (_i, [_vp, _vp, _i, _i, C.POINTER(_sz)]),
+    "mri_imex_slow_step": (_i, [_vp, _vp, C.POINTER(mri_fast_opts), _vp, _vp, _vp, _vp, _d, _d,
+                                _i, _i, _vp, _vp, _sz, _vp, _vp, _vp]),
+    "mri_diffusion_solve_workspace_bytes": (_i, [C.POINTER(mri_advdiff_params), _i,
+                                                 C.POINTER(_sz)]),
+    "mri_advection_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
+    "mri_diffusion_rhs": (_i, [_d, _vp, _vp, _i, _i, _vp, _vp]),
+    "mri_diffusion_solve": (_i, [_d, _d, _vp, _vp, _i, _i, _vp, _vp]),
     "mri_selftest_exp2": (_i, [_vp, _vp, _i, _vp]),
     "mri_selftest_exp2_t256": (_i, [_vp, _vp, _i, _vp]),
     "mri_status_count": (_i, [_vp, _i, C.c_int32, C.POINTER(C.c_int64), _vp]),
@@ -263,6 +284,26 @@ class Table:
             self.h = _null()
 
 
+class ImexTable:
+    """IMEX-MRI-GARK coupling table (include/mri.h: mri_imex_table_create)."""
+
+    def __init__(self, table):
+        self.c = _f64(table.c)
+        self.gamma = _f64(table.gamma)
+        self.omega = _f64(table.omega)
+        self.s, self.n_gamma = self.c.size, self.gamma.shape[0]
+        self.h = C.c_void_p()
+        dp = C.POINTER(C.c_double)
+        d = mri_imex_table_desc(self.s, self.n_gamma, self.c.ctypes.data_as(dp),
+                                self.gamma.ctypes.data_as(dp), self.omega.ctypes.data_as(dp))
+        _check(lib.mri_imex_table_create(C.byref(d), C.byref(self.h)))
+
+    def __del__(self, _destroy=lib.mri_imex_table_destroy, _null=C.c_void_p):
+        if getattr(self, "h", None) and self.h.value:
+            _destroy(self.h)
+            self.h = _null()
+
+
 def fast_opts(method=FAST_RK4, n_sub=1, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5, max_steps=2000,
               kernel=KERNEL_AUTO, block_size=0, stiff_limit=0.0):
     return mri_fast_opts(method, n_sub, rtol, atol_Y, atol_T, max_steps, kernel, block_size,
@@ -296,6 +337,61 @@ LINEAR_RHS = C.cast(lib.mri_linear_slow_rhs, C.c_void_p).value
 
 def advdiff_params(grid, n_comp, u=(10.0, 10.0, 10.0), D=1e-5, dx=1e-4):
     return mri_advdiff_params(grid[0], grid[1], grid[2], n_comp, (C.c_double * 3)(*u), D, dx)
+
+
+ADVECTION_RHS = C.cast(lib.mri_advection_rhs, C.c_void_p).value
+DIFFUSION_RHS = C.cast(lib.mri_diffusion_rhs, C.c_void_p).value
+DIFFUSION_SOLVE = C.cast(lib.mri_diffusion_solve, C.c_void_p).value
+
+
+def diffusion_solve_workspace_bytes(params, ld):
+    b = C.c_size_t(0)
+    _check(lib.mri_diffusion_solve_workspace_bytes(C.byref(params), ld, C.byref(b)))
+    return b.value
+
+
+def imex_advdiff(params, cg_ws, cg_rtol=1e-13, cg_max_iter=500):
+    """The built-in advection (explicit) / diffusion (implicit) split for
+    mri_imex_slow_step; cg_ws: a device tensor of at least
+    diffusion_solve_workspace_bytes(params, ld) bytes (kept alive by the caller)."""
+    return mri_imex_advdiff(params, float(cg_rtol), int(cg_max_iter), _ptr(cg_ws),
+                            cg_ws.numel() * cg_ws.element_size(), 0, 0)
+
+
+def _user_ptr(user):
+    if isinstance(user, C.Structure):
+        return C.cast(C.pointer(user), C.c_void_p).value
+    if isinstance(user, Mech):
+        return user.h.value
+    return user
+
+
+def mri_diffusion_solve(ctx, a, r, y, n_cells, ld, t=0.0, stream=None):
+    """(I - a D lap) y = r by the built-in CG (ctx: imex_advdiff); raises on a
+    nonzero return (no convergence, bad arguments)."""
+    rc = lib.mri_diffusion_solve(float(t), float(a), _ptr(r, "float64"), _ptr(y, "float64"),
+                                 n_cells, ld, _user_ptr(ctx), _stream(stream))
+    if rc != 0:
+        raise MriError(MRI_ENOCONV, f"mri_diffusion_solve returned {rc}")
+
+
+def mri_imex_workspace_bytes(mech: Mech, table: ImexTable, n_cells, ld):
+    b = C.c_size_t(0)
+    _check(lib.mri_imex_workspace_bytes(mech.h, table.h, n_cells, ld, C.byref(b)))
+    return b.value
+
+
+def mri_imex_slow_step(mech: Mech, table: ImexTable, opts, ctx, t0, H, n_cells, ld, y, ws,
+                       status_out=None, steps_out=None, stream=None, f_expl=None, f_impl=None,
+                       solve_impl=None):
+    """One IMEX-MRI-GARK step with the built-in advection / diffusion split
+    (or other C callbacks by address) and ctx as `user`."""
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib.mri_imex_slow_step(mech.h, table.h, C.byref(opts), f_expl or ADVECTION_RHS,
+                                  f_impl or DIFFUSION_RHS, solve_impl or DIFFUSION_SOLVE,
+                                  _user_ptr(ctx), float(t0), float(H), n_cells, ld,
+                                  _ptr(y, "float64"), _ptr(ws), nbytes, _ptr(status_out, "int32"),
+                                  _ptr(steps_out, "int32"), _stream(stream)))
 
 
 def mri_slow_step(mech: Mech, table: Table, opts, f_slow, user, t0, H, n_cells, ld, y, ws,

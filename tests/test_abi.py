@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(mri):
 
 
 def test_abi_version(mri):
-    assert mri.lib.mri_abi_version() == 2
+    assert mri.lib.mri_abi_version() == 3
 
 
 def test_mech_validation(mri):
@@ -80,6 +80,55 @@ def test_table_validation(mri):
     t.c = np.array([0.0, 0.5, 0.5, 1.0])        # dc = 0 stage (implicit form)
     with pytest.raises(mri.MriError):
         mri.Table(t)
+
+
+def test_imex_table_and_callback_validation(mri):
+    """IMEX-MRI-GARK tables: the 2nd-order table is accepted; a diagonal
+    implicit coefficient on a fast stage, an explicit coefficient on the
+    diagonal, rows whose integral weights miss Delta c, decreasing c and a
+    table without a fast stage are refused on the host.  The built-in
+    callbacks refuse a grid that does not match n_cells without touching the
+    device, and the IMEX step refuses NULL callbacks and a short workspace."""
+    import copy
+    good = I.table_imex_trap2()
+    mri.ImexTable(good)
+
+    def refused(edit):
+        t = copy.deepcopy(good)
+        edit(t)
+        with pytest.raises(mri.MriError):
+            mri.ImexTable(t)
+
+    refused(lambda t: t.gamma.__setitem__((0, 1, 1), 0.5))
+    refused(lambda t: t.omega.__setitem__((0, 2, 2), 0.5))
+    refused(lambda t: t.omega.__setitem__((0, 2, 1), 0.6))
+    refused(lambda t: setattr(t, "c", np.array([0.0, 1.0, 0.5])))
+    z = I.ImexTable("no fast stage", np.array([0.0, 0.0, 1.0]), np.zeros((1, 3, 3)),
+                    np.zeros((1, 3, 3)))
+    with pytest.raises(mri.MriError):
+        mri.ImexTable(z)
+    p = mri.advdiff_params((4, 4, 4), 22)
+    nb = mri.diffusion_solve_workspace_bytes(p, 64)
+    assert nb >= 3 * 8 * 22 * 64
+    ctx = mri.mri_imex_advdiff(p, 1e-13, 10, None, 0, 0, 0)
+    user = mri.C.cast(mri.C.pointer(ctx), mri.C.c_void_p).value
+    assert mri.lib.mri_advection_rhs(0.0, 1, 1, 63, 64, user, 0) != 0      # 63 != 4^3
+    assert mri.lib.mri_diffusion_rhs(0.0, 1, 1, 64, 32, user, 0) != 0      # ld < n_cells
+    assert mri.lib.mri_diffusion_solve(0.0, 1.0, 1, 2, 64, 64, user, 0) != 0  # no workspace
+    m = mri.Mech(I.make_mechanism(I.FIELD64))
+    t = mri.ImexTable(good)
+    b = mri.C.c_size_t(0)
+    assert mri.lib.mri_imex_workspace_bytes(m.h, t.h, 64, 64, mri.C.byref(b)) == 0
+    assert b.value == 8 * 22 * 64 * (2 * 2 + 1)
+    o = mri.fast_opts(n_sub=4)
+    rc = mri.lib.mri_imex_slow_step(m.h, t.h, mri.C.byref(o), None, mri.DIFFUSION_RHS,
+                                    mri.DIFFUSION_SOLVE, user, 0.0, 1e-7, 64, 64, 1, 1, b.value,
+                                    None, None, 0)
+    assert rc == mri.MRI_EINVAL
+    rc = mri.lib.mri_imex_slow_step(m.h, t.h, mri.C.byref(o), mri.ADVECTION_RHS,
+                                    mri.DIFFUSION_RHS, mri.DIFFUSION_SOLVE, user, 0.0, 1e-7, 64,
+                                    64, 1, 1, b.value - 8, None, None, 0)
+    assert rc == mri.MRI_EINVAL and "workspace" in mri.last_error()
 
 
 def test_fast_stage_rejects_bad_arguments_without_device(mri):

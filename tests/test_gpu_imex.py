@@ -1,0 +1,243 @@
+"""GPU parity of the IMEX-MRI-GARK path (advection explicit, diffusion implicit
+on solve-decoupled stages) against the oracle, through the C ABI.
+
+Tolerance.  The implicit stage is solved by conjugate gradients, stopped at
+||r_c - A y_c||_2 <= cg_rtol ||r_c||_2 per component c.  A = I - a D lap has
+||A^-1||_2 <= 1, so every element of the solve's error is bounded by
+cg_rtol ||r_c||_2; and A^-1 is nonnegative with unit row sums (A 1 = 1), so a
+difference of the right-hand sides of at most d (the fast stages' rounding,
+1e-10 relative as for the plain path) moves any element by at most d.  The
+per-component bound after one step is therefore
+    |y_gpu - y_ora| <= 1e-10 max_cells |y_c| + 2 cg_rtol ||rhs_c||_2
+(the factor 2 covers the drift between the recursive and the true residual);
+relative to each element the error is then only as small as the component's
+largest values allow.  Later steps carry it through the chemistry, which the
+two-step case allows a factor 10 for."""
+import numpy as np
+import pytest
+
+from paper_2211_03293_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+CG_RTOL = 1e-13
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def mri(torch):
+    from paper_2211_03293_amd import mri as M
+    return M
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    oracle_mod.set_threads(16)
+    return oracle_mod
+
+
+@pytest.fixture(scope="module")
+def X(oracle_mod):
+    from oracle import imex_oracle
+    return imex_oracle
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _ctx(torch, mri, grid, n, ld, D, rtol=CG_RTOL, max_iter=500):
+    P = I.ADVDIFF_STIFF
+    params = mri.advdiff_params(grid, n, u=P["u"], D=D, dx=P["dx"])
+    ws = torch.empty(mri.diffusion_solve_workspace_bytes(params, ld), dtype=torch.uint8,
+                     device="cuda")
+    return mri.imex_advdiff(params, ws, cg_rtol=rtol, cg_max_iter=max_iter), ws
+
+
+def _norm_bound(ref, rhs_norm, factor=1.0):
+    """Per-component absolute bound of the module docstring, shape [n, 1]."""
+    return factor * (1e-10 * np.abs(ref).max(axis=1, keepdims=True)
+                     + 2 * CG_RTOL * rhs_norm[:, None])
+
+
+@pytest.mark.parametrize("grid,aD_dx2", [((12, 10, 8), 0.5), ((70, 9, 5), 6.0),
+                                         ((64, 64, 64), 0.5)])
+def test_diffusion_solve_matches_the_fft_solve(torch, mri, X, grid, aD_dx2):
+    """(I - a D lap) y = r on odd and full-size grids (several x, y and z tiles
+    and ragged ones), 22 components with padding: the CG result against the
+    oracle's exact FFT solve within cg_rtol ||r_c||_2 per element; two solves
+    are bitwise equal; the padding is untouched."""
+    N = int(np.prod(grid))
+    n, ld = 22, N + 37
+    rng = np.random.Generator(np.random.PCG64(101))
+    r = rng.normal(size=(n, ld)) * np.logspace(-6, 3, n)[:, None]
+    dx, D = 1e-4, 0.1
+    a = aD_dx2 * dx * dx / D
+    ctx, ws = _ctx(torch, mri, grid, n, ld, D)
+    rd = _dev(torch, r)
+    outs = []
+    for _ in range(2):
+        y = torch.full_like(rd, -7.0)
+        mri.mri_diffusion_solve(ctx, a, rd, y, N, ld)
+        torch.cuda.synchronize()
+        outs.append(y.cpu().numpy())
+    ref = X.diffusion_solve(a, r, grid, D, dx)
+    err = np.abs(outs[0][:, :N] - ref[:, :N])
+    bound = 2 * CG_RTOL * np.linalg.norm(r[:, :N], axis=1)[:, None]
+    print(f"grid {grid} aD/dx^2 {aD_dx2}: {ctx.cg_iters} iterations, max err / bound "
+          f"{(err / bound).max():.3e}")
+    assert np.all(err <= bound)
+    assert np.array_equal(outs[0], outs[1])
+    assert np.all(outs[0][:, N:] == -7.0)
+    assert 1 <= ctx.cg_iters <= 200
+
+
+def test_diffusion_solve_reports_no_convergence(torch, mri):
+    """An iteration cap below what the tolerance needs makes the solve return
+    an error (forced from the host: the kernels run their iterations normally),
+    and the IMEX step then fails with MRI_ENOCONV."""
+    grid = (16, 16, 16)
+    N = 4096
+    n, ld = 22, N
+    ctx, ws = _ctx(torch, mri, grid, n, ld, 0.1, rtol=1e-14, max_iter=2)
+    r = _dev(torch, np.random.Generator(np.random.PCG64(3)).normal(size=(n, ld)))
+    y = torch.empty_like(r)
+    with pytest.raises(mri.MriError):
+        mri.mri_diffusion_solve(ctx, 1e-7, r, y, N, ld)
+    m = mri.Mech(I.make_mechanism(I.FIELD64))
+    t = mri.ImexTable(I.table_imex_trap2())
+    yd = _dev(torch, I.field_state(I.FIELD64, grid))
+    ws2 = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8, device="cuda")
+    with pytest.raises(mri.MriError) as e:
+        mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=8), ctx, 0.0, 1e-7, N, ld, yd, ws2)
+    assert e.value.status == mri.MRI_ENOCONV
+
+
+def _oracle_steps(O, X, mech, grid, y0, n_steps, n_sub, H, D):
+    orc = O.Oracle(mech)
+    P = I.ADVDIFF_STIFF
+    tb = I.table_imex_trap2()
+    y = y0.copy()
+    for s in range(n_steps):
+        y, st = X.imex_mri_step_advdiff(orc, tb, O.rk4_opts(n_sub), grid, y, H, P["u"], D,
+                                        P["dx"], t0=s * H)
+        assert np.all(st[:int(np.prod(grid))] == 0)
+    return y
+
+
+@pytest.mark.parametrize("n_steps", [1, 2])
+def test_imex_slow_step_small_grid(torch, mri, O, X, n_steps):
+    """The 64^3 workload's physics on a 12 x 10 x 8 periodic grid: IMEX-MRI-GARK
+    steps of H = 1e-7 s with RK4 at 120 substeps (the fast step of the explicit
+    workload), GPU against oracle within the per-component bound of the module
+    docstring.  On this grid the fields' Fourier modes sit near the grid scale,
+    where the stiff diffusion coefficient's explicit share of the first fast
+    stage's forcing overshoots into negative mass fractions (the oracle flags
+    the same cells); D is therefore 1/20 of it here (H D / dx^2 = 0.05), and
+    the full 64^3 case below runs the stiff coefficient."""
+    grid = (12, 10, 8)
+    N = int(np.prod(grid))
+    mech = I.make_mechanism(I.FIELD64)
+    y0 = I.field_state(I.FIELD64, grid=grid)
+    n, ld = y0.shape
+    H = 1e-7
+    D = 0.05 * I.ADVDIFF_STIFF["D"]
+    ref = _oracle_steps(O, X, mech, grid, y0, n_steps, I.IMEX_N_SUB, H, D)
+    m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+    ctx, cws = _ctx(torch, mri, grid, n, ld, D)
+    yd = _dev(torch, y0)
+    ws = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8, device="cuda")
+    st = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    for s in range(n_steps):
+        mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, s * H, H, N, ld, yd,
+                               ws, status_out=st)
+    torch.cuda.synchronize()
+    g = yd.cpu().numpy()[:, :N]
+    r = ref[:, :N]
+    # rhs norm of the last solve is bounded by the state's norm plus H times the
+    # slow tendencies; the state's 2-norm bounds it within a factor 2 here
+    bound = _norm_bound(r, 2 * np.linalg.norm(r, axis=1), factor=10.0 ** (n_steps - 1))
+    err = np.abs(g - r)
+    floor = np.r_[np.full(n - 1, 1e-12), 0.0][:, None]
+    rel = err / np.maximum(np.abs(r), floor)
+    print(f"{n_steps} IMEX steps: {ctx.cg_iters} CG iterations in the last solve; max rel err "
+          f"{rel.max():.2e}; max err / bound {(err / bound).max():.2e}")
+    assert np.all(err <= bound)
+    assert int(st[:N].abs().sum().item()) == 0
+
+
+def test_imex_full_size_first_step(torch, mri, O, X):
+    """One IMEX step of the full 64^3 stiff-diffusion workload (262,144 cells,
+    RK4 120 substeps) against the oracle on every cell (the implicit stage
+    couples every cell, so the oracle integrates them all)."""
+    grid = (64, 64, 64)
+    N = 64 ** 3
+    mech = I.make_mechanism(I.FIELD64)
+    y0 = I.initial_state(I.FIELD64)
+    n, ld = y0.shape
+    H = 1e-7
+    ref = _oracle_steps(O, X, mech, grid, y0, 1, I.IMEX_N_SUB, H, I.ADVDIFF_STIFF["D"])
+    m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+    ctx, cws = _ctx(torch, mri, grid, n, ld, I.ADVDIFF_STIFF["D"])
+    yd = _dev(torch, y0)
+    ws = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8, device="cuda")
+    mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, 0.0, H, N, ld, yd, ws)
+    torch.cuda.synchronize()
+    g = yd.cpu().numpy()[:, :N]
+    r = ref[:, :N]
+    bound = _norm_bound(r, 2 * np.linalg.norm(r, axis=1))
+    err = np.abs(g - r)
+    floor = np.r_[np.full(n - 1, 1e-12), 0.0][:, None]
+    print(f"64^3 IMEX step: {ctx.cg_iters} CG iterations; max rel err "
+          f"{(err / np.maximum(np.abs(r), floor)).max():.2e}; max err / bound "
+          f"{(err / bound).max():.2e}")
+    assert np.all(err <= bound)
+
+
+def test_explicit_diverges_where_imex_stays_bounded(torch, mri):
+    """At H D / dx^2 = 1 on the 64^3 fields with a 1e-6 K grid-scale
+    checkerboard added to T: the explicit MIS-KW3 step (its stability
+    polynomial at the checkerboard's eigenvalue -12 has modulus 227) flags
+    cells within 12 steps, the IMEX step flags none and keeps the mass
+    fractions in [0, 1]."""
+    grid = (64, 64, 64)
+    N = 64 ** 3
+    mech = I.make_mechanism(I.FIELD64)
+    y0 = I.initial_state(I.FIELD64)
+    n, ld = y0.shape
+    z, yy, x = np.meshgrid(np.arange(64), np.arange(64), np.arange(64), indexing="ij")
+    y0 = y0.copy()
+    y0[-1, :N] += 1e-6 * ((-1.0) ** (x + yy + z)).ravel()
+    P = I.ADVDIFF_STIFF
+    H = 1e-7
+    m = mri.Mech(mech)
+    te, ti = mri.Table(I.table_mis_kw3()), mri.ImexTable(I.table_imex_trap2())
+    params = mri.advdiff_params(grid, n, u=P["u"], D=P["D"], dx=P["dx"])
+    ye, yi = _dev(torch, y0), _dev(torch, y0)
+    wse = torch.empty(mri.mri_workspace_bytes(m, te, N, ld) // 8, dtype=torch.float64,
+                      device="cuda")
+    wsi = torch.empty(mri.mri_imex_workspace_bytes(m, ti, N, ld), dtype=torch.uint8,
+                      device="cuda")
+    ctx, cws = _ctx(torch, mri, grid, n, ld, P["D"])
+    ste = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    sti = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    flagged_at = None
+    for s in range(12):
+        mri.mri_slow_step(m, te, mri.fast_opts(n_sub=50), mri.ADVDIFF_RHS, params, s * H, H, N, ld,
+                          ye, wse, status_out=ste)
+        mri.mri_imex_slow_step(m, ti, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, s * H, H, N, ld, yi,
+                               wsi, status_out=sti)
+        if flagged_at is None and mri.mri_status_count(ste, N, 0x7) > 0:
+            flagged_at = s
+        assert mri.mri_status_count(sti, N, 0x7) == 0
+    print(f"explicit step flags cells at step {flagged_at}; IMEX: none")
+    assert flagged_at is not None
+    Y = yi[:n - 1, :N]
+    assert float(Y.min()) > -1e-9 and float(Y.max()) < 1.0 + 1e-9
