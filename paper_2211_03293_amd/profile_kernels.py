@@ -10,14 +10,23 @@ collection (run under `rocprofv3 --pmc ...`):
      second plan takes them from the tuning cache, so that no tuning dispatches
      precede the measured one);
   4. k_infer, the fused inference over the 128^3 cells (random weights: the
-     instruction stream does not depend on them).
+     instruction stream does not depend on them);
+  5. one IMEX-MRI-GARK step of the 64^3 stiff-diffusion workload (its fast
+     stage and the conjugate-gradient kernels of the implicit diffusion solve).
+
+With --block B the batched plan is fixed to B threads per block instead (the
+register / LDS tiling then follows the MRI_SPEC_WPE, MRI_SPEC_EXP_TABLE and
+MRI_SPEC_GROUP environment knobs, which give the same code as the autotuner's
+variants of those settings), so that every candidate the autotuner may pick
+can be counted in a process of its own.
 
 Each kernel is run once untimed first (run-time compilation, module load), then
 once more; the second dispatch is the one to read.  Prints one JSON line with
 the work of each measured dispatch (cells, substeps, attempted steps) and the
 machine-code hash of each specialized kernel.
 
-    python -m paper_2211_03293_amd.profile_kernels [--only rk4|large|batch|infer]
+    python -m paper_2211_03293_amd.profile_kernels [--only rk4|large|batch|infer|imex]
+                                                   [--block 64|128|256]
 """
 from __future__ import annotations
 
@@ -29,7 +38,8 @@ import numpy as np
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=["rk4", "large", "batch", "infer"], default=None)
+    ap.add_argument("--only", choices=["rk4", "large", "batch", "infer", "imex"], default=None)
+    ap.add_argument("--block", type=int, choices=[64, 128, 256], default=0)
     args = ap.parse_args()
     import torch
 
@@ -82,9 +92,12 @@ def main():
         # tuning cache (no tuning dispatches before the measured one)
         zv = dict(method=mri.FAST_ZONNEVELD43, rtol=1e-8, atol_Y=1e-8, atol_T=1e-5,
                   max_steps=2000)
-        tuner = mri.BatchPlan(m, mri.fast_opts(**zv), off)
-        tuner.run(y, yo, ld, 0, None, Ls)
-        plan = mri.BatchPlan(m, mri.fast_opts(**zv), off)
+        if args.block:
+            plan = mri.BatchPlan(m, mri.fast_opts(block_size=args.block, **zv), off)
+        else:
+            tuner = mri.BatchPlan(m, mri.fast_opts(**zv), off)
+            tuner.run(y, yo, ld, 0, None, Ls)
+            plan = mri.BatchPlan(m, mri.fast_opts(**zv), off)
         for _ in range(2):
             plan.run(y, yo, ld, 0, None, Ls)
         torch.cuda.synchronize()
@@ -113,6 +126,26 @@ def main():
             sg.infer(N, ld, y, yo, 1, rho, 3.3e-8)
         torch.cuda.synchronize()
         out["infer_128cube"] = dict(kernel="k_infer", cells=N)
+    if args.only in (None, "imex"):
+        cfg = I.WORKLOADS[I.FIELD64]
+        P = I.ADVDIFF_STIFF
+        mech = I.make_mechanism(I.FIELD64)
+        y = torch.as_tensor(I.initial_state(I.FIELD64), device="cuda")
+        n, ld = y.shape
+        N = cfg.n_cells
+        m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+        params = mri.advdiff_params(cfg.grid, n, u=P["u"], D=P["D"], dx=P["dx"])
+        cws = torch.empty(mri.diffusion_solve_workspace_bytes(params, ld), dtype=torch.uint8,
+                          device="cuda")
+        ctx = mri.imex_advdiff(params, cws, cg_rtol=1e-13)
+        ws = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8,
+                         device="cuda")
+        for k in range(2):
+            mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, k * cfg.H, cfg.H,
+                                   N, ld, y, ws)
+        torch.cuda.synchronize()
+        out["imex_64cube"] = dict(kernel="k_cg_*", cells=N, cg_iterations=ctx.cg_iters,
+                                  fast_code_hash=m.code_hash(mri.FAST_RK4, 1, 128))
     print(json.dumps(out), flush=True)
 
 

@@ -507,30 +507,30 @@ def test_gated_stage_limits_and_graph_replay(torch, mri, oracle_mod):
 def test_trained_network_gain(torch, mri):
     """What training buys, on every cell of the three fast stages of the 128^3
     workload's first slow step (errors against the plain FP64 stage of 50
-    substeps): the trained network's correction of the coarse 4-substep stage
-    is far more accurate than an untrained network's; with the check at half
-    the 1e-4 tolerance no accepted cell exceeds 1e-4, with or without the
-    network, and the gated stage is faster than the plain stage.  The same
-    pipeline with a zero correction (no network) is measured beside it: the
-    coarse stage is already within the tolerance on nearly every cell, so the
-    network's gain in accepted cells is small at best -- the test bounds how
-    much worse than the zero correction the trained one may be, not a gain."""
+    substeps), with the coarse stage of 2 substeps (it misses the 1e-4
+    tolerance on about 0.1% of the cells, so a correction has something to
+    fix): the trained network's correction is far more accurate than an
+    untrained network's, and with it fewer cells fall back than with a zero
+    correction (the same pipeline without the network, run beside it).  With
+    the check at a quarter of the tolerance no accepted cell exceeds 1e-4, with
+    or without the network, and the gated stage is faster than the plain
+    stage."""
     from paper_2211_03293_amd import surrogate as S
-    data = S.generate_stage_data(n_full=300_000, log=print)
-    res = S.train(data, steps=6000, batch=4096, log=print, log_every=3000)
+    nc, frac = 2, S.CHECK_FRACTION_COARSE2
+    data = S.generate_stage_data(n_full=1_000_000, n_coarse=nc, log=print)
+    res = S.train(data, steps=20000, batch=8192, log=print, log_every=10000)
     del data
-    ev = S.evaluate(res["params"], res["stats"], workload=I.FIELD128, gate_tol=1e-4, repeats=1,
-                    log=print)
-    ev0 = S.evaluate(S.init_params(), res["stats"], workload=I.FIELD128, gate_tol=1e-4,
-                     repeats=1, log=print)
+    kw = dict(workload=I.FIELD128, gate_tol=1e-4, check_tol=frac * 1e-4, n_coarse=nc, repeats=1,
+              log=print)
+    ev = S.evaluate(res["params"], res["stats"], **kw)
+    ev0 = S.evaluate(S.init_params(), res["stats"], **kw)
     e, e0 = ev["errors"], ev0["errors"]
     print({k: (v["median"], v["p999"], v["max"]) for k, v in e.items()})
     print(f"untrained network: median {e0['network']['median']:.2e}; fallback "
           f"{ev0['learned']['fallback_frac']:.2e}; trained {ev['learned']['fallback_frac']:.2e}; "
           f"no network {ev['no_network']['fallback_frac']:.2e}")
     assert e["network"]["median"] < 0.1 * e0["network"]["median"]
-    assert e["network"]["p999"] <= 1e-4
-    assert ev["learned"]["fallback_frac"] <= 1.5 * ev["no_network"]["fallback_frac"] + 1e-4
+    assert ev["learned"]["fallback_frac"] < 0.9 * ev["no_network"]["fallback_frac"]
     for name in ("learned", "no_network"):
         assert ev[name]["false_accepts"] == 0, name
         assert ev[name]["max_err"] <= 1e-4, name
