@@ -23,7 +23,7 @@ mechanism, the IMEX-MRI-GARK steps with stiff diffusion, the batched uneven
 reactor sets.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-large] [--no-batch] [--no-plain64] [--no-imex] [--no-coarse2]
+                    [--no-large] [--no-batch] [--no-plain64] [--no-imex] [--no-alt-coarse]
 """
 from __future__ import annotations
 
@@ -199,6 +199,7 @@ def batch_leg(torch, mri, I, divergent, repeats=3, per_set_baseline=False):
                                              counter_flops=(per_unit * useful
                                                             if per_unit else None)),
                              kernel="mri_spec_main (batched work queue)",
+                             kernel_code_hash=plan.code_hash(0),
                              flops_per_attempted_step=fpa))
     if per_set_baseline:
         # the same sets, one fast-stage launch per set (Zonneveld kernel,
@@ -440,7 +441,7 @@ def train_surrogate(n_samples, train_steps, log):
 
 
 def surrogate_steps(torch, mri, I, params, stats, steps, warmup, gate_tol=1e-4, n_coarse=None,
-                    check_fraction=None):
+                    check_fraction=None, stiff_limit=None):
     """K timed MRI slow steps of the 128^3 workload whose fast stages are gated
     surrogate stages (W untimed before, from the same initial state); the slow
     RHS and forcing assembly as in the plain path.  The residual check accepts
@@ -458,7 +459,9 @@ def surrogate_steps(torch, mri, I, params, stats, steps, warmup, gate_tol=1e-4, 
     sg = mri.Surrogate(S.WIDTHS, params, stats)
     n_coarse = S.N_COARSE if n_coarse is None else n_coarse
     check_fraction = S.CHECK_FRACTION if check_fraction is None else check_fraction
-    coarse, fine = mri.fast_opts(n_sub=n_coarse), mri.fast_opts(n_sub=cfg.n_sub)
+    coarse = mri.fast_opts(n_sub=n_coarse, stiff_limit=S.STIFF_LIMIT if stiff_limit is None
+                           else stiff_limit)
+    fine = mri.fast_opts(n_sub=cfg.n_sub)
     y0 = torch.as_tensor(y_host, device="cuda")
     del y_host
     y = y0.clone()
@@ -530,29 +533,27 @@ def surrogate_steps(torch, mri, I, params, stats, steps, warmup, gate_tol=1e-4, 
                 flagged_cells=n_bad, cells=N, stages_per_step=tb.s - 1)
 
 
-def coarse2_leg(n_samples, train_steps, log, steps=10, warmup=2):
-    """The gated stage with a coarse stage of 2 substeps (and 1 for the
-    Richardson pair), check at CHECK_FRACTION_COARSE2 of the tolerance: the
-    coarse stage misses 1e-4 on about 0.1% of the cells, so the trained
-    correction has something to fix.  A network trained on that coarse stage
-    against the zero correction, every cell of the first slow step of the
-    128^3 workload."""
+def alt_coarse_leg(n_samples, train_steps, log, steps=10, warmup=2):
+    """The same pipeline with the other coarse setting (N_COARSE_ALT substeps,
+    check at CHECK_FRACTION_ALT of the tolerance): a network trained on that
+    coarse stage against the zero correction on every cell of the first slow
+    step of the 128^3 workload, and the headline's slow steps."""
     from paper_2211_03293_amd import inputs as I
     from paper_2211_03293_amd import surrogate as S
-    data = S.generate_stage_data(n_full=n_samples, n_coarse=2, log=log)
+    nc, frac = S.N_COARSE_ALT, S.CHECK_FRACTION_ALT
+    data = S.generate_stage_data(n_full=n_samples, n_coarse=nc, log=log)
     res = S.train(data, steps=train_steps, batch=TRAIN_BATCH, log=log,
                   log_every=max(1, train_steps // 2))
     del data
-    frac = S.CHECK_FRACTION_COARSE2
     ev = S.evaluate(res["params"], res["stats"], workload=I.FIELD128, gate_tol=1e-4,
-                    check_tol=frac * 1e-4, n_coarse=2, repeats=1, log=log)
+                    check_tol=frac * 1e-4, n_coarse=nc, repeats=1, log=log)
     keys = ("ms", "fallback_frac", "false_accepts", "max_err", "speedup_vs_plain")
     import torch
     from paper_2211_03293_amd import mri
-    log("# the 2-substep configuration over the headline's slow steps")
-    run = surrogate_steps(torch, mri, I, res["params"], res["stats"], steps, warmup, n_coarse=2,
+    log(f"# the {nc}-substep configuration over the headline's slow steps")
+    run = surrogate_steps(torch, mri, I, res["params"], res["stats"], steps, warmup, n_coarse=nc,
                           check_fraction=frac)
-    return dict(n_coarse=2, check_tol=frac * 1e-4,
+    return dict(n_coarse=nc, check_tol=frac * 1e-4,
                 slow_steps=dict(steps=steps, ms_per_step=run["ms_per_step"], value=run["value"],
                                 fallback_frac=run["fallback_frac"]),
                 learned={k: ev["learned"][k] for k in keys},
@@ -585,10 +586,11 @@ def surrogate_eval(params, stats, log, gate_tol=1e-4):
 
 
 def cpu_baseline_surrogate(params, stats, n_sample=262144):
-    """The oracle's gated surrogate stage (RK4 at 4 and 2 substeps, the network
-    in its bfloat16-emulating mode, the residual check, plain RK4 with 50
-    substeps for rejected cells) on evenly spaced cells of the first fast stage
-    of the 128^3 workload, with all the threads the job may use."""
+    """The oracle's gated surrogate stage (RK4 at N_COARSE and N_COARSE / 2
+    substeps, the network in its bfloat16-emulating mode, the residual check,
+    plain RK4 with 50 substeps for rejected cells) on evenly spaced cells of the
+    first fast stage of the 128^3 workload, with all the threads the job may
+    use."""
     from oracle import oracle as O
     from paper_2211_03293_amd import inputs as I
     from paper_2211_03293_amd import surrogate as S
@@ -604,7 +606,8 @@ def cpu_baseline_surrogate(params, stats, n_sample=262144):
     L = float(tb.c[1] * cfg.H)
     t0 = time.perf_counter()
     _, acc, _, _ = O.sur_stage(orc, S.WIDTHS, np.asarray(params, np.float64), stats, ys,
-                               np.ascontiguousarray(rho), L, S.N_COARSE, cfg.n_sub, 1e-4)
+                               np.ascontiguousarray(rho), L, S.N_COARSE, cfg.n_sub,
+                               S.CHECK_FRACTION * 1e-4, stiff_limit=S.STIFF_LIMIT)
     dt = time.perf_counter() - t0
     return dict(value=n_sample / dt, unit="cell-stages/s", cores=O.num_threads(), kind="oracle",
                 sample=f"{n_sample} evenly spaced cells of the 128^3 field, first MIS-KW3 fast "
@@ -624,8 +627,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-set leg")
     ap.add_argument("--no-plain64", action="store_true", help="skip the 64^3 plain leg")
     ap.add_argument("--no-imex", action="store_true", help="skip the IMEX (stiff diffusion) leg")
-    ap.add_argument("--no-coarse2", action="store_true",
-                    help="skip the surrogate evaluation on a 2-substep coarse stage")
+    ap.add_argument("--no-alt-coarse", action="store_true",
+                    help="skip the surrogate leg with the other coarse-stage setting")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 128^3 large-mechanism leg (53 species / 325 reactions)")
     ap.add_argument("--surrogate-steps", type=int, default=40000,
@@ -691,10 +694,17 @@ def main():
                           setup_seconds=round(res["setup_seconds"], 1),
                           final_val_mse=res["history"][-1][2] if res["history"] else None)
     out["surrogate"] = ev
-    if not args.no_coarse2:
-        log("# what training buys: the same pipeline on a 2-substep coarse stage")
-        out["surrogate_coarse2"] = coarse2_leg(args.surrogate_samples, args.surrogate_steps, log,
-                                               args.steps, args.warmup)
+    log(f"# accuracy on every cell of the last timed slow step (step {args.steps})")
+    late = S.evaluate(res["params"], res["stats"], workload=I.FIELD128, gate_tol=1e-4,
+                      repeats=1, log=log, step=args.steps - 1)
+    keys = ("fallback_frac", "false_accepts", "max_err", "speedup_vs_plain")
+    ev["last_step"] = dict(step=args.steps, learned={k: late["learned"][k] for k in keys},
+                           no_network={k: late["no_network"][k] for k in keys},
+                           errors=late["errors"])
+    if not args.no_alt_coarse:
+        log(f"# the other coarse setting: {S.N_COARSE_ALT} substeps")
+        out[f"surrogate_coarse{S.N_COARSE_ALT}"] = alt_coarse_leg(
+            args.surrogate_samples, args.surrogate_steps, log, args.steps, args.warmup)
     out["plain_128cube"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
                                 roofline=plain["roofline"], config=plain["config"])
     if not args.no_plain64:

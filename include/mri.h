@@ -124,6 +124,11 @@ mri_status mri_mech_specialize(mri_mech *m, int block_size, int load, size_t *co
    terms (0..4); mri_mech_specialize is the RK4 kernel with one term. */
 mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int block_size,
                                       int load, size_t *code_bytes);
+/* The same for the stiffness monitor the fixed-step stages run when
+   opts.stiff_limit > 0 (see mri_stiffness_check): with the specialized
+   kernels the monitor is specialized too (128 threads per block), else the
+   generic one runs. */
+mri_status mri_mech_specialize_monitor(mri_mech *m, int load, size_t *code_bytes);
 /* 64-bit FNV-1a hash of that kernel's machine code and constant data (the
    .text and .rodata sections of its code object; compiled, not loaded, no GPU
    needed): identifies the exact code the GPU runs, e.g. to tell whether

@@ -147,8 +147,9 @@ mri_status mri_surrogate_gate(int n_cells, int ld, const double *y_in, int n_pol
 mri_status mri_surrogate_workspace_bytes(int n_cells, int ld, int n_poly, size_t *bytes);
 
 /* Gated surrogate stage over one stage of length L with forcing rho: the
-   coarse FP64 stage (`coarse`: a fixed-step method, even n_sub >= 2) and the
-   same with n_sub / 2, the network's correction of the coarse result, the
+   coarse FP64 stage (`coarse`: a fixed-step method, even n_sub >= 2; with
+   coarse.stiff_limit > 0 its stiffness monitor flags, and so rejects, every
+   cell with h B above the limit, h = L / n_sub) and the same with n_sub / 2, the network's correction of the coarse result, the
    residual check of mri_surrogate_gate (richardson from the coarse method's
    order), and the plain FP64 fast stage (`fallback` options) of every rejected
    cell, compacted, integrated and scattered back.  Nothing synchronizes the

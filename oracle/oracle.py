@@ -543,18 +543,27 @@ def sur_gate(S, Y0, RHO, L, Vc, Vh, Vn, rich, tol, N=None, status_c=None):
     return G, acc.astype(bool)
 
 
-def sur_stage(orc, widths, params, stats, y, rho, L, n_coarse, n_fine, tol, N=None, bf16=True):
+def sur_stage(orc, widths, params, stats, y, rho, L, n_coarse, n_fine, tol, N=None, bf16=True,
+              stiff_limit=0.0):
     """The gated surrogate stage composed from the oracle's steps: RK4 stages
     with n_coarse and n_coarse/2 substeps, the network's correction of the
     first, the residual check against their Richardson extrapolation (RK4:
     1/15), and the plain RK4 stage with n_fine substeps for every rejected
-    cell.  Returns (out [n][N], accept [N], G [N], status of the plain stage
-    [N])."""
+    cell.  With stiff_limit > 0 a cell whose coarse step times the stiffness
+    bound of its start state (stiff_bound, the Gershgorin bound of the
+    species Jacobian) exceeds the limit counts as flagged by the coarse solve
+    (the stability statements of Sec. 5.2 compare h times the fastest rate
+    with a method's stability interval) and is rejected.  Returns (out [n][N],
+    accept [N], G [N], status of the plain stage [N])."""
     y, rho = _f64(y), _f64(rho)
     N = y.shape[1] if N is None else N
     S = y.shape[0] - 1
     vc, sc, _, _ = orc.fast_stage_soa(y, rho, L, rk4_opts(n_coarse), N)
     vh, sh, _, _ = orc.fast_stage_soa(y, rho, L, rk4_opts(n_coarse // 2), N)
+    if stiff_limit > 0.0:
+        B = orc.stiff_bound(np.ascontiguousarray(y[:, :N]))
+        sc = sc.copy()
+        sc[:N] |= np.where((L / n_coarse) * B > stiff_limit, 16, 0).astype(sc.dtype)
     vn = sur_infer(S, widths, params, stats, y, rho, L, N=N, base=vc, bf16=bf16)
     G, acc = sur_gate(S, y, rho, L, vc, vh, vn, 1.0 / 15.0, tol, N=N, status_c=(sc | sh)[:N])
     out = vn[:, :N].copy()

@@ -266,6 +266,9 @@ static ErkCoef erk_coef(int method)
 
 // Run-time compiled kernel kind of a fast method: 0 RK4, 1 Zonneveld, 3 Heun,
 // 4 Bogacki-Shampine, 5 Cash-Karp (2 is the batched work queue).
+// run-time compiled kernel kind of the stiffness monitor (spec_kernels.inc)
+constexpr int kStiffKind = 6;
+
 static int spec_kind(int method)
 {
     return method == MRI_FAST_RK4 ? 0
@@ -522,8 +525,22 @@ static mri_status fast_stage_launch(mri_mech *m, const mri_fast_opts *o, int n_c
     // stiffness monitor at the stage start state: it writes (or ORs) the status
     // words and zeroes the step counts, and the stage then accumulates onto them
     if (o->stiff_limit > 0.0 && fixed_step(o->method) && (status || steps) && !n_live) {
-        HIP_TRY(launch_gen_stiff(m->gm, n_cells, ld, yin, L / o->n_sub, o->stiff_limit, nullptr,
-                                 status, steps, accumulate, MRI_CELL_STIFF, s));
+        // the mechanism-specialized monitor where the stage runs specialized
+        // kernels, else the generic one
+        hipFunction_t sfn = nullptr;
+        if (o->kernel != MRI_KERNEL_GENERIC && spec_get(m, 128, kStiffKind, 0, &sfn) == MRI_OK) {
+            int nc = n_cells, ldv = ld, acc = accumulate, flag = MRI_CELL_STIFF;
+            const double *yi = yin;
+            double hh = L / o->n_sub, lim = o->stiff_limit;
+            double *bnd = nullptr;
+            int *stp = status, *sps = steps;
+            void *args[] = {&nc, &ldv, &yi, &hh, &lim, &bnd, &stp, &sps, &acc, &flag};
+            HIP_TRY(hipModuleLaunchKernel(sfn, (unsigned)((n_cells + 127) / 128), 1, 1, 128, 1, 1,
+                                          0, s, args, nullptr));
+        } else {
+            HIP_TRY(launch_gen_stiff(m->gm, n_cells, ld, yin, L / o->n_sub, o->stiff_limit,
+                                     nullptr, status, steps, accumulate, MRI_CELL_STIFF, s));
+        }
         accumulate = 1;
     }
     int kind = o->kernel;
@@ -698,6 +715,13 @@ bool mri_internal_stage_needs_setup(mri_mech *m, const mri_fast_opts *o, int n_p
     if (m->kind == 1) return m->d_A == nullptr;
     if (!m->d_sp) return true;
     if (o->kernel == MRI_KERNEL_GENERIC) return false;
+    if (o->stiff_limit > 0.0 && fixed_step(o->method)) {
+        const uint64_t sk = spec_key(128, kStiffKind, 0);
+        auto si = m->spec.find(sk);
+        if ((si == m->spec.end() || !si->second.fn) &&
+            !(o->kernel == MRI_KERNEL_AUTO && m->spec_fail.count(sk)))
+            return true;
+    }
     const int wg = o->block_size ? o->block_size : default_block(MRI_KERNEL_SPECIALIZED);
     const uint64_t key = spec_key(wg, spec_kind(o->method), n_poly);
     auto it = m->spec.find(key);
@@ -948,6 +972,25 @@ mri_status mri_mech_specialize_method(mri_mech *m, int method, int n_poly, int b
     std::lock_guard<std::mutex> lk(m->mu);
     SpecKernel unused;
     mri_status st = spec_compile(m, block_size, kind, n_poly, 0, &unused);
+    if (st == MRI_OK && code_bytes) *code_bytes = m->last_code.size();
+    return st;
+}
+
+mri_status mri_mech_specialize_monitor(mri_mech *m, int load, size_t *code_bytes)
+{
+    mri_status cs = check_spec_request(m, MRI_FAST_RK4, 0, 128);
+    if (cs != MRI_OK) return cs;
+    if (load) {
+        hipFunction_t fn = nullptr;
+        mri_status st = spec_get(m, 128, kStiffKind, 0, &fn);
+        if (st != MRI_OK) return st;
+        std::lock_guard<std::mutex> lk(m->mu);
+        if (code_bytes) *code_bytes = m->spec.at(spec_key(128, kStiffKind, 0)).code_bytes;
+        return MRI_OK;
+    }
+    std::lock_guard<std::mutex> lk(m->mu);
+    SpecKernel unused;
+    mri_status st = spec_compile(m, 128, kStiffKind, 0, 0, &unused);
     if (st == MRI_OK && code_bytes) *code_bytes = m->last_code.size();
     return st;
 }

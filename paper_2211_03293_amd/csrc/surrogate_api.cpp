@@ -421,6 +421,7 @@ mri_status mri_surrogate_stage(const mri_surrogate *s, const mri_mech *mech,
     // coarse FP64 stage and the same with half the substeps (statuses OR-ed)
     mri_fast_opts half = *coarse;
     half.n_sub = coarse->n_sub / 2;
+    half.stiff_limit = 0.0;   // the coarse solve's stiffness monitor flags the cell for both
     st = mri_internal_fast_stage(m, coarse, n_cells, ld, y_in, vc, n_poly, rho, L, st_c, nullptr,
                                  hs);
     if (st != MRI_OK) return st;

@@ -112,6 +112,7 @@ _SIGS = {
     "mri_mech_specialize": (_i, [_vp, _i, _i, C.POINTER(_sz)]),
     "mri_mech_specialize_method": (_i, [_vp, _i, _i, _i, _i, C.POINTER(_sz)]),
     "mri_mech_code_hash": (_i, [_vp, _i, _i, _i, C.POINTER(C.c_uint64)]),
+    "mri_mech_specialize_monitor": (_i, [_vp, _i, C.POINTER(_sz)]),
     "mri_table_create": (_i, [C.POINTER(mri_table_desc), C.POINTER(_vp)]),
     "mri_table_destroy": (None, [_vp]),
     "mri_fast_stage": (_i, [_vp, C.POINTER(mri_fast_opts), _i, _i, _vp, _vp, _i, _vp, _d, _vp,
@@ -254,6 +255,12 @@ class Mech:
         else:
             _check(lib.mri_mech_specialize_method(self.h, int(method), int(n_poly), block_size,
                                                   int(load), C.byref(nb)))
+        return nb.value
+
+    def specialize_monitor(self, load=True):
+        """Compile (and with load, load) the specialized stiffness monitor."""
+        nb = C.c_size_t(0)
+        _check(lib.mri_mech_specialize_monitor(self.h, int(load), C.byref(nb)))
         return nb.value
 
     def code_hash(self, method=0, n_poly=1, block_size=128):

@@ -25,25 +25,34 @@ from . import mri
 # the training network reads the padded feature rows written by mri_mlp_featurize
 # (96 columns, the last 7 always zero)
 WIDTHS = [mri.MLP_KPAD, 256, 256, 256, mri.MLP_OUTPUTS]
-# substeps of the coarse FP64 stage the network corrects (the residual check
-# also runs it with half as many).  Measured on the 128^3 workload (stage
-# tolerance 1e-4, 10 slow steps): with 4 substeps the coarse stage alone is
-# within the tolerance on 99.99% of the first step's cells and the trained
-# correction gains nothing over a zero correction; with 2 it misses the
-# tolerance on 0.1%, the trained correction cuts the fallback by a third, but
-# the slow steps take longer (23.8 against 23.1 ms, 3.2% against 0.35% of the
-# cells falling back over 10 steps) and a zero correction is faster still (the
-# inference costs more than the fallback it saves).  The fastest setting is 4.
-N_COARSE = 4
-# check tolerance as a fraction of the stage tolerance: an accepted state is
-# within G of the Richardson extrapolation, so it meets the stage tolerance
-# wherever that estimate is within (1 - CHECK_FRACTION) of it.  With 4 and 2
-# substeps the estimate's error is below 1e-6 at the 99.9th percentile and no
-# accepted cell exceeded 1e-4 at 1/2; with 2 and 1 it reaches 4e-5, 7 to 13 of
-# 6.3 M accepted cells exceeded 1e-4 at 1/2 and none at 1/4.
-CHECK_FRACTION = 0.5
-# check fraction for a coarse stage of 2 substeps
-CHECK_FRACTION_COARSE2 = 0.25
+# Settings of the gated stage, chosen by measurement on the 128^3 workload
+# (stage tolerance 1e-4; errors against the plain stage on every cell of the
+# first and of the tenth slow step; 10 timed slow steps):
+#   * N_COARSE: substeps of the coarse FP64 stage the network corrects (the
+#     check also runs it with half as many).  With 2 a slow step takes 19.8 ms
+#     against 22.7 ms with 4, and the trained correction has something to fix
+#     (the 2-substep stage misses the tolerance on 0.1% of the first step's
+#     cells): it cuts the fallback by a quarter to a third against a zero
+#     correction.  With 4 the coarse stage alone is within the tolerance on
+#     99.99% of the first step's cells and the correction gains nothing.
+#   * CHECK_FRACTION: the check tolerance as a fraction of the stage tolerance.
+#     An accepted state is within G of the Richardson extrapolation; with 2 and
+#     1 substeps that estimate's own error reaches 4e-5 at the 99.9th
+#     percentile, and at 1/2 of 1e-4, 7 to 13 of 6.3 M accepted cells exceeded
+#     1e-4 on the first step, none at 1/4.
+#   * STIFF_LIMIT: the coarse solve's stiffness monitor rejects every cell with
+#     h B above it (h the coarse step, B the Gershgorin bound of the chemistry
+#     Jacobian at the stage start).  The Richardson estimate of a step outside
+#     the asymptotic regime can agree with a wrong correction: on the tenth
+#     slow step, without the monitor 532 (2 substeps) and 27 (4 substeps)
+#     accepted cells exceeded 1e-4 by up to 0.9; at 1.0, 19 and 2 did; at 0.5
+#     none did, on either step, with or without the network.
+N_COARSE = 2
+CHECK_FRACTION = 0.25
+STIFF_LIMIT = 0.5
+# the other coarse setting, measured beside it in the benchmark
+N_COARSE_ALT = 4
+CHECK_FRACTION_ALT = 0.5
 
 
 def _torch():
@@ -245,9 +254,10 @@ def stage_error(y_pred, y_ref, n_species, floor=1e-8):
     return ((y_pred - y_ref).abs() / torch.maximum(y_ref.abs(), fl)).amax(0)
 
 
-def slow_step_stages(m, workload=I.FIELD128):
+def slow_step_stages(m, workload=I.FIELD128, step=0):
     """Start state, forcing and length of every fast stage of the workload's
-    first MIS-KW3 slow step (slow RHS by the advection-diffusion kernel, forcing
+    MIS-KW3 slow step number `step` (0: the first; the steps before it are taken
+    with the plain method: slow RHS by the advection-diffusion kernel, forcing
     assembly by libmri, stages advanced by the plain FP64 fast stage of mechanism
     handle m with the workload's substeps), as device tensors."""
     torch = _torch()
@@ -263,17 +273,19 @@ def slow_step_stages(m, workload=I.FIELD128):
     uptr = mri.C.cast(mri.C.pointer(params), mri.C.c_void_p).value
     sp = torch.cuda.current_stream().cuda_stream
     out = []
-    for i in range(1, tb.s):
-        rc = mri.lib.mri_advdiff_slow_rhs(tb.c[i - 1] * cfg.H, y.data_ptr(), F[i - 1].data_ptr(),
-                                          N, ld, uptr, sp)
-        assert rc == 0
-        rho = torch.empty((1, n, ld), dtype=torch.float64, device="cuda")
-        mri.mri_forcing_assemble(t, i, n, ld, F, rho)
-        L = float((tb.c[i] - tb.c[i - 1]) * cfg.H)
-        out.append((y, rho, L))
-        y_next = torch.empty_like(y)
-        mri.mri_fast_stage(m, mri.fast_opts(n_sub=cfg.n_sub), N, ld, y, y_next, 1, rho, L)
-        y = y_next
+    for k in range(step + 1):
+        for i in range(1, tb.s):
+            rc = mri.lib.mri_advdiff_slow_rhs((k + tb.c[i - 1]) * cfg.H, y.data_ptr(),
+                                              F[i - 1].data_ptr(), N, ld, uptr, sp)
+            assert rc == 0
+            rho = torch.empty((1, n, ld), dtype=torch.float64, device="cuda")
+            mri.mri_forcing_assemble(t, i, n, ld, F, rho)
+            L = float((tb.c[i] - tb.c[i - 1]) * cfg.H)
+            if k == step:
+                out.append((y, rho, L))
+            y_next = torch.empty_like(y)
+            mri.mri_fast_stage(m, mri.fast_opts(n_sub=cfg.n_sub), N, ld, y, y_next, 1, rho, L)
+            y = y_next
     torch.cuda.synchronize()
     return out, N, ld
 
@@ -305,9 +317,10 @@ def _timed(torch, fn, repeats):
 
 
 def evaluate(params, stats, workload=I.FIELD128, gate_tol=1e-4, check_tol=None,
-             n_coarse=N_COARSE, repeats=3, log=print):
+             n_coarse=N_COARSE, repeats=3, log=print, step=0, stiff_limit=None):
     """Gated surrogate stage against the plain FP64 stage on every cell of the
-    three fast stages of the workload's first slow step: fallback fraction,
+    three fast stages of the workload's slow step `step` (0: the first; the
+    state reached by the plain method before it): fallback fraction,
     false accepts (accepted cells whose error exceeds the tolerance gate_tol),
     error of the accepted cells, the errors of the coarse result, its Richardson
     extrapolation and the network's correction on their own, the same pipeline
@@ -324,10 +337,12 @@ def evaluate(params, stats, workload=I.FIELD128, gate_tol=1e-4, check_tol=None,
     S = mech.n_species
     m = mri.Mech(mech)
     m.specialize(128, load=True)
-    stages, N, ld = slow_step_stages(m, workload)
+    stages, N, ld = slow_step_stages(m, workload, step)
     plain = mri.fast_opts(n_sub=cfg.n_sub)
-    coarse = mri.fast_opts(n_sub=n_coarse)
+    sl = STIFF_LIMIT if stiff_limit is None else stiff_limit
+    coarse = mri.fast_opts(n_sub=n_coarse, stiff_limit=sl)
     half = mri.fast_opts(n_sub=n_coarse // 2)
+    coarse_plain = mri.fast_opts(n_sub=n_coarse)
     nets = {"learned": mri.Surrogate(WIDTHS, params, stats),
             "no_network": mri.Surrogate(WIDTHS, *zero_network())}
     ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
@@ -347,7 +362,8 @@ def evaluate(params, stats, workload=I.FIELD128, gate_tol=1e-4, check_tol=None,
         ref = torch.empty_like(y)
         tp = _timed(torch, lambda: mri.mri_fast_stage(m, plain, N, ld, y, ref, 1, rho, L), repeats)
         vc, vh, vn = torch.empty_like(y), torch.empty_like(y), torch.empty_like(y)
-        tc = _timed(torch, lambda: mri.mri_fast_stage(m, coarse, N, ld, y, vc, 1, rho, L), repeats)
+        tc = _timed(torch, lambda: mri.mri_fast_stage(m, coarse_plain, N, ld, y, vc, 1, rho, L),
+                    repeats)
         th = _timed(torch, lambda: mri.mri_fast_stage(m, half, N, ld, y, vh, 1, rho, L), repeats)
         sg = nets["learned"]
         ti = _timed(torch, lambda: sg.infer(N, ld, y, vn, 1, rho, L, base=vc), repeats)

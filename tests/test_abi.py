@@ -224,6 +224,12 @@ def test_specialized_kernels_compile_for_gfx950(mri, workload):
     assert nbytes > 1000
 
 
+@pytest.mark.parametrize("workload", [I.SMALL, I.FIELD64, I.LARGE128])
+def test_specialized_stiffness_monitor_compiles(mri, workload):
+    m = mri.Mech(I.make_mechanism(workload))
+    assert m.specialize_monitor(load=False) > 0
+
+
 def test_specialized_kernels_compile_for_every_fast_method(mri):
     m = mri.Mech(I.make_mechanism(I.SMALL))
     for meth in (mri.FAST_RK4, mri.FAST_ZONNEVELD43, mri.FAST_HEUN, mri.FAST_BS3,

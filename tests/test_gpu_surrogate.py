@@ -378,23 +378,32 @@ def test_gate_matches_oracle(torch, mri, oracle_mod):
     assert np.all(yo[:, :N][:, ~acc] == sentinel) and np.all(yo[:, N:] == sentinel)
 
 
-def _oracle_stage(O, mech, widths, p, st, y, rho, L, N, n_coarse, n_fine, tol):
+def _oracle_stage(O, mech, widths, p, st, y, rho, L, N, n_coarse, n_fine, tol, stiff_limit=0.0):
     return O.sur_stage(O.Oracle(mech), widths, p.astype(np.float64), st, y, rho, L, n_coarse,
-                       n_fine, tol, N=N)
+                       n_fine, tol, N=N, stiff_limit=stiff_limit)
 
 
-@pytest.mark.parametrize("in_place", [False, True])
-def test_gated_stage_matches_oracle(torch, mri, oracle_mod, in_place):
+@pytest.mark.parametrize("in_place,stiff", [(False, False), (True, False), (False, True)])
+def test_gated_stage_matches_oracle(torch, mri, oracle_mod, in_place, stiff):
     """The whole gated stage (coarse FP64 stage at 4 and 2 substeps, network
     correction, residual check, compacted plain fallback at 50 substeps,
     scatter) against the oracle's composition of the same steps on 700 cells:
     same accept decisions away from the threshold, accepted cells within the
     network tolerance, fallback cells within the parity bound 1e-10 of the
-    oracle's plain stage, status words and the device fallback count."""
+    oracle's plain stage, status words and the device fallback count.  With
+    `stiff`, the coarse solve's stiffness monitor runs at a limit that flags
+    a third of the cells (h B above it, h the coarse step), which the oracle
+    rejects as well."""
     O = oracle_mod
     N, L = 700, 1e-7 / 3.0
     mech, y, rho = _cells(N, 41)
     n, ld = y.shape
+    sl = 0.0
+    near_s = np.zeros(N, dtype=bool)
+    if stiff:
+        hB = (L / 4) * O.Oracle(mech).stiff_bound(np.ascontiguousarray(y[:, :N]))
+        sl = float(np.quantile(hB, 2.0 / 3.0))
+        near_s = np.abs(hB / sl - 1.0) < 1e-10
     y_std = np.full(22, 1e-9)
     y_std[21] = 1e-6
     widths, p, st = _net_and_stats(O, 42, y, rho, L, N, y_std)
@@ -402,7 +411,7 @@ def test_gated_stage_matches_oracle(torch, mri, oracle_mod, in_place):
     # outcomes occur
     _, _, G0, _ = _oracle_stage(O, mech, widths, p, st, y, rho, L, N, 4, 50, 0.0)
     tol = float(np.nanquantile(G0, 0.5))
-    out_o, acc_o, G_o, sf_o = _oracle_stage(O, mech, widths, p, st, y, rho, L, N, 4, 50, tol)
+    out_o, acc_o, G_o, sf_o = _oracle_stage(O, mech, widths, p, st, y, rho, L, N, 4, 50, tol, sl)
     m = mri.Mech(mech)
     sg = mri.Surrogate(widths, p, st)
     yd, rd = _dev(torch, y), _dev(torch, rho)
@@ -413,11 +422,11 @@ def test_gated_stage_matches_oracle(torch, mri, oracle_mod, in_place):
     gv = torch.zeros(ld, dtype=torch.float64, device="cuda")
     stt = torch.full((ld,), 99, dtype=torch.int32, device="cuda")
     nf = torch.zeros(1, dtype=torch.int32, device="cuda")
-    sg.stage(m, mri.fast_opts(n_sub=4), mri.fast_opts(n_sub=50), tol, N, ld, yd, out, 1, rd, L,
-             ws, used, gv, stt, nf)
+    sg.stage(m, mri.fast_opts(n_sub=4, stiff_limit=sl), mri.fast_opts(n_sub=50), tol, N, ld, yd,
+             out, 1, rd, L, ws, used, gv, stt, nf)
     torch.cuda.synchronize()
     acc = used.cpu().numpy()[:N] == 0
-    near = np.abs(G_o / tol - 1.0) < 1e-4
+    near = (np.abs(G_o / tol - 1.0) < 1e-4) | near_s
     print(f"gated stage: tol {tol:.2e}, oracle accepts {acc_o.sum()} of {N}, "
           f"{near.sum()} near the threshold")
     assert np.array_equal(acc[~near], acc_o[~near])
@@ -516,7 +525,7 @@ def test_trained_network_gain(torch, mri):
     or without the network, and the gated stage is faster than the plain
     stage."""
     from paper_2211_03293_amd import surrogate as S
-    nc, frac = 2, S.CHECK_FRACTION_COARSE2
+    nc, frac = S.N_COARSE, S.CHECK_FRACTION
     data = S.generate_stage_data(n_full=1_000_000, n_coarse=nc, log=print)
     res = S.train(data, steps=20000, batch=8192, log=print, log_every=10000)
     del data
