@@ -257,22 +257,17 @@ def _net_and_stats(oracle_mod, seed, y, rho, L, N, y_std):
     return widths, p, st
 
 
-@pytest.mark.parametrize("n_poly", [1, 2, 3])
-def test_fused_inference_matches_oracle(torch, mri, oracle_mod, n_poly):
-    """The fused kernel (features in LDS, weights streamed, activations in
-    registers, FP64 de-standardization) against the oracle's bfloat16-mode
-    inference, element by element in standardized output units z, on 1000
-    cells (7 full blocks of 128 and a ragged tail) with a base state."""
-    O = oracle_mod
-    N = 1000
-    mech, y, rho = _cells(N, 15 + n_poly, n_poly=n_poly)
-    rng = np.random.Generator(np.random.PCG64(20 + n_poly))
+def _check_inference(torch, mri, O, N, seed, n_poly):
+    # statistics over at least 1000 cells (a handful of cells has degenerate
+    # feature deviations); the first N cells are inferred
+    mech, y, rho = _cells(max(N, 1000), seed, n_poly=n_poly)
+    rng = np.random.Generator(np.random.PCG64(seed + 5))
     n, ld = y.shape
     base = y * (1 + 1e-3 * rng.normal(size=y.shape))
     L = 3.3e-8
     y_std = np.full(22, 1e-3)
     y_std[21] = 0.5
-    widths, p, st = _net_and_stats(O, 21, y, rho, L, N, y_std)
+    widths, p, st = _net_and_stats(O, 21, y, rho, L, max(N, 1000), y_std)
     out_o, z_o = O.sur_infer(21, widths, p.astype(np.float64), st, y, rho, L, N=N, base=base,
                              bf16=True, want_z=True)
     sg = mri.Surrogate(widths, p, st)
@@ -287,16 +282,34 @@ def test_fused_inference_matches_oracle(torch, mri, oracle_mod, n_poly):
     a = np.abs(dz)
     rel = np.linalg.norm(dz) / np.linalg.norm(z_o)
     exact = (a.max(axis=0) <= 1e-4).mean()
-    print(f"n_poly {n_poly}: |dz| median {np.median(a):.1e}, p99 {np.quantile(a, 0.99):.1e}, "
-          f"max {a.max():.1e}; norm-wise {rel:.1e}; cells within 1e-4: {exact:.3f}")
+    print(f"N {N}, n_poly {n_poly}: |dz| median {np.median(a):.1e}, "
+          f"p99 {np.quantile(a, 0.99):.1e}, max {a.max():.1e}; norm-wise {rel:.1e}; "
+          f"cells within 1e-4: {exact:.3f}")
     # measured: norm-wise 1.0e-4, median 4e-13..4e-9, max 7e-4..9e-4, 99% of the
     # cells within 1e-4 (the rest moved by a flipped bfloat16 activation)
     assert rel <= 3e-4
     assert np.median(a) <= 1e-6
     assert a.max() <= 3e-3
-    assert exact >= 0.97
+    assert exact >= (0.97 if N >= 100 else 0.0)
     # cells beyond N are not written
     assert not g[:, N:].any()
+
+
+@pytest.mark.parametrize("n_poly", [1, 2, 3])
+def test_fused_inference_matches_oracle(torch, mri, oracle_mod, n_poly):
+    """The fused kernel (features in LDS, weights streamed, activations in
+    registers, FP64 de-standardization) against the oracle's bfloat16-mode
+    inference, element by element in standardized output units z, on 1000
+    cells (7 full blocks of 128 and a ragged tail) with a base state."""
+    _check_inference(torch, mri, oracle_mod, 1000, 15 + n_poly, n_poly)
+
+
+@pytest.mark.parametrize("N", [1, 33, 40_017])
+def test_fused_inference_sizes(torch, mri, oracle_mod, N):
+    """One cell, one wave's 32 cells plus one, and 40,017 cells (313 blocks
+    of 128, the last ragged): idle lanes, partly idle waves and a grid of
+    more blocks than compute units."""
+    _check_inference(torch, mri, oracle_mod, N, 40 + N % 7, 2)
 
 
 def _gate_inputs(seed, N=3000, S=21):
