@@ -334,24 +334,29 @@ def plain_leg(torch, mri, I, workload, steps, warmup, block, kernel_name):
                             flagged_cells=n_bad))
 
 
-def imex_leg(torch, mri, I, steps=5, warmup=1):
-    """IMEX-MRI-GARK steps (2nd-order solve-decoupled table: one fast stage over
-    the step, one implicit diffusion stage) on the 64^3 fields with the
-    diffusion number H D / dx^2 = 1, where the explicit MIS-KW3 table diverges;
-    RK4 with 120 substeps (the explicit workload's largest fast step).  Wall
+def imex_leg(torch, mri, I, steps=5, warmup=1, order=3):
+    """IMEX-MRI-GARK steps on the 64^3 fields with the diffusion number
+    H D / dx^2 = 1, where the explicit MIS-KW3 table diverges: the 3rd-order
+    solve-decoupled table (three fast stages of H/3, three implicit diffusion
+    stages) or the 2nd-order one (one fast stage over the step, one implicit
+    stage); RK4 at the explicit workload's largest fast step H / 120.  Wall
     time per step, fast-kernel time, conjugate-gradient iterations per solve,
     and one diffusion solve timed alone for its HBM roofline (algorithmic
     traffic 11 planes per iteration: the stencil reads p and writes q, the
     update reads x, p, r, q and writes x, r, the direction update reads r, p
-    and writes p).  The explicit table's first flagged step on the same state
-    plus a 1e-6 K checkerboard is reported beside it."""
+    and writes p).  With the 3rd-order table, the explicit table's first
+    flagged step on the same state plus a 1e-6 K checkerboard is reported
+    beside it."""
     cfg = I.WORKLOADS[I.FIELD64]
     P = I.ADVDIFF_STIFF
     mech = I.make_mechanism(I.FIELD64)
     N = cfg.n_cells
     y_host = I.initial_state(I.FIELD64)
     n, ld = y_host.shape
-    m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+    tab = I.table_imex_mri3() if order == 3 else I.table_imex_trap2()
+    n_sub = I.IMEX3_N_SUB if order == 3 else I.IMEX_N_SUB
+    a_diag = float(sum(tab.gamma[k, 2, 2] / (k + 1) for k in range(tab.gamma.shape[0])))
+    m, t = mri.Mech(mech), mri.ImexTable(tab)
     m.specialize(128, load=True)
     params = mri.advdiff_params(cfg.grid, n, u=P["u"], D=P["D"], dx=P["dx"])
     cws = torch.empty(mri.diffusion_solve_workspace_bytes(params, ld), dtype=torch.uint8,
@@ -361,7 +366,7 @@ def imex_leg(torch, mri, I, steps=5, warmup=1):
     y0 = torch.as_tensor(y_host, device="cuda")
     y = y0.clone()
     status = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    opts = mri.fast_opts(n_sub=I.IMEX_N_SUB)
+    opts = mri.fast_opts(n_sub=n_sub)
     H = cfg.H
     for k in range(warmup):
         mri.mri_imex_slow_step(m, t, opts, ctx, k * H, H, N, ld, y, ws, status_out=status)
@@ -382,13 +387,14 @@ def imex_leg(torch, mri, I, steps=5, warmup=1):
     fast_ms, n_launch = mri.timing_read(reset=True)
     mri.timing_enable(False)
     n_bad = mri.mri_status_count(status, N)
-    # one diffusion solve alone, on the current state, a = H / 2 as in the step
+    # one diffusion solve alone, on the current state, with the first implicit
+    # stage's coefficient a = gbar_33 H
     r = y.clone()
     out = torch.empty_like(r)
-    mri.mri_diffusion_solve(ctx, 0.5 * H, r, out, N, ld)
+    mri.mri_diffusion_solve(ctx, a_diag * H, r, out, N, ld)
     torch.cuda.synchronize()
     e0.record()
-    mri.mri_diffusion_solve(ctx, 0.5 * H, r, out, N, ld)
+    mri.mri_diffusion_solve(ctx, a_diag * H, r, out, N, ld)
     e1.record()
     torch.cuda.synchronize()
     solve_ms = e0.elapsed_time(e1)
@@ -396,6 +402,19 @@ def imex_leg(torch, mri, I, steps=5, warmup=1):
     bytes_alg = 11 * 8 * n * N * it
     gbs = bytes_alg / (solve_ms * 1e-3) / 1e9
     # the explicit table on the same fields with a grid-scale perturbation
+    flagged_at = None
+    if order == 3:
+        flagged_at = explicit_flag_step(torch, mri, I, m, cfg, y0, params, N, ld, H)
+    print(f"# imex (order {order}): {steps} steps {wall_ms:.1f} ms, fast kernels {fast_ms:.1f} ms, "
+          f"CG iterations {iters}, solve {solve_ms:.3f} ms ({gbs:.0f} GB/s algorithmic), explicit "
+          f"flagged at step {flagged_at}", file=sys.stderr, flush=True)
+    return imex_result(order, n, N, steps, wall_ms, fast_ms, iters, solve_ms, gbs, it, n_bad,
+                       flagged_at, n_sub)
+
+
+def explicit_flag_step(torch, mri, I, m, cfg, y0, params, N, ld, H):
+    """First MIS-KW3 step that flags a cell on the fields plus a 1e-6 K
+    grid-scale checkerboard (None within 12 steps)."""
     te = mri.Table(I.table_mis_kw3())
     wse = torch.empty(mri.mri_workspace_bytes(m, te, N, ld) // 8, dtype=torch.float64,
                       device="cuda")
@@ -403,28 +422,35 @@ def imex_leg(torch, mri, I, steps=5, warmup=1):
     ye = y0.clone()
     ye[-1, :N] += torch.as_tensor(1e-6 * ((-1.0) ** (x + yy + z)).ravel(), device="cuda")
     ste = torch.zeros(ld, dtype=torch.int32, device="cuda")
-    flagged_at = None
     for k in range(12):
         mri.mri_slow_step(m, te, mri.fast_opts(n_sub=cfg.n_sub), mri.ADVDIFF_RHS, params, k * H, H,
                           N, ld, ye, wse, status_out=ste)
         if mri.mri_status_count(ste, N) > 0:
-            flagged_at = k + 1
-            break
-    print(f"# imex: {steps} steps {wall_ms:.1f} ms, fast kernels {fast_ms:.1f} ms, CG iterations "
-          f"{iters}, solve {solve_ms:.3f} ms ({gbs:.0f} GB/s algorithmic), explicit flagged at "
-          f"step {flagged_at}", file=sys.stderr, flush=True)
-    return dict(workload="IMEX-MRI-GARK (2nd-order solve-decoupled table) steps, 64^3 cells, 21 "
-                         "species / 84 reactions, H = 1e-7 s, advection explicit, diffusion "
-                         "implicit with D = 0.1 m^2/s (H D / dx^2 = 1), RK4 120 substeps",
-                value=round(N * steps / (wall_ms * 1e-3), 1), unit="cell-steps/s",
-                ms_per_step=round(wall_ms / steps, 3), fast_kernel_ms_per_step=round(
-                    fast_ms / steps, 3), cg_iterations=iters, flagged_cells=n_bad,
-                diffusion_solve=dict(ms=round(solve_ms, 3), iterations=it, cg_rtol=1e-13,
-                                     roofline=dict(bound="hbm", achieved=round(gbs, 1),
-                                                   peak=8000.0, unit="GB/s",
-                                                   frac=round(gbs / 8000.0, 4),
-                                                   bytes_per_iteration=11 * 8 * n * N)),
-                explicit_mis_kw3_first_flagged_step=flagged_at)
+            return k + 1
+    return None
+
+
+def imex_result(order, n, N, steps, wall_ms, fast_ms, iters, solve_ms, gbs, it, n_bad, flagged_at,
+                n_sub):
+    table = ("3rd-order solve-decoupled table, three fast stages of H/3 with RK4 %d substeps, three "
+             "implicit stages" % n_sub if order == 3 else
+             "2nd-order solve-decoupled table, one fast stage over H with RK4 %d substeps, one "
+             "implicit stage" % n_sub)
+    out = dict(workload="IMEX-MRI-GARK steps (%s), 64^3 cells, 21 species / 84 reactions, "
+                        "H = 1e-7 s, advection explicit, diffusion implicit with D = 0.1 m^2/s "
+                        "(H D / dx^2 = 1)" % table,
+               order=order,
+               value=round(N * steps / (wall_ms * 1e-3), 1), unit="cell-steps/s",
+               ms_per_step=round(wall_ms / steps, 3), fast_kernel_ms_per_step=round(
+                   fast_ms / steps, 3), cg_iterations=iters, flagged_cells=n_bad,
+               diffusion_solve=dict(ms=round(solve_ms, 3), iterations=it, cg_rtol=1e-13,
+                                    roofline=dict(bound="hbm", achieved=round(gbs, 1),
+                                                  peak=8000.0, unit="GB/s",
+                                                  frac=round(gbs / 8000.0, 4),
+                                                  bytes_per_iteration=11 * 8 * n * N)))
+    if order == 3:
+        out["explicit_mis_kw3_first_flagged_step"] = flagged_at
+    return out
 
 
 def train_surrogate(n_samples, train_steps, log):
@@ -732,8 +758,9 @@ def main():
                           "synthetic mechanism)",
                 note="other hardware and another integrator; context, not the target"))
     if not args.no_imex:
-        log("# IMEX leg (stiff diffusion)")
-        out["imex"] = imex_leg(torch, mri, I)
+        log("# IMEX legs (stiff diffusion)")
+        out["imex"] = imex_leg(torch, mri, I, order=3)
+        out["imex_order2"] = imex_leg(torch, mri, I, order=2)
     if not args.no_batch:
         log("# batched uneven-set legs (the standard one tunes; the divergent one takes its "
             "choice from the tuning cache)")

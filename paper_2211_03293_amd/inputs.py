@@ -210,6 +210,40 @@ def table_imex_trap2() -> ImexTable:
     return ImexTable("IMEX-MRI-GARK-trap2", c, g, w)
 
 
+def table_imex_mri3() -> ImexTable:
+    """3rd-order solve-decoupled IMEX-MRI-GARK table, s = 7,
+    c = (0, 1/3, 1/3, 2/3, 2/3, 1, 1): fast stages 2, 4, 6 of length H/3 with
+    forcing linear in time, implicit stages 3, 5, 7 (dc = 0), y_(n+1) = Y_7.
+
+    Derived here (derive_imex3_table.py) from the order-3 conditions of one
+    step on three-way split quadratic vector fields against the exact flow,
+    exact row sums (a constant slow tendency is integrated exactly) and an
+    L-stable implicit part: with f^F = f^E = 0 the step is R(z) y_n with
+    R = (1 + 0.5370 z + 0.1050 z^2) / (1 - 0.4630 z + 0.0681 z^2 - 0.0032 z^3),
+    |R| <= 1 on the negative real axis and R(-inf) = 0.  The coefficients are
+    FP64 values of a least-squares solution (order residuals about 1e-13)."""
+    c = np.array([0.0, 1.0 / 3.0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 1.0, 1.0])
+    g = np.zeros((2, 7, 7))
+    w = np.zeros((2, 7, 7))
+    g[0, 1, :1] = [0.3333333333333333]
+    g[0, 2, :3] = [-0.14055348783455268, -0.08064985465503603, 0.22120334248958873]
+    g[0, 3, :3] = [0.032213781813120144, 0.0015626135167343203, 0.2995569380034795]
+    g[0, 4, :5] = [-0.619910360142106, 0.017227884821738967, 0.5851657760422352, -0.09702906068750315, 0.11454575996563497]
+    g[0, 5, :5] = [0.21589011306261846, -0.08814942074251945, 0.06456399842107294, 0.07104135732634824, 0.06998728526581233]
+    g[0, 6, :7] = [0.09710366871062757, 0.44053161781275346, -0.5815798475730799, -0.3142303216519329, 0.013992830250077448, 0.21690649560912834, 0.12727555684242597]
+    g[1, 3, :3] = [-0.08683135001680223, -0.16789024616451798, 0.2547215961813189]
+    g[1, 5, :5] = [0.06231314722761247, 0.21120795253535973, 0.008186915883229423, -0.14401739964512705, -0.13769061600107288]
+    w[0, 1, :1] = [0.3333333333333333]
+    w[0, 2, :2] = [-0.5400393337274775, 0.5400393337274775]
+    w[0, 3, :3] = [0.1125779016953933, -0.007602694356648855, 0.2283581259945884]
+    w[0, 4, :4] = [-0.22349883540104018, 0.14022454333535686, 0.6067439785945805, -0.5234696865288972]
+    w[0, 5, :5] = [0.10237739523931555, -0.24906115031496037, 0.15697749920835516, -0.0674812442659541, 0.39052083346657673]
+    w[0, 6, :6] = [0.15678040875694046, -0.2203952841190962, -0.23626446369293067, 0.14354728916280882, -0.23275118974956494, 0.38908323964184255]
+    w[1, 3, :3] = [-0.2548569527854706, -0.021027114350733775, 0.2758840671362053]
+    w[1, 5, :5] = [0.0936287337088565, -0.041147165330545056, 0.20274987364268302, -0.22879544909149913, -0.02643599292949447]
+    return ImexTable("IMEX-MRI-GARK3 (derived)", c, g, w)
+
+
 # The 64^3 fields with a diffusion coefficient raised so that the diffusion
 # number H D / dx^2 is 1 at H = 1e-7 s: beyond the stability limit of the
 # explicit slow tables (about 0.2 in 3-D for a 3rd-order explicit method), the
@@ -219,6 +253,9 @@ ADVDIFF_STIFF = dict(u=(10.0, 10.0, 10.0), D=0.1, dx=1e-4)
 # whole step): H / 120 is the largest fast step of the explicit 64^3 workload
 # (MIS-KW3's longest stage, 5H/12, over 50 substeps).
 IMEX_N_SUB = 120
+# RK4 substeps of each of table_imex_mri3's three fast stages (H/3 each): the
+# same fast step H / 120.
+IMEX3_N_SUB = 40
 
 
 def table_zero_forcing(c) -> Table:

@@ -11,8 +11,9 @@ collection (run under `rocprofv3 --pmc ...`):
      precede the measured one);
   4. k_infer, the fused inference over the 128^3 cells (random weights: the
      instruction stream does not depend on them);
-  5. one IMEX-MRI-GARK step of the 64^3 stiff-diffusion workload (its fast
-     stage and the conjugate-gradient kernels of the implicit diffusion solve).
+  5. two IMEX-MRI-GARK steps (3rd-order table) of the 64^3 stiff-diffusion
+     workload (its three fast stages per step and the conjugate-gradient
+     kernels of the three implicit diffusion solves).
 
 With --block B the batched plan is fixed to B threads per block instead (the
 register / LDS tiling then follows the MRI_SPEC_WPE, MRI_SPEC_EXP_TABLE and
@@ -133,7 +134,7 @@ def main():
         y = torch.as_tensor(I.initial_state(I.FIELD64), device="cuda")
         n, ld = y.shape
         N = cfg.n_cells
-        m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+        m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_mri3())
         params = mri.advdiff_params(cfg.grid, n, u=P["u"], D=P["D"], dx=P["dx"])
         cws = torch.empty(mri.diffusion_solve_workspace_bytes(params, ld), dtype=torch.uint8,
                           device="cuda")
@@ -141,11 +142,11 @@ def main():
         ws = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8,
                          device="cuda")
         for k in range(2):
-            mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, k * cfg.H, cfg.H,
-                                   N, ld, y, ws)
+            mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=I.IMEX3_N_SUB), ctx, k * cfg.H,
+                                   cfg.H, N, ld, y, ws)
         torch.cuda.synchronize()
         out["imex_64cube"] = dict(kernel="k_cg_*", cells=N, cg_iterations=ctx.cg_iters,
-                                  fast_code_hash=m.code_hash(mri.FAST_RK4, 1, 128))
+                                  fast_code_hash=m.code_hash(mri.FAST_RK4, 2, 128))
     print(json.dumps(out), flush=True)
 
 

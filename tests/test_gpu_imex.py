@@ -120,10 +120,16 @@ def test_diffusion_solve_reports_no_convergence(torch, mri):
     assert e.value.status == mri.MRI_ENOCONV
 
 
-def _oracle_steps(O, X, mech, grid, y0, n_steps, n_sub, H, D):
+# (table, RK4 substeps per fast stage): the 2nd-order table's one fast stage
+# spans H, the 3rd-order table's three span H/3 each; both give the fast step
+# H / 120
+TABLES = {"trap2": (I.table_imex_trap2, I.IMEX_N_SUB), "mri3": (I.table_imex_mri3, I.IMEX3_N_SUB)}
+
+
+def _oracle_steps(O, X, mech, grid, y0, n_steps, n_sub, H, D, tb=None):
     orc = O.Oracle(mech)
     P = I.ADVDIFF_STIFF
-    tb = I.table_imex_trap2()
+    tb = tb or I.table_imex_trap2()
     y = y0.copy()
     for s in range(n_steps):
         y, st = X.imex_mri_step_advdiff(orc, tb, O.rk4_opts(n_sub), grid, y, H, P["u"], D,
@@ -132,16 +138,18 @@ def _oracle_steps(O, X, mech, grid, y0, n_steps, n_sub, H, D):
     return y
 
 
+@pytest.mark.parametrize("table", ["trap2", "mri3"])
 @pytest.mark.parametrize("n_steps", [1, 2])
-def test_imex_slow_step_small_grid(torch, mri, O, X, n_steps):
+def test_imex_slow_step_small_grid(torch, mri, O, X, n_steps, table):
     """The 64^3 workload's physics on a 12 x 10 x 8 periodic grid: IMEX-MRI-GARK
-    steps of H = 1e-7 s with RK4 at 120 substeps (the fast step of the explicit
-    workload), GPU against oracle within the per-component bound of the module
-    docstring.  On this grid the fields' Fourier modes sit near the grid scale,
-    where the stiff diffusion coefficient's explicit share of the first fast
-    stage's forcing overshoots into negative mass fractions (the oracle flags
-    the same cells); D is therefore 1/20 of it here (H D / dx^2 = 0.05), and
-    the full 64^3 case below runs the stiff coefficient."""
+    steps of H = 1e-7 s with RK4 at the fast step H / 120 of the explicit
+    workload, 2nd- and 3rd-order tables, GPU against oracle within the
+    per-component bound of the module docstring.  On this grid the fields'
+    Fourier modes sit near the grid scale, where the stiff diffusion
+    coefficient's explicit share of the first fast stage's forcing overshoots
+    into negative mass fractions (the oracle flags the same cells); D is
+    therefore 1/20 of it here (H D / dx^2 = 0.05), and the full 64^3 case below
+    runs the stiff coefficient."""
     grid = (12, 10, 8)
     N = int(np.prod(grid))
     mech = I.make_mechanism(I.FIELD64)
@@ -149,14 +157,15 @@ def test_imex_slow_step_small_grid(torch, mri, O, X, n_steps):
     n, ld = y0.shape
     H = 1e-7
     D = 0.05 * I.ADVDIFF_STIFF["D"]
-    ref = _oracle_steps(O, X, mech, grid, y0, n_steps, I.IMEX_N_SUB, H, D)
-    m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+    make, n_sub = TABLES[table]
+    ref = _oracle_steps(O, X, mech, grid, y0, n_steps, n_sub, H, D, tb=make())
+    m, t = mri.Mech(mech), mri.ImexTable(make())
     ctx, cws = _ctx(torch, mri, grid, n, ld, D)
     yd = _dev(torch, y0)
     ws = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8, device="cuda")
     st = torch.zeros(ld, dtype=torch.int32, device="cuda")
     for s in range(n_steps):
-        mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, s * H, H, N, ld, yd,
+        mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=n_sub), ctx, s * H, H, N, ld, yd,
                                ws, status_out=st)
     torch.cuda.synchronize()
     g = yd.cpu().numpy()[:, :N]
@@ -167,41 +176,45 @@ def test_imex_slow_step_small_grid(torch, mri, O, X, n_steps):
     err = np.abs(g - r)
     floor = np.r_[np.full(n - 1, 1e-12), 0.0][:, None]
     rel = err / np.maximum(np.abs(r), floor)
-    print(f"{n_steps} IMEX steps: {ctx.cg_iters} CG iterations in the last solve; max rel err "
+    print(f"{table}, {n_steps} IMEX steps: {ctx.cg_iters} CG iterations in the last solve; max rel err "
           f"{rel.max():.2e}; max err / bound {(err / bound).max():.2e}")
     assert np.all(err <= bound)
     assert int(st[:N].abs().sum().item()) == 0
 
 
-def test_imex_full_size_first_step(torch, mri, O, X):
+@pytest.mark.parametrize("table", ["trap2", "mri3"])
+def test_imex_full_size_first_step(torch, mri, O, X, table):
     """One IMEX step of the full 64^3 stiff-diffusion workload (262,144 cells,
-    RK4 120 substeps) against the oracle on every cell (the implicit stage
-    couples every cell, so the oracle integrates them all)."""
+    RK4 at the fast step H / 120), 2nd- and 3rd-order tables, against the
+    oracle on every cell (the implicit stages couple every cell, so the oracle
+    integrates them all)."""
     grid = (64, 64, 64)
     N = 64 ** 3
     mech = I.make_mechanism(I.FIELD64)
     y0 = I.initial_state(I.FIELD64)
     n, ld = y0.shape
     H = 1e-7
-    ref = _oracle_steps(O, X, mech, grid, y0, 1, I.IMEX_N_SUB, H, I.ADVDIFF_STIFF["D"])
-    m, t = mri.Mech(mech), mri.ImexTable(I.table_imex_trap2())
+    make, n_sub = TABLES[table]
+    ref = _oracle_steps(O, X, mech, grid, y0, 1, n_sub, H, I.ADVDIFF_STIFF["D"], tb=make())
+    m, t = mri.Mech(mech), mri.ImexTable(make())
     ctx, cws = _ctx(torch, mri, grid, n, ld, I.ADVDIFF_STIFF["D"])
     yd = _dev(torch, y0)
     ws = torch.empty(mri.mri_imex_workspace_bytes(m, t, N, ld), dtype=torch.uint8, device="cuda")
-    mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, 0.0, H, N, ld, yd, ws)
+    mri.mri_imex_slow_step(m, t, mri.fast_opts(n_sub=n_sub), ctx, 0.0, H, N, ld, yd, ws)
     torch.cuda.synchronize()
     g = yd.cpu().numpy()[:, :N]
     r = ref[:, :N]
     bound = _norm_bound(r, 2 * np.linalg.norm(r, axis=1))
     err = np.abs(g - r)
     floor = np.r_[np.full(n - 1, 1e-12), 0.0][:, None]
-    print(f"64^3 IMEX step: {ctx.cg_iters} CG iterations; max rel err "
+    print(f"64^3 IMEX step ({table}): {ctx.cg_iters} CG iterations; max rel err "
           f"{(err / np.maximum(np.abs(r), floor)).max():.2e}; max err / bound "
           f"{(err / bound).max():.2e}")
     assert np.all(err <= bound)
 
 
-def test_explicit_diverges_where_imex_stays_bounded(torch, mri):
+@pytest.mark.parametrize("table", ["trap2", "mri3"])
+def test_explicit_diverges_where_imex_stays_bounded(torch, mri, table):
     """At H D / dx^2 = 1 on the 64^3 fields with a 1e-6 K grid-scale
     checkerboard added to T: the explicit MIS-KW3 step (its stability
     polynomial at the checkerboard's eigenvalue -12 has modulus 227) flags
@@ -218,7 +231,8 @@ def test_explicit_diverges_where_imex_stays_bounded(torch, mri):
     P = I.ADVDIFF_STIFF
     H = 1e-7
     m = mri.Mech(mech)
-    te, ti = mri.Table(I.table_mis_kw3()), mri.ImexTable(I.table_imex_trap2())
+    make, n_sub = TABLES[table]
+    te, ti = mri.Table(I.table_mis_kw3()), mri.ImexTable(make())
     params = mri.advdiff_params(grid, n, u=P["u"], D=P["D"], dx=P["dx"])
     ye, yi = _dev(torch, y0), _dev(torch, y0)
     wse = torch.empty(mri.mri_workspace_bytes(m, te, N, ld) // 8, dtype=torch.float64,
@@ -232,12 +246,12 @@ def test_explicit_diverges_where_imex_stays_bounded(torch, mri):
     for s in range(12):
         mri.mri_slow_step(m, te, mri.fast_opts(n_sub=50), mri.ADVDIFF_RHS, params, s * H, H, N, ld,
                           ye, wse, status_out=ste)
-        mri.mri_imex_slow_step(m, ti, mri.fast_opts(n_sub=I.IMEX_N_SUB), ctx, s * H, H, N, ld, yi,
+        mri.mri_imex_slow_step(m, ti, mri.fast_opts(n_sub=n_sub), ctx, s * H, H, N, ld, yi,
                                wsi, status_out=sti)
         if flagged_at is None and mri.mri_status_count(ste, N, 0x7) > 0:
             flagged_at = s
         assert mri.mri_status_count(sti, N, 0x7) == 0
-    print(f"explicit step flags cells at step {flagged_at}; IMEX: none")
+    print(f"explicit step flags cells at step {flagged_at}; IMEX ({table}): none")
     assert flagged_at is not None
     Y = yi[:n - 1, :N]
     assert float(Y.min()) > -1e-9 and float(Y.max()) < 1.0 + 1e-9
