@@ -100,6 +100,30 @@ def counter_flops_per_unit(code_hash: str):
     return None
 
 
+def batch_counters_profiled_build(block: int, choice: dict):
+    """Counter entry of the batched kernel taken under rocprofv3 for the same
+    block size and register / LDS variant.  Under the profiler the run-time
+    compilation of this kernel yields different machine code than in a plain
+    run, so this entry never matches the timed kernel's hash; it is reported
+    beside the algorithmic fraction, labelled with both hashes."""
+    p = os.path.join(ROOT, "profiles", "kernel_counters.json")
+    if not os.path.exists(p):
+        return None
+    if choice.get("waves_per_simd") == 1:
+        name = "one wave per SIMD"
+    elif choice.get("exp_table") == 0:
+        name = "polynomial exponential"
+    elif choice.get("sched_window") in (1, 4):
+        name = "scheduling window %d" % choice["sched_window"]
+    else:
+        name = "built-in"
+    for d in json.load(open(p)).get("entries", []):
+        if (d.get("workload", "").startswith("mri_batch_run") and d.get("tile", [0])[0] == block
+                and d.get("variant") == name):
+            return d
+    return None
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -201,6 +225,17 @@ def batch_leg(torch, mri, I, divergent, repeats=3, per_set_baseline=False):
                              kernel="mri_spec_main (batched work queue)",
                              kernel_code_hash=plan.code_hash(0),
                              flops_per_attempted_step=fpa))
+    if per_unit is None:
+        pb = batch_counters_profiled_build(choice["block_size"], choice)
+        if pb:
+            ach = pb["counter_fp64_flops_per_unit"] * useful / (ms * 1e-3) / 1e12
+            res["roofline"]["counters_profiled_build"] = dict(
+                achieved=round(ach, 3), frac=round(ach / PEAK_FP64_TFLOPS, 4),
+                counter_fp64_flops_per_attempted_step=pb["counter_fp64_flops_per_unit"],
+                hbm_over_algorithmic=pb.get("hbm_over_algorithmic"),
+                profiled_code_hash=pb["kernel_code_hash"], variant=pb["variant"],
+                note="counters of the same block size and variant compiled under rocprofv3, "
+                     "whose machine code differs from the timed kernel's")
     if per_set_baseline:
         # the same sets, one fast-stage launch per set (Zonneveld kernel,
         # specialized, default block), sets in order on one stream
