@@ -405,20 +405,44 @@ __host__ __device__ constexpr int chunk_loads(int c)
     return RB * (layer_kin(chunk_layer(c)) / 8) / 256;
 }
 
+// Byte offset, within a chunk's rows, of the piece that wave w's direct-to-LDS
+// load i writes to slot 256 i + 64 w + lane of a buffer with P pieces per row.
+template <int P>
+__device__ __forceinline__ unsigned chunk_src_off(int i, int w, int lane)
+{
+    const int slot = 256 * i + 64 * w + lane;
+    const int row = slot / P, p = (slot % P) ^ (row & 15);
+    return 2u * (unsigned)(row * 8 * P + 8 * p);
+}
+
+// Per-lane offsets of the direct-to-LDS loads (the same for every chunk with
+// the same row length) and the lane bases of the A-fragment reads.
+//
+// A-fragment piece 4 kb + g of row 16 mi + j of a buffer with P pieces per
+// row sits at slot (16 mi + j) P + ((4 kb + g) ^ j).  As (4 kb + g) ^ j =
+// 4 (kb ^ (j >> 2)) + (g ^ (j & 3)) and kb ^ (j >> 2) = (kb & ~3) +
+// ((kb & 3) ^ (j >> 2)), that slot is rd[kb & 3] + 16 mi P + 4 (kb & ~3): four
+// lane bases per row length and a compile-time offset per fragment.
+struct Slots {
+    unsigned ld16[2], ld32[4];   // chunk_src_off for P = 16 (2 loads), 32 (4 loads)
+    int rd16[4], rd32[4];        // A-fragment lane bases (slots) for P = 16, 32
+};
+
 // Issues the direct-to-LDS loads of chunk C into buffer `buf` (wave `w`): wave
-// w's load i fills slots 256 i + 64 w + lane.
+// w's load i fills slots 256 i + 64 w + lane.  `zs` is a scalar zero produced
+// after the preceding barrier (the loads must not move above it).
 template <int C>
-__device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, int w, int lane)
+__device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, int w,
+                                            const Slots &sl, int zs)
 {
     constexpr int l = chunk_layer(C), kin = layer_kin(l), P = kin / 8;
-    // uniform base of the chunk's rows + a lane offset that is the same for
-    // every chunk of the layer
-    const char *W = reinterpret_cast<const char *>(a.W[l] + (size_t)(RB * chunk_rb(C)) * kin);
+    static_assert(P == 16 || P == 32, "row lengths of the stream");
+    static_assert(chunk_loads(C) == (P == 16 ? 2 : 4), "loads per chunk");
+    const char *W =
+        reinterpret_cast<const char *>(a.W[l] + (size_t)(RB * chunk_rb(C)) * kin) + zs;
 #pragma unroll
     for (int i = 0; i < chunk_loads(C); ++i) {
-        const int slot = 256 * i + 64 * w + lane;
-        const int row = slot / P, p = (slot % P) ^ (row & 15);
-        const unsigned off = 2u * (unsigned)(row * kin + 8 * p);
+        const unsigned off = (P == 16) ? sl.ld16[i] : sl.ld32[i];
         __builtin_amdgcn_global_load_lds((const void *)(W + off),
                                          (lds_void_t *)(buf + 8 * (256 * i + 64 * w)), 16, 0, 0);
     }
@@ -428,10 +452,11 @@ __device__ __forceinline__ void chunk_issue(const InferArgs &a, uint16_t *buf, i
 // (loads complete in issue order) and all of its LDS reads have returned (the
 // buffer they read is refilled after this barrier), then joins the block
 // barrier.  Returns a zero that the compiler cannot see through, produced
-// after the barrier: LDS reads and direct-to-LDS loads whose addresses add it
-// cannot be scheduled before the barrier.
+// after the barrier, in a vector register (z) and in a scalar one (zs): LDS
+// reads and direct-to-LDS loads whose addresses add it cannot be scheduled
+// before the barrier.
 template <int N>
-__device__ __forceinline__ int wait_loads_and_barrier()
+__device__ __forceinline__ int wait_loads_and_barrier(int &zs)
 {
     static_assert(N >= 0 && N <= 15, "vmcnt field");
     asm volatile("" ::: "memory");
@@ -439,6 +464,8 @@ __device__ __forceinline__ int wait_loads_and_barrier()
     __builtin_amdgcn_s_barrier();
     int z = 0;
     asm volatile("" : "+v"(z)::"memory");
+    zs = 0;
+    asm volatile("" : "+s"(zs)::"memory");
     return z;
 }
 
@@ -496,7 +523,7 @@ __device__ __forceinline__ auto &layer_out(Act &s)
 // layer's input (the MFMA output layout is the next layer's B layout once its
 // input columns are permuted on the host).
 template <int C>
-__device__ __forceinline__ void chunk_activate(Act &s, const float *bias, int g)
+__device__ __forceinline__ void chunk_activate(Act &s)
 {
     constexpr int l = chunk_layer(C), rb = chunk_rb(C);
     auto &out = layer_out<l>(s);
@@ -506,10 +533,8 @@ __device__ __forceinline__ void chunk_activate(Act &s, const float *bias, int g)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int o = MLP_HID * l + RB * rb + 16 * h + 4 * g + r;
-                v[4 * h + r] = static_cast<__bf16>(silu_f(s.acc[C & 1][h][t][r] + bias[o]));
-            }
+            for (int r = 0; r < 4; ++r)
+                v[4 * h + r] = static_cast<__bf16>(silu_f(s.acc[C & 1][h][t][r]));
         out[rb][t] = v;
     }
 }
@@ -520,34 +545,47 @@ __device__ __forceinline__ void chunk_activate(Act &s, const float *bias, int g)
 // (before the products when chunk C starts a layer, which needs it as input).
 template <int C>
 __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring,
-                                            const float *bias, int w, int lane, int j, int g,
+                                            const float *bias, int w, int g, const Slots &sl,
                                             Act &s)
 {
     constexpr int l = chunk_layer(C), KB = layer_kb(l), P = layer_kin(l) / 8;
     constexpr bool prev_hidden = C > 0 && chunk_layer(C - 1) < 3;
     constexpr bool layer_start = C > 0 && chunk_layer(C - 1) != l;
-    const int z = wait_loads_and_barrier < C + 1 < N_CHUNKS ? chunk_loads(C + 1) : 0 > ();
-    if constexpr (C + 2 < N_CHUNKS) chunk_issue<C + 2>(a, ring.get<C + 2>(), w, lane + z);
-    if constexpr (prev_hidden && layer_start) chunk_activate<C - 1>(s, bias, g);
+    int zs;
+    const int z = wait_loads_and_barrier < C + 1 < N_CHUNKS ? chunk_loads(C + 1) : 0 > (zs);
+    if constexpr (C + 2 < N_CHUNKS) chunk_issue<C + 2>(a, ring.get<C + 2>(), w, sl, zs);
+    if constexpr (prev_hidden && layer_start) chunk_activate<C - 1>(s);
     const uint16_t *buf = ring.get<C>();
     auto &in = layer_in<l>(s);
+    // hidden layers: the accumulators start from the bias (lane (j, g) holds
+    // rows 4 g .. 4 g + 3 of each row tile), so the activation needs no add
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < 2; ++mi) {
+        f32x4 b0 = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (l < 3)
+            b0 = *reinterpret_cast<const f32x4 *>(bias + MLP_HID * l + RB * chunk_rb(C) + 16 * mi +
+                                                  4 * g);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) s.acc[C & 1][mi][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NT; ++t) s.acc[C & 1][mi][t] = b0;
+    }
     // All A fragments of the chunk are requested before the first product, so
     // the products start as soon as the first fragments arrive (LDS returns
     // in order).  The buffer is written only by direct-to-LDS loads, which the
     // compiler does not see as stores to it, so it would be free to move these
     // reads above the barrier that orders them after the other waves' loads of
     // the chunk: their addresses depend on `z`, which the barrier produces.
+    static_assert(P == 16 || P == 32, "row lengths of the stream");
+    const int *lb = (P == 16) ? sl.rd16 : sl.rd32;
+    const uint16_t *bq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bq[q] = buf + 8 * lb[q] + z;
     bf16x8 af[KB][2];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
             af[kb][mi] = *reinterpret_cast<const bf16x8 *>(
-                buf + 8 * ((16 * mi + j) * P + ((4 * kb + g) ^ j)) + z);
+                bq[kb & 3] + 8 * (16 * mi * P + 4 * (kb & ~3)));
     __builtin_amdgcn_sched_barrier(0);       // keep every read ahead of the products
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
@@ -556,15 +594,28 @@ __device__ __forceinline__ void weight_step(const InferArgs &a, const Ring &ring
 #pragma unroll
             for (int t = 0; t < NT; ++t)
                 s.acc[C & 1][mi][t] = mfma(af[kb][mi], in[kb][t], s.acc[C & 1][mi][t]);
-    if constexpr (prev_hidden && !layer_start) chunk_activate<C - 1>(s, bias, g);
+    if constexpr (prev_hidden && !layer_start) {
+        chunk_activate<C - 1>(s);
+#ifndef MLP_NO_INTERLEAVE
+        // The activation of chunk C - 1 does not depend on chunk C's
+        // products: interleave them (one product, then a few vector
+        // instructions), so the vector ALU works while the matrix core runs.
+        constexpr int NM = KB * 2 * NT, PER = (16 * NT * 6 + NM - 1) / NM;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, PER, 0);   // VALU
+        }
+#endif
+    }
 }
 
 template <int... C>
 __device__ __forceinline__ void weight_stream(const InferArgs &a, const Ring &ring,
-                                              const float *bias, int w, int lane, int j, int g,
+                                              const float *bias, int w, int g, const Slots &sl,
                                               Act &s, std::integer_sequence<int, C...>)
 {
-    (weight_step<C>(a, ring, bias, w, lane, j, g, s), ...);
+    (weight_step<C>(a, ring, bias, w, g, sl, s), ...);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WPE))) k_infer(InferArgs a)
@@ -574,13 +625,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
     __shared__ __attribute__((aligned(16))) uint16_t wb2[WCHUNK];
     __shared__ __attribute__((aligned(16))) uint16_t xs[CELLS_PER_BLOCK * XROW];
     const Ring ring{wb0, wb1, wb2};
-    __shared__ float bias[3 * MLP_HID];      // hidden-layer biases
+    __shared__ __attribute__((aligned(16))) float bias[3 * MLP_HID];   // hidden-layer biases
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, j = lane & 15;
+    Slots sl;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) sl.ld16[i] = chunk_src_off<16>(i, w, lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sl.ld32[i] = chunk_src_off<32>(i, w, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int lp = 4 * (q ^ (j >> 2)) + (g ^ (j & 3));
+        sl.rd16[q] = 16 * j + lp;
+        sl.rd32[q] = 32 * j + lp;
+    }
     // the first two weight chunks are in flight while the features are built
-    chunk_issue<0>(a, ring.get<0>(), w, lane);
-    chunk_issue<1>(a, ring.get<1>(), w, lane);
+    chunk_issue<0>(a, ring.get<0>(), w, sl, 0);
+    chunk_issue<1>(a, ring.get<1>(), w, sl, 0);
     for (int e = threadIdx.x; e < 3 * MLP_HID; e += 256) bias[e] = a.b[e / MLP_HID][e % MLP_HID];
     // every wave takes part in the block's barriers; idle cells are clamped
     const long long block0 = (long long)blockIdx.x * CELLS_PER_BLOCK;
@@ -644,7 +706,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
             st.x0[kb][t] = *reinterpret_cast<const bf16x8 *>(
                 xs + (w * 16 * NT + 16 * t + j) * XROW + 32 * kb + 8 * g);
     // ---- three hidden layers and the output layer, one weight stream
-    weight_stream(a, ring, bias, w, lane, j, g, st, std::make_integer_sequence<int, N_CHUNKS>{});
+    weight_stream(a, ring, bias, w, g, sl, st, std::make_integer_sequence<int, N_CHUNKS>{});
     // the output layer is chunk N_CHUNKS - 1 (accumulator set 0)
     static_assert(((N_CHUNKS - 1) & 1) == 0, "output accumulator set");
     const f32x4 (&acc)[2][NT] = st.acc[0];
