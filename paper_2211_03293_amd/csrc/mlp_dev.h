@@ -52,6 +52,14 @@ hipError_t mlp_stats(long long N, long long ld, const double *Y0, int n_poly, co
 hipError_t mlp_infer(const double *yin, const double *base, double *yout, const double *rho,
                      const uint16_t *const *W, const float *const *b, const double *stats,
                      long long ld, int n_cells, int n_poly, double L, hipStream_t s);
+// mlp_infer followed by mlp_gate's check in one launch (base = vc; the network
+// states are not written, accepted cells go to yout as with mlp_gate)
+hipError_t mlp_infer_gate(const double *yin, const double *vc, const double *vh,
+                          const double *rho, const uint16_t *const *W, const float *const *b,
+                          const double *stats, long long ld, int n_cells, int n_poly, double L,
+                          const int *status_c, double rich, double tol, double *yout,
+                          int *used_fallback, double *gval, int *status, int *list,
+                          unsigned int *count, hipStream_t s);
 hipError_t mlp_gate(int n_cells, long long ld, const double *yin, const double *rho, int n_poly,
                     double L, const double *vc, const double *vh, const double *vn,
                     const int *status_c, double rich, double tol, double *yout, int *used_fallback,

@@ -351,6 +351,80 @@ __global__ void k_stats_final(int n_blocks, long long N, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Residual check of the surrogate, G = max(D, I), on FP64 data:
+//   Ve = vc + rich (vc - vh), the Richardson extrapolation of the coarse stage
+//   vc (n substeps) and vh (n / 2 substeps), rich = 1 / (2^p - 1) for a fast
+//   method of order p: an estimate of the fine stage from FP64 work alone;
+//   D = max_c |vn_c - Ve_c| / max(|Ve_c|, floor_c) (floor 1e-8 for mass
+//   fractions, 0 for T), vn the network's correction of vc;
+//   I = the residual of the mass-sum invariant of vn: the chemistry conserves
+//   sum_k Y_k, so over the stage sum_k (vn_k - y0_k) must equal
+//   L sum_p sum_k rho_(p,k) / (p + 1), relative to sum_k |y0_k|.
+// A cell is accepted when G <= tol and neither coarse solve flagged it
+// (status_c, nullable); it takes vn and status 0.  Rejected cells are appended
+// to the fallback list (one atomic per wave, ranks from the ballot mask).
+// gate_cell is the check of cell i (vn_at(c) gives vn's component c); k_gate
+// and the fused inference-and-check run the same code.
+template <bool PRELOAD, typename VN>
+__device__ __forceinline__ bool gate_cell(long long i, long long ld, const double *yin,
+                                          const double *rho, int n_poly, double L,
+                                          const double *vc, const double *vh, VN vn_at,
+                                          const int *status_c, double rich, double tol, double &G)
+{
+    // PRELOAD (few waves per SIMD): every load of the cell is issued before
+    // the arithmetic; the arithmetic is the same, in component order
+    double va[MLP_NC], vb[MLP_NC], vv[MLP_NC], vy[MLP_NS];
+    if constexpr (PRELOAD) {
+#pragma unroll
+        for (int c = 0; c < MLP_NC; ++c) {
+            va[c] = vc[c * ld + i];
+            vb[c] = vh[c * ld + i];
+            vv[c] = vn_at(c);
+            if (c < MLP_NS) vy[c] = yin[c * ld + i];
+        }
+    }
+    double D = 0.0, dsum = 0.0, y0sum = 0.0, fsum = 0.0;
+    bool nan = false;
+#pragma unroll PRELOAD ? MLP_NC : 1
+    for (int c = 0; c < MLP_NC; ++c) {
+        const double a = PRELOAD ? va[c] : vc[c * ld + i];
+        const double h = PRELOAD ? vb[c] : vh[c * ld + i];
+        const double ve = a + rich * (a - h);
+        const double fl = (c < MLP_NS) ? 1e-8 : 0.0;
+        const double v = PRELOAD ? vv[c] : vn_at(c);
+        const double e = fabs(v - ve) / fmax(fabs(ve), fl);
+        nan = nan || (e != e);
+        D = (e > D) ? e : D;
+        if (c < MLP_NS) {
+            const double y0 = PRELOAD ? vy[c] : yin[c * ld + i];
+            dsum += v - y0;
+            y0sum += fabs(y0);
+            for (int p = 0; p < n_poly; ++p)
+                fsum += rho[((long long)p * MLP_NC + c) * ld + i] / (double)(p + 1);
+        }
+    }
+    const double I = fabs(dsum - L * fsum) / fmax(y0sum, 1e-300);
+    nan = nan || (I != I);
+    G = nan ? __builtin_nan("") : fmax(D, I);
+    return nan || !(G <= tol) || (status_c && status_c[i] != 0);
+}
+
+// Appends the wave's rejected cells to the fallback list: one atomic per wave,
+// ranks from the ballot mask (every lane of the wave calls it).
+__device__ __forceinline__ void append_rejected(bool reject, int i, int *list,
+                                                unsigned int *count)
+{
+    const unsigned long long m = __ballot(reject);
+    const int lane = threadIdx.x & 63;
+    unsigned int basepos = 0;
+    if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        if (lane == leader) basepos = atomicAdd(count, (unsigned int)__popcll(m));
+        basepos = __shfl(basepos, leader);
+        if (reject) list[basepos + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    }
+}
+
 // Fused inference: y_out = apply_target(base, y_mean + y_std * MLP(features(y_in,
 // rho', L'))): the network reads the stage start state and predicts the
 // correction of `base` (the coarse FP64 stage result; y_in itself for an
@@ -365,6 +439,17 @@ struct InferArgs {
     const double *yin;
     const double *base;         // state the predicted correction applies to
     double *yout;
+    // the residual check fused after the inference (k_infer<true>): base is
+    // the coarse stage vc, vh the half-resolution one; the other fields as
+    // for k_gate
+    const double *vh;
+    const int *status_c;
+    double rich, tol;
+    int *used_fallback;
+    double *gval;
+    int *status;
+    int *list;
+    unsigned int *count;
     const double *rho;
     const uint16_t *W[4];       // [out_pad][in_pad] bf16, permuted inputs
     const float *b[4];          // [out_pad]
@@ -618,7 +703,11 @@ __device__ __forceinline__ void weight_stream(const InferArgs &a, const Ring &ri
     (weight_step<C>(a, ring, bias, w, g, sl, s), ...);
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WPE))) k_infer(InferArgs a)
+// GATE: the residual check follows in the same launch (the network states go
+// through LDS to one lane per cell, which runs gate_cell exactly as k_gate).
+template <bool GATE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WPE)))
+    k_infer(InferArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint16_t wb0[WCHUNK];
     __shared__ __attribute__((aligned(16))) uint16_t wb1[WCHUNK];
@@ -735,6 +824,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
                 y0[t][mi][r4] = a.base[c * a.ld + cell];
             }
     }
+    // the network states of the wave's cells: to y_out, or (GATE) to LDS,
+    // [component][cell of the block] in the feature buffer, which no wave
+    // reads any more
+    double *vl = reinterpret_cast<double *>(xs);
+    static_assert(sizeof(double) * MLP_NC * CELLS_PER_BLOCK <= sizeof(xs), "gate staging");
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const long long cell = base + 16 * t + j;
@@ -746,23 +840,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
                 const int c = 16 * mi + 4 * g + r4;
                 if (c >= MLP_NC) continue;
                 const double d = mean[mi][r4] + sd[mi][r4] * (double)(acc[mi][t][r4] + bo[mi][r4]);
-                a.yout[c * a.ld + cell] = apply_target(c, y0[t][mi][r4], d);
+                const double v = apply_target(c, y0[t][mi][r4], d);
+                if constexpr (GATE)
+                    vl[c * CELLS_PER_BLOCK + w * 16 * NT + 16 * t + j] = v;
+                else
+                    a.yout[c * a.ld + cell] = v;
             }
+    }
+    if constexpr (GATE) {
+        __syncthreads();
+        // lane l < 16 NT checks cell base + l of its wave
+        const long long i = base + lane;
+        bool reject = false;
+        if (lane < 16 * NT && i < a.n_cells) {
+            const double *vrow = vl + w * 16 * NT + lane;
+            double G;
+            reject = gate_cell<true>(i, a.ld, a.yin, a.rho, a.n_poly, a.L, a.base, a.vh,
+                               [&](int c) { return vrow[c * CELLS_PER_BLOCK]; }, a.status_c,
+                               a.rich, a.tol, G);
+            if (!reject)
+                for (int c = 0; c < MLP_NC; ++c) a.yout[c * a.ld + i] = vrow[c * CELLS_PER_BLOCK];
+            if (a.used_fallback) a.used_fallback[i] = reject ? 1 : 0;
+            if (a.gval) a.gval[i] = G;
+            if (a.status && !reject) a.status[i] = 0;
+        }
+        append_rejected(reject, (int)i, a.list, a.count);
     }
 }
 
-// Residual check of the surrogate, G = max(D, I), on FP64 data:
-//   Ve = vc + rich (vc - vh), the Richardson extrapolation of the coarse stage
-//   vc (n substeps) and vh (n / 2 substeps), rich = 1 / (2^p - 1) for a fast
-//   method of order p: an estimate of the fine stage from FP64 work alone;
-//   D = max_c |vn_c - Ve_c| / max(|Ve_c|, floor_c) (floor 1e-8 for mass
-//   fractions, 0 for T), vn the network's correction of vc;
-//   I = the residual of the mass-sum invariant of vn: the chemistry conserves
-//   sum_k Y_k, so over the stage sum_k (vn_k - y0_k) must equal
-//   L sum_p sum_k rho_(p,k) / (p + 1), relative to sum_k |y0_k|.
-// A cell is accepted when G <= tol and neither coarse solve flagged it
-// (status_c, nullable); it takes vn and status 0.  Rejected cells are appended
-// to the fallback list (one atomic per wave, ranks from the ballot mask).
 __global__ void __launch_bounds__(256)
     k_gate(int n_cells, long long ld, const double *__restrict__ yin,
            const double *__restrict__ rho, int n_poly, double L, const double *__restrict__ vc,
@@ -772,45 +877,18 @@ __global__ void __launch_bounds__(256)
            int *__restrict__ list, unsigned int *count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i < n_cells;
     bool reject = false;
-    if (live) {
-        double D = 0.0, dsum = 0.0, y0sum = 0.0, fsum = 0.0;
-        bool nan = false;
-        for (int c = 0; c < MLP_NC; ++c) {
-            const double a = vc[c * ld + i], h = vh[c * ld + i];
-            const double ve = a + rich * (a - h);
-            const double fl = (c < MLP_NS) ? 1e-8 : 0.0;
-            const double e = fabs(vn[c * ld + i] - ve) / fmax(fabs(ve), fl);
-            nan = nan || (e != e);
-            D = (e > D) ? e : D;
-            if (c < MLP_NS) {
-                const double y0 = yin[c * ld + i];
-                dsum += vn[c * ld + i] - y0;
-                y0sum += fabs(y0);
-                for (int p = 0; p < n_poly; ++p)
-                    fsum += rho[((long long)p * MLP_NC + c) * ld + i] / (double)(p + 1);
-            }
-        }
-        const double I = fabs(dsum - L * fsum) / fmax(y0sum, 1e-300);
-        nan = nan || (I != I);
-        const double G = nan ? __builtin_nan("") : fmax(D, I);
-        reject = nan || !(G <= tol) || (status_c && status_c[i] != 0);
+    if (i < n_cells) {
+        double G;
+        reject = gate_cell<false>(i, ld, yin, rho, n_poly, L, vc, vh,
+                           [&](int c) { return vn[c * ld + i]; }, status_c, rich, tol, G);
         if (!reject)
             for (int c = 0; c < MLP_NC; ++c) yout[c * ld + i] = vn[c * ld + i];
         if (used_fallback) used_fallback[i] = reject ? 1 : 0;
         if (gval) gval[i] = G;
         if (status && !reject) status[i] = 0;
     }
-    const unsigned long long m = __ballot(reject);
-    const int lane = threadIdx.x & 63;
-    unsigned int basepos = 0;
-    if (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        if (lane == leader) basepos = atomicAdd(count, (unsigned int)__popcll(m));
-        basepos = __shfl(basepos, leader);
-        if (reject) list[basepos + __popcll(m & ((1ull << lane) - 1ull))] = i;
-    }
+    append_rejected(reject, i, list, count);
 }
 
 // dst[c*ldd + k] = src[c*lds + list[k]] for planes c < n_planes, k < *count.
@@ -952,7 +1030,7 @@ hipError_t mlp_infer(const double *yin, const double *base, double *yout, const 
                      const uint16_t *const *W, const float *const *b, const double *stats,
                      long long ld, int n_cells, int n_poly, double L, hipStream_t s)
 {
-    InferArgs a;
+    InferArgs a{};
     a.yin = yin;
     a.base = base ? base : yin;
     a.yout = yout;
@@ -966,7 +1044,42 @@ hipError_t mlp_infer(const double *yin, const double *base, double *yout, const 
     a.n_cells = n_cells;
     a.n_poly = n_poly;
     a.L = L;
-    hipLaunchKernelGGL(k_infer, grid1(n_cells, CELLS_PER_BLOCK), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_infer<false>, grid1(n_cells, CELLS_PER_BLOCK), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t mlp_infer_gate(const double *yin, const double *vc, const double *vh,
+                          const double *rho, const uint16_t *const *W, const float *const *b,
+                          const double *stats, long long ld, int n_cells, int n_poly, double L,
+                          const int *status_c, double rich, double tol, double *yout,
+                          int *used_fallback, double *gval, int *status, int *list,
+                          unsigned int *count, hipStream_t s)
+{
+    InferArgs a{};
+    a.yin = yin;
+    a.base = vc;
+    a.yout = yout;
+    a.rho = rho;
+    for (int l = 0; l < 4; ++l) {
+        a.W[l] = W[l];
+        a.b[l] = b[l];
+    }
+    a.stats = stats;
+    a.ld = ld;
+    a.n_cells = n_cells;
+    a.n_poly = n_poly;
+    a.L = L;
+    a.vh = vh;
+    a.status_c = status_c;
+    a.rich = rich;
+    a.tol = tol;
+    a.used_fallback = used_fallback;
+    a.gval = gval;
+    a.status = status;
+    a.list = list;
+    a.count = count;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, count);
+    hipLaunchKernelGGL(k_infer<true>, grid1(n_cells, CELLS_PER_BLOCK), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

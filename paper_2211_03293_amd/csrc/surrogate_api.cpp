@@ -428,13 +428,13 @@ mri_status mri_surrogate_stage(const mri_surrogate *s, const mri_mech *mech,
     st = mri_internal_fast_stage(m, &half, n_cells, ld, y_in, vh, n_poly, rho, L, st_c, nullptr,
                                  hs, nullptr, 1);
     if (st != MRI_OK) return st;
-    // the network's correction of the coarse result
-    HIP_TRY(mlp_infer(y_in, vc, vn, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, hs));
-    // residual check against the Richardson extrapolation; accepted cells take
-    // the corrected state, the others go to the fallback list
+    // the network's correction of the coarse result and, in the same launch,
+    // the residual check against the Richardson extrapolation; accepted cells
+    // take the corrected state, the others go to the fallback list
     const double rich = 1.0 / (std::ldexp(1.0, method_order(coarse->method)) - 1.0);
-    HIP_TRY(mlp_gate(n_cells, ld, y_in, rho, n_poly, L, vc, vh, vn, st_c, rich, gate_tol, y_out,
-                     used_fallback, gate_value, status_out, list, count, hs));
+    HIP_TRY(mlp_infer_gate(y_in, vc, vh, rho, s->W, s->b, s->stats, ld, n_cells, n_poly, L, st_c,
+                           rich, gate_tol, y_out, used_fallback, gate_value, status_out, list,
+                           count, hs));
     // plain FP64 stage of the rejected cells: compacted (state into vh, forcing
     // into rho_c), integrated into vn with a launch sized for every cell whose
     // kernels stop at the device count, scattered back; no host synchronization

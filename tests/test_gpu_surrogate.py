@@ -526,6 +526,65 @@ def test_gated_stage_limits_and_graph_replay(torch, mri, oracle_mod):
         assert int(nf.item()) == n_eager and float(scratch.item()) == float(scratch.item())
 
 
+@pytest.mark.parametrize("N", [1, 3000])
+def test_gated_stage_equals_separate_launches(torch, mri, oracle_mod, N):
+    """The gated stage runs the inference and the residual check in one launch.
+    The same steps as separate library calls (the coarse and half-resolution
+    stages, mri_surrogate_infer on the coarse result, mri_surrogate_gate) give
+    bitwise the same gate values, accept decisions, fallback count and accepted
+    states, on one cell and on 3000 (23 blocks of 128 cells and a ragged
+    tail)."""
+    L = 1e-7 / 3.0
+    mech, y, rho = _cells(max(N, 1000), 61)
+    n, ld = y.shape
+    y_std = np.full(22, 1e-9)
+    y_std[21] = 1e-6
+    widths, p, st = _net_and_stats(oracle_mod, 62, y, rho, L, max(N, 1000), y_std)
+    m = mri.Mech(mech)
+    sg = mri.Surrogate(widths, p, st)
+    yd, rd = _dev(torch, y), _dev(torch, rho)
+    coarse, half, fine = mri.fast_opts(n_sub=4), mri.fast_opts(n_sub=2), mri.fast_opts(n_sub=10)
+    vc, vh, net = (torch.empty_like(yd) for _ in range(3))
+    s_c = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    s_h = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    mri.mri_fast_stage(m, coarse, N, ld, yd, vc, 1, rd, L, status_out=s_c)
+    mri.mri_fast_stage(m, half, N, ld, yd, vh, 1, rd, L, status_out=s_h)
+    sg.infer(N, ld, yd, net, 1, rd, L, base=vc)
+    # a threshold that splits the cells, from the separate check's values
+    sep_out = torch.zeros_like(yd)
+    sep_used = torch.full((ld,), 5, dtype=torch.int32, device="cuda")
+    sep_gv = torch.zeros(ld, dtype=torch.float64, device="cuda")
+    lst = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st_c = s_c | s_h
+    mri.mri_surrogate_gate(N, ld, yd, 1, rd, L, vc, vh, net, 1.0 / 15.0, float("inf"), sep_out,
+                           lst, cnt, status_coarse=st_c, used_fallback=sep_used,
+                           gate_value=sep_gv)
+    torch.cuda.synchronize()
+    tol = float(torch.nanquantile(sep_gv[:N], 0.5).item())
+    mri.mri_surrogate_gate(N, ld, yd, 1, rd, L, vc, vh, net, 1.0 / 15.0, tol, sep_out, lst, cnt,
+                           status_coarse=st_c, used_fallback=sep_used, gate_value=sep_gv)
+    ws = torch.empty(mri.Surrogate.workspace_bytes(N, ld, 1) // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    out = torch.zeros_like(yd)
+    used = torch.full((ld,), 5, dtype=torch.int32, device="cuda")
+    gv = torch.zeros(ld, dtype=torch.float64, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sg.stage(m, coarse, fine, tol, N, ld, yd, out, 1, rd, L, ws, used, gv, n_fallback=nf)
+    torch.cuda.synchronize()
+    acc = sep_used[:N] == 0
+    print(f"N {N}: {int(acc.sum())} accepted, {int(cnt.item())} to the fallback")
+    assert torch.equal(used[:N], sep_used[:N])
+    g, gs = gv[:N], sep_gv[:N]
+    assert torch.equal(torch.isnan(g), torch.isnan(gs))
+    assert torch.equal(g[~torch.isnan(g)], gs[~torch.isnan(gs)])
+    assert int(nf.item()) == int(cnt.item()) == int((~acc).sum().item())
+    assert torch.equal(out[:, :N][:, acc], net[:, :N][:, acc])
+    assert torch.equal(out[:, :N][:, acc], sep_out[:, :N][:, acc])
+    if N > 1:
+        assert 0 < int(acc.sum()) < N
+
+
 def test_trained_network_gain(torch, mri):
     """What training buys, on every cell of the three fast stages of the 128^3
     workload's first slow step (errors against the plain FP64 stage of 50
