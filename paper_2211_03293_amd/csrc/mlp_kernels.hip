@@ -856,8 +856,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MLP_WP
             const double *vrow = vl + w * 16 * NT + lane;
             double G;
             reject = gate_cell<true>(i, a.ld, a.yin, a.rho, a.n_poly, a.L, a.base, a.vh,
-                               [&](int c) { return vrow[c * CELLS_PER_BLOCK]; }, a.status_c,
-                               a.rich, a.tol, G);
+                                     [&](int c) { return vrow[c * CELLS_PER_BLOCK]; },
+                                     a.status_c, a.rich, a.tol, G);
             if (!reject)
                 for (int c = 0; c < MLP_NC; ++c) a.yout[c * a.ld + i] = vrow[c * CELLS_PER_BLOCK];
             if (a.used_fallback) a.used_fallback[i] = reject ? 1 : 0;
@@ -881,7 +881,7 @@ __global__ void __launch_bounds__(256)
     if (i < n_cells) {
         double G;
         reject = gate_cell<false>(i, ld, yin, rho, n_poly, L, vc, vh,
-                           [&](int c) { return vn[c * ld + i]; }, status_c, rich, tol, G);
+                                  [&](int c) { return vn[c * ld + i]; }, status_c, rich, tol, G);
         if (!reject)
             for (int c = 0; c < MLP_NC; ++c) yout[c * ld + i] = vn[c * ld + i];
         if (used_fallback) used_fallback[i] = reject ? 1 : 0;
