@@ -151,8 +151,10 @@ mri_status mri_surrogate_workspace_bytes(int n_cells, int ld, int n_poly, size_t
    coarse.stiff_limit > 0 its stiffness monitor flags, and so rejects, every
    cell with h B above the limit, h = L / n_sub) and the same with n_sub / 2, the network's correction of the coarse result, the
    residual check of mri_surrogate_gate (richardson from the coarse method's
-   order), and the plain FP64 fast stage (`fallback` options) of every rejected
-   cell, compacted, integrated and scattered back.  Nothing synchronizes the
+   order; the correction and the check run in one launch and give bitwise the
+   results of mri_surrogate_infer followed by mri_surrogate_gate), and the
+   plain FP64 fast stage (`fallback` options) of every rejected cell,
+   compacted, integrated and scattered back.  Nothing synchronizes the
    host: the fallback launch is sized for n_cells and its kernels stop at the
    count the check left on the device.  used_fallback (nullable, int32
    [n_cells]), gate_value (nullable, FP64 [n_cells]) as in mri_surrogate_gate;
